@@ -1,0 +1,464 @@
+"""Independent checks ("pins") of the FP64 oracle against what the paper and the
+mathematics fix.  Every pin takes a ``mutation`` code so that the tests can
+plant a mistake in the oracle and show that at least one pin catches it.
+
+Each function returns (ok, detail) where ``detail`` carries the measured error.
+Nothing here reuses the oracle's arithmetic: the references are dense matrix
+exponentials built from the operator definitions, closed forms, ODE solutions
+of the Gaussian ansatz, brute-force sums and invariants.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.linalg
+from scipy.integrate import solve_ivp
+
+import oracle
+from oracle import Problem, SCHED_CONST, SCHED_NESTEROV, SCHED_TABLE, SCHEME_LIE, SCHEME_STRANG
+
+
+# ----------------------------------------------------------------------------------------
+# operator definitions (App. C.2.1 / E.1): V = diag(f); -1/2 Lap on the periodic mesh is
+# the Fourier multiplier |k|^2 / 2 with k = 2 pi n / L, n in {-N/2 .. N/2-1}
+
+
+def dense_kinetic_1d(n: int, length: float) -> np.ndarray:
+    """(-1/2 d^2/dx^2) on n periodic points of a box of the given length, written
+    out from its Fourier-series definition K_{mj} = (1/n) sum_p (k_p^2/2) e^{i k_p (x_m - x_j)}."""
+    h = length / n
+    x = np.arange(n) * h
+    ns = np.arange(-n // 2, n // 2)
+    k = 2.0 * math.pi * ns / length
+    diff = x[:, None] - x[None, :]
+    K = np.zeros((n, n), dtype=np.complex128)
+    for kp in k:
+        K += 0.5 * kp * kp * np.exp(1j * kp * diff)
+    return K / n
+
+
+def dense_kinetic(shape, box) -> np.ndarray:
+    """Kronecker sum of the 1-D operators, flat index in C order (last axis fastest)."""
+    nd = len(shape)
+    mats = [dense_kinetic_1d(shape[a], box[a][1] - box[a][0]) for a in range(nd)]
+    total = int(np.prod(shape))
+    K = np.zeros((total, total), dtype=np.complex128)
+    for a in range(nd):
+        term = np.array([[1.0]], dtype=np.complex128)
+        for b in range(nd):
+            term = np.kron(term, mats[b] if b == a else np.eye(shape[b]))
+        K += term
+    return K
+
+
+def brute_dft(x: np.ndarray, sign: int) -> np.ndarray:
+    """O(N^2)-per-axis DFT written out: X_k = sum_m x_m exp(sign 2 pi i m k / N)."""
+    out = np.asarray(x, dtype=np.complex128)
+    for ax in range(out.ndim):
+        n = out.shape[ax]
+        m = np.arange(n)
+        W = np.exp(sign * 2j * math.pi * np.outer(m, m) / n)
+        out = np.moveaxis(np.tensordot(W, np.moveaxis(out, ax, 0), axes=(1, 0)), 0, ax)
+    return out
+
+
+def nesterov_ab(t, eps):
+    return 2.0 / (eps + t ** 3), 2.0 * t ** 3
+
+
+# ----------------------------------------------------------------------------------------
+# pins
+
+
+def pin_fft_bruteforce(mutation=0, seed=0):
+    """Oracle DFT vs the written-out O(N^2) DFT and vs numpy.fft (both signs)."""
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for shape in [(8,), (32,), (4, 8), (16, 2), (4, 8, 2)]:
+        x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+        for sign in (-1, +1):
+            got = oracle.fft(x, sign) if mutation == 0 else _fft_mut(x, sign, mutation)
+            ref = brute_dft(x, sign)
+            lib = np.fft.fftn(x) if sign < 0 else np.fft.ifftn(x) * x.size
+            worst = max(worst, np.max(np.abs(got - ref)) / np.max(np.abs(ref)),
+                        np.max(np.abs(got - lib)) / np.max(np.abs(ref)))
+    return worst < 1e-13, worst
+
+
+def _fft_mut(x, sign, mutation):
+    prob = Problem(shape=x.shape, mutation=mutation)
+    out = np.ascontiguousarray(x, dtype=np.complex128).copy()
+    d = prob.desc()
+    import ctypes
+    oracle._load().oracle_fft(ctypes.byref(d), oracle._dp(out.view(np.float64)), int(sign))
+    return out
+
+
+def one_step_dense(shape, box, f, psi0, dt, a, b, scheme=SCHEME_STRANG):
+    K = dense_kinetic(shape, box)
+    v = f.reshape(-1)
+    if scheme == SCHEME_STRANG:
+        Vh = np.exp(-0.5j * dt * b * v)
+        U = (Vh[:, None] * scipy.linalg.expm(-1j * dt * a * K)) * Vh[None, :]
+    else:
+        U = scipy.linalg.expm(-1j * dt * a * K) * np.exp(-1j * dt * b * v)[None, :]
+    return (U @ psi0.reshape(-1)).reshape(shape)
+
+
+def pin_one_step_expm(mutation=0, seed=1):
+    """One step of the oracle equals the product of dense matrix exponentials of
+    the discretised operators (App. E.1: both factors are exact exponentials of
+    diagonal operators in their own bases), on 1-D 32, 2-D 8x8 and an anisotropic
+    2-D 4x16 box; constant coefficients and the QHD schedule at t ~ 0.3."""
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    cases = [((32,), [(0.0, 2.0)]), ((8, 8), [(0.0, 1.0), (0.0, 1.0)]),
+             ((4, 16), [(-1.0, 2.0), (0.5, 1.25)])]
+    for shape, box in cases:
+        f = rng.uniform(-1, 3, size=shape)
+        psi0 = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+        psi0 /= np.linalg.norm(psi0)
+        for sched, params, scheme in [(SCHED_CONST, (0.7, 1.3), SCHEME_STRANG),
+                                      (SCHED_NESTEROV, (1e-3, 0.0), SCHEME_STRANG),
+                                      (SCHED_NESTEROV, (1e-3, 0.0), SCHEME_LIE)]:
+            dt, j = 0.01, 29
+            prob = Problem(shape=shape, box=box, dt=dt, sched=sched, params=params,
+                           scheme=scheme, mutation=mutation)
+            got = oracle.evolve(prob, f, psi0, j0=j, nsteps=1)
+            if sched == SCHED_CONST:
+                a, b = params
+            else:
+                t = j * dt if scheme == SCHEME_LIE else (j + 0.5) * dt
+                a, b = nesterov_ab(t, params[0])
+            ref = one_step_dense(shape, box, f, psi0, dt, a, b, scheme)
+            worst = max(worst, np.max(np.abs(got - ref)))
+    return worst < 1e-12, worst
+
+
+def exact_propagate(K, v, ab, t0, t1, psi0):
+    """psi(t1) of i psi' = (a(t) K + b(t) diag(v)) psi by an adaptive 8th-order
+    Runge-Kutta integrator at rtol 1e-12 (a textbook ODE solver, independent of any
+    splitting)."""
+    n = K.shape[0]
+
+    def rhs(t, y):
+        a, b = ab(t)
+        z = y[:n] + 1j * y[n:]
+        dz = -1j * (a * (K @ z) + b * v * z)
+        return np.concatenate([dz.real, dz.imag])
+
+    z0 = psi0.reshape(-1)
+    sol = solve_ivp(rhs, (t0, t1), np.concatenate([z0.real, z0.imag]), method="DOP853",
+                    rtol=1e-12, atol=1e-14)
+    y = sol.y[:, -1]
+    return y[:n] + 1j * y[n:]
+
+
+def pin_time_order(mutation=0, seed=2, scheme=SCHEME_STRANG):
+    """Global error against the exact time-ordered evolution shrinks like dt^2
+    (Strang, midpoint coefficients) or dt (the paper's printed first-order
+    formula), on an 8x8 grid of an 8x6 box with a = 2/(eps+t^3), b = 2 t^3 (eps=1)."""
+    rng = np.random.default_rng(seed)
+    shape, box = (8, 8), [(0.0, 6.0), (0.0, 8.0)]
+    f = rng.uniform(0, 2, size=shape)
+    psi0 = oracle.uniform_state(shape)
+    eps, T = 1.0, 1.0
+    K = dense_kinetic(shape, box)
+    ref = exact_propagate(K, f.reshape(-1), lambda t: nesterov_ab(t, eps), 0.0, T,
+                          psi0).reshape(shape)
+    errs = []
+    for nst in (64, 128, 256):
+        prob = Problem(shape=shape, box=box, dt=T / nst, sched=SCHED_NESTEROV,
+                       params=(eps, 0.0), scheme=scheme, mutation=mutation)
+        got = oracle.evolve(prob, f, psi0, 0, nst)
+        errs.append(np.max(np.abs(got - ref)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    want = 4.0 if scheme == SCHEME_STRANG else 2.0
+    ok = all(abs(r - want) < 0.1 * want for r in (r1, r2))
+    return ok, (errs, r1, r2)
+
+
+def pin_norm(mutation=0, seed=3, nsteps=10000):
+    """Unitarity: sum |psi|^2 stays 1 (eq. wave-rep) over 10k steps of the QHD
+    schedule on a 16x16 grid."""
+    from qhd_inputs import landscape_grid
+    shape = (16, 16)
+    f = landscape_grid(seed, shape)
+    prob = Problem(shape=shape, dt=1e-3, sched=SCHED_NESTEROV, params=(1e-3, 0.0),
+                   mutation=mutation)
+    psi = oracle.evolve(prob, f, oracle.uniform_state(shape), 0, nsteps)
+    drift = abs(float(np.sum(np.abs(psi) ** 2)) - 1.0)
+    return drift < 1e-12, drift
+
+
+# ---- Gaussian ansatz (App. B, proof of prop. quadratic_rate, generalised) -------------
+# psi = exp(i[alpha (x-X)^2 + P (x-X) + gamma]) solves i psi_t = [a(-1/2 d2) + b w^2/2 (x-c)^2] psi
+# exactly when  X' = a P,  P' = -b w^2 (X - c),  alpha' = -2 a alpha^2 - b w^2 / 2,
+#               gamma' = a P^2 / 2 + i a alpha - (b w^2 / 2)(X - c)^2.
+
+
+def gaussian_ode(ab, w2, c, X0, P0, sigma0, t0, t1):
+    alpha0 = 1j / (4 * sigma0 ** 2)
+    gamma0 = 0.25j * math.log(2 * math.pi * sigma0 ** 2)
+
+    def rhs(t, y):
+        X, P, ar, ai, gr, gi = y
+        a, b = ab(t)
+        al = ar + 1j * ai
+        dal = -2 * a * al * al - 0.5 * b * w2
+        dg = 0.5 * a * P * P + 1j * a * al - 0.5 * b * w2 * (X - c) ** 2
+        return [a * P, -b * w2 * (X - c), dal.real, dal.imag, dg.real, dg.imag]
+
+    sol = solve_ivp(rhs, (t0, t1), [X0, P0, alpha0.real, alpha0.imag, gamma0.real, gamma0.imag],
+                    method="DOP853", rtol=1e-12, atol=1e-14)
+    X, P, ar, ai, gr, gi = sol.y[:, -1]
+    return X, P, ar + 1j * ai, gr + 1j * gi
+
+
+def gaussian_on_mesh(x, X, P, alpha, gamma, h):
+    return np.exp(1j * (alpha * (x - X) ** 2 + P * (x - X) + gamma)) * math.sqrt(h)
+
+
+def pin_free_packet(mutation=0):
+    """b = 0, constant a: the split step is exact in time, so the oracle must
+    reproduce the closed-form spreading packet to ~1e-12 (2-D, anisotropic box,
+    moving packet)."""
+    a_const = 0.8
+    T, nst = 2.0, 40
+    axes_spec = [  # (n, lo, hi, X0, P0, sigma0)   array order [y, x]
+        (128, -18.0, 22.0, -1.0, 0.7, 1.1),
+        (256, -25.0, 25.0, 1.5, -1.2, 0.9),
+    ]
+    psi0 = np.ones((1, 1), dtype=np.complex128)
+    ref = np.ones((1, 1), dtype=np.complex128)
+    box = []
+    for ax, (n, lo, hi, X0, P0, s0) in enumerate(axes_spec):
+        h = (hi - lo) / n
+        x = lo + np.arange(n) * h
+        box.append((lo, hi))
+        alpha0 = 1j / (4 * s0 ** 2)
+        g0 = 0.25j * math.log(2 * math.pi * s0 ** 2)
+        # closed form of the ansatz ODE for b = 0
+        alpha_t = alpha0 / (1 + 2 * a_const * alpha0 * T)
+        X_t = X0 + a_const * P0 * T
+        g_t = g0 + 0.5 * a_const * P0 ** 2 * T + 0.5j * np.log(1 + 2 * a_const * alpha0 * T)
+        p0 = gaussian_on_mesh(x, X0, P0, alpha0, g0, h)
+        pt = gaussian_on_mesh(x, X_t, P0, alpha_t, g_t, h)
+        sh = [1, 1]
+        sh[ax] = n
+        psi0 = psi0 * p0.reshape(sh)
+        ref = ref * pt.reshape(sh)
+    shape = (axes_spec[0][0], axes_spec[1][0])
+    prob = Problem(shape=shape, box=box, dt=T / nst, sched=SCHED_CONST, params=(a_const, 0.0),
+                   mutation=mutation)
+    got = oracle.evolve(prob, np.zeros(shape), psi0, 0, nst)
+    err = float(np.max(np.abs(got - ref)))
+    return err < 1e-12, err
+
+
+def _gaussian_run(ab, sched, params, table_fn, w2, c, X0, P0, s0, n, lo, hi, T, nst, mutation,
+                  eps_time=0.0):
+    h = (hi - lo) / n
+    x = lo + np.arange(n) * h
+    f = 0.5 * w2 * (x - c) ** 2
+    psi0 = gaussian_on_mesh(x, X0, P0, 1j / (4 * s0 ** 2), 0.25j * math.log(2 * math.pi * s0 ** 2), h)
+    X, P, al, g = gaussian_ode(ab, w2, c, X0, P0, s0, 0.0, T)
+    ref = gaussian_on_mesh(x, X, P, al, g, h)
+    table = table_fn(T / nst, nst) if table_fn else None
+    prob = Problem(shape=(n,), box=[(lo, hi)], dt=T / nst, sched=sched, params=params,
+                   table=table, mutation=mutation)
+    got = oracle.evolve(prob, f, psi0, 0, nst)
+    return float(np.max(np.abs(got - ref))), got, f, prob, (X, P, al, g)
+
+
+def pin_harmonic_coherent(mutation=0):
+    """a = b = 1, f = w^2 (x-c)^2 / 2: the coherent state keeps its width and its
+    centre follows the classical orbit; the oracle converges to it at second order."""
+    w2 = 1.7 ** 2
+    errs = []
+    for nst in (100, 200, 400):
+        e, *_ = _gaussian_run(lambda t: (1.0, 1.0), SCHED_CONST, (1.0, 1.0), None, w2, 0.3,
+                              -1.0, 0.5, 1.0 / math.sqrt(2 * 1.7), 256, -8.0, 8.0, 3.0, nst,
+                              mutation)
+        errs.append(e)
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    ok = abs(r1 - 4) < 0.4 and abs(r2 - 4) < 0.4 and errs[2] < 1e-4
+    return ok, (errs, r1, r2)
+
+
+def pin_qhd_quadratic(mutation=0):
+    """App. B, prop. quadratic_rate: f = x^2/2 with a = 2/(eps + t^3), b = 2 t^3
+    and the Gaussian initial state of eq. init_gaussian stays Gaussian; the
+    oracle's E[f] (from its own readout) and its psi converge at second order to
+    the ansatz ODE solution (eps = 1 keeps the packet on a modest mesh)."""
+    eps = 1.0
+    ab = lambda t: nesterov_ab(t, eps)
+    errs, eferr = [], []
+    for nst in (250, 500, 1000):
+        e, got, f, prob, (X, P, al, g) = _gaussian_run(ab, SCHED_NESTEROV, (eps, 0.0), None, 1.0,
+                                                       0.0, 0.0, 0.0, 1.0, 2048, -40.0, 40.0,
+                                                       5.0, nst, mutation)
+        ro = oracle.readout(prob, f, got)
+        sigma2 = 1.0 / (4.0 * al.imag)
+        ef_ref = 0.5 * (sigma2 + X * X)
+        errs.append(e)
+        eferr.append(abs(ro.e_f - ef_ref))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    q1 = eferr[0] / max(eferr[1], 1e-300)
+    ok = abs(r1 - 4) < 0.4 and abs(r2 - 4) < 0.4 and errs[2] < 1e-4 and eferr[2] < 1e-5 \
+        and 3.0 < q1 < 5.0
+    return ok, (errs, eferr, r1, r2)
+
+
+def pin_time_reversal(mutation=0, seed=4):
+    """The symmetric step is time-reversible: running the reversed coefficient
+    table with -dt undoes the forward run."""
+    from qhd_inputs import landscape_grid
+    shape = (16, 32)
+    f = landscape_grid(seed, shape)
+    nst, dt = 200, 1e-3
+    t = (np.arange(nst) + 0.5) * dt
+    a, b = nesterov_ab(t, 1e-3)
+    tab = np.stack([a, b], axis=1)
+    fwd = Problem(shape=shape, dt=dt, sched=SCHED_TABLE, table=tab, mutation=mutation)
+    bwd = Problem(shape=shape, dt=-dt, sched=SCHED_TABLE, table=tab[::-1].copy(), mutation=mutation)
+    psi0 = oracle.uniform_state(shape)
+    psi = oracle.evolve(fwd, f, psi0, 0, nst)
+    back = oracle.evolve(bwd, f, psi, 0, nst)
+    err = float(np.max(np.abs(back - psi0)))
+    return err < 1e-12, err
+
+
+def pin_translation(mutation=0, seed=5):
+    """Rolling f by whole cells rolls psi (uniform start, periodic mesh)."""
+    from qhd_inputs import landscape_grid
+    shape = (16, 32)
+    f = landscape_grid(seed, shape)
+    prob = Problem(shape=shape, dt=1e-2, sched=SCHED_NESTEROV, params=(1e-3, 0.0), mutation=mutation)
+    psi0 = oracle.uniform_state(shape)
+    p1 = oracle.evolve(prob, f, psi0, 0, 100)
+    p2 = oracle.evolve(prob, np.roll(f, (3, -5), axis=(0, 1)), psi0, 0, 100)
+    err = float(np.max(np.abs(np.roll(p1, (3, -5), axis=(0, 1)) - p2)))
+    return err < 1e-12, err
+
+
+def pin_constant_shift(mutation=0, seed=6):
+    """f + C multiplies psi by the global phase exp(-i C sum_j dt b_j)."""
+    from qhd_inputs import landscape_grid
+    shape = (16, 16)
+    f = landscape_grid(seed, shape)
+    C, nst, dt = 2.5, 150, 1e-2
+    prob = Problem(shape=shape, dt=dt, sched=SCHED_NESTEROV, params=(1e-3, 0.0), mutation=mutation)
+    psi0 = oracle.uniform_state(shape)
+    p1 = oracle.evolve(prob, f, psi0, 0, nst)
+    p2 = oracle.evolve(prob, f + C, psi0, 0, nst)
+    t = (np.arange(nst) + 0.5) * dt
+    phase = -C * math.fsum(dt * 2.0 * t ** 3)
+    err = float(np.max(np.abs(p1 * np.exp(1j * phase) - p2)))
+    return err < 1e-10, err
+
+
+def pin_mirror(mutation=0, seed=7):
+    """A landscape symmetric under x -> -x (about the mesh origin) gives a
+    symmetric density."""
+    rng = np.random.default_rng(seed)
+    n = 32
+    g = rng.uniform(0, 2, size=n // 2 + 1)
+    fx = np.concatenate([g, g[1:-1][::-1]])           # f[i] = f[-i mod n]
+    f = fx[None, :] + 0.5 * fx[:, None] ** 2
+    prob = Problem(shape=(n, n), dt=1e-2, sched=SCHED_NESTEROV, params=(1e-3, 0.0), mutation=mutation)
+    psi = oracle.evolve(prob, f, oracle.uniform_state((n, n)), 0, 100)
+    rho = np.abs(psi) ** 2
+    idx = (-np.arange(n)) % n
+    err = float(np.max(np.abs(rho - rho[:, idx])) + np.max(np.abs(rho - rho[idx, :])))
+    return err < 1e-13, err
+
+
+def pin_readouts(mutation=0, seed=8):
+    """Readouts vs brute force with math.fsum: norm, E[f], success mass within
+    |x - x*| < r (strict, unwrapped), x* = lowest-index grid minimiser."""
+    rng = np.random.default_rng(seed)
+    shape = (16, 32)
+    box = [(0.0, 0.5), (0.0, 1.0)]
+    f = rng.uniform(0, 1, size=shape)
+    f[13, 30] = -1.0     # minimiser near the corner: the circle crosses the seam
+    f[14, 31] = -1.0     # a tie at a higher flat index must not win
+    psi = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * 0.1
+    r = 0.15
+    prob = Problem(shape=shape, box=box, radius=r, mutation=mutation)
+    ro = oracle.readout(prob, f, psi)
+    rho = [abs(v) ** 2 for v in psi.reshape(-1)]
+    fl = f.reshape(-1)
+    norm = math.fsum(rho)
+    ef = math.fsum(fv * rv for fv, rv in zip(fl, rho)) / norm
+    amin = min(range(len(fl)), key=lambda i: (fl[i], i))
+    iy, ix = divmod(amin, shape[1])
+    hy, hx = 0.5 / 16, 1.0 / 32
+    succ = math.fsum(rho[i] for i in range(len(fl))
+                     if ((i // shape[1] - iy) * hy) ** 2 + ((i % shape[1] - ix) * hx) ** 2 < r * r)
+    succ /= norm
+    err = max(abs(ro.norm - norm) / norm, abs(ro.e_f - ef), abs(ro.success - succ),
+              float(ro.argmin != amin))
+    return err < 1e-14, err
+
+
+def pin_chunked(mutation=0, seed=9):
+    """Chunked evolution (checkpoint/resume at a global step index) is bitwise
+    identical to one uninterrupted run."""
+    from qhd_inputs import landscape_grid
+    shape = (8, 16)
+    f = landscape_grid(seed, shape)
+    prob = Problem(shape=shape, dt=1e-2, sched=SCHED_NESTEROV, params=(1e-3, 0.0), mutation=mutation)
+    psi0 = oracle.uniform_state(shape)
+    one = oracle.evolve(prob, f, psi0, 0, 300)
+    two = oracle.evolve(prob, f, oracle.evolve(prob, f, psi0, 0, 117), 117, 183)
+    err = float(np.max(np.abs(one - two)))
+    return err == 0.0, err
+
+
+def pin_time_dilation(mutation=0, seed=10):
+    """App. A, prop. time_dilation: with tau increasing, the coefficients
+    tau'(s) a(tau(s)), tau'(s) b(tau(s)) trace the same curve, so the discrete run
+    in the new clock converges (second order) to the exact state of the original
+    problem at T = tau(S)."""
+    from qhd_inputs import landscape_grid
+    shape, box = (8, 8), [(0.0, 6.0), (0.0, 8.0)]
+    f = landscape_grid(seed, shape)
+    eps, T = 1.0, 1.0
+    # tau(s) = s + s^2 / 2 on s in [0, S] with tau(S) = T
+    S = -1.0 + math.sqrt(1.0 + 2.0 * T)
+    psi0 = oracle.uniform_state(shape)
+    ref = exact_propagate(dense_kinetic(shape, box), f.reshape(-1),
+                          lambda t: nesterov_ab(t, eps), 0.0, T, psi0).reshape(shape)
+    errs = []
+    for nst in (64, 128, 256):
+        ds = S / nst
+        s = (np.arange(nst) + 0.5) * ds
+        tau, dtau = s + 0.5 * s * s, 1.0 + s
+        a, b = nesterov_ab(tau, eps)
+        tab = np.stack([dtau * a, dtau * b], axis=1)
+        prob = Problem(shape=shape, box=box, dt=ds, sched=SCHED_TABLE, table=tab,
+                       mutation=mutation)
+        errs.append(float(np.max(np.abs(oracle.evolve(prob, f, psi0, 0, nst) - ref))))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    ok = 3.6 < r1 < 4.4 and 3.6 < r2 < 4.4
+    return ok, (errs, r1, r2)
+
+
+ALL_PINS = {
+    "fft_bruteforce": pin_fft_bruteforce,
+    "one_step_expm": pin_one_step_expm,
+    "time_order_strang": pin_time_order,
+    "norm": pin_norm,
+    "free_packet": pin_free_packet,
+    "harmonic_coherent": pin_harmonic_coherent,
+    "qhd_quadratic": pin_qhd_quadratic,
+    "time_reversal": pin_time_reversal,
+    "translation": pin_translation,
+    "constant_shift": pin_constant_shift,
+    "mirror": pin_mirror,
+    "readouts": pin_readouts,
+    "chunked": pin_chunked,
+    "time_dilation": pin_time_dilation,
+}
