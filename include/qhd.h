@@ -1,0 +1,169 @@
+/*
+ * qhd.h - C ABI of the MI355X (gfx950) engine for the classical simulation of
+ * Quantum Hamiltonian Descent (Leng, Hickman, Li, Wu, arXiv 2303.01471).
+ *
+ * The library evolves batches of discretised wave functions under
+ *
+ *     i dpsi/dt = [ a(t) (-1/2 Lap) + b(t) f(x) ] psi
+ *
+ * (the QHD Hamiltonian: main text eq. main1, App. A eq. qhd_operator, with
+ * a = e^{phi_t}, b = e^{chi_t}) on the periodic mesh of App. E.1, by the
+ * pseudo-spectral product formula of App. C.2.1 (eqs. prod_qhd, prod_qhd_fft)
+ * taken in its symmetric (Strang) form with the coefficients at the step
+ * midpoint.  The statement of the problem follows Algorithm 1 of App. E.1:
+ * a box, 2^q points per axis, an initial state, the schedule, a step and an
+ * iteration count, then a position measurement.
+ *
+ * Conventions shared by every entry point:
+ *   - All functions return a qhd_status; none aborts or exits.  On failure,
+ *     qhd_last_error() returns a message for the calling thread.
+ *   - A plan is not thread-safe; distinct plans are independent.
+ *   - Device pointers are HIP device addresses on the device that was current
+ *     when the plan was created.  "stream" arguments are hipStream_t values
+ *     (NULL = the default stream).
+ *   - Grid arrays are row-major with axis 0 (x) fastest: flat index
+ *     i0 + n0 * (i1 + n1 * i2).  Complex values are interleaved (re, im) FP32.
+ */
+#ifndef QHD_H
+#define QHD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QHD_OK = 0,
+  QHD_EINVAL = 1,       /* invalid argument (descriptor, index, pointer, size)      */
+  QHD_EUNSUPPORTED = 2, /* valid but not supported by this build                    */
+  QHD_ENOMEM = 3,       /* device or host allocation failed                         */
+  QHD_EDEVICE = 4,      /* a HIP runtime call failed                                */
+  QHD_ESTATE = 5,       /* call out of order (e.g. evolve before set_potential)     */
+  QHD_ENUMERIC = 6      /* NaN/Inf in an observable, or |norm - 1| above tolerance */
+} qhd_status;
+
+/* Schedule of the damping coefficients a(t) = e^{phi_t}, b(t) = e^{chi_t}. */
+typedef enum {
+  /* App. C.2.1, eq. nonconvex_QHD_h: a = 2/(eps + t^3), b = 2 t^3, eps = sched_p[0] */
+  QHD_SCHED_NESTEROV = 0,
+  /* a = sched_p[0], b = sched_p[1] */
+  QHD_SCHED_CONST = 1,
+  /* per-step values: a_j = sched_table[2j], b_j = sched_table[2j+1], j = 0..nsteps-1,
+   * each applied over step j (the midpoint value of the step in the symmetric scheme) */
+  QHD_SCHED_TABLE = 2
+} qhd_sched_kind;
+
+typedef enum {
+  QHD_INIT_UNIFORM = 0, /* psi0 = N^{-1/2} at every mesh point (App. C.2.1 experiment) */
+  QHD_INIT_USER = 1     /* qhd_set_state must be called before the first evolve       */
+} qhd_init_kind;
+
+/* One problem instance (Algorithm 1 of App. E.1). */
+typedef struct {
+  int32_t ndim;         /* 1 or 2 (3 is reserved: QHD_EUNSUPPORTED)                   */
+  int32_t n[3];         /* points per axis, powers of two, 8 <= n <= 1024; unused = 1  */
+  double lo[3], hi[3];  /* periodic box [lo, hi) per axis, hi > lo (App. E.1 mesh)     */
+  double dt;            /* time step s > 0                                             */
+  int64_t nsteps;       /* number of steps, >= 0; the end time is T = nsteps * dt      */
+  int32_t sched_kind;   /* qhd_sched_kind                                              */
+  double sched_p[2];    /* schedule parameters (see qhd_sched_kind)                    */
+  const double *sched_table; /* QHD_SCHED_TABLE: host array of 2*nsteps doubles, copied
+                                at plan creation; ignored otherwise                      */
+  int32_t init_kind;    /* qhd_init_kind                                               */
+  double success_radius;/* r > 0 of the success test |x - x*| < r (main text, fig. 2)  */
+} qhd_instance;
+
+/* Plan options.  Zero-initialise and set what you need. */
+typedef struct {
+  uint32_t flags;          /* QHD_OPT_* bits                                          */
+  double norm_tolerance;   /* qhd_observe returns QHD_ENUMERIC if |norm-1| exceeds
+                              this; <= 0 selects 1e-3                                  */
+  int32_t timing_stride;   /* with QHD_OPT_TIME_PASSES: time one sub-step in this many
+                              (<= 0 selects 16)                                        */
+} qhd_plan_opts;
+
+#define QHD_OPT_TIME_PASSES 0x1u /* record HIP events around sampled pass launches   */
+
+typedef struct qhd_plan_s *qhd_plan;
+
+/* Per-instance readouts (App. B: E[f] = <f>; Algorithm 1: position measurement;
+ * main text fig. 2: success criterion |x - x*| < r). */
+typedef struct {
+  double norm;          /* sum |psi|^2 (FP64 accumulation)                              */
+  double e_f;           /* sum f |psi|^2 / norm                                          */
+  double success_mass;  /* sum over |x - x*| < r of |psi|^2 / norm (unwrapped distance)  */
+  double f_min;         /* f(x*)                                                         */
+  int64_t argmin_index; /* flat index of x*, the lowest-index minimiser of f on the mesh */
+  int64_t steps_done;   /* steps completed                                               */
+  double t;             /* steps_done * dt                                               */
+} qhd_observables;
+
+/* Per-kernel timing gathered with QHD_OPT_TIME_PASSES. */
+typedef struct {
+  char name[48];        /* kernel family, e.g. "row_pass_2d/n512"                        */
+  int64_t launches;     /* launches that were timed                                      */
+  double total_ms;      /* summed HIP-event durations of the timed launches              */
+  double points;        /* grid points processed by the timed launches                   */
+  double bytes_per_point; /* algorithmic HBM bytes moved per grid point by this kernel   */
+} qhd_kernel_timing;
+
+/* Create a plan for `batch` instances.  Validates every descriptor first (no
+ * device work happens for an invalid batch), then allocates all device memory
+ * the plan will ever use; later calls allocate nothing.  The uniform initial
+ * state is written here.  *out receives the plan, or NULL on failure. */
+qhd_status qhd_plan_create(const qhd_instance *inst, int32_t batch, const qhd_plan_opts *opts,
+                           qhd_plan *out);
+
+/* Upload f (FP64, n0*n1*n2 values, row-major) for instance i.  on_device != 0
+ * means `f` is a device pointer.  The call also finds x* and f(x*).  It is
+ * ordered on the plan's internal stream and synchronises before returning;
+ * the caller keeps ownership of `f`.  Must precede the first evolve. */
+qhd_status qhd_set_potential(qhd_plan plan, int32_t i, const double *f, int32_t on_device);
+
+/* Replace the state of instance i by psi (interleaved complex FP32, row-major),
+ * e.g. a user initial state or a checkpoint.  The state is taken as exact
+ * (no pending half step).  Synchronous, like qhd_set_potential. */
+qhd_status qhd_set_state(qhd_plan plan, int32_t i, const float *psi_c64, int32_t on_device);
+
+/* Set the global step index of instance i (0 <= j <= nsteps) so that a resumed
+ * run continues the schedule at t_{j+1/2}.  Use after qhd_set_state. */
+qhd_status qhd_set_steps_done(qhd_plan plan, int32_t i, int64_t j);
+
+/* Advance every instance by min(max_steps, remaining) steps (max_steps < 0:
+ * to the end).  Asynchronous on `stream`; allocates nothing.  Between evolve
+ * calls the state may carry a pending half step; the result does not depend on
+ * how the steps are split into calls. */
+qhd_status qhd_evolve(qhd_plan plan, int64_t max_steps, void *stream);
+
+/* Readouts for every instance.  Closes any pending half step on a copy (the
+ * plan state is untouched, evolution can continue).  host_out: `batch` entries.
+ * rho_dev / psi_dev: optional caller-owned device buffers receiving |psi|^2
+ * (FP32) and psi (interleaved FP32), instances concatenated in order; NULL to
+ * skip.  Synchronises `stream` before returning.  Returns QHD_ENUMERIC (with
+ * host_out filled) if an observable is not finite or |norm - 1| exceeds the
+ * plan's tolerance. */
+qhd_status qhd_observe(qhd_plan plan, void *stream, qhd_observables *host_out, float *rho_dev,
+                       float *psi_dev);
+
+/* Total mesh points of the plan (sum over instances), for sizing rho/psi buffers. */
+qhd_status qhd_plan_points(qhd_plan plan, int64_t *total_points);
+
+/* With QHD_OPT_TIME_PASSES: copy up to `cap` entries of per-kernel timing into
+ * `out`, set *count, and reset the counters.  Synchronises the plan's streams. */
+qhd_status qhd_kernel_timings(qhd_plan plan, qhd_kernel_timing *out, int32_t cap, int32_t *count);
+
+/* Release every resource of the plan.  NULL is accepted. */
+qhd_status qhd_plan_destroy(qhd_plan plan);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *qhd_last_error(void);
+
+/* Library version string. */
+const char *qhd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QHD_H */

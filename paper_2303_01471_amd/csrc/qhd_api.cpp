@@ -1,0 +1,645 @@
+// C ABI of the QHD engine: argument validation, plan (instances grouped into
+// shape classes, device arenas, twiddle tables), the evolve driver and the
+// readouts.  The statement of the problem follows Algorithm 1 of App. E.1 of
+// the paper; the kernels are in qhd_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <tuple>
+#include <string>
+#include <vector>
+
+#include "../../include/qhd.h"
+#include "qhd_internal.h"
+
+using namespace qhd;
+
+namespace {
+
+thread_local std::string g_err;
+
+qhd_status fail(qhd_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? QHD_ENOMEM : QHD_EDEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+  } while (0)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Host-only validation of one descriptor (no device work).
+qhd_status validate(const qhd_instance& d, int idx) {
+  if (d.ndim == 3) return fail(QHD_EUNSUPPORTED, "instance %d: ndim=3 is not supported by this build", idx);
+  if (d.ndim < 1 || d.ndim > 2) return fail(QHD_EINVAL, "instance %d: ndim must be 1 or 2 (got %d)", idx, d.ndim);
+  for (int a = 0; a < d.ndim; ++a) {
+    if (!is_pow2(d.n[a]) || d.n[a] < 8 || d.n[a] > 1024)
+      return fail(QHD_EINVAL, "instance %d: n[%d]=%d must be a power of two in [8, 1024]", idx, a, d.n[a]);
+    if (!std::isfinite(d.lo[a]) || !std::isfinite(d.hi[a]) || !(d.hi[a] > d.lo[a]))
+      return fail(QHD_EINVAL, "instance %d: box axis %d needs finite lo < hi", idx, a);
+  }
+  if (!std::isfinite(d.dt) || !(d.dt > 0.0)) return fail(QHD_EINVAL, "instance %d: dt must be finite and > 0", idx);
+  if (d.nsteps < 0) return fail(QHD_EINVAL, "instance %d: nsteps must be >= 0", idx);
+  if (!(d.success_radius > 0.0) || !std::isfinite(d.success_radius))
+    return fail(QHD_EINVAL, "instance %d: success_radius must be finite and > 0", idx);
+  switch (d.sched_kind) {
+    case QHD_SCHED_NESTEROV:
+      if (!std::isfinite(d.sched_p[0]) || !(d.sched_p[0] > 0.0))
+        return fail(QHD_EINVAL, "instance %d: NESTEROV schedule needs eps = sched_p[0] > 0", idx);
+      break;
+    case QHD_SCHED_CONST:
+      if (!std::isfinite(d.sched_p[0]) || !std::isfinite(d.sched_p[1]))
+        return fail(QHD_EINVAL, "instance %d: CONST schedule needs finite a0, b0", idx);
+      break;
+    case QHD_SCHED_TABLE:
+      if (d.nsteps > 0 && !d.sched_table) return fail(QHD_EINVAL, "instance %d: TABLE schedule needs sched_table", idx);
+      for (int64_t j = 0; j < 2 * d.nsteps; ++j)
+        if (!std::isfinite(d.sched_table[j])) return fail(QHD_EINVAL, "instance %d: sched_table[%lld] is not finite", idx, (long long)j);
+      break;
+    default:
+      return fail(QHD_EINVAL, "instance %d: unknown sched_kind %d", idx, d.sched_kind);
+  }
+  if (d.init_kind != QHD_INIT_UNIFORM && d.init_kind != QHD_INIT_USER)
+    return fail(QHD_EINVAL, "instance %d: unknown init_kind %d", idx, d.init_kind);
+  return QHD_OK;
+}
+
+struct Pending {
+  hipEvent_t start, stop;
+  int family;
+  double points;
+};
+
+struct Family {
+  std::string name;
+  int64_t launches = 0;
+  double total_ms = 0.0, points = 0.0, bytes_per_point = 0.0;
+};
+
+}  // namespace
+
+struct ShapeClass {
+  int ndim = 0, nx = 1, ny = 1;
+  long long points = 0;            // per instance
+  std::vector<int> members;        // plan indices, sorted by nsteps (descending)
+  std::vector<InstDev> host;       // mirror of the device array
+  InstDev* dev = nullptr;
+  float2* psi = nullptr;
+  double* f = nullptr;
+  double* partials = nullptr;      // 3 per line
+  double* results = nullptr;       // 3 per member
+  int lines = 0;                   // lines per instance for the readout partials
+  const double2* tw_x = nullptr;
+  const double2* tw_y = nullptr;
+  int fam_row = -1, fam_col = -1, fam_line = -1;
+};
+
+struct qhd_plan_s {
+  int device = 0;
+  hipStream_t internal = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool last_stream_valid = false;
+  qhd_plan_opts opts{};
+  std::vector<qhd_instance> inst;
+  std::vector<int> cls_of, pos_of;
+  std::vector<ShapeClass> classes;
+  std::vector<double*> dev_tables;
+  std::vector<char> potential_set, state_ready;
+  double2* twiddles = nullptr;
+  std::map<int, size_t> tw_off;
+  double* staging_f = nullptr;
+  float2* staging_psi = nullptr;
+  double* amin_val = nullptr;
+  long long* amin_idx = nullptr;
+  double* host_results = nullptr;   // pinned, 3 per member of the largest class
+  long long total_points = 0;
+  int grid_cap = 4096;
+  // timing
+  std::vector<Family> families;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> free_events;
+};
+
+namespace {
+
+void free_plan(qhd_plan p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  if (p->internal) (void)hipStreamSynchronize(p->internal);
+  if (p->last_stream_valid) (void)hipStreamSynchronize(p->last_stream);
+  for (auto& c : p->classes) {
+    (void)hipFree(c.dev);
+    (void)hipFree(c.psi);
+    (void)hipFree(c.f);
+    (void)hipFree(c.partials);
+    (void)hipFree(c.results);
+  }
+  for (double* t : p->dev_tables) (void)hipFree(t);
+  (void)hipFree(p->twiddles);
+  (void)hipFree(p->staging_f);
+  (void)hipFree(p->staging_psi);
+  (void)hipFree(p->amin_val);
+  (void)hipFree(p->amin_idx);
+  if (p->host_results) (void)hipHostFree(p->host_results);
+  for (auto& pe : p->pending) {
+    (void)hipEventDestroy(pe.start);
+    (void)hipEventDestroy(pe.stop);
+  }
+  for (auto e : p->free_events) (void)hipEventDestroy(e);
+  if (p->internal) (void)hipStreamDestroy(p->internal);
+  delete p;
+}
+
+int family_index(qhd_plan p, const std::string& name, double bpp) {
+  for (size_t k = 0; k < p->families.size(); ++k)
+    if (p->families[k].name == name) return (int)k;
+  Family f;
+  f.name = name;
+  f.bytes_per_point = bpp;
+  p->families.push_back(f);
+  return (int)p->families.size() - 1;
+}
+
+hipEvent_t take_event(qhd_plan p) {
+  if (!p->free_events.empty()) {
+    hipEvent_t e = p->free_events.back();
+    p->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+qhd_status sync_user_stream(qhd_plan p) {
+  if (p->last_stream_valid) HIP_TRY(hipStreamSynchronize(p->last_stream));
+  return QHD_OK;
+}
+
+qhd_status push_inst(qhd_plan p, int i) {
+  ShapeClass& c = p->classes[p->cls_of[i]];
+  const int pos = p->pos_of[i];
+  HIP_TRY(hipMemcpyAsync(c.dev + pos, &c.host[pos], sizeof(InstDev), hipMemcpyHostToDevice, p->internal));
+  HIP_TRY(hipStreamSynchronize(p->internal));
+  return QHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qhd_last_error(void) { return g_err.c_str(); }
+
+const char* qhd_version(void) { return "qhd-mi355x 0.1 (gfx950)"; }
+
+qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_plan_opts* opts,
+                           qhd_plan* out) {
+  g_err.clear();
+  if (!out) return fail(QHD_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (batch <= 0) return fail(QHD_EINVAL, "batch must be > 0 (got %d)", batch);
+  if (!inst) return fail(QHD_EINVAL, "inst must not be NULL");
+  for (int i = 0; i < batch; ++i) {
+    qhd_status st = validate(inst[i], i);
+    if (st != QHD_OK) return st;
+  }
+  qhd_plan p = new qhd_plan_s();
+  if (opts) p->opts = *opts;
+  if (!(p->opts.norm_tolerance > 0.0)) p->opts.norm_tolerance = 1e-3;
+  if (p->opts.timing_stride <= 0) p->opts.timing_stride = 16;
+  if (const char* gc = std::getenv("QHD_GRID_CAP")) p->grid_cap = std::max(0, std::atoi(gc));
+  p->inst.assign(inst, inst + batch);
+  p->cls_of.assign(batch, -1);
+  p->pos_of.assign(batch, -1);
+  p->potential_set.assign(batch, 0);
+  p->state_ready.assign(batch, 0);
+
+  auto bail = [&](qhd_status st) {
+    std::string keep = g_err;
+    free_plan(p);
+    g_err = keep;
+    return st;
+  };
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    fail(QHD_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    return bail(QHD_EDEVICE);
+  }
+  e = hipStreamCreateWithFlags(&p->internal, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    fail(QHD_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    return bail(QHD_EDEVICE);
+  }
+
+  // group into shape classes
+  std::map<std::tuple<int, int, int>, int> key2cls;
+  for (int i = 0; i < batch; ++i) {
+    const qhd_instance& d = inst[i];
+    const int nx = d.n[0], ny = d.ndim >= 2 ? d.n[1] : 1;
+    auto key = std::make_tuple(d.ndim, nx, ny);
+    auto it = key2cls.find(key);
+    int c;
+    if (it == key2cls.end()) {
+      c = (int)p->classes.size();
+      key2cls[key] = c;
+      ShapeClass sc;
+      sc.ndim = d.ndim;
+      sc.nx = nx;
+      sc.ny = ny;
+      sc.points = (long long)nx * ny;
+      p->classes.push_back(sc);
+    } else {
+      c = it->second;
+    }
+    p->classes[c].members.push_back(i);
+    p->cls_of[i] = c;
+  }
+  // twiddle tables W_N^j = exp(-2 pi i j / N) for every line length in use
+  std::vector<int> lengths;
+  for (auto& c : p->classes) {
+    lengths.push_back(c.nx);
+    if (c.ndim >= 2) lengths.push_back(c.ny);
+  }
+  std::sort(lengths.begin(), lengths.end());
+  lengths.erase(std::unique(lengths.begin(), lengths.end()), lengths.end());
+  size_t tw_total = 0;
+  for (int n : lengths) {
+    p->tw_off[n] = tw_total;
+    tw_total += (size_t)n;
+  }
+  {
+    std::vector<double2> tw(tw_total);
+    for (int n : lengths) {
+      for (int j = 0; j < n; ++j) {
+        const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)j / (long double)n;
+        tw[p->tw_off[n] + j] = make_double2((double)cosl(ang), -(double)sinl(ang));
+      }
+    }
+    e = hipMalloc(&p->twiddles, tw_total * sizeof(double2));
+    if (e == hipSuccess)
+      e = hipMemcpy(p->twiddles, tw.data(), tw_total * sizeof(double2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      fail(e == hipErrorOutOfMemory ? QHD_ENOMEM : QHD_EDEVICE, "twiddle upload: %s", hipGetErrorString(e));
+      return bail(g_err.find("out of memory") != std::string::npos ? QHD_ENOMEM : QHD_EDEVICE);
+    }
+  }
+
+  long long max_pts = 0;
+  size_t max_members = 0;
+  long long out_off = 0;
+  std::vector<long long> out_off_of(batch);
+  for (int i = 0; i < batch; ++i) {
+    const qhd_instance& d = inst[i];
+    out_off_of[i] = out_off;
+    out_off += (long long)d.n[0] * (d.ndim >= 2 ? d.n[1] : 1);
+  }
+  p->total_points = out_off;
+
+  for (size_t ci = 0; ci < p->classes.size(); ++ci) {
+    ShapeClass& c = p->classes[ci];
+    std::stable_sort(c.members.begin(), c.members.end(),
+                     [&](int a, int b) { return inst[a].nsteps > inst[b].nsteps; });
+    const int m = (int)c.members.size();
+    max_pts = std::max(max_pts, c.points);
+    max_members = std::max(max_members, (size_t)m);
+    c.lines = c.ndim == 2 ? c.ny : 1;
+    c.tw_x = p->twiddles + p->tw_off[c.nx];
+    c.tw_y = c.ndim >= 2 ? p->twiddles + p->tw_off[c.ny] : nullptr;
+    c.host.resize(m);
+    for (int pos = 0; pos < m; ++pos) {
+      const int i = c.members[pos];
+      const qhd_instance& d = inst[i];
+      p->pos_of[i] = pos;
+      InstDev& I = c.host[pos];
+      std::memset(&I, 0, sizeof I);
+      I.dt = d.dt;
+      for (int a = 0; a < 3; ++a) {
+        if (a < d.ndim) {
+          const double L = d.hi[a] - d.lo[a];
+          I.kin_turns[a] = 3.141592653589793 * d.dt / (L * L);
+          I.h[a] = L / (double)d.n[a];
+        }
+      }
+      I.sched = d.sched_kind;
+      I.sched_p0 = d.sched_p[0];
+      I.sched_p1 = d.sched_p[1];
+      I.r2 = d.success_radius * d.success_radius;
+      I.nsteps = d.nsteps;
+      I.steps_done = 0;
+      I.mode = kModeClean;
+      I.plan_index = i;
+      I.psi_off = (long long)pos * c.points;
+      I.out_off = out_off_of[i];
+      if (d.sched_kind == QHD_SCHED_TABLE && d.nsteps > 0) {
+        double* t = nullptr;
+        e = hipMalloc(&t, sizeof(double) * 2 * d.nsteps);
+        if (e == hipSuccess) {
+          p->dev_tables.push_back(t);
+          e = hipMemcpy(t, d.sched_table, sizeof(double) * 2 * d.nsteps, hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) {
+          fail(e == hipErrorOutOfMemory ? QHD_ENOMEM : QHD_EDEVICE, "schedule table upload: %s", hipGetErrorString(e));
+          return bail(e == hipErrorOutOfMemory ? QHD_ENOMEM : QHD_EDEVICE);
+        }
+        I.table = t;
+        p->inst[i].sched_table = nullptr;  // the caller's pointer is not kept
+      }
+    }
+    const size_t pts = (size_t)m * (size_t)c.points;
+    e = hipMalloc(&c.dev, sizeof(InstDev) * m);
+    if (e == hipSuccess) e = hipMalloc(&c.psi, sizeof(float2) * pts);
+    if (e == hipSuccess) e = hipMalloc(&c.f, sizeof(double) * pts);
+    if (e == hipSuccess) e = hipMalloc(&c.partials, sizeof(double) * 3 * (size_t)m * c.lines);
+    if (e == hipSuccess) e = hipMalloc(&c.results, sizeof(double) * 3 * (size_t)m);
+    if (e == hipSuccess) e = hipMemcpy(c.dev, c.host.data(), sizeof(InstDev) * m, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      // uniform initial state N^{-1/2} (App. C.2.1 experiment); USER states are
+      // overwritten by qhd_set_state
+      e = launch_fill_psi(c.psi, (long long)pts, (float)(1.0 / std::sqrt((double)c.points)), p->internal);
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(c.f, 0, sizeof(double) * pts, p->internal);
+    if (e != hipSuccess) {
+      fail(e == hipErrorOutOfMemory ? QHD_ENOMEM : QHD_EDEVICE, "class allocation: %s", hipGetErrorString(e));
+      return bail(e == hipErrorOutOfMemory ? QHD_ENOMEM : QHD_EDEVICE);
+    }
+    char name[48];
+    if (c.ndim == 2) {
+      snprintf(name, sizeof name, "row_pass_2d/n%d", c.nx);
+      c.fam_row = family_index(p, name, 24.0);
+      snprintf(name, sizeof name, "col_pass_2d/n%d", c.ny);
+      c.fam_col = family_index(p, name, 16.0);
+    } else {
+      snprintf(name, sizeof name, "line_pass_1d/n%d", c.nx);
+      c.fam_line = family_index(p, name, 24.0);
+    }
+  }
+  for (int i = 0; i < batch; ++i) p->state_ready[i] = inst[i].init_kind == QHD_INIT_UNIFORM;
+  e = hipMalloc(&p->staging_f, sizeof(double) * max_pts);
+  if (e == hipSuccess) e = hipMalloc(&p->staging_psi, sizeof(float2) * max_pts);
+  if (e == hipSuccess) e = hipMalloc(&p->amin_val, sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&p->amin_idx, 2 * sizeof(long long));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&p->host_results, sizeof(double) * 3 * max_members);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->internal);
+  if (e != hipSuccess) {
+    fail(e == hipErrorOutOfMemory ? QHD_ENOMEM : QHD_EDEVICE, "plan allocation: %s", hipGetErrorString(e));
+    return bail(e == hipErrorOutOfMemory ? QHD_ENOMEM : QHD_EDEVICE);
+  }
+  *out = p;
+  return QHD_OK;
+}
+
+qhd_status qhd_plan_destroy(qhd_plan plan) {
+  g_err.clear();
+  free_plan(plan);
+  return QHD_OK;
+}
+
+qhd_status qhd_plan_points(qhd_plan plan, int64_t* total_points) {
+  g_err.clear();
+  if (!plan || !total_points) return fail(QHD_EINVAL, "plan and total_points must not be NULL");
+  *total_points = plan->total_points;
+  return QHD_OK;
+}
+
+qhd_status qhd_set_potential(qhd_plan p, int32_t i, const double* f, int32_t on_device) {
+  g_err.clear();
+  if (!p) return fail(QHD_EINVAL, "plan is NULL");
+  if (i < 0 || i >= (int)p->inst.size()) return fail(QHD_EINVAL, "instance index %d out of range", i);
+  if (!f) return fail(QHD_EINVAL, "f is NULL");
+  HIP_TRY(hipSetDevice(p->device));
+  qhd_status st = sync_user_stream(p);
+  if (st != QHD_OK) return st;
+  ShapeClass& c = p->classes[p->cls_of[i]];
+  const int pos = p->pos_of[i];
+  HIP_TRY(hipMemcpyAsync(p->staging_f, f, sizeof(double) * c.points,
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->internal));
+  HIP_TRY(launch_argmin(p->staging_f, c.points, p->amin_val, p->amin_idx, p->internal));
+  HIP_TRY(launch_import_f(c.ndim, c.nx, c.ny, p->staging_f, c.f + c.host[pos].psi_off, p->internal));
+  double v = 0.0;
+  long long idx[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(&v, p->amin_val, sizeof v, hipMemcpyDeviceToHost, p->internal));
+  HIP_TRY(hipMemcpyAsync(idx, p->amin_idx, sizeof idx, hipMemcpyDeviceToHost, p->internal));
+  HIP_TRY(hipStreamSynchronize(p->internal));
+  if (idx[1] != 0) return fail(QHD_EINVAL, "instance %d: f has %lld non-finite values", i, idx[1]);
+  c.host[pos].f_min = v;
+  c.host[pos].argmin = idx[0];
+  p->potential_set[i] = 1;
+  return push_inst(p, i);
+}
+
+qhd_status qhd_set_state(qhd_plan p, int32_t i, const float* psi, int32_t on_device) {
+  g_err.clear();
+  if (!p) return fail(QHD_EINVAL, "plan is NULL");
+  if (i < 0 || i >= (int)p->inst.size()) return fail(QHD_EINVAL, "instance index %d out of range", i);
+  if (!psi) return fail(QHD_EINVAL, "psi is NULL");
+  HIP_TRY(hipSetDevice(p->device));
+  qhd_status st = sync_user_stream(p);
+  if (st != QHD_OK) return st;
+  ShapeClass& c = p->classes[p->cls_of[i]];
+  const int pos = p->pos_of[i];
+  HIP_TRY(hipMemcpyAsync(p->staging_psi, psi, sizeof(float2) * c.points,
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->internal));
+  HIP_TRY(launch_import_psi(c.ndim, c.nx, c.ny, p->staging_psi, c.psi + c.host[pos].psi_off, p->internal));
+  c.host[pos].mode = kModeClean;
+  p->state_ready[i] = 1;
+  return push_inst(p, i);
+}
+
+qhd_status qhd_set_steps_done(qhd_plan p, int32_t i, int64_t j) {
+  g_err.clear();
+  if (!p) return fail(QHD_EINVAL, "plan is NULL");
+  if (i < 0 || i >= (int)p->inst.size()) return fail(QHD_EINVAL, "instance index %d out of range", i);
+  if (j < 0 || j > p->inst[i].nsteps) return fail(QHD_EINVAL, "steps_done %lld outside [0, nsteps]", (long long)j);
+  HIP_TRY(hipSetDevice(p->device));
+  qhd_status st = sync_user_stream(p);
+  if (st != QHD_OK) return st;
+  ShapeClass& c = p->classes[p->cls_of[i]];
+  InstDev& I = c.host[p->pos_of[i]];
+  if (I.mode != kModeClean)
+    return fail(QHD_ESTATE, "instance %d: set_steps_done needs a clean state (call qhd_set_state first)", i);
+  I.steps_done = j;
+  return push_inst(p, i);
+}
+
+qhd_status qhd_evolve(qhd_plan p, int64_t max_steps, void* stream_v) {
+  g_err.clear();
+  if (!p) return fail(QHD_EINVAL, "plan is NULL");
+  const char* inj = std::getenv("QHD_FAULT_INJECT");
+  if (inj && std::strcmp(inj, "evolve") == 0) return fail(QHD_EDEVICE, "fault injected in qhd_evolve");
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    if (!p->potential_set[i]) return fail(QHD_ESTATE, "instance %zu: qhd_set_potential was not called", i);
+    if (!p->state_ready[i]) return fail(QHD_ESTATE, "instance %zu: INIT_USER needs qhd_set_state before evolve", i);
+  }
+  hipStream_t stream = (hipStream_t)stream_v;
+  HIP_TRY(hipSetDevice(p->device));
+  // host-side step limits (mirror of the device's)
+  long long S = 0;
+  std::vector<std::vector<long long>> lim(p->classes.size());
+  for (size_t ci = 0; ci < p->classes.size(); ++ci) {
+    ShapeClass& c = p->classes[ci];
+    lim[ci].resize(c.members.size());
+    for (size_t k = 0; k < c.members.size(); ++k) {
+      const long long rem = c.host[k].nsteps - c.host[k].steps_done;
+      const long long l = (max_steps < 0 || max_steps > rem) ? rem : max_steps;
+      lim[ci][k] = l;
+      S = std::max(S, l);
+    }
+  }
+  const bool timing = (p->opts.flags & QHD_OPT_TIME_PASSES) != 0;
+  const int stride = p->opts.timing_stride;
+  auto timed_launch = [&](int fam, double points, bool sample, auto&& fn) -> hipError_t {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (sample) {
+      a = take_event(p);
+      b = take_event(p);
+      if (a && b) (void)hipEventRecord(a, stream);
+    }
+    hipError_t r = fn();
+    if (sample && a && b) {
+      (void)hipEventRecord(b, stream);
+      p->pending.push_back({a, b, fam, points});
+    }
+    return r;
+  };
+  for (long long s = 0; s < S; ++s) {
+    const bool sample = timing && (s % stride == 0);
+    for (size_t ci = 0; ci < p->classes.size(); ++ci) {
+      ShapeClass& c = p->classes[ci];
+      int nact = 0;
+      for (size_t k = 0; k < c.members.size(); ++k)
+        if (lim[ci][k] > s) nact = (int)k + 1;
+      if (nact == 0) continue;
+      const double pts = (double)nact * (double)c.points;
+      if (c.ndim == 2) {
+        HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
+          return launch_row_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, (int)s, max_steps,
+                                    p->grid_cap, stream);
+        }));
+        HIP_TRY(timed_launch(c.fam_col, pts, sample, [&] {
+          return launch_col_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
+                                    p->grid_cap, stream);
+        }));
+      } else {
+        HIP_TRY(timed_launch(c.fam_line, pts, sample, [&] {
+          return launch_line_pass_1d(c.nx, c.dev, nact, c.psi, c.f, c.tw_x, (int)s, max_steps,
+                                     p->grid_cap, stream);
+        }));
+      }
+    }
+  }
+  for (size_t ci = 0; ci < p->classes.size(); ++ci) {
+    ShapeClass& c = p->classes[ci];
+    HIP_TRY(launch_commit(c.dev, (int)c.members.size(), max_steps, stream));
+    for (size_t k = 0; k < c.members.size(); ++k) {
+      if (lim[ci][k] > 0) {
+        c.host[k].steps_done += lim[ci][k];
+        c.host[k].mode = kModePending;
+      }
+    }
+  }
+  p->last_stream = stream;
+  p->last_stream_valid = true;
+  return QHD_OK;
+}
+
+qhd_status qhd_observe(qhd_plan p, void* stream_v, qhd_observables* out, float* rho_dev,
+                       float* psi_dev) {
+  g_err.clear();
+  if (!p) return fail(QHD_EINVAL, "plan is NULL");
+  if (!out) return fail(QHD_EINVAL, "host_out is NULL");
+  for (size_t i = 0; i < p->inst.size(); ++i)
+    if (!p->potential_set[i]) return fail(QHD_ESTATE, "instance %zu: qhd_set_potential was not called", i);
+  hipStream_t stream = (hipStream_t)stream_v;
+  HIP_TRY(hipSetDevice(p->device));
+  qhd_status status = QHD_OK;
+  for (auto& c : p->classes) {
+    const int m = (int)c.members.size();
+    if (c.ndim == 2)
+      HIP_TRY(launch_observe_2d(c.nx, c.ny, c.dev, m, c.psi, c.f, c.tw_x,
+                                reinterpret_cast<float2*>(psi_dev), rho_dev, c.partials, stream));
+    else
+      HIP_TRY(launch_observe_1d(c.nx, c.dev, m, c.psi, c.f, reinterpret_cast<float2*>(psi_dev),
+                                rho_dev, c.partials, stream));
+    HIP_TRY(launch_finalize(c.partials, c.lines, m, c.results, stream));
+    HIP_TRY(hipMemcpyAsync(p->host_results, c.results, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    for (int k = 0; k < m; ++k) {
+      const InstDev& I = c.host[k];
+      qhd_observables& o = out[I.plan_index];
+      const double* r = p->host_results + 3 * k;
+      o.norm = r[0];
+      o.e_f = r[1] / r[0];
+      o.success_mass = r[2] / r[0];
+      o.f_min = I.f_min;
+      o.argmin_index = I.argmin;
+      o.steps_done = I.steps_done;
+      o.t = (double)I.steps_done * I.dt;
+      if (!std::isfinite(o.norm) || !std::isfinite(o.e_f) || !std::isfinite(o.success_mass)) {
+        if (status == QHD_OK) status = fail(QHD_ENUMERIC, "instance %d: non-finite observable", I.plan_index);
+      } else if (std::fabs(o.norm - 1.0) > p->opts.norm_tolerance) {
+        if (status == QHD_OK)
+          status = fail(QHD_ENUMERIC, "instance %d: |norm - 1| = %.3e exceeds %.3e", I.plan_index,
+                        std::fabs(o.norm - 1.0), p->opts.norm_tolerance);
+      }
+    }
+  }
+  p->last_stream = stream;
+  p->last_stream_valid = true;
+  return status;
+}
+
+qhd_status qhd_kernel_timings(qhd_plan p, qhd_kernel_timing* out, int32_t cap, int32_t* count) {
+  g_err.clear();
+  if (!p || !count) return fail(QHD_EINVAL, "plan and count must not be NULL");
+  HIP_TRY(hipSetDevice(p->device));
+  qhd_status st = sync_user_stream(p);
+  if (st != QHD_OK) return st;
+  for (auto& pe : p->pending) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventSynchronize(pe.stop));
+    HIP_TRY(hipEventElapsedTime(&ms, pe.start, pe.stop));
+    Family& f = p->families[pe.family];
+    f.launches += 1;
+    f.total_ms += ms;
+    f.points += pe.points;
+    p->free_events.push_back(pe.start);
+    p->free_events.push_back(pe.stop);
+  }
+  p->pending.clear();
+  int n = 0;
+  for (auto& f : p->families) {
+    if (out && n < cap) {
+      qhd_kernel_timing& o = out[n];
+      std::memset(&o, 0, sizeof o);
+      std::snprintf(o.name, sizeof o.name, "%s", f.name.c_str());
+      o.launches = f.launches;
+      o.total_ms = f.total_ms;
+      o.points = f.points;
+      o.bytes_per_point = f.bytes_per_point;
+    }
+    ++n;
+    f.launches = 0;
+    f.total_ms = 0.0;
+    f.points = 0.0;
+  }
+  *count = n;
+  return QHD_OK;
+}
+
+}  // extern "C"

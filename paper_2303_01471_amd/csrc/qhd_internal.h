@@ -1,0 +1,79 @@
+// Internal types shared by the C-ABI layer (qhd_api.cpp) and the kernels
+// (qhd_kernels.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qhd {
+
+enum : int { kModeClean = 0, kModePending = 1 };
+enum : int { kSchedNesterov = 0, kSchedConst = 1, kSchedTable = 2 };
+
+// Per-instance parameters as the kernels see them.  One array per shape class.
+struct InstDev {
+  double dt;
+  double kin_turns[3];   // pi * dt / L_a^2: kinetic phase in turns per (a * n_a^2)
+  double h[3];           // mesh spacing per axis
+  double sched_p0, sched_p1;
+  const double* table;   // device copy of (a_j, b_j) pairs, kSchedTable only
+  double r2;             // success radius squared
+  double f_min;          // f(x*)
+  long long nsteps;
+  long long steps_done;  // authoritative device copy (updated by the commit kernel)
+  long long psi_off;     // element offset of the instance in its class buffers
+  long long out_off;     // element offset in plan-wide concatenated outputs
+  long long argmin;      // flat index of x*
+  int sched;
+  int mode;              // kModeClean / kModePending
+  int plan_index;        // position in the user's batch
+  int pad_;
+};
+
+// Sampled HIP-event timing of pass launches.
+struct TimingSink {
+  hipEvent_t* ev;        // pairs (start, stop); nullptr when timing is off
+  int* used;             // host counter of pairs in use for this launch family
+};
+
+// Launchers (qhd_kernels.hip).  All are asynchronous on `stream` and return
+// hipSuccess or the launch error.  `nx`, `ny` are the class's mesh sizes.
+hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
+                              const double* f, const double2* tw_nx, int s, long long max_steps,
+                              int grid_cap, hipStream_t stream);
+hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
+                              const double2* tw_ny, int s, long long max_steps, int grid_cap,
+                              hipStream_t stream);
+hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* psi, const double* f,
+                               const double2* tw, int s, long long max_steps, int grid_cap,
+                               hipStream_t stream);
+hipError_t launch_commit(InstDev* inst, int ninst, long long max_steps, hipStream_t stream);
+
+// Observe: closes the pending half step, writes the user-layout psi / rho
+// (optional, plan-wide concatenated buffers) and per-line FP64 partial sums
+// (3 per line: sum rho, sum f rho, sum of rho inside the success ball).
+hipError_t launch_observe_2d(int nx, int ny, const InstDev* inst, int ninst, const float2* psi,
+                             const double* f, const double2* tw_nx, float2* out_psi,
+                             float* out_rho, double* partials, hipStream_t stream);
+hipError_t launch_observe_1d(int n, const InstDev* inst, int ninst, const float2* psi,
+                             const double* f, float2* out_psi, float* out_rho, double* partials,
+                             hipStream_t stream);
+// Sum the per-line partials of each instance in a fixed order -> results[3*i + c].
+hipError_t launch_finalize(const double* partials, int lines_per_inst, int ninst, double* results,
+                           hipStream_t stream);
+
+// Potential / state upload helpers (user row-major <-> internal layout).
+hipError_t launch_import_f(int ndim, int nx, int ny, const double* user, double* dst,
+                           hipStream_t stream);
+hipError_t launch_import_psi(int ndim, int nx, int ny, const float2* user, float2* dst,
+                             hipStream_t stream);
+hipError_t launch_fill_psi(float2* dst, long long count, float value, hipStream_t stream);
+// Lowest-index minimiser of f (user row-major layout): out_val, out_idx.
+hipError_t launch_argmin(const double* f, long long count, double* out_val, long long* out_idx,
+                         hipStream_t stream);
+
+// Size the launch of the pass kernels (blocks actually used for a class).
+int pass_blocks_row_2d(int nx, int ny, int ninst, int grid_cap);
+int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap);
+
+}  // namespace qhd

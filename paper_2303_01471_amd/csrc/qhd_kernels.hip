@@ -1,0 +1,692 @@
+// HIP kernels of the QHD split-operator engine (gfx950 / CDNA4).
+//
+// One symmetric step of the product formula (App. C.2.1, eqs. prod_qhd and
+// prod_qhd_fft; App. E.1, Algorithm 1, taken in its symmetric form with
+// midpoint coefficients) is
+//
+//     psi <- V_j^{1/2} F^{-1} K_j F V_j^{1/2} psi,
+//     V_j^{1/2} = exp(-i (dt/2) b_j f(x)),   K_j = exp(-i dt a_j |k|^2 / 2),
+//
+// with a_j = a(t_{j+1/2}), b_j = b(t_{j+1/2}).  In 2-D, F = F_y F_x and the
+// state between steps is kept in (k_x, y) space, so one step costs two HBM
+// passes over the state:
+//
+//   row pass    (lines along x):  F_x . V_{j-1}^{1/2} V_j^{1/2} . F_x^{-1}
+//               (the trailing half step of step j-1 merged with the leading half
+//               of step j; on the first step of a clean state only V_j^{1/2} F_x)
+//   column pass (lines along y):  F_y^{-1} . K_j . F_y
+//
+// and the observe kernel closes the pending V_{k-1}^{1/2} F_x^{-1} on a copy.
+// In 1-D a single pass does V . F^{-1} K F.
+//
+// Memory layout in HBM (2-D): 8x8 tiles of 64 consecutive complex64 values,
+// tile rows of the mesh stored one after another, so that a tile row (8 mesh
+// rows) and a tile column (8 mesh columns) are both made of 512-byte contiguous
+// chunks.  f is stored as FP64 in the same layout: carrying f at FP64 precision
+// matters because the potential phase accumulates f * integral(b dt) (up to
+// ~8e4 f at T = 20), far beyond FP32's 2^-24 relative precision.
+//
+// Phases: every phase argument is formed in FP64, reduced to [-1/2, 1/2] turns,
+// evaluated with an FP32 sincospi, and the unit factor gets one Newton
+// magnitude correction in FP64 (w <- w (3 - |w|^2) / 2) so that phase factors
+// do not bias the norm.
+#include <climits>
+
+#include "line_fft.h"
+#include "qhd_internal.h"
+
+namespace qhd {
+
+constexpr double kInv2Pi = 0.15915494309189533577;
+
+__device__ __forceinline__ long long tile_index(int x, int y, int nx) {
+  return ((long long)((y >> 3) * (nx >> 3) + (x >> 3)) << 6) + ((y & 7) << 3) + (x & 7);
+}
+
+// a_j, b_j of global step j (App. C.2.1, eq. nonconvex_QHD_h at the midpoint)
+__device__ __forceinline__ void sched_ab(const InstDev& I, long long j, double& a, double& b) {
+  if (I.sched == kSchedTable) {
+    // lines of finished instances still evaluate (and discard) their step: never
+    // read outside the table
+    const bool in = (j >= 0 && j < I.nsteps);
+    a = in ? I.table[2 * j] : 0.0;
+    b = in ? I.table[2 * j + 1] : 0.0;
+  } else if (I.sched == kSchedConst) {
+    a = I.sched_p0;
+    b = I.sched_p1;
+  } else {
+    const double t = ((double)j + 0.5) * I.dt;
+    const double t3 = t * t * t;
+    a = 2.0 / (I.sched_p0 + t3);
+    b = 2.0 * t3;
+  }
+}
+
+// exp(-2 pi i tau) with tau in turns (FP64), Newton-normalised in FP64.
+__device__ __forceinline__ double2 phase_turns(double tau) {
+  const double r = tau - rint(tau);
+  float sn, cs;
+  sincospif(2.0f * (float)r, &sn, &cs);
+  const double c = (double)cs, s = (double)sn;
+  const double m = fma(c, c, s * s);
+  const double g = fma(-0.5, m, 1.5);
+  return make_double2(c * g, -s * g);
+}
+
+__device__ __forceinline__ long long step_limit(const InstDev& I, long long max_steps) {
+  const long long rem = I.nsteps - I.steps_done;
+  return (max_steps < 0 || max_steps > rem) ? rem : max_steps;
+}
+
+__device__ __forceinline__ int freq(int m, int n) { return m < (n >> 1) ? m : m - n; }
+
+// ------------------------------------------------------------------------------------
+// 2-D row pass: lines along x, one line per TPL lanes.
+
+template <int NX, int P>
+__global__ void __launch_bounds__(256) k_row_pass_2d(const InstDev* __restrict__ inst, int ninst,
+                                                     int ny, float2* __restrict__ psi,
+                                                     const double* __restrict__ f,
+                                                     const double2* __restrict__ twtab, int s,
+                                                     long long max_steps) {
+  constexpr int TPL = NX / P;
+  constexpr int LPW = 256 / TPL;
+  constexpr int SLOTS = LineLds<NX>::kSlots;
+  __shared__ float2 lds[LPW * SLOTS];
+  const int ll = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  float2* my = lds + ll * SLOTS;
+  Twiddles<NX, P> tw;
+  tw.load(twtab, t);
+  const long long total = (long long)ninst * ny;
+  for (long long l0 = (long long)blockIdx.x * LPW; l0 < total; l0 += (long long)gridDim.x * LPW) {
+    const long long L = l0 + ll;
+    const bool valid = L < total;
+    const long long Lc = valid ? L : total - 1;
+    const int i = (int)(Lc / ny), y = (int)(Lc - (long long)i * ny);
+    const InstDev& I = inst[i];
+    const bool active = valid && s < step_limit(I, max_steps);
+    const long long j = I.steps_done + s;
+    const bool entry = (s == 0 && I.mode == kModeClean);
+    double a, b, bp;
+    sched_ab(I, j, a, b);
+    double beta = 0.5 * I.dt * b;
+    if (!entry && j > 0) {
+      sched_ab(I, j - 1, a, bp);
+      beta += 0.5 * I.dt * bp;
+    }
+    const double cpot = beta * kInv2Pi;
+    const long long base = I.psi_off;
+    double2 reg[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) reg[q] = to_d2(psi[base + tile_index(t + q * TPL, y, NX)]);
+    if (!entry) line_fft<NX, P, +1>(reg, t, tw, my);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const double fv = f[base + tile_index(t + q * TPL, y, NX)];
+      reg[q] = cmul(reg[q], phase_turns(cpot * fv));
+    }
+    line_fft<NX, P, -1>(reg, t, tw, my);
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) psi[base + tile_index(t + q * TPL, y, NX)] = to_f2(reg[q]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// 2-D column pass: a tile column (8 mesh columns) is staged through LDS with
+// 512-byte tile loads; each column is then one line of TPL lanes.
+
+template <int NY, int P>
+struct ColCfg {
+  static constexpr int TPL = NY / P;
+  static constexpr int ITEMS = (8 * TPL >= 256) ? 1 : 256 / (8 * TPL);  // tile columns per block
+  static constexpr int NT = ITEMS * 8 * TPL;
+  // line stride in LDS slots, = 2 (mod 16) so the tile scatter hits distinct banks
+  static constexpr int STRIDE = ((LineLds<NY>::kSlots + 13) / 16) * 16 + 2;
+};
+
+template <int NY, int P>
+__global__ void __launch_bounds__((ColCfg<NY, P>::NT)) k_col_pass_2d(
+    const InstDev* __restrict__ inst, int ninst, int nx, float2* __restrict__ psi,
+    const double2* __restrict__ twtab, int s, long long max_steps) {
+  using C = ColCfg<NY, P>;
+  constexpr int TPL = C::TPL, ITEMS = C::ITEMS, NT = C::NT, STRIDE = C::STRIDE;
+  constexpr int TILES = NY / 8;
+  __shared__ float2 lds[ITEMS * 8 * STRIDE];
+  const int tid = threadIdx.x;
+  const int line = tid / TPL, t = tid % TPL;  // line in [0, ITEMS*8)
+  float2* my = lds + line * STRIDE;
+  Twiddles<NY, P> tw;
+  tw.load(twtab, t);
+  const int tcols = nx >> 3;
+  const long long total = (long long)ninst * tcols;
+  const double inv_n = 1.0 / ((double)nx * (double)NY);
+  for (long long g0 = (long long)blockIdx.x * ITEMS; g0 < total; g0 += (long long)gridDim.x * ITEMS) {
+    // stage the tile columns: each thread moves float4 = two complex values
+    for (int e = tid; e < ITEMS * TILES * 32; e += NT) {
+      const int it = e / (TILES * 32), rem = e - it * (TILES * 32);
+      const int ty = rem >> 5, w = rem & 31;
+      const long long g = g0 + it;
+      if (g < total) {
+        const int i = (int)(g / tcols), tc = (int)(g - (long long)i * tcols);
+        const InstDev& I = inst[i];
+        if (s < step_limit(I, max_steps)) {
+          const float4 v = reinterpret_cast<const float4*>(
+              psi + I.psi_off + ((long long)(ty * tcols + tc) << 6))[w];
+          const int yy = w >> 2, xx = (w & 3) << 1;
+          const int y = ty * 8 + yy;
+          lds[(it * 8 + xx) * STRIDE + lds_slot(y)] = make_float2(v.x, v.y);
+          lds[(it * 8 + xx + 1) * STRIDE + lds_slot(y)] = make_float2(v.z, v.w);
+        }
+      }
+    }
+    __syncthreads();
+    {
+      const long long g = g0 + line / 8;
+      const long long gc = g < total ? g : total - 1;
+      const int i = (int)(gc / tcols), tc = (int)(gc - (long long)i * tcols);
+      const InstDev& I = inst[i];
+      const int x = tc * 8 + (line & 7);
+      double a, b;
+      sched_ab(I, I.steps_done + s, a, b);
+      const int nxf = freq(x, nx);
+      const double cx = a * I.kin_turns[0] * (double)(nxf * nxf);
+      const double cy = a * I.kin_turns[1];
+      double2 reg[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) reg[q] = to_d2(my[lds_slot(t + q * TPL)]);
+      wave_lds_sync();
+      line_fft<NY, P, -1>(reg, t, tw, my);
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const int nyf = freq(t + q * TPL, NY);
+        double2 w = phase_turns(fma(cy, (double)(nyf * nyf), cx));
+        w.x *= inv_n;
+        w.y *= inv_n;
+        reg[q] = cmul(reg[q], w);
+      }
+      line_fft<NY, P, +1>(reg, t, tw, my);
+#pragma unroll
+      for (int q = 0; q < P; ++q) my[lds_slot(t + q * TPL)] = to_f2(reg[q]);
+    }
+    __syncthreads();
+    for (int e = tid; e < ITEMS * TILES * 32; e += NT) {
+      const int it = e / (TILES * 32), rem = e - it * (TILES * 32);
+      const int ty = rem >> 5, w = rem & 31;
+      const long long g = g0 + it;
+      if (g < total) {
+        const int i = (int)(g / tcols), tc = (int)(g - (long long)i * tcols);
+        const InstDev& I = inst[i];
+        if (s < step_limit(I, max_steps)) {
+          const int yy = w >> 2, xx = (w & 3) << 1;
+          const int y = ty * 8 + yy;
+          const float2 p0 = lds[(it * 8 + xx) * STRIDE + lds_slot(y)];
+          const float2 p1 = lds[(it * 8 + xx + 1) * STRIDE + lds_slot(y)];
+          reinterpret_cast<float4*>(psi + I.psi_off + ((long long)(ty * tcols + tc) << 6))[w] =
+              make_float4(p0.x, p0.y, p1.x, p1.y);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// 1-D pass: V (merged halves) . F . K . F^{-1}, the state stays in position space
+// with the trailing half step of the last step pending.
+
+template <int N, int P>
+__global__ void __launch_bounds__(256) k_line_pass_1d(const InstDev* __restrict__ inst, int ninst,
+                                                      float2* __restrict__ psi,
+                                                      const double* __restrict__ f,
+                                                      const double2* __restrict__ twtab, int s,
+                                                      long long max_steps) {
+  constexpr int TPL = N / P;
+  constexpr int LPW = (256 / TPL) > 0 ? 256 / TPL : 1;
+  constexpr int SLOTS = LineLds<N>::kSlots;
+  __shared__ float2 lds[LPW * SLOTS];
+  const int ll = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  float2* my = lds + ll * SLOTS;
+  Twiddles<N, P> tw;
+  tw.load(twtab, t);
+  for (long long l0 = (long long)blockIdx.x * LPW; l0 < ninst; l0 += (long long)gridDim.x * LPW) {
+    const long long L = l0 + ll;
+    const bool valid = L < ninst;
+    const int i = (int)(valid ? L : ninst - 1);
+    const InstDev& I = inst[i];
+    const bool active = valid && s < step_limit(I, max_steps);
+    const long long j = I.steps_done + s;
+    const bool entry = (s == 0 && I.mode == kModeClean);
+    double a, b, ap, bp;
+    sched_ab(I, j, a, b);
+    double beta = 0.5 * I.dt * b;
+    if (!entry && j > 0) {
+      sched_ab(I, j - 1, ap, bp);
+      beta += 0.5 * I.dt * bp;
+    }
+    const double cpot = beta * kInv2Pi;
+    const double ck = a * I.kin_turns[0];
+    const double inv_n = 1.0 / (double)N;
+    const long long base = I.psi_off;
+    double2 reg[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const long long p = base + t + q * TPL;
+      reg[q] = cmul(to_d2(psi[p]), phase_turns(cpot * f[p]));
+    }
+    line_fft<N, P, -1>(reg, t, tw, my);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const int nf = freq(t + q * TPL, N);
+      double2 w = phase_turns(ck * (double)(nf * nf));
+      w.x *= inv_n;
+      w.y *= inv_n;
+      reg[q] = cmul(reg[q], w);
+    }
+    line_fft<N, P, +1>(reg, t, tw, my);
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) psi[base + t + q * TPL] = to_f2(reg[q]);
+    }
+  }
+}
+
+__global__ void k_commit(InstDev* __restrict__ inst, int ninst, long long max_steps) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  const long long lim = step_limit(inst[i], max_steps);
+  if (lim > 0) {
+    inst[i].steps_done += lim;
+    inst[i].mode = kModePending;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Observe (readouts of App. B / Algorithm 1 / main-text fig. 2)
+
+// deterministic sum over the TPL lanes of one line (lanes are contiguous)
+template <int TPL>
+__device__ __forceinline__ double line_sum(double v) {
+#pragma unroll
+  for (int o = TPL / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ bool in_ball(int dxi, int dyi, const InstDev& I) {
+  // same FP64 operations, in the same order and without contraction, as the oracle
+  const double dx = __dmul_rn((double)dxi, I.h[0]);
+  const double dy = __dmul_rn((double)dyi, I.h[1]);
+  return __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)) < I.r2;
+}
+
+template <int NX, int P>
+__global__ void __launch_bounds__(256) k_observe_2d(const InstDev* __restrict__ inst, int ninst,
+                                                    int ny, const float2* __restrict__ psi,
+                                                    const double* __restrict__ f,
+                                                    const double2* __restrict__ twtab,
+                                                    float2* __restrict__ out_psi,
+                                                    float* __restrict__ out_rho,
+                                                    double* __restrict__ partials) {
+  constexpr int TPL = NX / P;
+  constexpr int LPW = 256 / TPL;
+  constexpr int SLOTS = LineLds<NX>::kSlots;
+  __shared__ float2 lds[LPW * SLOTS];
+  const int ll = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  float2* my = lds + ll * SLOTS;
+  Twiddles<NX, P> tw;
+  tw.load(twtab, t);
+  const long long total = (long long)ninst * ny;
+  for (long long l0 = (long long)blockIdx.x * LPW; l0 < total; l0 += (long long)gridDim.x * LPW) {
+    const long long L = l0 + ll;
+    const bool valid = L < total;
+    const long long Lc = valid ? L : total - 1;
+    const int i = (int)(Lc / ny), y = (int)(Lc - (long long)i * ny);
+    const InstDev& I = inst[i];
+    const bool pending = (I.mode == kModePending);
+    const long long base = I.psi_off;
+    double2 reg[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) reg[q] = to_d2(psi[base + tile_index(t + q * TPL, y, NX)]);
+    double fv[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) fv[q] = f[base + tile_index(t + q * TPL, y, NX)];
+    if (pending) {
+      double a, b;
+      sched_ab(I, I.steps_done - 1, a, b);
+      const double cpot = 0.5 * I.dt * b * kInv2Pi;
+      line_fft<NX, P, +1>(reg, t, tw, my);
+#pragma unroll
+      for (int q = 0; q < P; ++q) reg[q] = cmul(reg[q], phase_turns(cpot * fv[q]));
+    }
+    const int xs = (int)(I.argmin % NX), ys = (int)(I.argmin / NX);
+    double sr = 0.0, sf = 0.0, sm = 0.0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const int x = t + q * TPL;
+      const float2 v = to_f2(reg[q]);
+      const double rho = (double)v.x * v.x + (double)v.y * v.y;
+      sr += rho;
+      sf += fv[q] * rho;
+      if (in_ball(x - xs, y - ys, I)) sm += rho;
+      if (valid) {
+        const long long o = I.out_off + (long long)y * NX + x;
+        if (out_psi) out_psi[o] = v;
+        if (out_rho) out_rho[o] = (float)rho;
+      }
+    }
+    sr = line_sum<TPL>(sr);
+    sf = line_sum<TPL>(sf);
+    sm = line_sum<TPL>(sm);
+    if (valid && t == 0) {
+      partials[3 * L + 0] = sr;
+      partials[3 * L + 1] = sf;
+      partials[3 * L + 2] = sm;
+    }
+  }
+}
+
+template <int N, int P>
+__global__ void __launch_bounds__(256) k_observe_1d(const InstDev* __restrict__ inst, int ninst,
+                                                    const float2* __restrict__ psi,
+                                                    const double* __restrict__ f,
+                                                    float2* __restrict__ out_psi,
+                                                    float* __restrict__ out_rho,
+                                                    double* __restrict__ partials) {
+  constexpr int TPL = N / P;
+  constexpr int LPW = (256 / TPL) > 0 ? 256 / TPL : 1;
+  const int ll = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  for (long long l0 = (long long)blockIdx.x * LPW; l0 < ninst; l0 += (long long)gridDim.x * LPW) {
+    const long long L = l0 + ll;
+    const bool valid = L < ninst;
+    const int i = (int)(valid ? L : ninst - 1);
+    const InstDev& I = inst[i];
+    double cpot = 0.0;
+    if (I.mode == kModePending) {
+      double a, b;
+      sched_ab(I, I.steps_done - 1, a, b);
+      cpot = 0.5 * I.dt * b * kInv2Pi;
+    }
+    const int xs = (int)I.argmin;
+    double sr = 0.0, sf = 0.0, sm = 0.0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const int x = t + q * TPL;
+      const long long p = I.psi_off + x;
+      const double fv = f[p];
+      double2 r = to_d2(psi[p]);
+      if (I.mode == kModePending) r = cmul(r, phase_turns(cpot * fv));
+      const float2 v = to_f2(r);
+      const double rho = (double)v.x * v.x + (double)v.y * v.y;
+      sr += rho;
+      sf += fv * rho;
+      const double dx = __dmul_rn((double)(x - xs), I.h[0]);
+      if (__dmul_rn(dx, dx) < I.r2) sm += rho;
+      if (valid) {
+        const long long o = I.out_off + x;
+        if (out_psi) out_psi[o] = v;
+        if (out_rho) out_rho[o] = (float)rho;
+      }
+    }
+    sr = line_sum<TPL>(sr);
+    sf = line_sum<TPL>(sf);
+    sm = line_sum<TPL>(sm);
+    if (valid && t == 0) {
+      partials[3 * L + 0] = sr;
+      partials[3 * L + 1] = sf;
+      partials[3 * L + 2] = sm;
+    }
+  }
+}
+
+// Neumaier-compensated, fixed-order sum of each instance's line partials.
+__global__ void k_finalize(const double* __restrict__ partials, int lines, int ninst,
+                           double* __restrict__ results) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double s = 0.0, comp = 0.0;
+    for (int l = 0; l < lines; ++l) {
+      const double v = partials[3 * ((long long)i * lines + l) + c];
+      const double tt = s + v;
+      comp += (fabs(s) >= fabs(v)) ? ((s - tt) + v) : ((v - tt) + s);
+      s = tt;
+    }
+    results[3 * i + c] = s + comp;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// uploads
+
+__global__ void k_import_f_2d(const double* __restrict__ user, double* __restrict__ dst, int nx,
+                              int ny) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (long long)nx * ny) return;
+  const int x = (int)(p % nx), y = (int)(p / nx);
+  dst[tile_index(x, y, nx)] = user[p];
+}
+
+__global__ void k_import_psi_2d(const float2* __restrict__ user, float2* __restrict__ dst, int nx,
+                                int ny) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (long long)nx * ny) return;
+  const int x = (int)(p % nx), y = (int)(p / nx);
+  dst[tile_index(x, y, nx)] = user[p];
+}
+
+__global__ void k_copy_f(const double* __restrict__ src, double* __restrict__ dst, long long n) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) dst[p] = src[p];
+}
+
+__global__ void k_copy_psi(const float2* __restrict__ src, float2* __restrict__ dst, long long n) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) dst[p] = src[p];
+}
+
+__global__ void k_fill(float2* __restrict__ dst, long long n, float v) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) dst[p] = make_float2(v, 0.0f);
+}
+
+// lowest-index minimiser; also counts non-finite entries (reported in out_idx[1])
+__global__ void __launch_bounds__(1024) k_argmin(const double* __restrict__ f, long long n,
+                                                 double* __restrict__ out_val,
+                                                 long long* __restrict__ out_idx) {
+  __shared__ double sv[1024];
+  __shared__ long long si[1024];
+  __shared__ int sbad[1024];
+  double bv = INFINITY;
+  long long bi = LLONG_MAX;
+  int bad = 0;
+  for (long long p = threadIdx.x; p < n; p += blockDim.x) {
+    const double v = f[p];
+    if (!isfinite(v)) {
+      ++bad;
+      continue;
+    }
+    if (v < bv || (v == bv && p < bi)) {
+      bv = v;
+      bi = p;
+    }
+  }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      const double v = sv[threadIdx.x + o];
+      const long long id = si[threadIdx.x + o];
+      if (v < sv[threadIdx.x] || (v == sv[threadIdx.x] && id < si[threadIdx.x])) {
+        sv[threadIdx.x] = v;
+        si[threadIdx.x] = id;
+      }
+      sbad[threadIdx.x] += sbad[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out_val[0] = sv[0];
+    out_idx[0] = si[0];
+    out_idx[1] = sbad[0];
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// launchers
+
+namespace {
+
+template <int N>
+constexpr int pts_per_lane() { return N >= 1024 ? 16 : 8; }
+
+inline int blocks_for(long long items, int per_block, int cap) {
+  long long b = (items + per_block - 1) / per_block;
+  if (cap > 0 && b > cap) b = cap;
+  return (int)(b < 1 ? 1 : b);
+}
+
+#define QHD_SWITCH_N(n, BODY)                 \
+  switch (n) {                                \
+    case 8: { constexpr int N_ = 8; BODY; }     \
+    case 16: { constexpr int N_ = 16; BODY; }   \
+    case 32: { constexpr int N_ = 32; BODY; }   \
+    case 64: { constexpr int N_ = 64; BODY; }   \
+    case 128: { constexpr int N_ = 128; BODY; } \
+    case 256: { constexpr int N_ = 256; BODY; } \
+    case 512: { constexpr int N_ = 512; BODY; } \
+    case 1024: { constexpr int N_ = 1024; BODY; } \
+    default: return hipErrorInvalidValue;     \
+  }
+
+}  // namespace
+
+int pass_blocks_row_2d(int nx, int ny, int ninst, int grid_cap) {
+  const int P = nx >= 1024 ? 16 : 8;
+  const int lpw = 256 / (nx / P);
+  return blocks_for((long long)ninst * ny, lpw, grid_cap);
+}
+
+int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap) {
+  const int P = ny >= 1024 ? 16 : 8;
+  const int tpl = ny / P;
+  const int items = (8 * tpl >= 256) ? 1 : 256 / (8 * tpl);
+  return blocks_for((long long)ninst * (nx / 8), items, grid_cap);
+}
+
+hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
+                              const double* f, const double2* tw, int s, long long max_steps,
+                              int grid_cap, hipStream_t stream) {
+  const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap);
+  QHD_SWITCH_N(nx, {
+    constexpr int P_ = pts_per_lane<N_>();
+    hipLaunchKernelGGL((k_row_pass_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+                       ny, psi, f, tw, s, max_steps);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
+                              const double2* tw, int s, long long max_steps, int grid_cap,
+                              hipStream_t stream) {
+  const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap);
+  QHD_SWITCH_N(ny, {
+    constexpr int P_ = pts_per_lane<N_>();
+    hipLaunchKernelGGL((k_col_pass_2d<N_, P_>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0, stream,
+                       inst, ninst, nx, psi, tw, s, max_steps);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* psi, const double* f,
+                               const double2* tw, int s, long long max_steps, int grid_cap,
+                               hipStream_t stream) {
+  QHD_SWITCH_N(n, {
+    constexpr int P_ = pts_per_lane<N_>();
+    constexpr int TPL_ = N_ / P_;
+    constexpr int LPW_ = (256 / TPL_) > 0 ? 256 / TPL_ : 1;
+    const int blocks = blocks_for(ninst, LPW_, grid_cap);
+    hipLaunchKernelGGL((k_line_pass_1d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+                       psi, f, tw, s, max_steps);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_commit(InstDev* inst, int ninst, long long max_steps, hipStream_t stream) {
+  hipLaunchKernelGGL(k_commit, dim3((ninst + 255) / 256), dim3(256), 0, stream, inst, ninst,
+                     max_steps);
+  return hipGetLastError();
+}
+
+hipError_t launch_observe_2d(int nx, int ny, const InstDev* inst, int ninst, const float2* psi,
+                             const double* f, const double2* tw, float2* out_psi, float* out_rho,
+                             double* partials, hipStream_t stream) {
+  QHD_SWITCH_N(nx, {
+    constexpr int P_ = pts_per_lane<N_>();
+    constexpr int LPW_ = 256 / (N_ / P_);
+    const int blocks = blocks_for((long long)ninst * ny, LPW_, 4096);
+    hipLaunchKernelGGL((k_observe_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst, ny,
+                       psi, f, tw, out_psi, out_rho, partials);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_observe_1d(int n, const InstDev* inst, int ninst, const float2* psi,
+                             const double* f, float2* out_psi, float* out_rho, double* partials,
+                             hipStream_t stream) {
+  QHD_SWITCH_N(n, {
+    constexpr int P_ = pts_per_lane<N_>();
+    constexpr int TPL_ = N_ / P_;
+    constexpr int LPW_ = (256 / TPL_) > 0 ? 256 / TPL_ : 1;
+    const int blocks = blocks_for(ninst, LPW_, 4096);
+    hipLaunchKernelGGL((k_observe_1d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+                       psi, f, out_psi, out_rho, partials);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_finalize(const double* partials, int lines_per_inst, int ninst, double* results,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(k_finalize, dim3((ninst + 63) / 64), dim3(64), 0, stream, partials,
+                     lines_per_inst, ninst, results);
+  return hipGetLastError();
+}
+
+hipError_t launch_import_f(int ndim, int nx, int ny, const double* user, double* dst,
+                           hipStream_t stream) {
+  const long long n = (long long)nx * ny;
+  const int blocks = (int)((n + 255) / 256);
+  if (ndim == 2)
+    hipLaunchKernelGGL(k_import_f_2d, dim3(blocks), dim3(256), 0, stream, user, dst, nx, ny);
+  else
+    hipLaunchKernelGGL(k_copy_f, dim3(blocks), dim3(256), 0, stream, user, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_import_psi(int ndim, int nx, int ny, const float2* user, float2* dst,
+                             hipStream_t stream) {
+  const long long n = (long long)nx * ny;
+  const int blocks = (int)((n + 255) / 256);
+  if (ndim == 2)
+    hipLaunchKernelGGL(k_import_psi_2d, dim3(blocks), dim3(256), 0, stream, user, dst, nx, ny);
+  else
+    hipLaunchKernelGGL(k_copy_psi, dim3(blocks), dim3(256), 0, stream, user, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_psi(float2* dst, long long count, float value, hipStream_t stream) {
+  const int blocks = (int)((count + 255) / 256);
+  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, stream, dst, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_argmin(const double* f, long long count, double* out_val, long long* out_idx,
+                         hipStream_t stream) {
+  hipLaunchKernelGGL(k_argmin, dim3(1), dim3(1024), 0, stream, f, count, out_val, out_idx);
+  return hipGetLastError();
+}
+
+}  // namespace qhd

@@ -1,0 +1,93 @@
+"""C-ABI library checks that need no GPU: it loads, exports every symbol that
+include/qhd.h declares, and rejects invalid descriptors in its host-only
+validation layer before touching any device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2303_01471_amd import qhd as q
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qhd.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qhd_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = q.load_library()
+    syms = declared_symbols()
+    assert "qhd_plan_create" in syms and "qhd_evolve" in syms and "qhd_observe" in syms
+    for s in syms:
+        assert hasattr(lib, s), f"libqhd.so does not export {s}"
+        assert s in q._SIGNATURES, f"binding has no signature for {s}"
+
+
+def test_version_string():
+    assert "gfx950" in q.qhd_version()
+
+
+def _inst(**kw):
+    spec = dict(shape=(64, 64), nsteps=10, dt=1e-2)
+    spec.update(kw)
+    return q.InstanceSpec(**spec).to_c([])
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda d: setattr(d, "ndim", 0), q.QHD_EINVAL),
+    (lambda d: setattr(d, "ndim", 3), q.QHD_EUNSUPPORTED),
+    (lambda d: d.n.__setitem__(0, 48), q.QHD_EINVAL),
+    (lambda d: d.n.__setitem__(1, 2048), q.QHD_EINVAL),
+    (lambda d: d.n.__setitem__(0, 4), q.QHD_EINVAL),
+    (lambda d: setattr(d, "dt", 0.0), q.QHD_EINVAL),
+    (lambda d: setattr(d, "dt", float("nan")), q.QHD_EINVAL),
+    (lambda d: setattr(d, "nsteps", -1), q.QHD_EINVAL),
+    (lambda d: d.hi.__setitem__(0, d.lo[0]), q.QHD_EINVAL),
+    (lambda d: setattr(d, "success_radius", 0.0), q.QHD_EINVAL),
+    (lambda d: setattr(d, "sched_kind", 7), q.QHD_EINVAL),
+    (lambda d: d.sched_p.__setitem__(0, 0.0), q.QHD_EINVAL),
+    (lambda d: setattr(d, "sched_kind", q.QHD_SCHED_TABLE), q.QHD_EINVAL),  # NULL table
+    (lambda d: setattr(d, "init_kind", 5), q.QHD_EINVAL),
+])
+def test_invalid_descriptor_rejected_before_device_work(mutate, status):
+    good = _inst()
+    bad = _inst()
+    mutate(bad)
+    with pytest.raises(q.QHDError) as ei:
+        q.qhd_plan_create([good, bad])
+    assert ei.value.status == status
+    assert "instance 1" in ei.value.message
+
+
+def test_table_with_nan_rejected():
+    tab = np.ones((10, 2))
+    tab[3, 1] = np.nan
+    keep = []
+    d = q.InstanceSpec(shape=(8, 8), nsteps=10, dt=1e-2, sched=q.QHD_SCHED_TABLE, table=tab).to_c(keep)
+    with pytest.raises(q.QHDError) as ei:
+        q.qhd_plan_create([d])
+    assert ei.value.status == q.QHD_EINVAL and "sched_table" in ei.value.message
+
+
+def test_null_arguments():
+    lib = q.load_library()
+    out = ctypes.c_void_p()
+    assert lib.qhd_plan_create(None, 1, None, ctypes.byref(out)) == q.QHD_EINVAL
+    assert q.qhd_last_error()
+    arr = (q.qhd_instance * 1)(_inst())
+    assert lib.qhd_plan_create(arr, 0, None, ctypes.byref(out)) == q.QHD_EINVAL
+    assert lib.qhd_plan_create(arr, 1, None, None) == q.QHD_EINVAL
+    assert lib.qhd_evolve(None, 1, None) == q.QHD_EINVAL
+    assert lib.qhd_observe(None, None, None, None, None) == q.QHD_EINVAL
+    assert lib.qhd_set_potential(None, 0, None, 0) == q.QHD_EINVAL
+    assert lib.qhd_set_state(None, 0, None, 0) == q.QHD_EINVAL
+    assert lib.qhd_set_steps_done(None, 0, 0) == q.QHD_EINVAL
+    n = ctypes.c_int64()
+    assert lib.qhd_plan_points(None, ctypes.byref(n)) == q.QHD_EINVAL
+    assert lib.qhd_plan_destroy(None) == q.QHD_OK

@@ -1,0 +1,189 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the GPU.
+
+Bar: max |psi_gpu - psi_oracle| <= 1e-4 (FP32 state; discrete normalisation
+sum |psi|^2 = 1 of App. E.1, eq. wave-rep) and |norm - 1| <= 1e-5 per 10k steps;
+the readouts E[f] and the success mass are compared too, x* and f(x*) exactly.
+"""
+import numpy as np
+import pytest
+
+import qhd_inputs
+from gpu_helpers import NORM_TOL, PSI_TOL, compare, note, run_gpu, run_oracle
+from paper_2303_01471_amd import qhd as q
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    q.load_library()
+
+
+def _check(specs, fs, res, psis, label, psi_tol=PSI_TOL, states=None, j0s=None):
+    for i, (spec, f) in enumerate(zip(specs, fs)):
+        psi0 = None if not states or i not in states else states[i]
+        j0 = 0 if not j0s or i not in j0s else j0s[i]
+        ref, ro = run_oracle(spec, f, psi0, j0)
+        err, nd, d_ef, d_p = compare(spec, f, res[i], psis[i], ref, ro, f"{label}[{i}]")
+        assert err <= psi_tol, f"{label}[{i}]: max|dpsi| {err:.3e} > {psi_tol}"
+        drift_allow = NORM_TOL * max(1.0, (spec.nsteps - j0) / 1e4)
+        assert abs(res[i]["norm"] - ro.norm) <= drift_allow
+        assert d_ef <= 1e-3 and d_p <= 1e-4
+        assert res[i]["argmin_index"] == ro.argmin and res[i]["f_min"] == ro.f_min
+        assert res[i]["steps_done"] == spec.nsteps
+
+
+def test_config0_64x64_1000_steps():
+    """64x64 on [0,1]^2, a = 2/(1e-3 + t^3), b = 2 t^3, dt = 0.01, 1000 steps."""
+    note("case: 64x64 seed 1234, 1000 steps")
+    spec = q.InstanceSpec(shape=(64, 64), nsteps=1000, dt=1e-2)
+    f = qhd_inputs.landscape_grid(1234, (64, 64))
+    res, psis, rhos, st = run_gpu([spec], [f])
+    assert st == q.QHD_OK
+    _check([spec], [f], res, psis, "c0")
+    assert np.allclose(rhos[0], np.abs(psis[0]) ** 2, rtol=1e-6, atol=1e-12)
+
+
+def test_ragged_batch_shapes_and_schedules():
+    """One launch sequence over uneven shapes (1-D and 2-D, square and
+    rectangular, anisotropic boxes), uneven step counts and all schedule kinds."""
+    note("case: ragged batch")
+    rng = np.random.default_rng(7)
+    tab_n = 150
+    t = (np.arange(tab_n) + 0.5) * 2e-3
+    table = np.stack([1.0 / (0.1 + t), 3.0 * t * t], axis=1)
+    specs = [
+        q.InstanceSpec(shape=(8, 8), nsteps=300, dt=1e-2),
+        q.InstanceSpec(shape=(16, 32), nsteps=120, dt=5e-3, box=[(0.0, 0.5), (-1.0, 1.0)], radius=0.2),
+        q.InstanceSpec(shape=(128, 64), nsteps=257, dt=1e-2),
+        q.InstanceSpec(shape=(64, 64), nsteps=0, dt=1e-2),
+        q.InstanceSpec(shape=(32, 256), nsteps=90, dt=1e-3, sched=q.QHD_SCHED_CONST, sched_p=(0.7, 2.0)),
+        q.InstanceSpec(shape=(64, 128), nsteps=tab_n, dt=2e-3, sched=q.QHD_SCHED_TABLE, table=table),
+        q.InstanceSpec(shape=(1024, 8), nsteps=40, dt=1e-2),
+        q.InstanceSpec(shape=(8, 1024), nsteps=40, dt=1e-2),
+        q.InstanceSpec(shape=(8,), nsteps=500, dt=1e-2),
+        q.InstanceSpec(shape=(256,), nsteps=333, dt=1e-2, box=[(-3.0, 3.0)], radius=0.5),
+        q.InstanceSpec(shape=(1024,), nsteps=200, dt=1e-3),
+        q.InstanceSpec(shape=(64, 64), nsteps=300, dt=1e-2),
+    ]
+    fs = []
+    for k, s in enumerate(specs):
+        if len(s.shape) == 2:
+            fs.append(qhd_inputs.evaluate(qhd_inputs.draw_landscape(100 + k), s.shape, s.box))
+        else:
+            fs.append(rng.uniform(0.0, 3.0, size=s.shape))
+    res, psis, _, st = run_gpu(specs, fs)
+    assert st == q.QHD_OK
+    _check(specs, fs, res, psis, "ragged")
+
+
+def test_chunked_evolve_is_bitwise_one_shot():
+    note("case: chunked vs one-shot")
+    specs = [q.InstanceSpec(shape=(64, 64), nsteps=400, dt=1e-2),
+             q.InstanceSpec(shape=(32, 128), nsteps=250, dt=1e-2),
+             q.InstanceSpec(shape=(256,), nsteps=300, dt=1e-2)]
+    fs = [qhd_inputs.landscape_grid(11, (64, 64)), qhd_inputs.landscape_grid(12, (32, 128)),
+          np.linspace(0, 2, 256) ** 2]
+    r1, p1, _, _ = run_gpu(specs, fs)
+    r2, p2, _, _ = run_gpu(specs, fs, chunks=[1, 37, 100, 5])
+    for a, b in zip(p1, p2):
+        assert np.array_equal(a, b)
+    for a, b in zip(r1, r2):
+        assert a == b
+
+
+def test_repeat_run_is_bitwise_identical():
+    note("case: determinism")
+    spec = q.InstanceSpec(shape=(128, 128), nsteps=300, dt=1e-2)
+    f = qhd_inputs.landscape_grid(5, (128, 128))
+    r1, p1, _, _ = run_gpu([spec], [f])
+    r2, p2, _, _ = run_gpu([spec], [f])
+    assert np.array_equal(p1[0], p2[0]) and r1 == r2
+
+
+def test_resume_from_checkpoint():
+    """ψ_k read back, then a new plan with INIT_USER, qhd_set_state and
+    qhd_set_steps_done(k) continues the schedule at t_{k+1/2}."""
+    note("case: resume")
+    n, k, total = 64, 300, 700
+    f = qhd_inputs.landscape_grid(21, (n, n))
+    first = q.InstanceSpec(shape=(n, n), nsteps=total, dt=1e-2)
+    import torch
+    plan = q.Plan([first])
+    plan.set_potential(0, f)
+    plan.evolve(k)
+    _, psi, _, _ = plan.observe(want_psi=True)
+    psi_k = plan.psi_of(psi, 0).contiguous()
+    plan.close()
+    second = q.InstanceSpec(shape=(n, n), nsteps=total, dt=1e-2, init=q.QHD_INIT_USER)
+    res, psis, _, st = run_gpu([second], [f], states={0: psi_k}, steps_done={0: k})
+    torch.cuda.synchronize()
+    _check([second], [f], res, psis, "resume", states={0: psi_k.cpu().numpy()}, j0s={0: k})
+
+
+def test_user_initial_state():
+    note("case: user psi0")
+    rng = np.random.default_rng(3)
+    n = 32
+    psi0 = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))).astype(np.complex64)
+    psi0 /= np.sqrt(np.sum(np.abs(psi0.astype(np.complex128)) ** 2))
+    psi0 = psi0.astype(np.complex64)
+    spec = q.InstanceSpec(shape=(n, n), nsteps=200, dt=1e-2, init=q.QHD_INIT_USER)
+    f = qhd_inputs.landscape_grid(8, (n, n))
+    res, psis, _, st = run_gpu([spec], [f], states={0: psi0})
+    _check([spec], [f], res, psis, "user", states={0: psi0})
+
+
+def test_translation_equivariance_on_device():
+    note("case: translation")
+    n = 128
+    f = qhd_inputs.landscape_grid(31, (n, n))
+    spec = q.InstanceSpec(shape=(n, n), nsteps=300, dt=1e-2)
+    _, p1, _, _ = run_gpu([spec], [f])
+    _, p2, _, _ = run_gpu([spec], [np.roll(f, (16, -40), axis=(0, 1))])
+    err = float(np.max(np.abs(np.roll(p1[0], (16, -40), axis=(0, 1)) - p2[0])))
+    note(f"  translation max diff {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_error_paths():
+    note("case: error paths")
+    spec = q.InstanceSpec(shape=(16, 16), nsteps=10, dt=1e-2)
+    plan = q.Plan([spec])
+    with pytest.raises(q.QHDError) as ei:
+        plan.evolve()
+    assert ei.value.status == q.QHD_ESTATE
+    f = np.ones((16, 16))
+    f[3, 4] = np.nan
+    with pytest.raises(q.QHDError) as ei:
+        plan.set_potential(0, f)
+    assert ei.value.status == q.QHD_EINVAL
+    plan.set_potential(0, np.ones((16, 16)))
+    with pytest.raises(q.QHDError) as ei:
+        plan.set_steps_done(0, 11)
+    assert ei.value.status == q.QHD_EINVAL
+    # a state of norm 4 is reported as a numeric failure by observe
+    plan.set_state(0, np.full((16, 16), 2.0 / 16, dtype=np.complex64))
+    plan.evolve()
+    res, _, _, st = plan.observe()
+    assert st == q.QHD_ENUMERIC and abs(res[0]["norm"] - 4.0) < 1e-4
+    plan.close()
+
+
+def test_fault_injection_hook(monkeypatch):
+    spec = q.InstanceSpec(shape=(16, 16), nsteps=10, dt=1e-2)
+    plan = q.Plan([spec])
+    plan.set_potential(0, np.ones((16, 16)))
+    monkeypatch.setenv("QHD_FAULT_INJECT", "evolve")
+    with pytest.raises(q.QHDError) as ei:
+        plan.evolve()
+    assert ei.value.status == q.QHD_EDEVICE
+    monkeypatch.delenv("QHD_FAULT_INJECT")
+    plan.evolve()
+    res, _, _, st = plan.observe()
+    assert st == q.QHD_OK and res[0]["steps_done"] == 10
+    plan.close()
