@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""Throughput of the batched QHD split-operator evolution on one MI355X.
+
+One bench "step" is one pass of the whole hot path over the batch: reset to
+psi0 (uniform), evolve every instance to its own end time, readouts.  The
+inputs (potentials) are resident in HBM before timing starts.
+
+Workload (default): 768 independent 2-D instances on [0,1]^2 with sizes drawn
+uniformly from {128^2, 256^2, 512^2}, T ~ U[5, 20], dt = 1e-3 (n = round(T/dt)
+steps each), seeded synthetic landscapes with 8..24 cosine terms, the schedule
+a = 2/(1e-3 + t^3), b = 2 t^3 (App. C.2.1).  value = grid-point-steps per
+second of the whole job.
+
+Also reported on the same JSON line:
+  roofline      dominant kernel: algorithmic bytes per launch / mean HIP-event
+                duration of its sampled launches in the timed region, vs 8 TB/s;
+                traffic from the committed rocprofv3 counter summary when it
+                matches the current kernel sources, else null.
+  cpu_baseline  the FP64 oracle on the host cores on a bounded sample.
+  plain         the same instances solved one at a time (single-instance
+                solver), per size, and the 256^2 x 10k-step single instance.
+  parity        the GPU state against the oracle on a sample instance.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point-steps/s (batched vs plain, 1 GPU) at max|Δψ|≤1e-4 vs FP64 oracle"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in ("paper_2303_01471_amd/csrc/qhd_kernels.hip", "paper_2303_01471_amd/csrc/line_fft.h",
+                "paper_2303_01471_amd/csrc/qhd_internal.h"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def build_plan(specs, q, flags=0, timing_stride=0):
+    cspecs = [q.InstanceSpec(shape=s.shape, nsteps=s.nsteps, dt=s.dt) for s in specs]
+    return q.Plan(cspecs, flags=flags, timing_stride=timing_stride)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--count", type=int, default=768, help="instances in the batch")
+    ap.add_argument("--cap-steps", type=int, default=0,
+                    help="cap every instance's step count (profiling runs only; changes the workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--timing-stride", type=int, default=16)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this engine targets one GPU; instances are independent and a multi-GPU run "
+              "would only split the batch (see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import qhd_inputs
+    from paper_2303_01471_amd import qhd as q
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    q.load_library()
+
+    specs = qhd_inputs.batched_2d(count=args.count)
+    if args.cap_steps > 0:
+        for s in specs:
+            s.nsteps = min(s.nsteps, args.cap_steps)
+    total_gp = float(sum(s.points * s.nsteps for s in specs))
+    log(f"{len(specs)} instances, {sum(s.points for s in specs)/1e6:.1f} M points, "
+        f"{total_gp:.3e} grid-point-steps per bench step")
+
+    plan = build_plan(specs, q, flags=q.QHD_OPT_TIME_PASSES, timing_stride=args.timing_stride)
+    t0 = time.time()
+    grids = {}
+    for i, s in enumerate(specs):
+        f = s.grid()
+        plan.set_potential(i, f)
+        if i < 8 or s.shape[0] not in grids:
+            grids.setdefault(s.shape[0], (i, f))
+        if (i + 1) % 128 == 0:
+            log(f"  potentials uploaded: {i + 1}/{len(specs)} ({time.time() - t0:.1f}s)")
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        plan.reset(stream)
+        plan.evolve(-1, stream)
+        res, _, _, st = plan.observe(stream)
+        return res, st
+
+    for w in range(args.warmup):
+        t = time.time()
+        one_step()
+        torch.cuda.synchronize()
+        log(f"warmup {w + 1}/{args.warmup}: {time.time() - t:.2f}s")
+    plan.kernel_timings()  # drop warmup samples
+
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    last = None
+    for k in range(args.steps):
+        last = one_step()
+        log(f"timed step {k + 1}/{args.steps} issued")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    res, st = last
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = total_gp * args.steps / elapsed
+    norm_drift = max(abs(r["norm"] - 1.0) for r in res)
+    log(f"timed: {elapsed:.2f}s for {args.steps} steps -> {value / 1e9:.2f} G gp-steps/s, "
+        f"max |norm-1| = {norm_drift:.2e}, status {st}")
+
+    kt = [t for t in plan.kernel_timings() if t["launches"] > 0]
+    kernels = []
+    for t in kt:
+        gbs = t["points"] * t["bytes_per_point"] / (t["total_ms"] * 1e-3) / 1e9
+        kernels.append(dict(name=t["name"], sampled_launches=t["launches"],
+                            mean_us=round(t["total_ms"] * 1e3 / t["launches"], 2),
+                            achieved_GBps=round(gbs, 1), bytes_per_point=t["bytes_per_point"]))
+    dom = max(kt, key=lambda t: t["total_ms"]) if kt else None
+    roofline = None
+    if dom is not None:
+        achieved = dom["points"] * dom["bytes_per_point"] / (dom["total_ms"] * 1e-3) / 1e9
+        traffic = None
+        src_hash = kernel_source_hash()
+        if os.path.exists(TRAFFIC_FILE):
+            try:
+                tj = json.load(open(TRAFFIC_FILE))
+                ent = tj.get("kernels", {}).get(dom["name"])
+                if tj.get("source_hash") == src_hash and ent:
+                    traffic = ent.get("hbm_bytes_per_point")
+            except Exception:
+                traffic = None
+        roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic, "algorithmic_bytes_per_point": dom["bytes_per_point"],
+                    "mean_launch_us": round(dom["total_ms"] * 1e3 / dom["launches"], 2)}
+    plan.close()
+
+    # ---- plain: the single-instance solver on the same GPU ---------------------------
+    plain = None
+    if not args.no_plain:
+        rates = {}
+        for n, (i, f) in sorted(grids.items()):
+            sp = specs[i]
+            steps = 2000 if n <= 256 else 1000
+            p1 = build_plan([type(sp)(sp.seed, sp.shape, steps + 200, sp.dt, sp.n_terms, sp.kmax)], q)
+            p1.set_potential(0, f)
+            p1.evolve(200, stream)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            p1.evolve(-1, stream)
+            torch.cuda.synchronize()
+            rates[n] = sp.points * steps / (time.perf_counter() - t)
+            p1.close()
+            log(f"plain {n}x{n}: {rates[n] / 1e9:.2f} G gp-steps/s")
+        plain_time = sum(s.points * s.nsteps / rates[s.shape[0]] for s in specs)
+        plain_equiv = total_gp / plain_time
+        # the single-instance 256^2 x 10k-step configuration
+        c1 = qhd_inputs.single_2d(256)
+        p1 = build_plan([c1], q)
+        p1.set_potential(0, c1.grid())
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        p1.evolve(-1, stream)
+        r1, _, _, _ = p1.observe(stream)
+        torch.cuda.synchronize()
+        c1_rate = c1.points * c1.nsteps / (time.perf_counter() - t)
+        p1.close()
+        plain = {"per_size_gp_steps_per_s": {str(k): round(v, 1) for k, v in rates.items()},
+                 "batch_one_at_a_time_gp_steps_per_s": round(plain_equiv, 1),
+                 "batched_vs_plain": round(value / plain_equiv, 3),
+                 "single_256x256_10k_steps_gp_steps_per_s": round(c1_rate, 1),
+                 "single_256x256_norm_drift": abs(r1[0]["norm"] - 1.0),
+                 "method": "per-size rates of the single-instance solver (one plan per instance, "
+                           "2000/1000 steps after 200 warm steps), applied to the batch's own sizes "
+                           "and step counts"}
+        log(f"plain equivalent {plain_equiv / 1e9:.2f} G gp-steps/s; batched/plain "
+            f"{value / plain_equiv:.2f}x; single 256^2 10k: {c1_rate / 1e9:.2f} G gp-steps/s")
+
+    # ---- CPU baseline (FP64 oracle) and parity on a sample ----------------------------
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n0 = 128 if 128 in grids else min(grids)
+        i0, f0 = grids[n0]
+        sp = specs[i0]
+        sample_steps = 1500
+        prob = oracle.Problem(shape=sp.shape, dt=sp.dt)
+        psi = oracle.uniform_state(sp.shape)
+        t = time.perf_counter()
+        psi = oracle.evolve(prob, f0, psi, 0, sample_steps)
+        tcpu = time.perf_counter() - t
+        cpu_rate = sp.points * sample_steps / tcpu
+        cpu = {"value": round(cpu_rate, 1), "unit": "grid-point-steps/s", "cores": oracle.max_threads(),
+               "kind": "oracle",
+               "sample": f"instance {i0} of the batch ({n0}x{n0}), first {sample_steps} of its "
+                         f"{sp.nsteps} steps, FP64, {tcpu:.1f}s"}
+        log(f"cpu oracle: {cpu_rate / 1e6:.2f} M gp-steps/s on {cpu['cores']} threads ({tcpu:.1f}s)")
+        p1 = build_plan([type(sp)(sp.seed, sp.shape, sample_steps, sp.dt, sp.n_terms, sp.kmax)], q)
+        p1.set_potential(0, f0)
+        p1.evolve(-1, stream)
+        r1, psig, _, _ = p1.observe(stream, want_psi=True)
+        torch.cuda.synchronize()
+        got = psig.cpu().numpy().reshape(sp.shape).astype(np.complex128)
+        p1.close()
+        parity = {"sample": f"instance {i0} ({n0}x{n0}), {sample_steps} steps",
+                  "max_abs_dpsi": float(np.max(np.abs(got - psi))),
+                  "norm_drift": abs(r1[0]["norm"] - 1.0), "tolerance": 1e-4}
+        log(f"parity sample: max|dpsi| = {parity['max_abs_dpsi']:.3e}")
+
+    sizes = sorted({s.shape[0] for s in specs})
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"batched-{len(specs)}: 2-D instances, n in {sizes}^2 (uniform), "
+                               f"T~U[5,20], dt=1e-3, Nesterov schedule, 8-24 cosine-term landscapes"
+                               + (f", steps capped at {args.cap_steps}" if args.cap_steps else ""),
+                   "instances": len(specs), "grid_point_steps": total_gp,
+                   "max_norm_drift": norm_drift},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain": plain,
+        "parity": parity,
+        "kernels": kernels,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -136,6 +136,11 @@ qhd_status qhd_set_steps_done(qhd_plan plan, int32_t i, int64_t j);
  * how the steps are split into calls. */
 qhd_status qhd_evolve(qhd_plan plan, int64_t max_steps, void *stream);
 
+/* Return every instance to step 0: UNIFORM instances get psi0 = N^{-1/2} again,
+ * USER instances need a new qhd_set_state before the next evolve.  Potentials
+ * are kept.  Asynchronous on `stream`; allocates nothing. */
+qhd_status qhd_reset(qhd_plan plan, void *stream);
+
 /* Readouts for every instance.  Closes any pending half step on a copy (the
  * plan state is untouched, evolution can continue).  host_out: `batch` entries.
  * rho_dev / psi_dev: optional caller-owned device buffers receiving |psi|^2

@@ -558,6 +558,27 @@ qhd_status qhd_evolve(qhd_plan p, int64_t max_steps, void* stream_v) {
   return QHD_OK;
 }
 
+qhd_status qhd_reset(qhd_plan p, void* stream_v) {
+  g_err.clear();
+  if (!p) return fail(QHD_EINVAL, "plan is NULL");
+  hipStream_t stream = (hipStream_t)stream_v;
+  HIP_TRY(hipSetDevice(p->device));
+  for (auto& c : p->classes) {
+    const int m = (int)c.members.size();
+    HIP_TRY(launch_fill_psi(c.psi, (long long)m * c.points, (float)(1.0 / std::sqrt((double)c.points)), stream));
+    HIP_TRY(launch_reset_inst(c.dev, m, stream));
+    for (int k = 0; k < m; ++k) {
+      c.host[k].steps_done = 0;
+      c.host[k].mode = kModeClean;
+      const int i = c.host[k].plan_index;
+      p->state_ready[i] = p->inst[i].init_kind == QHD_INIT_UNIFORM;
+    }
+  }
+  p->last_stream = stream;
+  p->last_stream_valid = true;
+  return QHD_OK;
+}
+
 qhd_status qhd_observe(qhd_plan p, void* stream_v, qhd_observables* out, float* rho_dev,
                        float* psi_dev) {
   g_err.clear();

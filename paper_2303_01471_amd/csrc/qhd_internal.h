@@ -68,6 +68,8 @@ hipError_t launch_import_f(int ndim, int nx, int ny, const double* user, double*
 hipError_t launch_import_psi(int ndim, int nx, int ny, const float2* user, float2* dst,
                              hipStream_t stream);
 hipError_t launch_fill_psi(float2* dst, long long count, float value, hipStream_t stream);
+// steps_done = 0, mode = clean for every instance of a class
+hipError_t launch_reset_inst(InstDev* inst, int ninst, hipStream_t stream);
 // Lowest-index minimiser of f (user row-major layout): out_val, out_idx.
 hipError_t launch_argmin(const double* f, long long count, double* out_val, long long* out_idx,
                          hipStream_t stream);

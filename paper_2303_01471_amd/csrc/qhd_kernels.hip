@@ -292,6 +292,13 @@ __global__ void __launch_bounds__(256) k_line_pass_1d(const InstDev* __restrict_
   }
 }
 
+__global__ void k_reset_inst(InstDev* __restrict__ inst, int ninst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  inst[i].steps_done = 0;
+  inst[i].mode = kModeClean;
+}
+
 __global__ void k_commit(InstDev* __restrict__ inst, int ninst, long long max_steps) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ninst) return;
@@ -618,6 +625,11 @@ hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* ps
 hipError_t launch_commit(InstDev* inst, int ninst, long long max_steps, hipStream_t stream) {
   hipLaunchKernelGGL(k_commit, dim3((ninst + 255) / 256), dim3(256), 0, stream, inst, ninst,
                      max_steps);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_inst(InstDev* inst, int ninst, hipStream_t stream) {
+  hipLaunchKernelGGL(k_reset_inst, dim3((ninst + 255) / 256), dim3(256), 0, stream, inst, ninst);
   return hipGetLastError();
 }
 

@@ -94,6 +94,7 @@ _SIGNATURES = {
     "qhd_evolve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "qhd_observe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(qhd_observables),
                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "qhd_reset": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "qhd_plan_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "qhd_kernel_timings": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(qhd_kernel_timing),
                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -159,6 +160,10 @@ def qhd_set_steps_done(plan: int, i: int, j: int):
 
 def qhd_evolve(plan: int, max_steps: int, stream: int):
     _check(load_library().qhd_evolve(plan, max_steps, stream))
+
+
+def qhd_reset(plan: int, stream: int):
+    _check(load_library().qhd_reset(plan, stream))
 
 
 def qhd_observe(plan: int, stream: int, out, rho_ptr: int, psi_ptr: int) -> int:
@@ -285,6 +290,9 @@ class Plan:
     # evolution ---------------------------------------------------------------------
     def evolve(self, max_steps: int = -1, stream=None):
         qhd_evolve(self.handle, int(max_steps), _stream_handle(stream))
+
+    def reset(self, stream=None):
+        qhd_reset(self.handle, _stream_handle(stream))
 
     def observe(self, stream=None, want_psi: bool = False, want_rho: bool = False):
         """Returns (list of dicts, psi tensor or None, rho tensor or None, status)."""
