@@ -3,7 +3,7 @@
 // The kinetic factor of the product formula is diagonal in the Fourier basis
 // (App. C.2.1, eq. prod_qhd_fft; App. E.1): every pass transforms whole mesh
 // lines, multiplies by a diagonal phase and transforms back.  This header holds
-// the per-line transform used by every pass kernel.
+// the per-line transform used by every pass kernel and the phase helpers.
 //
 // Design (CDNA4):
 //   * A line of N points is owned by TPL = N / P lanes of ONE wavefront; lane t
@@ -11,17 +11,18 @@
 //     of a full transform are in that same layout, so a pass loads a line
 //     straight from HBM, transforms, applies its phase and transforms back
 //     without any reordering.
-//   * Stockham auto-sort stages of radix R = min(P, N/Ns); the butterflies and
-//     all twiddle products run in FP64 registers (FP64 FMA issues at the same
-//     rate as unpacked FP32 on this chip), so each twiddle product is rounded
-//     once, in FP64.  Rounding FP32-stored twiddles instead biases |w| and drains
-//     the norm by ~5e-8 per transform, which 10^4 steps cannot afford.
-//   * Between stages the line is exchanged through LDS as FP32 complex (one
-//     unbiased rounding of the data per stage), with one pad slot every 8
-//     entries so that the radix-8 scatter is bank-conflict free.  A line never
-//     spans two wavefronts, so the exchange needs no workgroup barrier.
-//   * Twiddles are W_N^j = exp(-2 pi i j / N) from an FP64 table computed on the
-//     host; each lane keeps the few it needs in registers for its whole life.
+//   * Stockham auto-sort stages of radix R = min(P, N/Ns).  Data and butterfly
+//     additions are FP32.  Every product by an irrational constant is formed so
+//     that the constant carries more than FP32 precision: inter-stage twiddles
+//     are FP64 (the FP32 value is widened, multiplied in FP64 and rounded once),
+//     and the radix-8/16 internal constants are FP32 hi+lo pairs.  A twiddle
+//     rounded to FP32 has |w| != 1 by a fixed amount; used on every transform it
+//     drains the norm by ~5e-8 per transform, which 10^4 steps cannot afford.
+//   * Between stages the line is exchanged through LDS in FP32 with one pad slot
+//     every 8 entries (the radix-8 scatter then hits distinct banks).  A line
+//     never spans two wavefronts, so the exchange needs no workgroup barrier.
+//   * Twiddles W_N^j = exp(-2 pi i j / N) come from an FP64 table computed on
+//     the host; each lane keeps the few it needs in registers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,48 +30,67 @@
 namespace qhd {
 
 // ---------------------------------------------------------------------------------
-// complex FP64 helpers
+// complex FP32 helpers
 
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 w) {
-  return make_double2(fma(a.x, w.x, -a.y * w.y), fma(a.x, w.y, a.y * w.x));
+__device__ __forceinline__ float2 fadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 fsub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// z * w with z in FP32 and w in FP64: one rounding per component
+__device__ __forceinline__ float2 cmul_fd(float2 z, double2 w) {
+  const double zr = (double)z.x, zi = (double)z.y;
+  return make_float2((float)fma(zr, w.x, -zi * w.y), (float)fma(zr, w.y, zi * w.x));
 }
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
-__device__ __forceinline__ float2 to_f2(double2 v) { return make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ float2 cmul_fd_conj(float2 z, double2 w) {
+  const double zr = (double)z.x, zi = (double)z.y;
+  return make_float2((float)fma(zr, w.x, zi * w.y), (float)fma(zi, w.x, -zr * w.y));
+}
 
-// multiply by S*i (S = -1: -i z, S = +1: +i z)
+// z * w, both FP32 (used for unit phase factors; random, unbiased rounding)
+__device__ __forceinline__ float2 cmul_ff(float2 z, float2 w) {
+  return make_float2(fmaf(z.x, w.x, -z.y * w.y), fmaf(z.x, w.y, z.y * w.x));
+}
+
+// multiply by S*i (S = -1: -i z, S = +1: +i z), exact
 template <int S>
-__device__ __forceinline__ double2 mul_si(double2 z) {
-  if constexpr (S < 0) return make_double2(z.y, -z.x);
-  else return make_double2(-z.y, z.x);
+__device__ __forceinline__ float2 mul_si(float2 z) {
+  if constexpr (S < 0) return make_float2(z.y, -z.x);
+  else return make_float2(-z.y, z.x);
 }
 
-// e^{S 2 pi i k / 16} for k = 0..7 (cos, sin of multiples of pi/8)
-__device__ __forceinline__ constexpr double c16(int k) {
+// cos, sin of k pi / 8 as FP64, and their FP32 hi+lo splits
+__host__ __device__ constexpr double c16d(int k) {
   return k == 0 ? 1.0 : k == 1 ? 0.92387953251128675613 : k == 2 ? 0.70710678118654752440
        : k == 3 ? 0.38268343236508977173 : k == 4 ? 0.0 : k == 5 ? -0.38268343236508977173
        : k == 6 ? -0.70710678118654752440 : -0.92387953251128675613;
 }
-__device__ __forceinline__ constexpr double s16(int k) {
+__host__ __device__ constexpr double s16d(int k) {
   return k == 0 ? 0.0 : k == 1 ? 0.38268343236508977173 : k == 2 ? 0.70710678118654752440
        : k == 3 ? 0.92387953251128675613 : k == 4 ? 1.0 : k == 5 ? 0.92387953251128675613
        : k == 6 ? 0.70710678118654752440 : 0.38268343236508977173;
 }
+__host__ __device__ constexpr float hi32(double v) { return (float)v; }
+__host__ __device__ constexpr float lo32(double v) { return (float)(v - (double)(float)v); }
 
-// z * e^{S 2 pi i k / 16}, exact for multiples of pi/2
+// z * e^{S 2 pi i K / 16}: exact for multiples of pi/2; otherwise an FP32 product
+// with a hi+lo constant (the small cross terms first, the large ones last)
 template <int S, int K>
-__device__ __forceinline__ double2 rot16(double2 z) {
-  if constexpr (K == 0) return z;
-  else if constexpr (K == 4) return mul_si<S>(z);
-  else if constexpr (K == 2 || K == 6) {
-    // c * (z.x - S z.y, S z.x + z.y) for K=2 ; c * (-z.x - S z.y, S z.x - z.y) for K=6
-    constexpr double c = 0.70710678118654752440;
-    if constexpr (K == 2) return make_double2(c * (z.x - S * z.y), c * (S * z.x + z.y));
-    else return make_double2(c * (-z.x - S * z.y), c * (S * z.x - z.y));
+__device__ __forceinline__ float2 rot16(float2 z) {
+  if constexpr (K == 0) {
+    return z;
+  } else if constexpr (K == 4) {
+    return mul_si<S>(z);
+  } else if constexpr (K == 2 || K == 6) {
+    // (1/sqrt2) (z.x - S z.y, S z.x + z.y) for K=2 ; (1/sqrt2)(-z.x - S z.y, S z.x - z.y) for K=6
+    constexpr float ch = hi32(0.70710678118654752440), cl = lo32(0.70710678118654752440);
+    const float u = (K == 2) ? (S < 0 ? z.x + z.y : z.x - z.y) : (S < 0 ? z.y - z.x : -z.x - z.y);
+    const float v = (K == 2) ? (S < 0 ? z.y - z.x : z.x + z.y) : (S < 0 ? -z.x - z.y : z.x - z.y);
+    return make_float2(fmaf(u, ch, u * cl), fmaf(v, ch, v * cl));
   } else {
-    return cmul(z, make_double2(c16(K), S * s16(K)));
+    constexpr float crh = hi32(c16d(K)), crl = lo32(c16d(K));
+    constexpr float cih = hi32(S * s16d(K)), cil = lo32(S * s16d(K));
+    const float re = fmaf(z.x, crh, fmaf(-z.y, cih, fmaf(z.x, crl, -z.y * cil)));
+    const float im = fmaf(z.x, cih, fmaf(z.y, crh, fmaf(z.x, cil, z.y * crl)));
+    return make_float2(re, im);
   }
 }
 
@@ -78,26 +98,26 @@ __device__ __forceinline__ double2 rot16(double2 z) {
 // small DFTs on registers: X_k = sum_m x_m e^{S 2 pi i m k / R}, in place, natural order
 
 template <int S>
-__device__ __forceinline__ void dft2(double2 (&u)[2]) {
-  const double2 a = u[0], b = u[1];
-  u[0] = cadd(a, b);
-  u[1] = csub(a, b);
+__device__ __forceinline__ void dft2(float2 (&u)[2]) {
+  const float2 a = u[0], b = u[1];
+  u[0] = fadd(a, b);
+  u[1] = fsub(a, b);
 }
 
 template <int S>
-__device__ __forceinline__ void dft4(double2 (&u)[4]) {
-  const double2 s02 = cadd(u[0], u[2]), d02 = csub(u[0], u[2]);
-  const double2 s13 = cadd(u[1], u[3]), d13 = mul_si<S>(csub(u[1], u[3]));
-  u[0] = cadd(s02, s13);
-  u[2] = csub(s02, s13);
-  u[1] = cadd(d02, d13);
-  u[3] = csub(d02, d13);
+__device__ __forceinline__ void dft4(float2 (&u)[4]) {
+  const float2 s02 = fadd(u[0], u[2]), d02 = fsub(u[0], u[2]);
+  const float2 s13 = fadd(u[1], u[3]), d13 = mul_si<S>(fsub(u[1], u[3]));
+  u[0] = fadd(s02, s13);
+  u[2] = fsub(s02, s13);
+  u[1] = fadd(d02, d13);
+  u[3] = fsub(d02, d13);
 }
 
 template <int S>
-__device__ __forceinline__ void dft8(double2 (&u)[8]) {
-  double2 e[4] = {u[0], u[2], u[4], u[6]};
-  double2 o[4] = {u[1], u[3], u[5], u[7]};
+__device__ __forceinline__ void dft8(float2 (&u)[8]) {
+  float2 e[4] = {u[0], u[2], u[4], u[6]};
+  float2 o[4] = {u[1], u[3], u[5], u[7]};
   dft4<S>(e);
   dft4<S>(o);
   o[1] = rot16<S, 2>(o[1]);
@@ -105,14 +125,14 @@ __device__ __forceinline__ void dft8(double2 (&u)[8]) {
   o[3] = rot16<S, 6>(o[3]);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    u[k] = cadd(e[k], o[k]);
-    u[k + 4] = csub(e[k], o[k]);
+    u[k] = fadd(e[k], o[k]);
+    u[k + 4] = fsub(e[k], o[k]);
   }
 }
 
 template <int S>
-__device__ __forceinline__ void dft16(double2 (&u)[16]) {
-  double2 e[8], o[8];
+__device__ __forceinline__ void dft16(float2 (&u)[16]) {
+  float2 e[8], o[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     e[k] = u[2 * k];
@@ -129,13 +149,13 @@ __device__ __forceinline__ void dft16(double2 (&u)[16]) {
   o[7] = rot16<S, 7>(o[7]);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    u[k] = cadd(e[k], o[k]);
-    u[k + 8] = csub(e[k], o[k]);
+    u[k] = fadd(e[k], o[k]);
+    u[k + 8] = fsub(e[k], o[k]);
   }
 }
 
 template <int R, int S>
-__device__ __forceinline__ void dft(double2 (&u)[R]) {
+__device__ __forceinline__ void dft(float2 (&u)[R]) {
   if constexpr (R == 2) dft2<S>(u);
   else if constexpr (R == 4) dft4<S>(u);
   else if constexpr (R == 8) dft8<S>(u);
@@ -164,7 +184,7 @@ struct StagePlan {
 };
 
 // LDS slot of line position i: one pad entry after every 8
-__device__ __forceinline__ constexpr int lds_slot(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int lds_slot(int i) { return i + (i >> 3); }
 template <int N>
 struct LineLds {
   static constexpr int kSlots = N + N / 8;
@@ -179,7 +199,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // ---------------------------------------------------------------------------------
 // per-lane twiddle cache: for each stage s >= 1 and butterfly m of the lane,
-// w^r = W_{Ns R}^{(v mod Ns) r}, r = 1..R-1, stored for the forward sign.
+// w^r = W_{Ns R}^{(v mod Ns) r}, r = 1..R-1, stored (FP64) for the forward sign.
 
 template <int N, int P>
 struct Twiddles {
@@ -209,7 +229,7 @@ struct Twiddles {
 // One Stockham stage on the lane's registers.  If LAST, results stay in the
 // lane's own layout; otherwise they are scattered to LDS for the next stage.
 template <int N, int P, int S, int STAGE>
-__device__ __forceinline__ void fft_stage(double2 (&reg)[P], int t, const Twiddles<N, P>& tw,
+__device__ __forceinline__ void fft_stage(float2 (&reg)[P], int t, const Twiddles<N, P>& tw,
                                           float2* __restrict__ lds) {
   using SP = StagePlan<N, P>;
   constexpr int NS = SP::ns(STAGE);
@@ -219,14 +239,14 @@ __device__ __forceinline__ void fft_stage(double2 (&reg)[P], int t, const Twiddl
   constexpr bool LAST = (STAGE == SP::count() - 1);
 #pragma unroll
   for (int m = 0; m < NB; ++m) {
-    double2 u[R];
+    float2 u[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = reg[m + r * NB];
     if constexpr (STAGE > 0) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         const double2 w = tw.w[STAGE - 1][m * (R - 1) + (r - 1)];
-        u[r] = cmul(u[r], S < 0 ? w : cconj(w));
+        u[r] = S < 0 ? cmul_fd(u[r], w) : cmul_fd_conj(u[r], w);
       }
     }
     dft<R, S>(u);
@@ -237,19 +257,19 @@ __device__ __forceinline__ void fft_stage(double2 (&reg)[P], int t, const Twiddl
       const int v = t + m * TPL;
       const int base = (v / NS) * NS * R + (v % NS);
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[lds_slot(base + r * NS)] = to_f2(u[r]);
+      for (int r = 0; r < R; ++r) lds[lds_slot(base + r * NS)] = u[r];
     }
   }
   if constexpr (!LAST) {
     wave_lds_sync();
 #pragma unroll
-    for (int q = 0; q < P; ++q) reg[q] = to_d2(lds[lds_slot(t + q * TPL)]);
+    for (int q = 0; q < P; ++q) reg[q] = lds[lds_slot(t + q * TPL)];
     wave_lds_sync();
   }
 }
 
 template <int N, int P, int S, int STAGE = 0>
-__device__ __forceinline__ void line_fft_from(double2 (&reg)[P], int t, const Twiddles<N, P>& tw,
+__device__ __forceinline__ void line_fft_from(float2 (&reg)[P], int t, const Twiddles<N, P>& tw,
                                               float2* __restrict__ lds) {
   if constexpr (STAGE < StagePlan<N, P>::count()) {
     fft_stage<N, P, S, STAGE>(reg, t, tw, lds);
@@ -259,9 +279,61 @@ __device__ __forceinline__ void line_fft_from(double2 (&reg)[P], int t, const Tw
 
 // Full unnormalised transform of one line, X_k = sum_m x_m e^{S 2 pi i m k / N}.
 template <int N, int P, int S>
-__device__ __forceinline__ void line_fft(double2 (&reg)[P], int t, const Twiddles<N, P>& tw,
+__device__ __forceinline__ void line_fft(float2 (&reg)[P], int t, const Twiddles<N, P>& tw,
                                          float2* __restrict__ lds) {
   line_fft_from<N, P, S, 0>(reg, t, tw, lds);
+}
+
+// ---------------------------------------------------------------------------------
+// unit phase factors
+
+// sin(2 pi r), cos(2 pi r) for |r| <= 1/2 (turns).
+//   kHwSinCos: the CDNA transcendental unit (v_sin_f32 / v_cos_f32 take turns;
+//   measured max error 1.2e-7 on [-1/2, 1/2]).
+//   otherwise: exact reduction to the octant |y| <= 1/8 (r - q/4 is exact by
+//   Sterbenz), then polynomials in y fitted (weighted least squares, Chebyshev
+//   nodes) to sin(2 pi y) and cos(2 pi y); max error ~1.5 ulp of 1.
+#ifndef QHD_HW_SINCOS
+#define QHD_HW_SINCOS 1
+#endif
+__device__ __forceinline__ void sincos_turns(float r, float& s, float& c) {
+#if QHD_HW_SINCOS
+  s = __builtin_amdgcn_sinf(r);
+  c = __builtin_amdgcn_cosf(r);
+#else
+  const float q = rintf(4.0f * r);
+  const float y = fmaf(-0.25f, q, r);
+  const float y2 = y * y;
+  float ps = fmaf(y2, -75.240064049398f, 81.58812463672584f);
+  ps = fmaf(ps, y2, -41.34162804267381f);
+  ps = fmaf(ps, y2, 6.283185220341756f);
+  const float sn = ps * y;
+  float pc = fmaf(y2, 59.220407261791806f, -85.44285212009325f);
+  pc = fmaf(pc, y2, 64.93931620843469f);
+  pc = fmaf(pc, y2, -19.73920865035785f);
+  const float cn = fmaf(pc, y2, 0.9999999999526002f);
+  const int qi = (int)q;
+  const bool swap = qi & 1;
+  float so = swap ? cn : sn, co = swap ? sn : cn;
+  so = (qi & 2) ? -so : so;
+  co = ((qi + 1) & 2) ? -co : co;
+  s = so;
+  c = co;
+#endif
+}
+
+// exp(-2 pi i tau), tau in turns (FP64), with one Newton magnitude step
+// w <- w (3 - |w|^2) / 2 taken in FP64, so |w| = 1 to ~1e-14.  (In FP32 the
+// step is one-sided: 1 + 2^-25 is not representable, so magnitudes just below
+// 1 would never be corrected and the norm would shrink step after step.)
+__device__ __forceinline__ double2 phase_turns_d(double tau) {
+  const float r = (float)(tau - rint(tau));
+  float s, c;
+  sincos_turns(r, s, c);
+  const double cd = (double)c, sd = (double)s;
+  const double m = fma(cd, cd, sd * sd);
+  const double g = fma(-0.5, m, 1.5);
+  return make_double2(cd * g, -sd * g);
 }
 
 }  // namespace qhd

@@ -129,7 +129,7 @@ struct qhd_plan_s {
   long long* amin_idx = nullptr;
   double* host_results = nullptr;   // pinned, 3 per member of the largest class
   long long total_points = 0;
-  int grid_cap = 4096;
+  int grid_cap = 2048;
   // timing
   std::vector<Family> families;
   std::vector<Pending> pending;

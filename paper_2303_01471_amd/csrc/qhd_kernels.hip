@@ -26,10 +26,12 @@
 // matters because the potential phase accumulates f * integral(b dt) (up to
 // ~8e4 f at T = 20), far beyond FP32's 2^-24 relative precision.
 //
-// Phases: every phase argument is formed in FP64, reduced to [-1/2, 1/2] turns,
-// evaluated with an FP32 sincospi, and the unit factor gets one Newton
-// magnitude correction in FP64 (w <- w (3 - |w|^2) / 2) so that phase factors
-// do not bias the norm.
+// Phases: every phase argument is formed in FP64 and reduced to [-1/2, 1/2]
+// turns, then evaluated in FP32 and given one Newton magnitude correction
+// (w <- w (3 - |w|^2) / 2) so that phase factors do not bias the norm.  The
+// kinetic factor is separable, K = E_x(k_x) E_y(k_y); E_y is computed once per
+// lane, instance and step (FP64 Newton step, with the 1/(nx ny) of the inverse
+// transforms folded in exactly) and E_x once per column.
 #include <climits>
 
 #include "line_fft.h"
@@ -62,17 +64,6 @@ __device__ __forceinline__ void sched_ab(const InstDev& I, long long j, double& 
   }
 }
 
-// exp(-2 pi i tau) with tau in turns (FP64), Newton-normalised in FP64.
-__device__ __forceinline__ double2 phase_turns(double tau) {
-  const double r = tau - rint(tau);
-  float sn, cs;
-  sincospif(2.0f * (float)r, &sn, &cs);
-  const double c = (double)cs, s = (double)sn;
-  const double m = fma(c, c, s * s);
-  const double g = fma(-0.5, m, 1.5);
-  return make_double2(c * g, -s * g);
-}
-
 __device__ __forceinline__ long long step_limit(const InstDev& I, long long max_steps) {
   const long long rem = I.nsteps - I.steps_done;
   return (max_steps < 0 || max_steps > rem) ? rem : max_steps;
@@ -80,12 +71,33 @@ __device__ __forceinline__ long long step_limit(const InstDev& I, long long max_
 
 __device__ __forceinline__ int freq(int m, int n) { return m < (n >> 1) ? m : m - n; }
 
+// offset of slot q of lane t on tiled row y (x = t + q*TPL); compile-time stride
+// between slots once a slot spans whole tiles
+template <int NX, int TPL>
+__device__ __forceinline__ long long row_slot(int t, int q, int y) {
+  if constexpr (TPL % 8 == 0) {
+    return ((long long)((y >> 3) * (NX >> 3) + (t >> 3)) << 6) + ((y & 7) << 3) + (t & 7) +
+           (long long)q * (TPL * 8);
+  } else {
+    return tile_index(t + q * TPL, y, NX);
+  }
+}
+
+// contiguous share [begin, end) of `total` work items for this block, in units of `step`
+__device__ __forceinline__ void block_share(long long total, int step, long long& begin, long long& end) {
+  const long long units = (total + step - 1) / step;
+  const long long per = (units + gridDim.x - 1) / gridDim.x;
+  begin = (long long)blockIdx.x * per * step;
+  end = begin + per * step;
+  if (end > total) end = total;
+}
+
 // ------------------------------------------------------------------------------------
 // 2-D row pass: lines along x, one line per TPL lanes.
 
 template <int NX, int P>
 __global__ void __launch_bounds__(256) k_row_pass_2d(const InstDev* __restrict__ inst, int ninst,
-                                                     int ny, float2* __restrict__ psi,
+                                                     int ny_log2, float2* __restrict__ psi,
                                                      const double* __restrict__ f,
                                                      const double2* __restrict__ twtab, int s,
                                                      long long max_steps) {
@@ -97,12 +109,14 @@ __global__ void __launch_bounds__(256) k_row_pass_2d(const InstDev* __restrict__
   float2* my = lds + ll * SLOTS;
   Twiddles<NX, P> tw;
   tw.load(twtab, t);
-  const long long total = (long long)ninst * ny;
-  for (long long l0 = (long long)blockIdx.x * LPW; l0 < total; l0 += (long long)gridDim.x * LPW) {
+  const long long total = (long long)ninst << ny_log2;
+  long long begin, end;
+  block_share(total, LPW, begin, end);
+  for (long long l0 = begin; l0 < end; l0 += LPW) {
     const long long L = l0 + ll;
-    const bool valid = L < total;
-    const long long Lc = valid ? L : total - 1;
-    const int i = (int)(Lc / ny), y = (int)(Lc - (long long)i * ny);
+    const bool valid = L < end;
+    const long long Lc = valid ? L : end - 1;
+    const int i = (int)(Lc >> ny_log2), y = (int)(Lc & ((1 << ny_log2) - 1));
     const InstDev& I = inst[i];
     const bool active = valid && s < step_limit(I, max_steps);
     const long long j = I.steps_done + s;
@@ -115,20 +129,18 @@ __global__ void __launch_bounds__(256) k_row_pass_2d(const InstDev* __restrict__
       beta += 0.5 * I.dt * bp;
     }
     const double cpot = beta * kInv2Pi;
-    const long long base = I.psi_off;
-    double2 reg[P];
+    float2* __restrict__ pl = psi + I.psi_off;
+    const double* __restrict__ fl = f + I.psi_off;
+    float2 reg[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) reg[q] = to_d2(psi[base + tile_index(t + q * TPL, y, NX)]);
+    for (int q = 0; q < P; ++q) reg[q] = pl[row_slot<NX, TPL>(t, q, y)];
     if (!entry) line_fft<NX, P, +1>(reg, t, tw, my);
 #pragma unroll
-    for (int q = 0; q < P; ++q) {
-      const double fv = f[base + tile_index(t + q * TPL, y, NX)];
-      reg[q] = cmul(reg[q], phase_turns(cpot * fv));
-    }
+    for (int q = 0; q < P; ++q) reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fl[row_slot<NX, TPL>(t, q, y)]));
     line_fft<NX, P, -1>(reg, t, tw, my);
     if (active) {
 #pragma unroll
-      for (int q = 0; q < P; ++q) psi[base + tile_index(t + q * TPL, y, NX)] = to_f2(reg[q]);
+      for (int q = 0; q < P; ++q) pl[row_slot<NX, TPL>(t, q, y)] = reg[q];
     }
   }
 }
@@ -140,91 +152,113 @@ __global__ void __launch_bounds__(256) k_row_pass_2d(const InstDev* __restrict__
 template <int NY, int P>
 struct ColCfg {
   static constexpr int TPL = NY / P;
-  static constexpr int ITEMS = (8 * TPL >= 256) ? 1 : 256 / (8 * TPL);  // tile columns per block
-  static constexpr int NT = ITEMS * 8 * TPL;
+  static constexpr int NT = 256;                                          // threads per block
+  static constexpr int ITEMS = (8 * TPL >= NT) ? 1 : NT / (8 * TPL);     // tile columns per block
+  static constexpr int LINES = ITEMS * 8;                                 // columns per block
+  static constexpr int SUBS = (LINES * TPL) / NT;                         // column rounds per item
   // line stride in LDS slots, = 2 (mod 16) so the tile scatter hits distinct banks
   static constexpr int STRIDE = ((LineLds<NY>::kSlots + 13) / 16) * 16 + 2;
 };
 
 template <int NY, int P>
-__global__ void __launch_bounds__((ColCfg<NY, P>::NT)) k_col_pass_2d(
-    const InstDev* __restrict__ inst, int ninst, int nx, float2* __restrict__ psi,
+__global__ void __launch_bounds__(256) k_col_pass_2d(
+    const InstDev* __restrict__ inst, int ninst, int nx_log2, float2* __restrict__ psi,
     const double2* __restrict__ twtab, int s, long long max_steps) {
   using C = ColCfg<NY, P>;
-  constexpr int TPL = C::TPL, ITEMS = C::ITEMS, NT = C::NT, STRIDE = C::STRIDE;
+  constexpr int TPL = C::TPL, ITEMS = C::ITEMS, NT = C::NT, STRIDE = C::STRIDE, SUBS = C::SUBS;
   constexpr int TILES = NY / 8;
-  __shared__ float2 lds[ITEMS * 8 * STRIDE];
+  __shared__ float2 lds[C::LINES * STRIDE];
   const int tid = threadIdx.x;
-  const int line = tid / TPL, t = tid % TPL;  // line in [0, ITEMS*8)
-  float2* my = lds + line * STRIDE;
+  const int line0 = tid / TPL, t = tid % TPL;  // first column of this lane group
   Twiddles<NY, P> tw;
   tw.load(twtab, t);
-  const int tcols = nx >> 3;
-  const long long total = (long long)ninst * tcols;
+  const int nx = 1 << nx_log2, tc_log2 = nx_log2 - 3, tcols = nx >> 3;
+  const long long total = (long long)ninst << tc_log2;
   const double inv_n = 1.0 / ((double)nx * (double)NY);
-  for (long long g0 = (long long)blockIdx.x * ITEMS; g0 < total; g0 += (long long)gridDim.x * ITEMS) {
-    // stage the tile columns: each thread moves float4 = two complex values
-    for (int e = tid; e < ITEMS * TILES * 32; e += NT) {
-      const int it = e / (TILES * 32), rem = e - it * (TILES * 32);
-      const int ty = rem >> 5, w = rem & 31;
+  long long begin, end;
+  block_share(total, ITEMS, begin, end);
+  int cached = -1;
+  double2 ey[P];
+  for (long long g0 = begin; g0 < end; g0 += ITEMS) {
+    // stage the tile columns: each thread moves float4 = two complex values; the
+    // item decode is wave-uniform
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
       const long long g = g0 + it;
-      if (g < total) {
-        const int i = (int)(g / tcols), tc = (int)(g - (long long)i * tcols);
+      if (g < end) {
+        const int i = (int)(g >> tc_log2), tc = (int)(g & (tcols - 1));
         const InstDev& I = inst[i];
         if (s < step_limit(I, max_steps)) {
-          const float4 v = reinterpret_cast<const float4*>(
-              psi + I.psi_off + ((long long)(ty * tcols + tc) << 6))[w];
-          const int yy = w >> 2, xx = (w & 3) << 1;
-          const int y = ty * 8 + yy;
-          lds[(it * 8 + xx) * STRIDE + lds_slot(y)] = make_float2(v.x, v.y);
-          lds[(it * 8 + xx + 1) * STRIDE + lds_slot(y)] = make_float2(v.z, v.w);
+          const float4* __restrict__ src = reinterpret_cast<const float4*>(psi + I.psi_off) + tc * 32;
+          float2* __restrict__ dst = lds + it * 8 * STRIDE;
+#pragma unroll
+          for (int e = tid; e < TILES * 32; e += NT) {
+            const int ty = e >> 5, w = e & 31;
+            const float4 v = src[(long long)ty * tcols * 32 + w];
+            const int y = ty * 8 + (w >> 2), xx = (w & 3) << 1;
+            dst[xx * STRIDE + lds_slot(y)] = make_float2(v.x, v.y);
+            dst[(xx + 1) * STRIDE + lds_slot(y)] = make_float2(v.z, v.w);
+          }
         }
       }
     }
     __syncthreads();
-    {
+#pragma unroll
+    for (int sub = 0; sub < SUBS; ++sub) {
+      const int line = line0 + sub * (NT / TPL);
+      float2* my = lds + line * STRIDE;
       const long long g = g0 + line / 8;
-      const long long gc = g < total ? g : total - 1;
-      const int i = (int)(gc / tcols), tc = (int)(gc - (long long)i * tcols);
+      const long long gc = g < end ? g : end - 1;
+      const int i = (int)(gc >> tc_log2), tc = (int)(gc & (tcols - 1));
       const InstDev& I = inst[i];
       const int x = tc * 8 + (line & 7);
       double a, b;
       sched_ab(I, I.steps_done + s, a, b);
-      const int nxf = freq(x, nx);
-      const double cx = a * I.kin_turns[0] * (double)(nxf * nxf);
-      const double cy = a * I.kin_turns[1];
-      double2 reg[P];
+      if (i != cached) {
+        // E_y(k_y) / (nx ny) for this lane's slots: computed once per instance and step
+        const double cy = a * I.kin_turns[1];
 #pragma unroll
-      for (int q = 0; q < P; ++q) reg[q] = to_d2(my[lds_slot(t + q * TPL)]);
+        for (int q = 0; q < P; ++q) {
+          const int nyf = freq(t + q * TPL, NY);
+          const double2 e = phase_turns_d(cy * (double)(nyf * nyf));
+          ey[q] = make_double2(e.x * inv_n, e.y * inv_n);
+        }
+        cached = i;
+      }
+      const int nxf = freq(x, nx);
+      const double2 ex = phase_turns_d(a * I.kin_turns[0] * (double)(nxf * nxf));
+      float2 reg[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) reg[q] = my[lds_slot(t + q * TPL)];
       wave_lds_sync();
       line_fft<NY, P, -1>(reg, t, tw, my);
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        const int nyf = freq(t + q * TPL, NY);
-        double2 w = phase_turns(fma(cy, (double)(nyf * nyf), cx));
-        w.x *= inv_n;
-        w.y *= inv_n;
-        reg[q] = cmul(reg[q], w);
+        const double2 k = make_double2(fma(ex.x, ey[q].x, -ex.y * ey[q].y), fma(ex.x, ey[q].y, ex.y * ey[q].x));
+        reg[q] = cmul_ff(reg[q], make_float2((float)k.x, (float)k.y));
       }
       line_fft<NY, P, +1>(reg, t, tw, my);
 #pragma unroll
-      for (int q = 0; q < P; ++q) my[lds_slot(t + q * TPL)] = to_f2(reg[q]);
+      for (int q = 0; q < P; ++q) my[lds_slot(t + q * TPL)] = reg[q];
     }
     __syncthreads();
-    for (int e = tid; e < ITEMS * TILES * 32; e += NT) {
-      const int it = e / (TILES * 32), rem = e - it * (TILES * 32);
-      const int ty = rem >> 5, w = rem & 31;
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
       const long long g = g0 + it;
-      if (g < total) {
-        const int i = (int)(g / tcols), tc = (int)(g - (long long)i * tcols);
+      if (g < end) {
+        const int i = (int)(g >> tc_log2), tc = (int)(g & (tcols - 1));
         const InstDev& I = inst[i];
         if (s < step_limit(I, max_steps)) {
-          const int yy = w >> 2, xx = (w & 3) << 1;
-          const int y = ty * 8 + yy;
-          const float2 p0 = lds[(it * 8 + xx) * STRIDE + lds_slot(y)];
-          const float2 p1 = lds[(it * 8 + xx + 1) * STRIDE + lds_slot(y)];
-          reinterpret_cast<float4*>(psi + I.psi_off + ((long long)(ty * tcols + tc) << 6))[w] =
-              make_float4(p0.x, p0.y, p1.x, p1.y);
+          float4* __restrict__ dstg = reinterpret_cast<float4*>(psi + I.psi_off) + tc * 32;
+          const float2* __restrict__ srcl = lds + it * 8 * STRIDE;
+#pragma unroll
+          for (int e = tid; e < TILES * 32; e += NT) {
+            const int ty = e >> 5, w = e & 31;
+            const int y = ty * 8 + (w >> 2), xx = (w & 3) << 1;
+            const float2 p0 = srcl[xx * STRIDE + lds_slot(y)];
+            const float2 p1 = srcl[(xx + 1) * STRIDE + lds_slot(y)];
+            dstg[(long long)ty * tcols * 32 + w] = make_float4(p0.x, p0.y, p1.x, p1.y);
+          }
         }
       }
     }
@@ -269,25 +303,23 @@ __global__ void __launch_bounds__(256) k_line_pass_1d(const InstDev* __restrict_
     const double ck = a * I.kin_turns[0];
     const double inv_n = 1.0 / (double)N;
     const long long base = I.psi_off;
-    double2 reg[P];
+    float2 reg[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       const long long p = base + t + q * TPL;
-      reg[q] = cmul(to_d2(psi[p]), phase_turns(cpot * f[p]));
+      reg[q] = cmul_fd(psi[p], phase_turns_d(cpot * f[p]));
     }
     line_fft<N, P, -1>(reg, t, tw, my);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       const int nf = freq(t + q * TPL, N);
-      double2 w = phase_turns(ck * (double)(nf * nf));
-      w.x *= inv_n;
-      w.y *= inv_n;
-      reg[q] = cmul(reg[q], w);
+      const double2 w = phase_turns_d(ck * (double)(nf * nf));
+      reg[q] = cmul_ff(reg[q], make_float2((float)(w.x * inv_n), (float)(w.y * inv_n)));
     }
     line_fft<N, P, +1>(reg, t, tw, my);
     if (active) {
 #pragma unroll
-      for (int q = 0; q < P; ++q) psi[base + t + q * TPL] = to_f2(reg[q]);
+      for (int q = 0; q < P; ++q) psi[base + t + q * TPL] = reg[q];
     }
   }
 }
@@ -329,7 +361,7 @@ __device__ __forceinline__ bool in_ball(int dxi, int dyi, const InstDev& I) {
 
 template <int NX, int P>
 __global__ void __launch_bounds__(256) k_observe_2d(const InstDev* __restrict__ inst, int ninst,
-                                                    int ny, const float2* __restrict__ psi,
+                                                    int ny_log2, const float2* __restrict__ psi,
                                                     const double* __restrict__ f,
                                                     const double2* __restrict__ twtab,
                                                     float2* __restrict__ out_psi,
@@ -343,18 +375,18 @@ __global__ void __launch_bounds__(256) k_observe_2d(const InstDev* __restrict__ 
   float2* my = lds + ll * SLOTS;
   Twiddles<NX, P> tw;
   tw.load(twtab, t);
-  const long long total = (long long)ninst * ny;
+  const long long total = (long long)ninst << ny_log2;
   for (long long l0 = (long long)blockIdx.x * LPW; l0 < total; l0 += (long long)gridDim.x * LPW) {
     const long long L = l0 + ll;
     const bool valid = L < total;
     const long long Lc = valid ? L : total - 1;
-    const int i = (int)(Lc / ny), y = (int)(Lc - (long long)i * ny);
+    const int i = (int)(Lc >> ny_log2), y = (int)(Lc & ((1 << ny_log2) - 1));
     const InstDev& I = inst[i];
     const bool pending = (I.mode == kModePending);
     const long long base = I.psi_off;
-    double2 reg[P];
+    float2 reg[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) reg[q] = to_d2(psi[base + tile_index(t + q * TPL, y, NX)]);
+    for (int q = 0; q < P; ++q) reg[q] = psi[base + tile_index(t + q * TPL, y, NX)];
     double fv[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) fv[q] = f[base + tile_index(t + q * TPL, y, NX)];
@@ -364,14 +396,14 @@ __global__ void __launch_bounds__(256) k_observe_2d(const InstDev* __restrict__ 
       const double cpot = 0.5 * I.dt * b * kInv2Pi;
       line_fft<NX, P, +1>(reg, t, tw, my);
 #pragma unroll
-      for (int q = 0; q < P; ++q) reg[q] = cmul(reg[q], phase_turns(cpot * fv[q]));
+      for (int q = 0; q < P; ++q) reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fv[q]));
     }
     const int xs = (int)(I.argmin % NX), ys = (int)(I.argmin / NX);
     double sr = 0.0, sf = 0.0, sm = 0.0;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       const int x = t + q * TPL;
-      const float2 v = to_f2(reg[q]);
+      const float2 v = reg[q];
       const double rho = (double)v.x * v.x + (double)v.y * v.y;
       sr += rho;
       sf += fv[q] * rho;
@@ -421,9 +453,8 @@ __global__ void __launch_bounds__(256) k_observe_1d(const InstDev* __restrict__ 
       const int x = t + q * TPL;
       const long long p = I.psi_off + x;
       const double fv = f[p];
-      double2 r = to_d2(psi[p]);
-      if (I.mode == kModePending) r = cmul(r, phase_turns(cpot * fv));
-      const float2 v = to_f2(r);
+      float2 v = psi[p];
+      if (I.mode == kModePending) v = cmul_fd(v, phase_turns_d(cpot * fv));
       const double rho = (double)v.x * v.x + (double)v.y * v.y;
       sr += rho;
       sf += fv * rho;
@@ -550,6 +581,12 @@ namespace {
 template <int N>
 constexpr int pts_per_lane() { return N >= 1024 ? 16 : 8; }
 
+inline int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
 inline int blocks_for(long long items, int per_block, int cap) {
   long long b = (items + per_block - 1) / per_block;
   if (cap > 0 && b > cap) b = cap;
@@ -591,7 +628,7 @@ hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, fl
   QHD_SWITCH_N(nx, {
     constexpr int P_ = pts_per_lane<N_>();
     hipLaunchKernelGGL((k_row_pass_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
-                       ny, psi, f, tw, s, max_steps);
+                       ilog2(ny), psi, f, tw, s, max_steps);
     return hipGetLastError();
   });
 }
@@ -603,7 +640,7 @@ hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, fl
   QHD_SWITCH_N(ny, {
     constexpr int P_ = pts_per_lane<N_>();
     hipLaunchKernelGGL((k_col_pass_2d<N_, P_>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0, stream,
-                       inst, ninst, nx, psi, tw, s, max_steps);
+                       inst, ninst, ilog2(nx), psi, tw, s, max_steps);
     return hipGetLastError();
   });
 }
@@ -640,7 +677,7 @@ hipError_t launch_observe_2d(int nx, int ny, const InstDev* inst, int ninst, con
     constexpr int P_ = pts_per_lane<N_>();
     constexpr int LPW_ = 256 / (N_ / P_);
     const int blocks = blocks_for((long long)ninst * ny, LPW_, 4096);
-    hipLaunchKernelGGL((k_observe_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst, ny,
+    hipLaunchKernelGGL((k_observe_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst, ilog2(ny),
                        psi, f, tw, out_psi, out_rho, partials);
     return hipGetLastError();
   });
