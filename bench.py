@@ -67,7 +67,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--timing-stride", type=int, default=16)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--points-json", default="",
+                    help="write {kernel family: grid points per dispatch with every instance active}")
+    ap.add_argument("--print-source-hash", action="store_true")
     args = ap.parse_args()
+    if args.print_source_hash:
+        print(kernel_source_hash())
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this engine targets one GPU; instances are independent and a multi-GPU run "
@@ -84,10 +92,27 @@ def main():
     torch.cuda.set_device(0)
     q.load_library()
 
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"copy calibration: {args.copy_calibration_mib} MiB device copy done")
+
     specs = qhd_inputs.batched_2d(count=args.count)
     if args.cap_steps > 0:
         for s in specs:
             s.nsteps = min(s.nsteps, args.cap_steps)
+    if args.points_json:
+        pts = {}
+        for s in specs:
+            n = s.shape[0]
+            for fam in (f"row_pass_2d/n{n}", f"col_pass_2d/n{n}"):
+                pts[fam] = pts.get(fam, 0) + s.points
+        with open(args.points_json, "w") as fh:
+            json.dump(pts, fh)
     total_gp = float(sum(s.points * s.nsteps for s in specs))
     log(f"{len(specs)} instances, {sum(s.points for s in specs)/1e6:.1f} M points, "
         f"{total_gp:.3e} grid-point-steps per bench step")
@@ -150,7 +175,8 @@ def main():
                 tj = json.load(open(TRAFFIC_FILE))
                 ent = tj.get("kernels", {}).get(dom["name"])
                 if tj.get("source_hash") == src_hash and ent:
-                    traffic = ent.get("hbm_bytes_per_point")
+                    # HBM bytes of one mean launch, like `achieved`
+                    traffic = round(ent["hbm_bytes_per_point"] * dom["points"] / dom["launches"], 1)
             except Exception:
                 traffic = None
         roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),

@@ -228,7 +228,15 @@ struct Twiddles {
 
 // One Stockham stage on the lane's registers.  If LAST, results stay in the
 // lane's own layout; otherwise they are scattered to LDS for the next stage.
-template <int N, int P, int S, int STAGE>
+// BLOCK_SYNC: the lanes of one line span several wavefronts of the block, so the
+// exchange needs a workgroup barrier instead of a wavefront-local one.
+template <bool BLOCK_SYNC>
+__device__ __forceinline__ void line_lds_sync() {
+  if constexpr (BLOCK_SYNC) __syncthreads();
+  else wave_lds_sync();
+}
+
+template <int N, int P, int S, int STAGE, bool BLOCK_SYNC = false>
 __device__ __forceinline__ void fft_stage(float2 (&reg)[P], int t, const Twiddles<N, P>& tw,
                                           float2* __restrict__ lds) {
   using SP = StagePlan<N, P>;
@@ -261,27 +269,27 @@ __device__ __forceinline__ void fft_stage(float2 (&reg)[P], int t, const Twiddle
     }
   }
   if constexpr (!LAST) {
-    wave_lds_sync();
+    line_lds_sync<BLOCK_SYNC>();
 #pragma unroll
     for (int q = 0; q < P; ++q) reg[q] = lds[lds_slot(t + q * TPL)];
-    wave_lds_sync();
+    line_lds_sync<BLOCK_SYNC>();
   }
 }
 
-template <int N, int P, int S, int STAGE = 0>
+template <int N, int P, int S, bool BLOCK_SYNC, int STAGE = 0>
 __device__ __forceinline__ void line_fft_from(float2 (&reg)[P], int t, const Twiddles<N, P>& tw,
                                               float2* __restrict__ lds) {
   if constexpr (STAGE < StagePlan<N, P>::count()) {
-    fft_stage<N, P, S, STAGE>(reg, t, tw, lds);
-    line_fft_from<N, P, S, STAGE + 1>(reg, t, tw, lds);
+    fft_stage<N, P, S, STAGE, BLOCK_SYNC>(reg, t, tw, lds);
+    line_fft_from<N, P, S, BLOCK_SYNC, STAGE + 1>(reg, t, tw, lds);
   }
 }
 
 // Full unnormalised transform of one line, X_k = sum_m x_m e^{S 2 pi i m k / N}.
-template <int N, int P, int S>
+template <int N, int P, int S, bool BLOCK_SYNC = false>
 __device__ __forceinline__ void line_fft(float2 (&reg)[P], int t, const Twiddles<N, P>& tw,
                                          float2* __restrict__ lds) {
-  line_fft_from<N, P, S, 0>(reg, t, tw, lds);
+  line_fft_from<N, P, S, BLOCK_SYNC, 0>(reg, t, tw, lds);
 }
 
 // ---------------------------------------------------------------------------------

@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(256) k_col_pass_2d(
   const double inv_n = 1.0 / ((double)nx * (double)NY);
   long long begin, end;
   block_share(total, ITEMS, begin, end);
-  int cached = -1;
+  double cached = -1.0;  // E_y depends on the instance only through a_j * pi dt / L_y^2
   double2 ey[P];
   for (long long g0 = begin; g0 < end; g0 += ITEMS) {
     // stage the tile columns: each thread moves float4 = two complex values; the
@@ -214,16 +214,16 @@ __global__ void __launch_bounds__(256) k_col_pass_2d(
       const int x = tc * 8 + (line & 7);
       double a, b;
       sched_ab(I, I.steps_done + s, a, b);
-      if (i != cached) {
-        // E_y(k_y) / (nx ny) for this lane's slots: computed once per instance and step
-        const double cy = a * I.kin_turns[1];
+      const double cy = a * I.kin_turns[1];
+      if (cy != cached) {
+        // E_y(k_y) / (nx ny) for this lane's slots: computed once per distinct coefficient
 #pragma unroll
         for (int q = 0; q < P; ++q) {
           const int nyf = freq(t + q * TPL, NY);
           const double2 e = phase_turns_d(cy * (double)(nyf * nyf));
           ey[q] = make_double2(e.x * inv_n, e.y * inv_n);
         }
-        cached = i;
+        cached = cy;
       }
       const int nxf = freq(x, nx);
       const double2 ex = phase_turns_d(a * I.kin_turns[0] * (double)(nxf * nxf));
@@ -263,6 +263,84 @@ __global__ void __launch_bounds__(256) k_col_pass_2d(
       }
     }
     __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// 2-D column pass, tile-wave form (NY >= 64).  Lane l of wavefront w of an item
+// owns column c = l & 7 of a tile column and row group t = (l >> 3) + 8 w, and
+// holds the rows t + q*TPL (q = 0..P-1).  Slot q of a wavefront is then exactly
+// one 8x8 tile (64 consecutive complex values, 512 bytes): loads and stores are
+// fully coalesced and go straight to registers.  A column spans W = TPL/8
+// wavefronts; with W > 1 the FFT exchanges use workgroup barriers.
+
+template <int NY, int P>
+struct ColTwCfg {
+  static constexpr int TPL = NY / P;
+  static constexpr int W = TPL / 8;                       // wavefronts per tile column
+  static constexpr int ITEMS = W >= 4 ? 1 : 4 / W;        // tile columns per block
+  static constexpr int NT = ITEMS * W * 64;
+  static constexpr int STRIDE = ((LineLds<NY>::kSlots + 13) / 16) * 16 + 2;
+  static_assert(TPL % 8 == 0, "tile-wave column pass needs TPL multiple of 8");
+};
+
+template <int NY, int P>
+__global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
+    const InstDev* __restrict__ inst, int ninst, int nx_log2, float2* __restrict__ psi,
+    const double2* __restrict__ twtab, int s, long long max_steps) {
+  using C = ColTwCfg<NY, P>;
+  constexpr int TPL = C::TPL, W = C::W, ITEMS = C::ITEMS, STRIDE = C::STRIDE;
+  __shared__ float2 lds[ITEMS * 8 * STRIDE];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int item = wave / W, wv = wave - item * W;  // item within the block, wave within the item
+  const int c = lane & 7;
+  const int t = (lane >> 3) + 8 * wv;
+  float2* my = lds + (item * 8 + c) * STRIDE;
+  Twiddles<NY, P> tw;
+  tw.load(twtab, t);
+  const int nx = 1 << nx_log2, tc_log2 = nx_log2 - 3, tcols = nx >> 3;
+  const long long total = (long long)ninst << tc_log2;
+  const double inv_n = 1.0 / ((double)nx * (double)NY);
+  long long begin, end;
+  block_share(total, ITEMS, begin, end);
+  double cached = -1.0;  // E_y depends on the instance only through a_j * pi dt / L_y^2
+  double2 ey[P];
+  for (long long g0 = begin; g0 < end; g0 += ITEMS) {
+    const long long g = g0 + item;
+    const bool valid = g < end;
+    const long long gc = valid ? g : end - 1;
+    const int i = (int)(gc >> tc_log2), tc = (int)(gc & (tcols - 1));
+    const InstDev& I = inst[i];
+    const bool active = valid && s < step_limit(I, max_steps);
+    double a, b;
+    sched_ab(I, I.steps_done + s, a, b);
+    const double cy = a * I.kin_turns[1];
+    if (cy != cached) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const int nyf = freq(t + q * TPL, NY);
+        const double2 e = phase_turns_d(cy * (double)(nyf * nyf));
+        ey[q] = make_double2(e.x * inv_n, e.y * inv_n);
+      }
+      cached = cy;
+    }
+    const int nxf = freq(tc * 8 + c, nx);
+    const double2 ex = phase_turns_d(a * I.kin_turns[0] * (double)(nxf * nxf));
+    float2* __restrict__ base = psi + I.psi_off + ((long long)(wv * tcols + tc) << 6) + lane;
+    float2 reg[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) reg[q] = base[(long long)q * W * tcols * 64];
+    line_fft<NY, P, -1, (W > 1)>(reg, t, tw, my);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const double2 k = make_double2(fma(ex.x, ey[q].x, -ex.y * ey[q].y), fma(ex.x, ey[q].y, ex.y * ey[q].x));
+      reg[q] = cmul_ff(reg[q], make_float2((float)k.x, (float)k.y));
+    }
+    line_fft<NY, P, +1, (W > 1)>(reg, t, tw, my);
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) base[(long long)q * W * tcols * 64] = reg[q];
+    }
   }
 }
 
@@ -614,10 +692,32 @@ int pass_blocks_row_2d(int nx, int ny, int ninst, int grid_cap) {
   return blocks_for((long long)ninst * ny, lpw, grid_cap);
 }
 
+template <int N>
+constexpr int col_tw_p() { return N >= 1024 ? 16 : 8; }
+
+template <int N>
+hipError_t launch_col_tw(int blocks, int nx, const InstDev* inst, int ninst, float2* psi,
+                         const double2* tw, int s, long long max_steps, hipStream_t stream) {
+  if constexpr (N >= 64 && N <= 256) {
+    constexpr int P_ = col_tw_p<N>();
+    hipLaunchKernelGGL((k_col_pass_tw<N, P_>), dim3(blocks), dim3(ColTwCfg<N, P_>::NT), 0, stream,
+                       inst, ninst, ilog2(nx), psi, tw, s, max_steps);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
 int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap) {
-  const int P = ny >= 1024 ? 16 : 8;
-  const int tpl = ny / P;
-  const int items = (8 * tpl >= 256) ? 1 : 256 / (8 * tpl);
+  int items;
+  if (ny >= 64 && ny <= 256) {
+    const int P = ny >= 1024 ? 16 : 8;
+    const int w = ny / P / 8;
+    items = w >= 4 ? 1 : 4 / w;
+  } else {
+    const int tpl = ny / 8;
+    items = (8 * tpl >= 256) ? 1 : 256 / (8 * tpl);
+  }
   return blocks_for((long long)ninst * (nx / 8), items, grid_cap);
 }
 
@@ -637,12 +737,15 @@ hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, fl
                               const double2* tw, int s, long long max_steps, int grid_cap,
                               hipStream_t stream) {
   const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap);
-  QHD_SWITCH_N(ny, {
-    constexpr int P_ = pts_per_lane<N_>();
-    hipLaunchKernelGGL((k_col_pass_2d<N_, P_>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0, stream,
-                       inst, ninst, ilog2(nx), psi, tw, s, max_steps);
-    return hipGetLastError();
-  });
+  switch (ny) {
+    case 512: { hipLaunchKernelGGL((k_col_pass_2d<512, 8>), dim3(blocks), dim3(ColCfg<512, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
+    case 1024: { hipLaunchKernelGGL((k_col_pass_2d<1024, 16>), dim3(blocks), dim3(ColCfg<1024, 16>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
+    case 8: { hipLaunchKernelGGL((k_col_pass_2d<8, 8>), dim3(blocks), dim3(ColCfg<8, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
+    case 16: { hipLaunchKernelGGL((k_col_pass_2d<16, 8>), dim3(blocks), dim3(ColCfg<16, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
+    case 32: { hipLaunchKernelGGL((k_col_pass_2d<32, 8>), dim3(blocks), dim3(ColCfg<32, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
+    default: break;
+  }
+  QHD_SWITCH_N(ny, { return launch_col_tw<N_>(blocks, nx, inst, ninst, psi, tw, s, max_steps, stream); });
 }
 
 hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* psi, const double* f,

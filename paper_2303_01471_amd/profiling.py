@@ -1,0 +1,130 @@
+"""Summaries of rocprofv3 output (rocpd SQLite databases) for the engine.
+
+    python -m paper_2303_01471_amd.profiling kernels DB
+        per-kernel dispatch count, total / mean / min / max duration (the
+        --kernel-trace --stats view), one line per kernel
+    python -m paper_2303_01471_amd.profiling counters DB
+        mean value per dispatch of every collected counter, per kernel
+    python -m paper_2303_01471_amd.profiling traffic FETCH_DB WRITE_DB --copy-bytes B --source-hash H
+        HBM bytes per grid point of every pass kernel from FETCH_SIZE and
+        WRITE_SIZE, each scaled by what the same counter reads for a plain copy
+        of B bytes in the same run; JSON (profiles/traffic.json format)
+
+Dispatch sizes (grid points per launch) come from the kernel arguments of the
+pass kernels as recorded by the benchmark (every instance active, steps capped).
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import re
+import sqlite3
+import sys
+
+
+def _short(name: str) -> str:
+    n = name.split("(")[0]
+    for pre in ("void ", "qhd::"):
+        n = n.replace(pre, "")
+    return n.strip()
+
+
+def kernel_stats(db: str):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, duration from kernels").fetchall()
+    agg = collections.defaultdict(list)
+    for name, dur in rows:
+        agg[_short(name)].append(dur)
+    out = []
+    for k, v in agg.items():
+        out.append(dict(kernel=k, calls=len(v), total_ns=sum(v), mean_ns=sum(v) / len(v), min_ns=min(v),
+                        max_ns=max(v)))
+    out.sort(key=lambda r: -r["total_ns"])
+    return out
+
+
+def counter_means(db: str):
+    con = sqlite3.connect(db)
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    for name, cname, val, d in con.execute(
+            "select kernel_name, counter_name, value, dispatch_id from counters_collection"):
+        k = _short(name)
+        agg[k][cname] += val
+        disp[k].add(d)
+    return {k: {c: v / len(disp[k]) for c, v in d.items()} for k, d in agg.items()}, \
+        {k: len(v) for k, v in disp.items()}
+
+
+# pass kernel -> (family name used by the library's timing, algorithmic bytes per point)
+_FAMILY = [
+    (re.compile(r"k_row_pass_2d<(\d+),"), "row_pass_2d/n{}", 24.0),
+    (re.compile(r"k_col_pass_(?:2d|tw)<(\d+),"), "col_pass_2d/n{}", 16.0),
+    (re.compile(r"k_line_pass_1d<(\d+),"), "line_pass_1d/n{}", 24.0),
+]
+
+
+def traffic(fetch_db: str, write_db: str, copy_bytes: float, points_per_dispatch: dict,
+            source_hash: str) -> dict:
+    fe, _ = counter_means(fetch_db)
+    wr, _ = counter_means(write_db)
+    copy_k = [k for k in fe if "copy" in k.lower() or "elementwise" in k.lower()]
+    if not copy_k:
+        raise SystemExit("no copy kernel found for the calibration")
+    ck = max(copy_k, key=lambda k: fe[k].get("FETCH_SIZE", 0.0))
+    f_scale = copy_bytes / (fe[ck]["FETCH_SIZE"] * 1024.0)
+    w_scale = copy_bytes / (wr[ck]["WRITE_SIZE"] * 1024.0)
+    out = {"source_hash": source_hash, "copy_kernel": ck, "copy_bytes": copy_bytes,
+           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
+    for k, v in fe.items():
+        for rx, fam, bpp in _FAMILY:
+            m = rx.search(k)
+            if not m:
+                continue
+            name = fam.format(m.group(1))
+            pts = points_per_dispatch.get(name)
+            if not pts:
+                continue
+            fetch = v["FETCH_SIZE"] * 1024.0 * f_scale
+            write = wr.get(k, {}).get("WRITE_SIZE", 0.0) * 1024.0 * w_scale
+            out["kernels"][name] = {"kernel": k, "points_per_dispatch": pts,
+                                    "fetch_bytes_per_point": fetch / pts,
+                                    "write_bytes_per_point": write / pts,
+                                    "hbm_bytes_per_point": (fetch + write) / pts,
+                                    "algorithmic_bytes_per_point": bpp}
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("kernels")
+    a.add_argument("db")
+    b = sub.add_parser("counters")
+    b.add_argument("db")
+    c = sub.add_parser("traffic")
+    c.add_argument("fetch_db")
+    c.add_argument("write_db")
+    c.add_argument("--copy-bytes", type=float, required=True)
+    c.add_argument("--points", required=True, help="JSON map family -> points per dispatch")
+    c.add_argument("--source-hash", required=True)
+    args = ap.parse_args(argv)
+    if args.cmd == "kernels":
+        print(f"{'calls':>8} {'total_ms':>10} {'mean_us':>10} {'min_us':>9} {'max_us':>9}  kernel")
+        for r in kernel_stats(args.db):
+            print(f"{r['calls']:8d} {r['total_ns'] / 1e6:10.3f} {r['mean_ns'] / 1e3:10.2f} "
+                  f"{r['min_ns'] / 1e3:9.2f} {r['max_ns'] / 1e3:9.2f}  {r['kernel']}")
+    elif args.cmd == "counters":
+        means, n = counter_means(args.db)
+        for k, d in sorted(means.items()):
+            print(f"{k} dispatches={n[k]} " + " ".join(f"{c}={v:.1f}" for c, v in sorted(d.items())))
+    else:
+        pts = json.loads(args.points)
+        json.dump(traffic(args.fetch_db, args.write_db, args.copy_bytes, pts, args.source_hash),
+                  sys.stdout, indent=1)
+        print()
+
+
+if __name__ == "__main__":
+    main()
