@@ -45,7 +45,7 @@ def log(msg):
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for rel in ("paper_2303_01471_amd/csrc/qhd_kernels.hip", "paper_2303_01471_amd/csrc/line_fft.h",
-                "paper_2303_01471_amd/csrc/qhd_internal.h"):
+                "paper_2303_01471_amd/csrc/pass_common.h", "paper_2303_01471_amd/csrc/qhd_internal.h"):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -61,8 +61,9 @@ typedef enum {
 
 /* One problem instance (Algorithm 1 of App. E.1). */
 typedef struct {
-  int32_t ndim;         /* 1 or 2 (3 is reserved: QHD_EUNSUPPORTED)                   */
-  int32_t n[3];         /* points per axis, powers of two, 8 <= n <= 1024; unused = 1  */
+  int32_t ndim;         /* 1, 2 or 3                                                   */
+  int32_t n[3];         /* points per axis, powers of two, 8 <= n <= 1024 (3-D: 16 <= n
+                           <= 128, else QHD_EUNSUPPORTED); unused axes are ignored     */
   double lo[3], hi[3];  /* periodic box [lo, hi) per axis, hi > lo (App. E.1 mesh)     */
   double dt;            /* time step s > 0                                             */
   int64_t nsteps;       /* number of steps, >= 0; the end time is T = nsteps * dt      */

@@ -10,8 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqhd.so")
 
-SOURCES = ["qhd_api.cpp", "qhd_kernels.hip"]
-HEADERS = ["line_fft.h", "qhd_internal.h"]
+SOURCES = ["qhd_api.cpp", "qhd_kernels.hip", "qhd_kernels_3d.hip"]
+HEADERS = ["line_fft.h", "qhd_internal.h", "pass_common.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1,0 +1,66 @@
+// Device helpers shared by the pass kernels (2-D/1-D in qhd_kernels.hip, 3-D in
+// qhd_kernels_3d.hip): tiled indexing, the schedule, step limits, work shares.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "qhd_internal.h"
+
+namespace qhd {
+
+constexpr double kInv2Pi = 0.15915494309189533577;
+
+// 8x8-tiled index of mesh point (x, y) on an nx-wide slab (rows y may run over
+// several z slabs: row = y + ny z)
+__device__ __forceinline__ long long tile_index(int x, int y, int nx) {
+  return ((long long)((y >> 3) * (nx >> 3) + (x >> 3)) << 6) + ((y & 7) << 3) + (x & 7);
+}
+
+// a_j, b_j of global step j (App. C.2.1, eq. nonconvex_QHD_h at the midpoint)
+__device__ __forceinline__ void sched_ab(const InstDev& I, long long j, double& a, double& b) {
+  if (I.sched == kSchedTable) {
+    // lines of finished instances still evaluate (and discard) their step: never
+    // read outside the table
+    const bool in = (j >= 0 && j < I.nsteps);
+    a = in ? I.table[2 * j] : 0.0;
+    b = in ? I.table[2 * j + 1] : 0.0;
+  } else if (I.sched == kSchedConst) {
+    a = I.sched_p0;
+    b = I.sched_p1;
+  } else {
+    const double t = ((double)j + 0.5) * I.dt;
+    const double t3 = t * t * t;
+    a = 2.0 / (I.sched_p0 + t3);
+    b = 2.0 * t3;
+  }
+}
+
+__device__ __forceinline__ long long step_limit(const InstDev& I, long long max_steps) {
+  const long long rem = I.nsteps - I.steps_done;
+  return (max_steps < 0 || max_steps > rem) ? rem : max_steps;
+}
+
+__device__ __forceinline__ int freq(int m, int n) { return m < (n >> 1) ? m : m - n; }
+
+// offset of slot q of lane t on tiled row y (x = t + q*TPL); compile-time stride
+// between slots once a slot spans whole tiles
+template <int NX, int TPL>
+__device__ __forceinline__ long long row_slot(int t, int q, int y) {
+  if constexpr (TPL % 8 == 0) {
+    return ((long long)((y >> 3) * (NX >> 3) + (t >> 3)) << 6) + ((y & 7) << 3) + (t & 7) +
+           (long long)q * (TPL * 8);
+  } else {
+    return tile_index(t + q * TPL, y, NX);
+  }
+}
+
+// contiguous share [begin, end) of `total` work items for this block, in units of `step`
+__device__ __forceinline__ void block_share(long long total, int step, long long& begin, long long& end) {
+  const long long units = (total + step - 1) / step;
+  const long long per = (units + gridDim.x - 1) / gridDim.x;
+  begin = (long long)blockIdx.x * per * step;
+  end = begin + per * step;
+  if (end > total) end = total;
+}
+
+}  // namespace qhd

@@ -46,11 +46,12 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // Host-only validation of one descriptor (no device work).
 qhd_status validate(const qhd_instance& d, int idx) {
-  if (d.ndim == 3) return fail(QHD_EUNSUPPORTED, "instance %d: ndim=3 is not supported by this build", idx);
-  if (d.ndim < 1 || d.ndim > 2) return fail(QHD_EINVAL, "instance %d: ndim must be 1 or 2 (got %d)", idx, d.ndim);
+  if (d.ndim < 1 || d.ndim > 3) return fail(QHD_EINVAL, "instance %d: ndim must be 1, 2 or 3 (got %d)", idx, d.ndim);
   for (int a = 0; a < d.ndim; ++a) {
     if (!is_pow2(d.n[a]) || d.n[a] < 8 || d.n[a] > 1024)
       return fail(QHD_EINVAL, "instance %d: n[%d]=%d must be a power of two in [8, 1024]", idx, a, d.n[a]);
+    if (d.ndim == 3 && (d.n[a] < 16 || d.n[a] > 128))
+      return fail(QHD_EUNSUPPORTED, "instance %d: 3-D axes need 16 <= n <= 128 (n[%d]=%d)", idx, a, d.n[a]);
     if (!std::isfinite(d.lo[a]) || !std::isfinite(d.hi[a]) || !(d.hi[a] > d.lo[a]))
       return fail(QHD_EINVAL, "instance %d: box axis %d needs finite lo < hi", idx, a);
   }
@@ -95,7 +96,7 @@ struct Family {
 }  // namespace
 
 struct ShapeClass {
-  int ndim = 0, nx = 1, ny = 1;
+  int ndim = 0, nx = 1, ny = 1, nz = 1;
   long long points = 0;            // per instance
   std::vector<int> members;        // plan indices, sorted by nsteps (descending)
   std::vector<InstDev> host;       // mirror of the device array
@@ -107,7 +108,8 @@ struct ShapeClass {
   int lines = 0;                   // lines per instance for the readout partials
   const double2* tw_x = nullptr;
   const double2* tw_y = nullptr;
-  int fam_row = -1, fam_col = -1, fam_line = -1;
+  const double2* tw_z = nullptr;
+  int fam_row = -1, fam_col = -1, fam_line = -1, fam_y = -1, fam_z = -1;
 };
 
 struct qhd_plan_s {
@@ -248,11 +250,11 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
   }
 
   // group into shape classes
-  std::map<std::tuple<int, int, int>, int> key2cls;
+  std::map<std::tuple<int, int, int, int>, int> key2cls;
   for (int i = 0; i < batch; ++i) {
     const qhd_instance& d = inst[i];
-    const int nx = d.n[0], ny = d.ndim >= 2 ? d.n[1] : 1;
-    auto key = std::make_tuple(d.ndim, nx, ny);
+    const int nx = d.n[0], ny = d.ndim >= 2 ? d.n[1] : 1, nz = d.ndim >= 3 ? d.n[2] : 1;
+    auto key = std::make_tuple(d.ndim, nx, ny, nz);
     auto it = key2cls.find(key);
     int c;
     if (it == key2cls.end()) {
@@ -262,7 +264,8 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       sc.ndim = d.ndim;
       sc.nx = nx;
       sc.ny = ny;
-      sc.points = (long long)nx * ny;
+      sc.nz = nz;
+      sc.points = (long long)nx * ny * nz;
       p->classes.push_back(sc);
     } else {
       c = it->second;
@@ -275,6 +278,7 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
   for (auto& c : p->classes) {
     lengths.push_back(c.nx);
     if (c.ndim >= 2) lengths.push_back(c.ny);
+    if (c.ndim >= 3) lengths.push_back(c.nz);
   }
   std::sort(lengths.begin(), lengths.end());
   lengths.erase(std::unique(lengths.begin(), lengths.end()), lengths.end());
@@ -307,7 +311,7 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
   for (int i = 0; i < batch; ++i) {
     const qhd_instance& d = inst[i];
     out_off_of[i] = out_off;
-    out_off += (long long)d.n[0] * (d.ndim >= 2 ? d.n[1] : 1);
+    out_off += (long long)d.n[0] * (d.ndim >= 2 ? d.n[1] : 1) * (d.ndim >= 3 ? d.n[2] : 1);
   }
   p->total_points = out_off;
 
@@ -318,9 +322,10 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
     const int m = (int)c.members.size();
     max_pts = std::max(max_pts, c.points);
     max_members = std::max(max_members, (size_t)m);
-    c.lines = c.ndim == 2 ? c.ny : 1;
+    c.lines = c.ndim >= 2 ? c.ny * c.nz : 1;
     c.tw_x = p->twiddles + p->tw_off[c.nx];
     c.tw_y = c.ndim >= 2 ? p->twiddles + p->tw_off[c.ny] : nullptr;
+    c.tw_z = c.ndim >= 3 ? p->twiddles + p->tw_off[c.nz] : nullptr;
     c.host.resize(m);
     for (int pos = 0; pos < m; ++pos) {
       const int i = c.members[pos];
@@ -379,7 +384,14 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       return bail(e == hipErrorOutOfMemory ? QHD_ENOMEM : QHD_EDEVICE);
     }
     char name[48];
-    if (c.ndim == 2) {
+    if (c.ndim == 3) {
+      snprintf(name, sizeof name, "xpass_3d/n%d", c.nx);
+      c.fam_row = family_index(p, name, 24.0);
+      snprintf(name, sizeof name, "ypass_3d/n%d", c.ny);
+      c.fam_y = family_index(p, name, 16.0);
+      snprintf(name, sizeof name, "zpass_3d/n%d", c.nz);
+      c.fam_z = family_index(p, name, 16.0);
+    } else if (c.ndim == 2) {
       snprintf(name, sizeof name, "row_pass_2d/n%d", c.nx);
       c.fam_row = family_index(p, name, 24.0);
       snprintf(name, sizeof name, "col_pass_2d/n%d", c.ny);
@@ -430,7 +442,7 @@ qhd_status qhd_set_potential(qhd_plan p, int32_t i, const double* f, int32_t on_
   HIP_TRY(hipMemcpyAsync(p->staging_f, f, sizeof(double) * c.points,
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->internal));
   HIP_TRY(launch_argmin(p->staging_f, c.points, p->amin_val, p->amin_idx, p->internal));
-  HIP_TRY(launch_import_f(c.ndim, c.nx, c.ny, p->staging_f, c.f + c.host[pos].psi_off, p->internal));
+  HIP_TRY(launch_import_f(c.ndim >= 2 ? 2 : 1, c.nx, c.ny * c.nz, p->staging_f, c.f + c.host[pos].psi_off, p->internal));
   double v = 0.0;
   long long idx[2] = {0, 0};
   HIP_TRY(hipMemcpyAsync(&v, p->amin_val, sizeof v, hipMemcpyDeviceToHost, p->internal));
@@ -455,7 +467,7 @@ qhd_status qhd_set_state(qhd_plan p, int32_t i, const float* psi, int32_t on_dev
   const int pos = p->pos_of[i];
   HIP_TRY(hipMemcpyAsync(p->staging_psi, psi, sizeof(float2) * c.points,
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->internal));
-  HIP_TRY(launch_import_psi(c.ndim, c.nx, c.ny, p->staging_psi, c.psi + c.host[pos].psi_off, p->internal));
+  HIP_TRY(launch_import_psi(c.ndim >= 2 ? 2 : 1, c.nx, c.ny * c.nz, p->staging_psi, c.psi + c.host[pos].psi_off, p->internal));
   c.host[pos].mode = kModeClean;
   p->state_ready[i] = 1;
   return push_inst(p, i);
@@ -526,7 +538,24 @@ qhd_status qhd_evolve(qhd_plan p, int64_t max_steps, void* stream_v) {
         if (lim[ci][k] > s) nact = (int)k + 1;
       if (nact == 0) continue;
       const double pts = (double)nact * (double)c.points;
-      if (c.ndim == 2) {
+      if (c.ndim == 3) {
+        HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
+          return launch_row_pass_2d(c.nx, c.ny * c.nz, c.dev, nact, c.psi, c.f, c.tw_x, (int)s,
+                                    max_steps, p->grid_cap, stream);
+        }));
+        HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
+          return launch_ypass_3d(c.nx, c.ny, c.nz, -1, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
+                                 p->grid_cap, stream);
+        }));
+        HIP_TRY(timed_launch(c.fam_z, pts, sample, [&] {
+          return launch_zpass_3d(c.nx, c.ny, c.nz, c.dev, nact, c.psi, c.tw_z, (int)s, max_steps,
+                                 p->grid_cap, stream);
+        }));
+        HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
+          return launch_ypass_3d(c.nx, c.ny, c.nz, +1, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
+                                 p->grid_cap, stream);
+        }));
+      } else if (c.ndim == 2) {
         HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
           return launch_row_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, (int)s, max_steps,
                                     p->grid_cap, stream);
@@ -591,8 +620,8 @@ qhd_status qhd_observe(qhd_plan p, void* stream_v, qhd_observables* out, float* 
   qhd_status status = QHD_OK;
   for (auto& c : p->classes) {
     const int m = (int)c.members.size();
-    if (c.ndim == 2)
-      HIP_TRY(launch_observe_2d(c.nx, c.ny, c.dev, m, c.psi, c.f, c.tw_x,
+    if (c.ndim >= 2)
+      HIP_TRY(launch_observe_2d(c.nx, c.ny * c.nz, c.ny, c.dev, m, c.psi, c.f, c.tw_x,
                                 reinterpret_cast<float2*>(psi_dev), rho_dev, c.partials, stream));
     else
       HIP_TRY(launch_observe_1d(c.nx, c.dev, m, c.psi, c.f, reinterpret_cast<float2*>(psi_dev),

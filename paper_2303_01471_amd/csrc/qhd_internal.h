@@ -49,12 +49,24 @@ hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* ps
                                hipStream_t stream);
 hipError_t launch_commit(InstDev* inst, int ninst, long long max_steps, hipStream_t stream);
 
+// 3-D (qhd_kernels_3d.hip): y-lines (dir -1 forward, +1 inverse) and the z-pass
+// with the kinetic factor.  The x-pass is launch_row_pass_2d with rows = ny*nz.
+hipError_t launch_ypass_3d(int nx, int ny, int nz, int dir, const InstDev* inst, int ninst,
+                           float2* psi, const double2* tw_y, int s, long long max_steps,
+                           int grid_cap, hipStream_t stream);
+hipError_t launch_zpass_3d(int nx, int ny, int nz, const InstDev* inst, int ninst, float2* psi,
+                           const double2* tw_z, int s, long long max_steps, int grid_cap,
+                           hipStream_t stream);
+
 // Observe: closes the pending half step, writes the user-layout psi / rho
 // (optional, plan-wide concatenated buffers) and per-line FP64 partial sums
 // (3 per line: sum rho, sum f rho, sum of rho inside the success ball).
-hipError_t launch_observe_2d(int nx, int ny, const InstDev* inst, int ninst, const float2* psi,
-                             const double* f, const double2* tw_nx, float2* out_psi,
-                             float* out_rho, double* partials, hipStream_t stream);
+// `rows` = ny (2-D) or ny*nz (3-D); `ny` is the slab height used to recover
+// (y, z) from a row for the success test.
+hipError_t launch_observe_2d(int nx, int rows, int ny, const InstDev* inst, int ninst,
+                             const float2* psi, const double* f, const double2* tw_nx,
+                             float2* out_psi, float* out_rho, double* partials,
+                             hipStream_t stream);
 hipError_t launch_observe_1d(int n, const InstDev* inst, int ninst, const float2* psi,
                              const double* f, float2* out_psi, float* out_rho, double* partials,
                              hipStream_t stream);

@@ -35,62 +35,10 @@
 #include <climits>
 
 #include "line_fft.h"
+#include "pass_common.h"
 #include "qhd_internal.h"
 
 namespace qhd {
-
-constexpr double kInv2Pi = 0.15915494309189533577;
-
-__device__ __forceinline__ long long tile_index(int x, int y, int nx) {
-  return ((long long)((y >> 3) * (nx >> 3) + (x >> 3)) << 6) + ((y & 7) << 3) + (x & 7);
-}
-
-// a_j, b_j of global step j (App. C.2.1, eq. nonconvex_QHD_h at the midpoint)
-__device__ __forceinline__ void sched_ab(const InstDev& I, long long j, double& a, double& b) {
-  if (I.sched == kSchedTable) {
-    // lines of finished instances still evaluate (and discard) their step: never
-    // read outside the table
-    const bool in = (j >= 0 && j < I.nsteps);
-    a = in ? I.table[2 * j] : 0.0;
-    b = in ? I.table[2 * j + 1] : 0.0;
-  } else if (I.sched == kSchedConst) {
-    a = I.sched_p0;
-    b = I.sched_p1;
-  } else {
-    const double t = ((double)j + 0.5) * I.dt;
-    const double t3 = t * t * t;
-    a = 2.0 / (I.sched_p0 + t3);
-    b = 2.0 * t3;
-  }
-}
-
-__device__ __forceinline__ long long step_limit(const InstDev& I, long long max_steps) {
-  const long long rem = I.nsteps - I.steps_done;
-  return (max_steps < 0 || max_steps > rem) ? rem : max_steps;
-}
-
-__device__ __forceinline__ int freq(int m, int n) { return m < (n >> 1) ? m : m - n; }
-
-// offset of slot q of lane t on tiled row y (x = t + q*TPL); compile-time stride
-// between slots once a slot spans whole tiles
-template <int NX, int TPL>
-__device__ __forceinline__ long long row_slot(int t, int q, int y) {
-  if constexpr (TPL % 8 == 0) {
-    return ((long long)((y >> 3) * (NX >> 3) + (t >> 3)) << 6) + ((y & 7) << 3) + (t & 7) +
-           (long long)q * (TPL * 8);
-  } else {
-    return tile_index(t + q * TPL, y, NX);
-  }
-}
-
-// contiguous share [begin, end) of `total` work items for this block, in units of `step`
-__device__ __forceinline__ void block_share(long long total, int step, long long& begin, long long& end) {
-  const long long units = (total + step - 1) / step;
-  const long long per = (units + gridDim.x - 1) / gridDim.x;
-  begin = (long long)blockIdx.x * per * step;
-  end = begin + per * step;
-  if (end > total) end = total;
-}
 
 // ------------------------------------------------------------------------------------
 // 2-D row pass: lines along x, one line per TPL lanes.
@@ -430,16 +378,18 @@ __device__ __forceinline__ double line_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ bool in_ball(int dxi, int dyi, const InstDev& I) {
+__device__ __forceinline__ bool in_ball(int dxi, int dyi, int dzi, const InstDev& I) {
   // same FP64 operations, in the same order and without contraction, as the oracle
   const double dx = __dmul_rn((double)dxi, I.h[0]);
   const double dy = __dmul_rn((double)dyi, I.h[1]);
-  return __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)) < I.r2;
+  const double dz = __dmul_rn((double)dzi, I.h[2]);
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz)) < I.r2;
 }
 
 template <int NX, int P>
 __global__ void __launch_bounds__(256) k_observe_2d(const InstDev* __restrict__ inst, int ninst,
-                                                    int ny_log2, const float2* __restrict__ psi,
+                                                    int ny_log2, int slab_log2,
+                                                    const float2* __restrict__ psi,
                                                     const double* __restrict__ f,
                                                     const double2* __restrict__ twtab,
                                                     float2* __restrict__ out_psi,
@@ -476,7 +426,10 @@ __global__ void __launch_bounds__(256) k_observe_2d(const InstDev* __restrict__ 
 #pragma unroll
       for (int q = 0; q < P; ++q) reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fv[q]));
     }
-    const int xs = (int)(I.argmin % NX), ys = (int)(I.argmin / NX);
+    const long long rs = I.argmin / NX;
+    const int xs = (int)(I.argmin % NX);
+    const int ys = (int)(rs & ((1 << slab_log2) - 1)), zs = (int)(rs >> slab_log2);
+    const int yy = y & ((1 << slab_log2) - 1), zz = y >> slab_log2;
     double sr = 0.0, sf = 0.0, sm = 0.0;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
@@ -485,7 +438,7 @@ __global__ void __launch_bounds__(256) k_observe_2d(const InstDev* __restrict__ 
       const double rho = (double)v.x * v.x + (double)v.y * v.y;
       sr += rho;
       sf += fv[q] * rho;
-      if (in_ball(x - xs, y - ys, I)) sm += rho;
+      if (in_ball(x - xs, yy - ys, zz - zs, I)) sm += rho;
       if (valid) {
         const long long o = I.out_off + (long long)y * NX + x;
         if (out_psi) out_psi[o] = v;
@@ -773,15 +726,16 @@ hipError_t launch_reset_inst(InstDev* inst, int ninst, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_observe_2d(int nx, int ny, const InstDev* inst, int ninst, const float2* psi,
-                             const double* f, const double2* tw, float2* out_psi, float* out_rho,
-                             double* partials, hipStream_t stream) {
+hipError_t launch_observe_2d(int nx, int rows, int ny, const InstDev* inst, int ninst,
+                             const float2* psi, const double* f, const double2* tw,
+                             float2* out_psi, float* out_rho, double* partials,
+                             hipStream_t stream) {
   QHD_SWITCH_N(nx, {
     constexpr int P_ = pts_per_lane<N_>();
     constexpr int LPW_ = 256 / (N_ / P_);
-    const int blocks = blocks_for((long long)ninst * ny, LPW_, 4096);
-    hipLaunchKernelGGL((k_observe_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst, ilog2(ny),
-                       psi, f, tw, out_psi, out_rho, partials);
+    const int blocks = blocks_for((long long)ninst * rows, LPW_, 4096);
+    hipLaunchKernelGGL((k_observe_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+                       ilog2(rows), ilog2(ny), psi, f, tw, out_psi, out_rho, partials);
     return hipGetLastError();
   });
 }

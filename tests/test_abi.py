@@ -41,7 +41,9 @@ def _inst(**kw):
 
 @pytest.mark.parametrize("mutate,status", [
     (lambda d: setattr(d, "ndim", 0), q.QHD_EINVAL),
-    (lambda d: setattr(d, "ndim", 3), q.QHD_EUNSUPPORTED),
+    (lambda d: setattr(d, "ndim", 4), q.QHD_EINVAL),
+    (lambda d: (setattr(d, "ndim", 3), d.n.__setitem__(2, 256)), q.QHD_EUNSUPPORTED),
+    (lambda d: (setattr(d, "ndim", 3), d.n.__setitem__(2, 8)), q.QHD_EUNSUPPORTED),
     (lambda d: d.n.__setitem__(0, 48), q.QHD_EINVAL),
     (lambda d: d.n.__setitem__(1, 2048), q.QHD_EINVAL),
     (lambda d: d.n.__setitem__(0, 4), q.QHD_EINVAL),

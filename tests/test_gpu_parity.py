@@ -187,3 +187,46 @@ def test_fault_injection_hook(monkeypatch):
     res, _, _, st = plan.observe()
     assert st == q.QHD_OK and res[0]["steps_done"] == 10
     plan.close()
+
+
+def test_single_256x256_10k_steps_full_size():
+    """The single-instance 256^2 workload at its full length: 10^4 steps of
+    dt = 1e-3 to T = 10 on [0,1]^2 (App. C.2.1 experiment shape)."""
+    note("case: 256x256 seed 1234, 10000 steps")
+    spec = q.InstanceSpec(shape=(256, 256), nsteps=10000, dt=1e-3)
+    f = qhd_inputs.landscape_grid(1234, (256, 256))
+    res, psis, _, st = run_gpu([spec], [f])
+    assert st == q.QHD_OK
+    _check([spec], [f], res, psis, "c1")
+
+
+@pytest.mark.parametrize("n,nsteps", [(512, 2000), (1024, 300)])
+def test_large_grids_against_oracle(n, nsteps):
+    note(f"case: {n}x{n}, {nsteps} steps")
+    spec = q.InstanceSpec(shape=(n, n), nsteps=nsteps, dt=1e-3)
+    f = qhd_inputs.landscape_grid(77, (n, n))
+    res, psis, _, st = run_gpu([spec], [f])
+    assert st == q.QHD_OK
+    _check([spec], [f], res, psis, f"n{n}")
+
+
+def test_batched_launch_sampled_against_oracle():
+    """Instances drawn by the batched-workload recipe (sizes 128/256/512, 8-24
+    terms), run together in one plan with the same launch configuration as the
+    benchmark, step counts capped at 1500 so the oracle can follow; one sampled
+    instance per size is compared with the oracle, all are checked for norm."""
+    note("case: batched sample")
+    specs_in = qhd_inputs.batched_2d(count=24)
+    specs = [q.InstanceSpec(shape=s.shape, nsteps=min(s.nsteps, 1500) - (i % 5), dt=s.dt)
+             for i, s in enumerate(specs_in)]
+    fs = [s.grid() for s in specs_in]
+    res, psis, _, st = run_gpu(specs, fs)
+    assert st == q.QHD_OK
+    for r in res:
+        assert abs(r["norm"] - 1.0) <= 1e-5
+    picked = {}
+    for i, s in enumerate(specs):
+        picked.setdefault(s.shape[0], i)
+    idx = sorted(picked.values())
+    _check([specs[i] for i in idx], [fs[i] for i in idx], [res[i] for i in idx],
+           [psis[i] for i in idx], "batch")
