@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code
 with the HIP library (``paper_2303_01471_amd``); the two sides meet only through
-the seeded input arrays of ``paper_2303_01471_amd.inputs``.
+the seeded input arrays of the top-level ``qhd_inputs`` module.
 
 The arithmetic lives in ``qhd_oracle.c`` (plain C, FP64, OpenMP over lines);
 this module only marshals numpy arrays.  Section/equation citations for every

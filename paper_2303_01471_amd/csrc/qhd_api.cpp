@@ -204,6 +204,11 @@ qhd_status push_inst(qhd_plan p, int i) {
 
 }  // namespace
 
+namespace qhd {
+// shared with the surrogate's entry points, which report through qhd_last_error()
+void set_error_message(const char* msg) { g_err = msg ? msg : ""; }
+}  // namespace qhd
+
 extern "C" {
 
 const char* qhd_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,61 @@
+// Internal interfaces of the spectral neural-operator surrogate (sno.cpp,
+// sno_gemm.hip, sno_kernels.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace qhd {
+
+// C[b] = alpha * op(A[b]) op(B[b]) + beta * C[b], b = 0..batch-1, row-major
+// storage with leading dimensions; op(X) = X^T when trans is set.
+struct GemmArgs {
+  int M = 0, N = 0, K = 0, batch = 1;
+  const void* A = nullptr;
+  int lda = 0;
+  long long sA = 0;
+  bool transA = false;
+  const void* B = nullptr;
+  int ldb = 0;
+  long long sB = 0;
+  bool transB = false;
+  void* C = nullptr;
+  int ldc = 0;
+  long long sC = 0;
+  float alpha = 1.0f, beta = 0.0f;
+  // optional second product accumulated in the same registers:
+  // C = alpha (op(A) op(B) + scale2 op(A2) op(B2)) + beta C, with A2/B2 sharing
+  // the leading dimensions, strides and transposition of A/B; scale2 is +1 or -1
+  const void* A2 = nullptr;
+  const void* B2 = nullptr;
+  float scale2 = 1.0f;
+  bool in_bf16 = true;   // operands BF16 (else FP32)
+  bool out_bf16 = false; // C BF16 (only with BF16 operands), else FP32
+};
+
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t stream);
+
+// Elementwise / reduction kernels (sno_kernels.hip).  `bf16` selects the
+// activation storage type (BF16 or FP32).
+hipError_t sno_prep_input(const double* f, int batch, int S, void* in, bool bf16, hipStream_t st);
+// z += bias; h = z (act 0) or GELU(z) (act 1)
+hipError_t sno_bias_act(float* z, const float* bias, long long rows, int C, void* h, bool bf16, int act,
+                        hipStream_t st);
+hipError_t sno_project_softmax(const void* h, const float* wp, const float* bp, int batch, int npix,
+                               int C, bool bf16, float* rho, hipStream_t st);
+hipError_t sno_loss_grad(const float* rho_hat, const float* rho, int batch, int npix, float* dq,
+                         double* loss_per_sample, hipStream_t st);
+hipError_t sno_project_backward(const float* dq, const void* h, const float* wp, int batch, int npix,
+                                int C, bool bf16, float* dh, float* partials, int nparts,
+                                hipStream_t st);
+hipError_t sno_gelu_backward(const float* dh, const float* z, long long n, void* dz, bool bf16,
+                             hipStream_t st);
+hipError_t sno_colsum(const void* x, bool bf16, long long rows, int C, float* partials, int nparts,
+                      hipStream_t st);
+hipError_t sno_reduce_partials(const float* partials, int nparts, int len, float* out, bool accumulate,
+                               hipStream_t st);
+hipError_t sno_cast(const float* src, void* dst, long long n, bool bf16, hipStream_t st);
+hipError_t sno_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1,
+                    float b2, float eps, float c1, float c2, void* copy, bool bf16, hipStream_t st);
+hipError_t sno_fill(float* p, long long n, float v, hipStream_t st);
+
+}  // namespace qhd

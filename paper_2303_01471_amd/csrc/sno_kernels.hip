@@ -1,0 +1,325 @@
+// Elementwise and reduction kernels of the spectral neural-operator surrogate.
+// Activation storage is BF16 (training / inference) or FP32 (gradient checks);
+// every reduction accumulates in FP32 within a thread and FP64 across threads.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "sno_internal.h"
+
+namespace qhd {
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ float ld(const T* p, long long i) { return (float)p[i]; }
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+}
+
+// block-wide FP64 sum over 256 threads
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ float block_max(float v, float* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const float r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// features per pixel: standardised f, x / S, y / S
+template <typename T>
+__global__ void __launch_bounds__(256) k_prep(const double* __restrict__ f, int S, T* __restrict__ in) {
+  __shared__ double sh[256];
+  const int b = blockIdx.x, npix = S * S;
+  const double* fb = f + (long long)b * npix;
+  double s1 = 0.0, s2 = 0.0;
+  for (int p = threadIdx.x; p < npix; p += 256) {
+    s1 += fb[p];
+    s2 += fb[p] * fb[p];
+  }
+  const double mean = block_sum(s1, sh) / npix;
+  const double var = block_sum(s2, sh) / npix - mean * mean;
+  const double inv = 1.0 / sqrt(var > 1e-24 ? var : 1e-24);
+  T* ib = in + (long long)b * npix * 3;
+  for (int p = threadIdx.x; p < npix; p += 256) {
+    ib[3 * p + 0] = (T)(float)((fb[p] - mean) * inv);
+    ib[3 * p + 1] = (T)((float)(p % S) / (float)S);
+    ib[3 * p + 2] = (T)((float)(p / S) / (float)S);
+  }
+}
+
+// z += bias (kept for the backward pass); h = act(z), act = identity (0) or GELU (1)
+template <typename T>
+__global__ void k_bias_act(float* __restrict__ z, const float* __restrict__ bias, long long n, int C,
+                           T* __restrict__ h, int act) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const float v = z[e] + bias[e % C];
+  z[e] = v;
+  h[e] = (T)(act ? gelu(v) : v);
+}
+
+// one block per sample: logits q = h . wp + bp, then softmax over the grid
+template <typename T>
+__global__ void __launch_bounds__(256) k_project_softmax(const T* __restrict__ h, const float* __restrict__ wp,
+                                                         const float* __restrict__ bp, int npix, int C,
+                                                         float* __restrict__ rho) {
+  __shared__ double sh[256];
+  __shared__ float shf[256];
+  const int b = blockIdx.x;
+  const T* hb = h + (long long)b * npix * C;
+  float* rb = rho + (long long)b * npix;
+  float mx = -INFINITY;
+  for (int p = threadIdx.x; p < npix; p += 256) {
+    float q = bp[0];
+    for (int c = 0; c < C; ++c) q = fmaf(ld(hb, (long long)p * C + c), wp[c], q);
+    rb[p] = q;
+    mx = fmaxf(mx, q);
+  }
+  mx = block_max(mx, shf);
+  double s = 0.0;
+  for (int p = threadIdx.x; p < npix; p += 256) {
+    const float e = __expf(rb[p] - mx);
+    rb[p] = e;
+    s += e;
+  }
+  const double tot = block_sum(s, sh);
+  const float inv = (float)(1.0 / tot);
+  for (int p = threadIdx.x; p < npix; p += 256) rb[p] *= inv;
+}
+
+// one block per sample: loss_b = sum |rho_hat - rho|; dq = rho_hat (g - <rho_hat, g>), g = sign / B
+__global__ void __launch_bounds__(256) k_loss_grad(const float* __restrict__ rh, const float* __restrict__ r,
+                                                   int batch, int npix, float* __restrict__ dq,
+                                                   double* __restrict__ loss) {
+  __shared__ double sh[256];
+  const int b = blockIdx.x;
+  const float* a = rh + (long long)b * npix;
+  const float* t = r + (long long)b * npix;
+  float* d = dq + (long long)b * npix;
+  const float invb = 1.0f / (float)batch;
+  double l = 0.0, s = 0.0;
+  for (int p = threadIdx.x; p < npix; p += 256) {
+    const float diff = a[p] - t[p];
+    const float g = diff > 0.0f ? invb : (diff < 0.0f ? -invb : 0.0f);
+    l += fabs((double)diff);
+    s += (double)a[p] * g;
+    d[p] = g;
+  }
+  const double lt = block_sum(l, sh);
+  const float st = (float)block_sum(s, sh);
+  for (int p = threadIdx.x; p < npix; p += 256) d[p] = a[p] * (d[p] - st);
+  if (threadIdx.x == 0) loss[b] = lt;
+}
+
+// dh = dq wp (outer product), and per-block partial sums of dWp = sum dq h, dbp = sum dq
+template <typename T>
+__global__ void __launch_bounds__(256) k_project_backward(const float* __restrict__ dq, const T* __restrict__ h,
+                                                          const float* __restrict__ wp, long long rows, int C,
+                                                          float* __restrict__ dh, float* __restrict__ partials) {
+  __shared__ double sh[256];
+  const int c = threadIdx.x % C, r0 = threadIdx.x / C, rstep = 256 / C;
+  const long long per = (rows + gridDim.x - 1) / gridDim.x;
+  const long long beg = (long long)blockIdx.x * per;
+  const long long end = beg + per < rows ? beg + per : rows;
+  float accw = 0.0f, accb = 0.0f;
+  for (long long r = beg + r0; r < end; r += rstep) {
+    const float g = dq[r];
+    accw = fmaf(g, ld(h, r * C + c), accw);
+    if (c == 0) accb += g;
+    dh[r * C + c] = g * wp[c];
+  }
+  // reduce over the row groups of equal c
+  sh[threadIdx.x] = accw;
+  __syncthreads();
+  if ((int)threadIdx.x < C) {
+    double s = 0.0;
+    for (int k = 0; k < rstep; ++k) s += sh[threadIdx.x + k * C];
+    partials[(long long)blockIdx.x * (C + 1) + threadIdx.x] = (float)s;
+  }
+  __syncthreads();
+  sh[threadIdx.x] = accb;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < rstep; ++k) s += sh[k * C];
+    partials[(long long)blockIdx.x * (C + 1) + C] = (float)s;
+  }
+}
+
+template <typename T>
+__global__ void k_gelu_backward(const float* __restrict__ dh, const float* __restrict__ z, long long n,
+                                T* __restrict__ dz) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  dz[e] = (T)(dh[e] * gelu_grad(z[e]));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_colsum(const T* __restrict__ x, long long rows, int C,
+                                                float* __restrict__ partials) {
+  __shared__ double sh[256];
+  const int c = threadIdx.x % C, r0 = threadIdx.x / C, rstep = 256 / C;
+  const long long per = (rows + gridDim.x - 1) / gridDim.x;
+  const long long beg = (long long)blockIdx.x * per;
+  const long long end = beg + per < rows ? beg + per : rows;
+  float acc = 0.0f;
+  for (long long r = beg + r0; r < end; r += rstep) acc += ld(x, r * C + c);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < C) {
+    double s = 0.0;
+    for (int k = 0; k < rstep; ++k) s += sh[threadIdx.x + k * C];
+    partials[(long long)blockIdx.x * C + threadIdx.x] = (float)s;
+  }
+}
+
+__global__ void k_reduce_partials(const float* __restrict__ partials, int nparts, int len,
+                                  float* __restrict__ out, int accumulate) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= len) return;
+  double s = 0.0;
+  for (int k = 0; k < nparts; ++k) s += partials[(long long)k * len + j];
+  out[j] = accumulate ? out[j] + (float)s : (float)s;
+}
+
+template <typename T>
+__global__ void k_cast(const float* __restrict__ src, T* __restrict__ dst, long long n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = (T)src[e];
+}
+
+template <typename T>
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, long long n, float lr, float b1, float b2, float eps,
+                       float c1, float c2, T* __restrict__ copy) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const float gi = g[e];
+  const float mi = b1 * m[e] + (1.0f - b1) * gi;
+  const float vi = b2 * v[e] + (1.0f - b2) * gi * gi;
+  m[e] = mi;
+  v[e] = vi;
+  const float pi = p[e] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[e] = pi;
+  if (copy) copy[e] = (T)pi;
+}
+
+__global__ void k_fill(float* __restrict__ p, long long n, float v) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
+inline dim3 grid1(long long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+}  // namespace
+
+hipError_t sno_prep_input(const double* f, int batch, int S, void* in, bool bf16, hipStream_t st) {
+  if (bf16) hipLaunchKernelGGL(k_prep<__bf16>, dim3(batch), dim3(256), 0, st, f, S, (__bf16*)in);
+  else hipLaunchKernelGGL(k_prep<float>, dim3(batch), dim3(256), 0, st, f, S, (float*)in);
+  return hipGetLastError();
+}
+
+hipError_t sno_bias_act(float* z, const float* bias, long long rows, int C, void* h, bool bf16, int act,
+                        hipStream_t st) {
+  const long long n = rows * C;
+  if (bf16) hipLaunchKernelGGL(k_bias_act<__bf16>, grid1(n), dim3(256), 0, st, z, bias, n, C, (__bf16*)h, act);
+  else hipLaunchKernelGGL(k_bias_act<float>, grid1(n), dim3(256), 0, st, z, bias, n, C, (float*)h, act);
+  return hipGetLastError();
+}
+
+hipError_t sno_project_softmax(const void* h, const float* wp, const float* bp, int batch, int npix,
+                               int C, bool bf16, float* rho, hipStream_t st) {
+  if (bf16)
+    hipLaunchKernelGGL(k_project_softmax<__bf16>, dim3(batch), dim3(256), 0, st, (const __bf16*)h, wp, bp,
+                       npix, C, rho);
+  else
+    hipLaunchKernelGGL(k_project_softmax<float>, dim3(batch), dim3(256), 0, st, (const float*)h, wp, bp,
+                       npix, C, rho);
+  return hipGetLastError();
+}
+
+hipError_t sno_loss_grad(const float* rho_hat, const float* rho, int batch, int npix, float* dq,
+                         double* loss_per_sample, hipStream_t st) {
+  hipLaunchKernelGGL(k_loss_grad, dim3(batch), dim3(256), 0, st, rho_hat, rho, batch, npix, dq,
+                     loss_per_sample);
+  return hipGetLastError();
+}
+
+hipError_t sno_project_backward(const float* dq, const void* h, const float* wp, int batch, int npix,
+                                int C, bool bf16, float* dh, float* partials, int nparts,
+                                hipStream_t st) {
+  const long long rows = (long long)batch * npix;
+  if (bf16)
+    hipLaunchKernelGGL(k_project_backward<__bf16>, dim3(nparts), dim3(256), 0, st, dq, (const __bf16*)h,
+                       wp, rows, C, dh, partials);
+  else
+    hipLaunchKernelGGL(k_project_backward<float>, dim3(nparts), dim3(256), 0, st, dq, (const float*)h, wp,
+                       rows, C, dh, partials);
+  return hipGetLastError();
+}
+
+hipError_t sno_gelu_backward(const float* dh, const float* z, long long n, void* dz, bool bf16,
+                             hipStream_t st) {
+  if (bf16) hipLaunchKernelGGL(k_gelu_backward<__bf16>, grid1(n), dim3(256), 0, st, dh, z, n, (__bf16*)dz);
+  else hipLaunchKernelGGL(k_gelu_backward<float>, grid1(n), dim3(256), 0, st, dh, z, n, (float*)dz);
+  return hipGetLastError();
+}
+
+hipError_t sno_colsum(const void* x, bool bf16, long long rows, int C, float* partials, int nparts,
+                      hipStream_t st) {
+  if (bf16)
+    hipLaunchKernelGGL(k_colsum<__bf16>, dim3(nparts), dim3(256), 0, st, (const __bf16*)x, rows, C, partials);
+  else
+    hipLaunchKernelGGL(k_colsum<float>, dim3(nparts), dim3(256), 0, st, (const float*)x, rows, C, partials);
+  return hipGetLastError();
+}
+
+hipError_t sno_reduce_partials(const float* partials, int nparts, int len, float* out, bool accumulate,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partials, grid1(len), dim3(256), 0, st, partials, nparts, len, out,
+                     accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t sno_cast(const float* src, void* dst, long long n, bool bf16, hipStream_t st) {
+  if (bf16) hipLaunchKernelGGL(k_cast<__bf16>, grid1(n), dim3(256), 0, st, src, (__bf16*)dst, n);
+  else hipLaunchKernelGGL(k_cast<float>, grid1(n), dim3(256), 0, st, src, (float*)dst, n);
+  return hipGetLastError();
+}
+
+hipError_t sno_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1,
+                    float b2, float eps, float c1, float c2, void* copy, bool bf16, hipStream_t st) {
+  if (bf16)
+    hipLaunchKernelGGL(k_adam<__bf16>, grid1(n), dim3(256), 0, st, p, g, m, v, n, lr, b1, b2, eps, c1, c2,
+                       (__bf16*)copy);
+  else
+    hipLaunchKernelGGL(k_adam<float>, grid1(n), dim3(256), 0, st, p, g, m, v, n, lr, b1, b2, eps, c1, c2,
+                       (float*)copy);
+  return hipGetLastError();
+}
+
+hipError_t sno_fill(float* p, long long n, float v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, grid1(n), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace qhd

@@ -82,9 +82,25 @@ class qhd_kernel_timing(ctypes.Structure):
     ]
 
 
+QHD_SNO_BF16, QHD_SNO_FP32 = 0, 1
+
+
+class qhd_sno_desc(ctypes.Structure):
+    _fields_ = [
+        ("grid", ctypes.c_int32),
+        ("width", ctypes.c_int32),
+        ("modes", ctypes.c_int32),
+        ("layers", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("train", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
 _lib = None
 
-# every entry point declared in include/qhd.h, with its ctypes signature
+# every entry point declared in include/qhd.h and include/qhd_sno.h, with its ctypes signature
 _SIGNATURES = {
     "qhd_plan_create": (ctypes.c_int, [ctypes.POINTER(qhd_instance), ctypes.c_int32,
                                        ctypes.POINTER(qhd_plan_opts), ctypes.POINTER(ctypes.c_void_p)]),
@@ -101,6 +117,16 @@ _SIGNATURES = {
     "qhd_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "qhd_last_error": (ctypes.c_char_p, []),
     "qhd_version": (ctypes.c_char_p, []),
+    "qhd_sno_create": (ctypes.c_int, [ctypes.POINTER(qhd_sno_desc), ctypes.POINTER(ctypes.c_void_p)]),
+    "qhd_sno_param_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "qhd_sno_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "qhd_sno_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "qhd_sno_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "qhd_sno_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p]),
+    "qhd_sno_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
+    "qhd_sno_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 
@@ -189,6 +215,46 @@ def qhd_kernel_timings(plan: int, cap: int = 64):
 
 def qhd_plan_destroy(plan: int):
     _check(load_library().qhd_plan_destroy(plan))
+
+
+def qhd_sno_create(desc: qhd_sno_desc) -> int:
+    out = ctypes.c_void_p()
+    _check(load_library().qhd_sno_create(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def qhd_sno_param_count(sno: int) -> int:
+    v = ctypes.c_int64()
+    _check(load_library().qhd_sno_param_count(sno, ctypes.byref(v)))
+    return v.value
+
+
+def qhd_sno_get_params(sno: int, host_ptr: int):
+    _check(load_library().qhd_sno_get_params(sno, host_ptr))
+
+
+def qhd_sno_set_params(sno: int, host_ptr: int):
+    _check(load_library().qhd_sno_set_params(sno, host_ptr))
+
+
+def qhd_sno_forward(sno: int, f_ptr: int, batch: int, rho_ptr: int, stream: int):
+    _check(load_library().qhd_sno_forward(sno, f_ptr, batch, rho_ptr, stream))
+
+
+def qhd_sno_backward(sno: int, f_ptr: int, target_ptr: int, batch: int, grad_host_ptr: int,
+                     stream: int) -> float:
+    loss = ctypes.c_double()
+    _check(load_library().qhd_sno_backward(sno, f_ptr, target_ptr, batch, ctypes.byref(loss),
+                                           grad_host_ptr or None, stream))
+    return loss.value
+
+
+def qhd_sno_step(sno: int, lr: float, stream: int):
+    _check(load_library().qhd_sno_step(sno, lr, stream))
+
+
+def qhd_sno_destroy(sno: int):
+    _check(load_library().qhd_sno_destroy(sno))
 
 
 # ------------------------------------------------------------------------------------

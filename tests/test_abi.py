@@ -1,6 +1,6 @@
 """C-ABI library checks that need no GPU: it loads, exports every symbol that
-include/qhd.h declares, and rejects invalid descriptors in its host-only
-validation layer before touching any device."""
+include/qhd.h and include/qhd_sno.h declare, and rejects invalid descriptors in
+its host-only validation layer before touching any device."""
 import ctypes
 import os
 import re
@@ -11,19 +11,22 @@ import pytest
 from paper_2303_01471_amd import qhd as q
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "qhd.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("qhd.h", "qhd_sno.h")]
 
 
 def declared_symbols():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(qhd_[a-z_]+)\s*\(", text)))
+    out = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        out |= set(re.findall(r"\b(qhd_[a-z_]+)\s*\(", text))
+    return sorted(out)
 
 
 def test_library_exports_every_declared_symbol():
     lib = q.load_library()
     syms = declared_symbols()
     assert "qhd_plan_create" in syms and "qhd_evolve" in syms and "qhd_observe" in syms
+    assert "qhd_sno_forward" in syms and "qhd_sno_backward" in syms
     for s in syms:
         assert hasattr(lib, s), f"libqhd.so does not export {s}"
         assert s in q._SIGNATURES, f"binding has no signature for {s}"

@@ -1,0 +1,194 @@
+"""The surrogate's HIP forward / backward / Adam kernels against the FP64 CPU
+reference (oracle/sno_reference.py), through the C ABI of include/qhd_sno.h.
+
+FP32 mode checks the kernels' arithmetic tightly (FP32 operands, FP32
+accumulation on the matrix cores); BF16 mode (the training precision) is held
+to error bounds of BF16 rounding."""
+import numpy as np
+import pytest
+
+from gpu_helpers import note
+from oracle import sno_reference as ref
+from paper_2303_01471_amd import qhd as q
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    q.load_library()
+
+
+def _inputs(cfg, B, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f = rng.standard_normal((B, cfg.S, cfg.S)) * 2.0 + 1.0
+    rho = rng.dirichlet(np.ones(cfg.S * cfg.S), size=B).reshape(B, cfg.S, cfg.S)
+    return f, rho
+
+
+def _net(cfg, B, precision, train=True):
+    from paper_2303_01471_amd.sno import Surrogate
+    return Surrogate(grid=cfg.S, width=cfg.C, modes=cfg.M, layers=cfg.L, max_batch=B, precision=precision,
+                     train=train, seed=5)
+
+
+def _dev(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+def _block_errors(cfg, g, gref):
+    """Relative error per parameter block.  The output bias bp is left out: the
+    softmax is invariant under a constant shift of the logits, so its exact
+    gradient is zero (checked absolutely by the callers)."""
+    out, o = {}, 0
+    for name, shape in ref.param_layout(cfg):
+        n = int(np.prod(shape))
+        a, b = g[o:o + n].astype(np.float64), gref[o:o + n]
+        if name != "bp":
+            out[name] = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+        o += n
+    return out
+
+
+CASES = [ref.Config(S=32, C=8, M=4, L=2), ref.Config(S=64, C=16, M=8, L=1), ref.Config(S=128, C=32, M=16, L=4)]
+
+
+@pytest.mark.parametrize("cfg", CASES, ids=lambda c: f"S{c.S}C{c.C}M{c.M}L{c.L}")
+def test_forward_fp32_matches_reference(cfg):
+    import torch
+    B = 3
+    note(f"case: surrogate forward fp32 {cfg}")
+    p = ref.random_params(cfg, 21).astype(np.float32)
+    f, _ = _inputs(cfg, B, 22)
+    net = _net(cfg, B, "fp32", train=False)
+    try:
+        net.set_params(p)
+        rho = net.forward(_dev(f, torch.float64))
+        torch.cuda.synchronize()
+        got = rho.cpu().numpy().astype(np.float64)
+    finally:
+        net.close()
+    want = ref.forward(p.astype(np.float64), f, cfg)
+    rel = np.max(np.abs(got - want)) / np.max(want)
+    note(f"  max|drho|/max rho = {rel:.2e}; sums {got.reshape(B, -1).sum(axis=1)}")
+    assert rel < 1e-4
+    assert np.allclose(got.reshape(B, -1).sum(axis=1), 1.0, atol=1e-5)
+
+
+@pytest.mark.parametrize("cfg", CASES, ids=lambda c: f"S{c.S}C{c.C}M{c.M}L{c.L}")
+def test_backward_fp32_matches_reference(cfg):
+    import torch
+    B = 2
+    note(f"case: surrogate backward fp32 {cfg}")
+    p = ref.random_params(cfg, 31).astype(np.float32)
+    f, rho = _inputs(cfg, B, 32)
+    net = _net(cfg, B, "fp32")
+    try:
+        net.set_params(p)
+        loss, g = net.backward(_dev(f, torch.float64), _dev(rho, torch.float32), want_grad=True)
+    finally:
+        net.close()
+    lref, gref = ref.backward(p.astype(np.float64), f, rho.astype(np.float32).astype(np.float64), cfg)
+    errs = _block_errors(cfg, g, gref)
+    note(f"  loss {loss:.8f} vs {lref:.8f}; worst block {max(errs, key=errs.get)} {max(errs.values()):.2e}")
+    assert abs(loss - lref) <= 1e-5 * lref
+    assert max(errs.values()) < 1e-4, errs
+    assert abs(g[-1]) < 1e-6
+
+
+def test_bf16_forward_and_gradient_within_rounding_bounds():
+    import torch
+    cfg = ref.Config(S=128, C=32, M=16, L=4)
+    B = 2
+    note("case: surrogate bf16 forward/backward, production shape")
+    p = ref.random_params(cfg, 41).astype(np.float32)
+    f, rho = _inputs(cfg, B, 42)
+    net = _net(cfg, B, "bf16")
+    try:
+        net.set_params(p)
+        out = net.forward(_dev(f, torch.float64))
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().astype(np.float64)
+        loss, g = net.backward(_dev(f, torch.float64), _dev(rho, torch.float32), want_grad=True)
+    finally:
+        net.close()
+    want = ref.forward(p.astype(np.float64), f, cfg)
+    l1 = np.abs(got - want).reshape(B, -1).sum(axis=1)
+    lref, gref = ref.backward(p.astype(np.float64), f, rho.astype(np.float32).astype(np.float64), cfg)
+    cos = float(g.astype(np.float64) @ gref / (np.linalg.norm(g) * np.linalg.norm(gref)))
+    errs = _block_errors(cfg, g, gref)
+    note(f"  L1(rho_bf16, rho_fp64) = {l1}; loss {loss:.6f} vs {lref:.6f}; grad cosine {cos:.6f}; "
+         f"worst block {max(errs, key=errs.get)} {max(errs.values()):.2e}")
+    assert np.all(l1 < 0.05)
+    assert abs(loss - lref) < 0.02 * lref
+    assert cos > 0.99
+
+
+def test_adam_step_matches_closed_form_first_step():
+    import torch
+    cfg = ref.Config(S=32, C=8, M=4, L=1)
+    B = 2
+    p = ref.random_params(cfg, 51).astype(np.float32)
+    f, rho = _inputs(cfg, B, 52)
+    net = _net(cfg, B, "fp32")
+    try:
+        net.set_params(p)
+        _, g = net.backward(_dev(f, torch.float64), _dev(rho, torch.float32), want_grad=True)
+        lr = 1e-3
+        net.step(lr)
+        torch.cuda.synchronize()
+        p1 = net.get_params()
+    finally:
+        net.close()
+    # first Adam step: bias-corrected moments are g and g^2
+    g64 = g.astype(np.float64)
+    want = p.astype(np.float64) - lr * g64 / (np.abs(g64) + 1e-8)
+    assert np.max(np.abs(p1 - want)) < 1e-6
+
+
+def test_training_reduces_loss_on_fixed_batch():
+    import torch
+    cfg = ref.Config(S=32, C=8, M=4, L=2)
+    B = 8
+    f, rho = _inputs(cfg, B, 61)
+    # a smooth target so that the network can fit it
+    yy, xx = np.meshgrid(np.arange(32), np.arange(32), indexing="ij")
+    tgt = np.exp(-((xx - 12) ** 2 + (yy - 20) ** 2) / 30.0)
+    rho = np.broadcast_to(tgt / tgt.sum(), (B, 32, 32)).astype(np.float32)
+    net = _net(cfg, B, "bf16")
+    try:
+        fd, rd = _dev(f, torch.float64), _dev(rho, torch.float32)
+        first, _ = net.backward(fd, rd)
+        for _ in range(150):
+            net.backward(fd, rd)
+            net.step(3e-3)
+        last, _ = net.backward(fd, rd)
+    finally:
+        net.close()
+    note(f"  loss {first:.4f} -> {last:.4f}")
+    assert last < 0.5 * first
+
+
+def test_error_paths():
+    import torch
+    cfg = ref.Config(S=32, C=8, M=4, L=1)
+    net = _net(cfg, 2, "bf16", train=False)
+    try:
+        f, rho = _inputs(cfg, 2, 71)
+        fd, rd = _dev(f, torch.float64), _dev(rho, torch.float32)
+        with pytest.raises(q.QHDError) as e:
+            net.backward(fd, rd)
+        assert e.value.status == q.QHD_ESTATE
+        with pytest.raises(q.QHDError) as e:
+            net.step(1e-3)
+        assert e.value.status == q.QHD_ESTATE
+        with pytest.raises(q.QHDError) as e:
+            q.qhd_sno_forward(net.handle, fd.data_ptr(), 3, rd.data_ptr(), 0)
+        assert e.value.status == q.QHD_EINVAL
+    finally:
+        net.close()
