@@ -353,8 +353,8 @@ qhd_status backward(qhd_sno_s* m, const float* target, int B, hipStream_t st) {
                 "projection reduce"));
   for (int l = m->L - 1; l >= 0; --l) {
     ST_TRY(check(m, m->dz, rows * C * es, "dz"));
-    ST_TRY(launch(m, DEV(m, sno_gelu_backward(m->dh, m->z[l], rows * C, m->dz, m->bf16, st)), "GELU backward"));
-    ST_TRY(launch(m, DEV(m, sno_colsum(m->dz, m->bf16, rows, C, m->partials, nparts, st)), "bias gradient"));
+    ST_TRY(launch(m, DEV(m, sno_gelu_backward(m->dh, m->z[l], rows, C, m->dz, m->bf16, m->partials, nparts, st)),
+                  "GELU backward"));
     ST_TRY(launch(m, DEV(m, sno_reduce_partials(m->partials, nparts, C, m->grad + m->o_b[l], false, st)),
                   "bias reduce"));
     ST_TRY(splitk(m, m->dz, C, m->h[l], C, rows, m->grad + m->o_w[l], st));

@@ -47,8 +47,9 @@ hipError_t sno_loss_grad(const float* rho_hat, const float* rho, int batch, int 
 hipError_t sno_project_backward(const float* dq, const void* h, const float* wp, int batch, int npix,
                                 int C, bool bf16, float* dh, float* partials, int nparts,
                                 hipStream_t st);
-hipError_t sno_gelu_backward(const float* dh, const float* z, long long n, void* dz, bool bf16,
-                             hipStream_t st);
+// dz = dh * GELU'(z) (stored as T) and nparts x C partial column sums of dz (FP32, before rounding)
+hipError_t sno_gelu_backward(const float* dh, const float* z, long long rows, int C, void* dz, bool bf16,
+                             float* partials, int nparts, hipStream_t st);
 hipError_t sno_colsum(const void* x, bool bf16, long long rows, int C, float* partials, int nparts,
                       hipStream_t st);
 hipError_t sno_reduce_partials(const float* partials, int nparts, int len, float* out, bool accumulate,

@@ -165,12 +165,32 @@ __global__ void __launch_bounds__(256) k_project_backward(const float* __restric
   }
 }
 
+// dz = dh * GELU'(z), stored as T, and per-block partial column sums of dz taken
+// from the FP32 products before rounding (the bias gradient: its terms cancel
+// heavily, since the softmax gradient sums to zero over each sample)
 template <typename T>
-__global__ void k_gelu_backward(const float* __restrict__ dh, const float* __restrict__ z, long long n,
-                                T* __restrict__ dz) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  dz[e] = (T)(dh[e] * gelu_grad(z[e]));
+__global__ void __launch_bounds__(256) k_gelu_backward(const float* __restrict__ dh, const float* __restrict__ z,
+                                                       long long rows, int C, T* __restrict__ dz,
+                                                       float* __restrict__ partials) {
+  __shared__ double sh[256];
+  const int c = threadIdx.x % C, r0 = threadIdx.x / C, rstep = 256 / C;
+  const long long per = (rows + gridDim.x - 1) / gridDim.x;
+  const long long beg = (long long)blockIdx.x * per;
+  const long long end = beg + per < rows ? beg + per : rows;
+  float acc = 0.0f;
+  for (long long r = beg + r0; r < end; r += rstep) {
+    const long long e = r * C + c;
+    const float v = dh[e] * gelu_grad(z[e]);
+    dz[e] = (T)v;
+    acc += v;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < C) {
+    double s = 0.0;
+    for (int k = 0; k < rstep; ++k) s += sh[threadIdx.x + k * C];
+    partials[(long long)blockIdx.x * C + threadIdx.x] = (float)s;
+  }
 }
 
 template <typename T>
@@ -277,10 +297,14 @@ hipError_t sno_project_backward(const float* dq, const void* h, const float* wp,
   return hipGetLastError();
 }
 
-hipError_t sno_gelu_backward(const float* dh, const float* z, long long n, void* dz, bool bf16,
-                             hipStream_t st) {
-  if (bf16) hipLaunchKernelGGL(k_gelu_backward<__bf16>, grid1(n), dim3(256), 0, st, dh, z, n, (__bf16*)dz);
-  else hipLaunchKernelGGL(k_gelu_backward<float>, grid1(n), dim3(256), 0, st, dh, z, n, (float*)dz);
+hipError_t sno_gelu_backward(const float* dh, const float* z, long long rows, int C, void* dz, bool bf16,
+                             float* partials, int nparts, hipStream_t st) {
+  if (bf16)
+    hipLaunchKernelGGL(k_gelu_backward<__bf16>, dim3(nparts), dim3(256), 0, st, dh, z, rows, C, (__bf16*)dz,
+                       partials);
+  else
+    hipLaunchKernelGGL(k_gelu_backward<float>, dim3(nparts), dim3(256), 0, st, dh, z, rows, C, (float*)dz,
+                       partials);
   return hipGetLastError();
 }
 
