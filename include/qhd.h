@@ -82,9 +82,17 @@ typedef struct {
                               this; <= 0 selects 1e-3                                  */
   int32_t timing_stride;   /* with QHD_OPT_TIME_PASSES: time one sub-step in this many
                               (<= 0 selects 16)                                        */
+  const char *tune_cache;  /* path of a text tuning cache, or NULL.  Entries found for
+                              a shape class are used; with QHD_OPT_AUTOTUNE, classes
+                              without an entry are tuned and appended.  A missing or
+                              unreadable file is treated as empty                      */
 } qhd_plan_opts;
 
 #define QHD_OPT_TIME_PASSES 0x1u /* record HIP events around sampled pass launches   */
+#define QHD_OPT_AUTOTUNE 0x2u    /* at plan creation, time the column-pass variants and
+                                    the grid sizes of every 2-D shape class on its own
+                                    batch and keep the fastest (a few ms per class)     */
+#define QHD_OPT_NO_GRAPH 0x4u    /* never replay captured step chunks (see qhd_evolve)  */
 
 typedef struct qhd_plan_s *qhd_plan;
 
@@ -108,6 +116,17 @@ typedef struct {
   double points;        /* grid points processed by the timed launches                   */
   double bytes_per_point; /* algorithmic HBM bytes moved per grid point by this kernel   */
 } qhd_kernel_timing;
+
+/* Launch configuration of one shape class of a plan (instances with equal ndim
+ * and n), as chosen at plan creation. */
+typedef struct {
+  int32_t ndim, n[3];
+  int32_t members;       /* instances in the class                                      */
+  int32_t col_variant;   /* 2-D column pass: 1 staged through LDS, 2 tile-wave          */
+  int32_t grid_cap_row;  /* workgroup caps of the row (x) and column passes             */
+  int32_t grid_cap_col;
+  int32_t tuned;         /* 1 if the autotuner chose them while creating this plan      */
+} qhd_class_info;
 
 /* Create a plan for `batch` instances.  Validates every descriptor first (no
  * device work happens for an invalid batch), then allocates all device memory
@@ -134,8 +153,20 @@ qhd_status qhd_set_steps_done(qhd_plan plan, int32_t i, int64_t j);
 /* Advance every instance by min(max_steps, remaining) steps (max_steps < 0:
  * to the end).  Asynchronous on `stream`; allocates nothing.  Between evolve
  * calls the state may carry a pending half step; the result does not depend on
- * how the steps are split into calls. */
+ * how the steps are split into calls.
+ * When every instance of the plan has the same number of steps left, whole
+ * chunks of steps are replayed from a HIP graph captured at plan creation (one
+ * launch per chunk instead of one per pass); the arithmetic is the same, so the
+ * results are bitwise identical to direct launches.  Not with
+ * QHD_OPT_TIME_PASSES or QHD_OPT_NO_GRAPH, and not while `stream` is itself being
+ * captured (the passes are then launched directly into the caller's capture). */
 qhd_status qhd_evolve(qhd_plan plan, int64_t max_steps, void *stream);
+
+/* Launch configuration: up to `cap` classes into out[], their number into
+ * *n_classes, and the steps per captured graph chunk into *graph_steps (0: no
+ * graph).  Host-only. */
+qhd_status qhd_plan_info(qhd_plan plan, qhd_class_info *out, int32_t cap, int32_t *n_classes,
+                         int32_t *graph_steps);
 
 /* Return every instance to step 0: UNIFORM instances get psi0 = N^{-1/2} again,
  * USER instances need a new qhd_set_state before the next evolve.  Potentials

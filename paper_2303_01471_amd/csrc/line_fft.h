@@ -27,6 +27,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace qhd {
 
 // ---------------------------------------------------------------------------------
@@ -224,6 +226,57 @@ struct Twiddles {
   }
 
   __device__ __forceinline__ void load(const double2* __restrict__ tab, int t) { load_stage<1>(tab, t); }
+
+  template <int STAGE>
+  __device__ __forceinline__ double2 get(int j) const { return w[STAGE - 1][j]; }
+};
+
+// The same twiddles read from LDS, laid out in lane order: for every stage s >= 1,
+// butterfly m and r = 1..R-1 there is a row of TPL entries, entry t holding lane
+// t's twiddle.  A lane keeps only its base address; each read is one ds_read_b128
+// with an immediate offset, and consecutive lanes read consecutive entries (no
+// bank conflicts).  Same values as Twiddles, so results are bitwise identical.
+template <int N, int P>
+struct TwiddlesLds {
+  using SP = StagePlan<N, P>;
+  static constexpr int kStages = SP::count();
+  static constexpr int kTPL = N / P;
+  // rows before stage s (s >= 1)
+  static constexpr int rows_before(int st) {
+    int c = 0;
+    for (int q = 1; q < st; ++q) c += (P / SP::radix(q)) * (SP::radix(q) - 1);
+    return c;
+  }
+  static constexpr int kRows = rows_before(kStages);
+  static constexpr int kEntries = kRows > 0 ? kRows * kTPL : 1;
+  const double2* tab;  // this lane's column of the table
+
+  // rows of stage ST: row (m, r) holds lane tt's W^{k r STEP}, k = (tt + m TPL) mod NS
+  template <int ST>
+  __device__ __forceinline__ static void fill_stage(const double2* __restrict__ g, double2* lds_tab) {
+    if constexpr (ST < kStages) {
+      constexpr int NS = SP::ns(ST), R = SP::radix(ST), NB = P / R, STEP = N / (NS * R);
+      constexpr int ROWS = NB * (R - 1), BASE = rows_before(ST);
+      for (int e = threadIdx.x; e < ROWS * kTPL; e += blockDim.x) {
+        const int j = e / kTPL, tt = e % kTPL;  // powers of two: shifts and masks
+        const int m = j / (R - 1), r = j - m * (R - 1) + 1;
+        const int k = (tt + m * kTPL) % NS;
+        lds_tab[BASE * kTPL + e] = g[(k * r * STEP) & (N - 1)];
+      }
+      fill_stage<ST + 1>(g, lds_tab);
+    }
+  }
+
+  // lds_tab: kEntries entries of LDS, filled from the global table W_N^j by the whole
+  // block (ends with a block barrier: call it where every thread of the block arrives)
+  __device__ __forceinline__ void load(const double2* __restrict__ global_tab, double2* lds_tab, int t) {
+    fill_stage<1>(global_tab, lds_tab);
+    __syncthreads();
+    tab = lds_tab + t;
+  }
+
+  template <int STAGE>
+  __device__ __forceinline__ double2 get(int j) const { return tab[(rows_before(STAGE) + j) * kTPL]; }
 };
 
 // One Stockham stage on the lane's registers.  If LAST, results stay in the
@@ -236,9 +289,8 @@ __device__ __forceinline__ void line_lds_sync() {
   else wave_lds_sync();
 }
 
-template <int N, int P, int S, int STAGE, bool BLOCK_SYNC = false>
-__device__ __forceinline__ void fft_stage(float2 (&reg)[P], int t, const Twiddles<N, P>& tw,
-                                          float2* __restrict__ lds) {
+template <int N, int P, int S, int STAGE, bool BLOCK_SYNC = false, typename TW>
+__device__ __forceinline__ void fft_stage(float2 (&reg)[P], int t, const TW& tw, float2* __restrict__ lds) {
   using SP = StagePlan<N, P>;
   constexpr int NS = SP::ns(STAGE);
   constexpr int R = SP::radix(STAGE);
@@ -253,7 +305,7 @@ __device__ __forceinline__ void fft_stage(float2 (&reg)[P], int t, const Twiddle
     if constexpr (STAGE > 0) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const double2 w = tw.w[STAGE - 1][m * (R - 1) + (r - 1)];
+        const double2 w = tw.template get<STAGE>(m * (R - 1) + (r - 1));
         u[r] = S < 0 ? cmul_fd(u[r], w) : cmul_fd_conj(u[r], w);
       }
     }
@@ -276,20 +328,40 @@ __device__ __forceinline__ void fft_stage(float2 (&reg)[P], int t, const Twiddle
   }
 }
 
-template <int N, int P, int S, bool BLOCK_SYNC, int STAGE = 0>
-__device__ __forceinline__ void line_fft_from(float2 (&reg)[P], int t, const Twiddles<N, P>& tw,
-                                              float2* __restrict__ lds) {
+template <int N, int P, int S, bool BLOCK_SYNC, int STAGE = 0, typename TW>
+__device__ __forceinline__ void line_fft_from(float2 (&reg)[P], int t, const TW& tw, float2* __restrict__ lds) {
   if constexpr (STAGE < StagePlan<N, P>::count()) {
     fft_stage<N, P, S, STAGE, BLOCK_SYNC>(reg, t, tw, lds);
     line_fft_from<N, P, S, BLOCK_SYNC, STAGE + 1>(reg, t, tw, lds);
   }
 }
 
-// Full unnormalised transform of one line, X_k = sum_m x_m e^{S 2 pi i m k / N}.
-template <int N, int P, int S, bool BLOCK_SYNC = false>
-__device__ __forceinline__ void line_fft(float2 (&reg)[P], int t, const Twiddles<N, P>& tw,
-                                         float2* __restrict__ lds) {
+// Full unnormalised transform of one line, X_k = sum_m x_m e^{S 2 pi i m k / N};
+// TW is Twiddles<N, P> or TwiddlesLds<N, P>.
+template <int N, int P, int S, bool BLOCK_SYNC = false, typename TW>
+__device__ __forceinline__ void line_fft(float2 (&reg)[P], int t, const TW& tw, float2* __restrict__ lds) {
   line_fft_from<N, P, S, BLOCK_SYNC, 0>(reg, t, tw, lds);
+}
+
+// Twiddle storage per line length: an LDS table for the long lines (register
+// pressure), per-lane registers for the short ones.
+template <int N, int P>
+using TwiddlesFor = typename std::conditional<(N >= 128), TwiddlesLds<N, P>, Twiddles<N, P>>::type;
+
+template <int N, int P>
+struct TwLdsSize {
+  static constexpr int value = N >= 128 ? TwiddlesLds<N, P>::kEntries : 1;
+};
+
+// load either kind (the LDS kind needs its table slot and a block-uniform call site)
+template <int N, int P>
+__device__ __forceinline__ void load_twiddles(Twiddles<N, P>& tw, const double2* __restrict__ g, double2*, int t) {
+  tw.load(g, t);
+}
+template <int N, int P>
+__device__ __forceinline__ void load_twiddles(TwiddlesLds<N, P>& tw, const double2* __restrict__ g, double2* l,
+                                              int t) {
+  tw.load(g, l, t);
 }
 
 // ---------------------------------------------------------------------------------

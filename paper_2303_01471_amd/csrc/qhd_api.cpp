@@ -110,6 +110,10 @@ struct ShapeClass {
   const double2* tw_y = nullptr;
   const double2* tw_z = nullptr;
   int fam_row = -1, fam_col = -1, fam_line = -1, fam_y = -1, fam_z = -1;
+  // launch configuration (defaults, a tuning-cache entry, or the autotuner's choice)
+  int col_variant = kColAuto;
+  int cap_row = 2048, cap_col = 2048;
+  bool tuned = false;
 };
 
 struct qhd_plan_s {
@@ -132,6 +136,11 @@ struct qhd_plan_s {
   double* host_results = nullptr;   // pinned, 3 per member of the largest class
   long long total_points = 0;
   int grid_cap = 2048;
+  std::string tune_cache;
+  // a chunk of graph_k steps of every class, captured at plan creation (see qhd_evolve)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_k = 0;
   // timing
   std::vector<Family> families;
   std::vector<Pending> pending;
@@ -164,6 +173,8 @@ void free_plan(qhd_plan p) {
     (void)hipEventDestroy(pe.stop);
   }
   for (auto e : p->free_events) (void)hipEventDestroy(e);
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->internal) (void)hipStreamDestroy(p->internal);
   delete p;
 }
@@ -199,6 +210,195 @@ qhd_status push_inst(qhd_plan p, int i) {
   const int pos = p->pos_of[i];
   HIP_TRY(hipMemcpyAsync(c.dev + pos, &c.host[pos], sizeof(InstDev), hipMemcpyHostToDevice, p->internal));
   HIP_TRY(hipStreamSynchronize(p->internal));
+  return QHD_OK;
+}
+
+// Launch sub-steps s = 0..S-1 of every class (lim: steps each member takes in this
+// call; kmax: the step cap the kernels apply) and the commit that advances the
+// device step counters by min(kmax, remaining).
+qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<long long>>& lim,
+                         long long max_steps, hipStream_t stream, bool timing) {
+  const int stride = p->opts.timing_stride;
+  auto timed_launch = [&](int fam, double points, bool sample, auto&& fn) -> hipError_t {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (sample) {
+      a = take_event(p);
+      b = take_event(p);
+      if (a && b) (void)hipEventRecord(a, stream);
+    }
+    hipError_t r = fn();
+    if (sample && a && b) {
+      (void)hipEventRecord(b, stream);
+      p->pending.push_back({a, b, fam, points});
+    }
+    return r;
+  };
+  for (long long s = 0; s < S; ++s) {
+    const bool sample = timing && (s % stride == 0);
+    for (size_t ci = 0; ci < p->classes.size(); ++ci) {
+      ShapeClass& c = p->classes[ci];
+      int nact = 0;
+      for (size_t k = 0; k < c.members.size(); ++k)
+        if (lim[ci][k] > s) nact = (int)k + 1;
+      if (nact == 0) continue;
+      const double pts = (double)nact * (double)c.points;
+      if (c.ndim == 3) {
+        HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
+          return launch_row_pass_2d(c.nx, c.ny * c.nz, c.dev, nact, c.psi, c.f, c.tw_x, (int)s,
+                                    max_steps, p->grid_cap, stream);
+        }));
+        HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
+          return launch_ypass_3d(c.nx, c.ny, c.nz, -1, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
+                                 p->grid_cap, stream);
+        }));
+        HIP_TRY(timed_launch(c.fam_z, pts, sample, [&] {
+          return launch_zpass_3d(c.nx, c.ny, c.nz, c.dev, nact, c.psi, c.tw_z, (int)s, max_steps,
+                                 p->grid_cap, stream);
+        }));
+        HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
+          return launch_ypass_3d(c.nx, c.ny, c.nz, +1, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
+                                 p->grid_cap, stream);
+        }));
+      } else if (c.ndim == 2) {
+        HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
+          return launch_row_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, (int)s, max_steps,
+                                    c.cap_row, stream);
+        }));
+        HIP_TRY(timed_launch(c.fam_col, pts, sample, [&] {
+          return launch_col_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
+                                    c.cap_col, c.col_variant, stream);
+        }));
+      } else {
+        HIP_TRY(timed_launch(c.fam_line, pts, sample, [&] {
+          return launch_line_pass_1d(c.nx, c.dev, nact, c.psi, c.f, c.tw_x, (int)s, max_steps,
+                                     p->grid_cap, stream);
+        }));
+      }
+    }
+  }
+  for (auto& c : p->classes) HIP_TRY(launch_commit(c.dev, (int)c.members.size(), max_steps, stream));
+  return QHD_OK;
+}
+
+// ---- launch tuning ----------------------------------------------------------------
+
+// Tuning-cache lines: "qhd-tune 1 <arch> <nx> <ny> <members_pow2> <col_variant> <cap_row> <cap_col>"
+std::string tune_key(const std::string& arch, const ShapeClass& c) {
+  int m = 1;
+  while (m < (int)c.members.size()) m <<= 1;
+  char buf[160];
+  snprintf(buf, sizeof buf, "qhd-tune 1 %s %d %d %d", arch.c_str(), c.nx, c.ny, m);
+  return buf;
+}
+
+bool tune_lookup(const std::string& path, const std::string& key, ShapeClass& c) {
+  FILE* fh = fopen(path.c_str(), "r");
+  if (!fh) return false;
+  char line[256];
+  bool found = false;
+  while (fgets(line, sizeof line, fh)) {
+    const size_t k = key.size();
+    if (strncmp(line, key.c_str(), k) != 0 || line[k] != ' ') continue;
+    int v = 0, cr = 0, cc = 0;
+    if (sscanf(line + k, "%d %d %d", &v, &cr, &cc) == 3 && v >= kColAuto && v <= kColTileWave && cr >= 0 &&
+        cc >= 0) {
+      c.col_variant = v;  // the last matching line wins
+      c.cap_row = cr;
+      c.cap_col = cc;
+      found = true;
+    }
+  }
+  fclose(fh);
+  return found;
+}
+
+void tune_append(const std::string& path, const std::string& key, const ShapeClass& c, double us_row,
+                 double us_col) {
+  FILE* fh = fopen(path.c_str(), "a");
+  if (!fh) return;
+  fprintf(fh, "%s %d %d %d  # row %.2f us, col %.2f us\n", key.c_str(), c.col_variant, c.cap_row, c.cap_col,
+          us_row, us_col);
+  fclose(fh);
+}
+
+// mean duration (us) of `reps` launches after two untimed ones; negative on error
+template <typename F>
+double time_launches(hipStream_t st, hipEvent_t a, hipEvent_t b, int reps, F&& fn) {
+  for (int k = 0; k < 2; ++k)
+    if (fn() != hipSuccess) return -1.0;
+  if (hipEventRecord(a, st) != hipSuccess) return -1.0;
+  for (int k = 0; k < reps; ++k)
+    if (fn() != hipSuccess) return -1.0;
+  if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) return -1.0;
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.0;
+  return 1e3 * ms / reps;
+}
+
+// Time the row pass over grid caps and the column pass over variants x grid caps on
+// the class's own buffers (one sub-step with every member active), keep the
+// fastest.  The state is overwritten; the caller restores it.
+qhd_status autotune_class(qhd_plan p, ShapeClass& c, double& us_row, double& us_col) {
+  const int m = (int)c.members.size();
+  static const int caps[] = {512, 1024, 2048, 4096, 8192};
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(QHD_EDEVICE, "hipEventCreate failed");
+  }
+  const int reps = 4;
+  us_row = 1e30;
+  us_col = 1e30;
+  int best_row = c.cap_row, best_col = c.cap_col, best_var = c.col_variant;
+  bool ok = true;
+  for (int cap : caps) {
+    const double t = time_launches(p->internal, a, b, reps, [&] {
+      return launch_row_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.f, c.tw_x, 0, 1, cap, p->internal);
+    });
+    if (t < 0) ok = false;
+    else if (t < us_row) us_row = t, best_row = cap;
+  }
+  std::vector<int> variants = {kColStaged};
+  if (col_variant_resolve(c.ny, kColTileWave) == kColTileWave) variants.push_back(kColTileWave);
+  for (int v : variants)
+    for (int cap : caps) {
+      const double t = time_launches(p->internal, a, b, reps, [&] {
+        return launch_col_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.tw_y, 0, 1, cap, v, p->internal);
+      });
+      if (t < 0) ok = false;
+      else if (t < us_col) us_col = t, best_col = cap, best_var = v;
+    }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (!ok) return fail(QHD_EDEVICE, "autotune launch failed: %s", hipGetErrorString(hipGetLastError()));
+  c.cap_row = best_row;
+  c.cap_col = best_col;
+  c.col_variant = best_var;
+  c.tuned = true;
+  return QHD_OK;
+}
+
+// Capture graph_k steps of every class (all members active) plus the commit.
+qhd_status build_step_graph(qhd_plan p, int k) {
+  std::vector<std::vector<long long>> lim(p->classes.size());
+  for (size_t ci = 0; ci < p->classes.size(); ++ci) lim[ci].assign(p->classes[ci].members.size(), k);
+  HIP_TRY(hipStreamBeginCapture(p->internal, hipStreamCaptureModeThreadLocal));
+  qhd_status st = enqueue_steps(p, k, lim, k, p->internal, false);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(p->internal, &g);
+  if (st != QHD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(QHD_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(QHD_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+  }
+  p->graph = g;
+  p->graph_k = k;
   return QHD_OK;
 }
 
@@ -407,6 +607,55 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
     }
   }
   for (int i = 0; i < batch; ++i) p->state_ready[i] = inst[i].init_kind == QHD_INIT_UNIFORM;
+  // launch configuration per class: tuning cache, else autotune (QHD_OPT_AUTOTUNE), else defaults
+  if (p->opts.tune_cache) p->tune_cache = p->opts.tune_cache;
+  p->opts.tune_cache = nullptr;  // the caller's string is not kept
+  {
+    std::string arch = "gfx";
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
+    for (auto& c : arch) if (c == ' ' || c == ':') c = '_';
+    bool refill = false;
+    const bool env_cap = std::getenv("QHD_GRID_CAP") != nullptr;
+    for (auto& c : p->classes) {
+      c.cap_row = c.cap_col = p->grid_cap;
+      if (c.ndim != 2) continue;
+      if (!env_cap) {
+        // measured defaults (uniform batches of 256 instances per size on MI355X)
+        c.cap_row = c.nx >= 512 ? 8192 : (c.nx >= 256 ? 4096 : 1024);
+        c.cap_col = c.ny >= 512 ? 4096 : (c.ny >= 256 ? 2048 : 1024);
+      }
+      const std::string key = tune_key(arch, c);
+      if (!p->tune_cache.empty() && tune_lookup(p->tune_cache, key, c)) continue;
+      if (!(p->opts.flags & QHD_OPT_AUTOTUNE)) continue;
+      double us_row = 0.0, us_col = 0.0;
+      qhd_status st = autotune_class(p, c, us_row, us_col);
+      if (st != QHD_OK) return bail(st);
+      refill = true;
+      if (!p->tune_cache.empty()) tune_append(p->tune_cache, key, c, us_row, us_col);
+    }
+    if (refill) {
+      for (auto& c : p->classes) {
+        e = launch_fill_psi(c.psi, (long long)c.members.size() * c.points,
+                            (float)(1.0 / std::sqrt((double)c.points)), p->internal);
+        if (e != hipSuccess) {
+          fail(QHD_EDEVICE, "state fill after tuning: %s", hipGetErrorString(e));
+          return bail(QHD_EDEVICE);
+        }
+      }
+    }
+  }
+  // step-chunk graph for plans whose instances all take the same number of steps
+  {
+    long long n0 = inst[0].nsteps;
+    bool same = true;
+    for (int i = 1; i < batch; ++i) same = same && inst[i].nsteps == n0;
+    const int k = (int)std::min<long long>(64, n0);
+    if (same && k >= 8 && !(p->opts.flags & (QHD_OPT_NO_GRAPH | QHD_OPT_TIME_PASSES))) {
+      qhd_status st = build_step_graph(p, k);
+      if (st != QHD_OK) return bail(st);
+    }
+  }
   e = hipMalloc(&p->staging_f, sizeof(double) * max_pts);
   if (e == hipSuccess) e = hipMalloc(&p->staging_psi, sizeof(float2) * max_pts);
   if (e == hipSuccess) e = hipMalloc(&p->amin_val, sizeof(double));
@@ -519,67 +768,27 @@ qhd_status qhd_evolve(qhd_plan p, int64_t max_steps, void* stream_v) {
     }
   }
   const bool timing = (p->opts.flags & QHD_OPT_TIME_PASSES) != 0;
-  const int stride = p->opts.timing_stride;
-  auto timed_launch = [&](int fam, double points, bool sample, auto&& fn) -> hipError_t {
-    hipEvent_t a = nullptr, b = nullptr;
-    if (sample) {
-      a = take_event(p);
-      b = take_event(p);
-      if (a && b) (void)hipEventRecord(a, stream);
-    }
-    hipError_t r = fn();
-    if (sample && a && b) {
-      (void)hipEventRecord(b, stream);
-      p->pending.push_back({a, b, fam, points});
-    }
-    return r;
-  };
-  for (long long s = 0; s < S; ++s) {
-    const bool sample = timing && (s % stride == 0);
-    for (size_t ci = 0; ci < p->classes.size(); ++ci) {
-      ShapeClass& c = p->classes[ci];
-      int nact = 0;
-      for (size_t k = 0; k < c.members.size(); ++k)
-        if (lim[ci][k] > s) nact = (int)k + 1;
-      if (nact == 0) continue;
-      const double pts = (double)nact * (double)c.points;
-      if (c.ndim == 3) {
-        HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
-          return launch_row_pass_2d(c.nx, c.ny * c.nz, c.dev, nact, c.psi, c.f, c.tw_x, (int)s,
-                                    max_steps, p->grid_cap, stream);
-        }));
-        HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
-          return launch_ypass_3d(c.nx, c.ny, c.nz, -1, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
-                                 p->grid_cap, stream);
-        }));
-        HIP_TRY(timed_launch(c.fam_z, pts, sample, [&] {
-          return launch_zpass_3d(c.nx, c.ny, c.nz, c.dev, nact, c.psi, c.tw_z, (int)s, max_steps,
-                                 p->grid_cap, stream);
-        }));
-        HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
-          return launch_ypass_3d(c.nx, c.ny, c.nz, +1, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
-                                 p->grid_cap, stream);
-        }));
-      } else if (c.ndim == 2) {
-        HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
-          return launch_row_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, (int)s, max_steps,
-                                    p->grid_cap, stream);
-        }));
-        HIP_TRY(timed_launch(c.fam_col, pts, sample, [&] {
-          return launch_col_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
-                                    p->grid_cap, stream);
-        }));
-      } else {
-        HIP_TRY(timed_launch(c.fam_line, pts, sample, [&] {
-          return launch_line_pass_1d(c.nx, c.dev, nact, c.psi, c.f, c.tw_x, (int)s, max_steps,
-                                     p->grid_cap, stream);
-        }));
-      }
-    }
+  // whole chunks from the captured graph when every instance has the same number of
+  // steps left (the graph's kernels run every member for exactly graph_k steps)
+  bool uniform = true;
+  for (size_t ci = 0; ci < p->classes.size(); ++ci)
+    for (long long l : lim[ci]) uniform = uniform && (l == S);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(stream, &cap));
+  long long done = 0;
+  if (p->graph_exec && !timing && uniform && cap == hipStreamCaptureStatusNone &&
+      !(p->opts.flags & QHD_OPT_NO_GRAPH)) {
+    for (; done + p->graph_k <= S; done += p->graph_k) HIP_TRY(hipGraphLaunch(p->graph_exec, stream));
+  }
+  if (done < S) {
+    std::vector<std::vector<long long>> rest(lim);
+    for (auto& v : rest)
+      for (auto& l : v) l -= done;
+    qhd_status st = enqueue_steps(p, S - done, rest, done > 0 ? S - done : max_steps, stream, timing);
+    if (st != QHD_OK) return st;
   }
   for (size_t ci = 0; ci < p->classes.size(); ++ci) {
     ShapeClass& c = p->classes[ci];
-    HIP_TRY(launch_commit(c.dev, (int)c.members.size(), max_steps, stream));
     for (size_t k = 0; k < c.members.size(); ++k) {
       if (lim[ci][k] > 0) {
         c.host[k].steps_done += lim[ci][k];
@@ -589,6 +798,28 @@ qhd_status qhd_evolve(qhd_plan p, int64_t max_steps, void* stream_v) {
   }
   p->last_stream = stream;
   p->last_stream_valid = true;
+  return QHD_OK;
+}
+
+qhd_status qhd_plan_info(qhd_plan p, qhd_class_info* out, int32_t cap, int32_t* n_classes,
+                         int32_t* graph_steps) {
+  g_err.clear();
+  if (!p || !n_classes || !graph_steps || (cap > 0 && !out)) return fail(QHD_EINVAL, "NULL argument");
+  *n_classes = (int32_t)p->classes.size();
+  *graph_steps = p->graph_exec ? p->graph_k : 0;
+  for (int k = 0; k < cap && k < (int)p->classes.size(); ++k) {
+    const ShapeClass& c = p->classes[k];
+    qhd_class_info& o = out[k];
+    o.ndim = c.ndim;
+    o.n[0] = c.nx;
+    o.n[1] = c.ny;
+    o.n[2] = c.nz;
+    o.members = (int32_t)c.members.size();
+    o.col_variant = c.ndim == 2 ? col_variant_resolve(c.ny, c.col_variant) : 0;
+    o.grid_cap_row = c.cap_row;
+    o.grid_cap_col = c.cap_col;
+    o.tuned = c.tuned ? 1 : 0;
+  }
   return QHD_OK;
 }
 

@@ -41,9 +41,14 @@ struct TimingSink {
 hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double* f, const double2* tw_nx, int s, long long max_steps,
                               int grid_cap, hipStream_t stream);
+// column-pass variants: staged (tile column through LDS, one wavefront per line) or
+// tile-wave (8x8 tiles straight to registers, a line spread over TPL/8 wavefronts);
+// kColAuto takes the measured default for the size
+enum { kColAuto = 0, kColStaged = 1, kColTileWave = 2 };
+int col_variant_resolve(int ny, int variant);
 hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double2* tw_ny, int s, long long max_steps, int grid_cap,
-                              hipStream_t stream);
+                              int variant, hipStream_t stream);
 hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* psi, const double* f,
                                const double2* tw, int s, long long max_steps, int grid_cap,
                                hipStream_t stream);
@@ -88,6 +93,6 @@ hipError_t launch_argmin(const double* f, long long count, double* out_val, long
 
 // Size the launch of the pass kernels (blocks actually used for a class).
 int pass_blocks_row_2d(int nx, int ny, int ninst, int grid_cap);
-int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap);
+int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant);
 
 }  // namespace qhd

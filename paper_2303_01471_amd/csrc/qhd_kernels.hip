@@ -55,8 +55,9 @@ __global__ void __launch_bounds__(256) k_row_pass_2d(const InstDev* __restrict__
   __shared__ float2 lds[LPW * SLOTS];
   const int ll = threadIdx.x / TPL, t = threadIdx.x % TPL;
   float2* my = lds + ll * SLOTS;
-  Twiddles<NX, P> tw;
-  tw.load(twtab, t);
+  __shared__ double2 twl[TwLdsSize<NX, P>::value];
+  TwiddlesFor<NX, P> tw;
+  load_twiddles(tw, twtab, twl, t);
   const long long total = (long long)ninst << ny_log2;
   long long begin, end;
   block_share(total, LPW, begin, end);
@@ -118,8 +119,9 @@ __global__ void __launch_bounds__(256) k_col_pass_2d(
   __shared__ float2 lds[C::LINES * STRIDE];
   const int tid = threadIdx.x;
   const int line0 = tid / TPL, t = tid % TPL;  // first column of this lane group
-  Twiddles<NY, P> tw;
-  tw.load(twtab, t);
+  __shared__ double2 twl[TwLdsSize<NY, P>::value];
+  TwiddlesFor<NY, P> tw;
+  load_twiddles(tw, twtab, twl, t);
   const int nx = 1 << nx_log2, tc_log2 = nx_log2 - 3, tcols = nx >> 3;
   const long long total = (long long)ninst << tc_log2;
   const double inv_n = 1.0 / ((double)nx * (double)NY);
@@ -182,6 +184,8 @@ __global__ void __launch_bounds__(256) k_col_pass_2d(
       line_fft<NY, P, -1>(reg, t, tw, my);
 #pragma unroll
       for (int q = 0; q < P; ++q) {
+        // E_x E_y in FP64, rounded once: FP32 factors rounded separately gain a one-sided
+        // magnitude error where the phase is tiny (cos rounds to 1, sin does not)
         const double2 k = make_double2(fma(ex.x, ey[q].x, -ex.y * ey[q].y), fma(ex.x, ey[q].y, ex.y * ey[q].x));
         reg[q] = cmul_ff(reg[q], make_float2((float)k.x, (float)k.y));
       }
@@ -244,8 +248,9 @@ __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
   const int c = lane & 7;
   const int t = (lane >> 3) + 8 * wv;
   float2* my = lds + (item * 8 + c) * STRIDE;
-  Twiddles<NY, P> tw;
-  tw.load(twtab, t);
+  __shared__ double2 twl[TwLdsSize<NY, P>::value];
+  TwiddlesFor<NY, P> tw;
+  load_twiddles(tw, twtab, twl, t);
   const int nx = 1 << nx_log2, tc_log2 = nx_log2 - 3, tcols = nx >> 3;
   const long long total = (long long)ninst << tc_log2;
   const double inv_n = 1.0 / ((double)nx * (double)NY);
@@ -651,7 +656,7 @@ constexpr int col_tw_p() { return N >= 1024 ? 16 : 8; }
 template <int N>
 hipError_t launch_col_tw(int blocks, int nx, const InstDev* inst, int ninst, float2* psi,
                          const double2* tw, int s, long long max_steps, hipStream_t stream) {
-  if constexpr (N >= 64 && N <= 256) {
+  if constexpr (N >= 64 && N <= 512) {
     constexpr int P_ = col_tw_p<N>();
     hipLaunchKernelGGL((k_col_pass_tw<N, P_>), dim3(blocks), dim3(ColTwCfg<N, P_>::NT), 0, stream,
                        inst, ninst, ilog2(nx), psi, tw, s, max_steps);
@@ -661,10 +666,17 @@ hipError_t launch_col_tw(int blocks, int nx, const InstDev* inst, int ninst, flo
   }
 }
 
-int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap) {
+int col_variant_resolve(int ny, int variant) {
+  const bool tw_ok = ny >= 64 && ny <= 512;
+  if (variant == kColTileWave && tw_ok) return kColTileWave;
+  if (variant == kColStaged) return kColStaged;
+  return (ny >= 64 && ny <= 256) ? kColTileWave : kColStaged;  // measured defaults
+}
+
+int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant) {
   int items;
-  if (ny >= 64 && ny <= 256) {
-    const int P = ny >= 1024 ? 16 : 8;
+  if (col_variant_resolve(ny, variant) == kColTileWave) {
+    const int P = 8;  // col_tw_p<N>() for every tile-wave size
     const int w = ny / P / 8;
     items = w >= 4 ? 1 : 4 / w;
   } else {
@@ -688,9 +700,15 @@ hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, fl
 
 hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double2* tw, int s, long long max_steps, int grid_cap,
-                              hipStream_t stream) {
-  const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap);
+                              int variant, hipStream_t stream) {
+  const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap, variant);
+  if (col_variant_resolve(ny, variant) == kColTileWave) {
+    QHD_SWITCH_N(ny, { return launch_col_tw<N_>(blocks, nx, inst, ninst, psi, tw, s, max_steps, stream); });
+  }
   switch (ny) {
+    case 64: { hipLaunchKernelGGL((k_col_pass_2d<64, 8>), dim3(blocks), dim3(ColCfg<64, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
+    case 128: { hipLaunchKernelGGL((k_col_pass_2d<128, 8>), dim3(blocks), dim3(ColCfg<128, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
+    case 256: { hipLaunchKernelGGL((k_col_pass_2d<256, 8>), dim3(blocks), dim3(ColCfg<256, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
     case 512: { hipLaunchKernelGGL((k_col_pass_2d<512, 8>), dim3(blocks), dim3(ColCfg<512, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
     case 1024: { hipLaunchKernelGGL((k_col_pass_2d<1024, 16>), dim3(blocks), dim3(ColCfg<1024, 16>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
     case 8: { hipLaunchKernelGGL((k_col_pass_2d<8, 8>), dim3(blocks), dim3(ColCfg<8, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
@@ -698,7 +716,7 @@ hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, fl
     case 32: { hipLaunchKernelGGL((k_col_pass_2d<32, 8>), dim3(blocks), dim3(ColCfg<32, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
     default: break;
   }
-  QHD_SWITCH_N(ny, { return launch_col_tw<N_>(blocks, nx, inst, ninst, psi, tw, s, max_steps, stream); });
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* psi, const double* f,

@@ -27,6 +27,8 @@ STATUS_NAMES = {0: "QHD_OK", 1: "QHD_EINVAL", 2: "QHD_EUNSUPPORTED", 3: "QHD_ENO
 QHD_SCHED_NESTEROV, QHD_SCHED_CONST, QHD_SCHED_TABLE = 0, 1, 2
 QHD_INIT_UNIFORM, QHD_INIT_USER = 0, 1
 QHD_OPT_TIME_PASSES = 0x1
+QHD_OPT_AUTOTUNE = 0x2
+QHD_OPT_NO_GRAPH = 0x4
 
 
 class QHDError(RuntimeError):
@@ -57,6 +59,7 @@ class qhd_plan_opts(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("norm_tolerance", ctypes.c_double),
         ("timing_stride", ctypes.c_int32),
+        ("tune_cache", ctypes.c_char_p),
     ]
 
 
@@ -98,6 +101,18 @@ class qhd_sno_desc(ctypes.Structure):
     ]
 
 
+class qhd_class_info(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 3),
+        ("members", ctypes.c_int32),
+        ("col_variant", ctypes.c_int32),
+        ("grid_cap_row", ctypes.c_int32),
+        ("grid_cap_col", ctypes.c_int32),
+        ("tuned", ctypes.c_int32),
+    ]
+
+
 _lib = None
 
 # every entry point declared in include/qhd.h and include/qhd_sno.h, with its ctypes signature
@@ -115,6 +130,8 @@ _SIGNATURES = {
     "qhd_kernel_timings": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(qhd_kernel_timing),
                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "qhd_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "qhd_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(qhd_class_info), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "qhd_last_error": (ctypes.c_char_p, []),
     "qhd_version": (ctypes.c_char_p, []),
     "qhd_sno_create": (ctypes.c_int, [ctypes.POINTER(qhd_sno_desc), ctypes.POINTER(ctypes.c_void_p)]),
@@ -211,6 +228,14 @@ def qhd_kernel_timings(plan: int, cap: int = 64):
     n = ctypes.c_int32()
     _check(load_library().qhd_kernel_timings(plan, arr, cap, ctypes.byref(n)))
     return [arr[k] for k in range(min(n.value, cap))]
+
+
+def qhd_plan_info(plan: int, cap: int = 16):
+    arr = (qhd_class_info * cap)()
+    n = ctypes.c_int32()
+    g = ctypes.c_int32()
+    _check(load_library().qhd_plan_info(plan, arr, cap, ctypes.byref(n), ctypes.byref(g)))
+    return [arr[k] for k in range(min(n.value, cap))], g.value
 
 
 def qhd_plan_destroy(plan: int):
@@ -318,11 +343,12 @@ class Plan:
     """A batch of QHD instances on the current GPU."""
 
     def __init__(self, specs: Sequence[InstanceSpec], flags: int = 0, norm_tolerance: float = 0.0,
-                 timing_stride: int = 0):
+                 timing_stride: int = 0, tune_cache: Optional[str] = None):
         self.specs = list(specs)
         keep: list = []
         cinst = [s.to_c(keep) for s in self.specs]
-        opts = qhd_plan_opts(flags, norm_tolerance, timing_stride)
+        opts = qhd_plan_opts(flags, norm_tolerance, timing_stride,
+                             tune_cache.encode() if tune_cache else None)
         self.handle = qhd_plan_create(cinst, opts)
         self.points = qhd_plan_points(self.handle)
         self.offsets = np.concatenate([[0], np.cumsum([s.points for s in self.specs])]).astype(np.int64)
@@ -376,6 +402,13 @@ class Plan:
     def psi_of(self, psi_flat, i: int):
         a, b = int(self.offsets[i]), int(self.offsets[i + 1])
         return psi_flat[a:b].reshape(tuple(self.specs[i].shape))
+
+    def graph_info(self) -> dict:
+        """Launch configuration chosen at plan creation (classes, graph chunk)."""
+        cls, g = qhd_plan_info(self.handle)
+        return dict(graph_steps=g, classes=[dict(ndim=c.ndim, n=tuple(c.n), members=c.members,
+                                                 col_variant=c.col_variant, cap_row=c.grid_cap_row,
+                                                 cap_col=c.grid_cap_col, tuned=bool(c.tuned)) for c in cls])
 
     def kernel_timings(self) -> List[dict]:
         return [dict(name=t.name.decode(), launches=t.launches, total_ms=t.total_ms, points=t.points,
