@@ -93,6 +93,12 @@ typedef struct {
                                     the grid sizes of every 2-D shape class on its own
                                     batch and keep the fastest (a few ms per class)     */
 #define QHD_OPT_NO_GRAPH 0x4u    /* never replay captured step chunks (see qhd_evolve)  */
+#define QHD_OPT_MFMA_DFT 0x8u    /* 3-D instances with n = 128 on every axis: the line
+                                    transforms run as dense 128 x 128 DFT products on
+                                    the matrix cores with split FP16 hi/lo operands and
+                                    FP32 accumulation (relative error ~2^-22 per
+                                    transform, against ~2^-24 for the FP32 FFT); other
+                                    instances are unaffected                            */
 
 typedef struct qhd_plan_s *qhd_plan;
 
@@ -126,6 +132,7 @@ typedef struct {
   int32_t grid_cap_row;  /* workgroup caps of the row (x) and column passes             */
   int32_t grid_cap_col;
   int32_t tuned;         /* 1 if the autotuner chose them while creating this plan      */
+  int32_t mfma_dft;      /* 1 if the class runs the matrix-core DFT passes              */
 } qhd_class_info;
 
 /* Create a plan for `batch` instances.  Validates every descriptor first (no

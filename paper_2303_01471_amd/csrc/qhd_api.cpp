@@ -114,6 +114,7 @@ struct ShapeClass {
   int col_variant = kColAuto;
   int cap_row = 2048, cap_col = 2048;
   bool tuned = false;
+  bool mfma = false;  // 3-D 128^3 with QHD_OPT_MFMA_DFT
 };
 
 struct qhd_plan_s {
@@ -137,6 +138,7 @@ struct qhd_plan_s {
   long long total_points = 0;
   int grid_cap = 2048;
   std::string tune_cache;
+  void* dft_tables = nullptr;  // FP16 split DFT matrices for the matrix-core 3-D passes
   // a chunk of graph_k steps of every class, captured at plan creation (see qhd_evolve)
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -163,6 +165,7 @@ void free_plan(qhd_plan p) {
   }
   for (double* t : p->dev_tables) (void)hipFree(t);
   (void)hipFree(p->twiddles);
+  (void)hipFree(p->dft_tables);
   (void)hipFree(p->staging_f);
   (void)hipFree(p->staging_psi);
   (void)hipFree(p->amin_val);
@@ -242,7 +245,24 @@ qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<
         if (lim[ci][k] > s) nact = (int)k + 1;
       if (nact == 0) continue;
       const double pts = (double)nact * (double)c.points;
-      if (c.ndim == 3) {
+      if (c.ndim == 3 && c.mfma) {
+        HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
+          return launch_mfma_pass_3d(0, 0, c.dev, nact, p->dft_tables, c.psi, c.f, (int)s, max_steps,
+                                     p->grid_cap, stream);
+        }));
+        HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
+          return launch_mfma_pass_3d(1, -1, c.dev, nact, p->dft_tables, c.psi, c.f, (int)s, max_steps,
+                                     p->grid_cap, stream);
+        }));
+        HIP_TRY(timed_launch(c.fam_z, pts, sample, [&] {
+          return launch_mfma_pass_3d(2, 0, c.dev, nact, p->dft_tables, c.psi, c.f, (int)s, max_steps,
+                                     p->grid_cap, stream);
+        }));
+        HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
+          return launch_mfma_pass_3d(1, +1, c.dev, nact, p->dft_tables, c.psi, c.f, (int)s, max_steps,
+                                     p->grid_cap, stream);
+        }));
+      } else if (c.ndim == 3) {
         HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
           return launch_row_pass_2d(c.nx, c.ny * c.nz, c.dev, nact, c.psi, c.f, c.tw_x, (int)s,
                                     max_steps, p->grid_cap, stream);
@@ -589,7 +609,12 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       return bail(e == hipErrorOutOfMemory ? QHD_ENOMEM : QHD_EDEVICE);
     }
     char name[48];
-    if (c.ndim == 3) {
+    c.mfma = (p->opts.flags & QHD_OPT_MFMA_DFT) && c.ndim == 3 && c.nx == 128 && c.ny == 128 && c.nz == 128;
+    if (c.mfma) {
+      c.fam_row = family_index(p, "xpass_3d_mfma/n128", 24.0);
+      c.fam_y = family_index(p, "ypass_3d_mfma/n128", 16.0);
+      c.fam_z = family_index(p, "zpass_3d_mfma/n128", 16.0);
+    } else if (c.ndim == 3) {
       snprintf(name, sizeof name, "xpass_3d/n%d", c.nx);
       c.fam_row = family_index(p, name, 24.0);
       snprintf(name, sizeof name, "ypass_3d/n%d", c.ny);
@@ -607,6 +632,29 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
     }
   }
   for (int i = 0; i < batch; ++i) p->state_ready[i] = inst[i].init_kind == QHD_INIT_UNIFORM;
+  if (std::any_of(p->classes.begin(), p->classes.end(), [](const ShapeClass& c) { return c.mfma; })) {
+    // W_jk = e^{-+2 pi i jk / 128} as FP16 hi/lo pairs of the real and imaginary parts
+    const int n = 128;
+    std::vector<_Float16> tab((size_t)2 * 4 * n * n);
+    for (int sg = 0; sg < 2; ++sg)
+      for (int jj = 0; jj < n; ++jj)
+        for (int kk = 0; kk < n; ++kk) {
+          const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)((jj * kk) % n) / n;
+          const double re = (double)cosl(ang), im = (sg == 0 ? -1.0 : 1.0) * (double)sinl(ang);
+          const _Float16 rh = (_Float16)re, ih = (_Float16)im;
+          const size_t o = (size_t)jj * n + kk;
+          tab[((size_t)sg * 4 + 0) * n * n + o] = rh;
+          tab[((size_t)sg * 4 + 1) * n * n + o] = (_Float16)(re - (double)rh);
+          tab[((size_t)sg * 4 + 2) * n * n + o] = ih;
+          tab[((size_t)sg * 4 + 3) * n * n + o] = (_Float16)(im - (double)ih);
+        }
+    e = hipMalloc(&p->dft_tables, tab.size() * sizeof(_Float16));
+    if (e == hipSuccess) e = hipMemcpy(p->dft_tables, tab.data(), tab.size() * sizeof(_Float16), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      fail(e == hipErrorOutOfMemory ? QHD_ENOMEM : QHD_EDEVICE, "DFT table upload: %s", hipGetErrorString(e));
+      return bail(e == hipErrorOutOfMemory ? QHD_ENOMEM : QHD_EDEVICE);
+    }
+  }
   // launch configuration per class: tuning cache, else autotune (QHD_OPT_AUTOTUNE), else defaults
   if (p->opts.tune_cache) p->tune_cache = p->opts.tune_cache;
   p->opts.tune_cache = nullptr;  // the caller's string is not kept
@@ -819,6 +867,7 @@ qhd_status qhd_plan_info(qhd_plan p, qhd_class_info* out, int32_t cap, int32_t* 
     o.grid_cap_row = c.cap_row;
     o.grid_cap_col = c.cap_col;
     o.tuned = c.tuned ? 1 : 0;
+    o.mfma_dft = c.mfma ? 1 : 0;
   }
   return QHD_OK;
 }

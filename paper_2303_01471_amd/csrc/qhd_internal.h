@@ -92,6 +92,14 @@ hipError_t launch_argmin(const double* f, long long count, double* out_val, long
                          hipStream_t stream);
 
 // Size the launch of the pass kernels (blocks actually used for a class).
+// 3-D pass with the line transforms as split-FP16 DFT products on the matrix cores
+// (128^3 only): axis 0 = x-pass (F_x V F_x^{-1}), 1 = y-pass (dir -1 forward, +1
+// inverse), 2 = z-pass (F_z^{-1} K F_z).  tables: FP16 [sign][re hi, re lo, im hi,
+// im lo][128][128], sign 0 = e^{-2 pi i jk/128}, 1 = e^{+2 pi i jk/128}.
+hipError_t launch_mfma_pass_3d(int axis, int dir, const InstDev* inst, int ninst, const void* tables,
+                               float2* psi, const double* f, int s, long long max_steps, int grid_cap,
+                               hipStream_t stream);
+
 int pass_blocks_row_2d(int nx, int ny, int ninst, int grid_cap);
 int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant);
 

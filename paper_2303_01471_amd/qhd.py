@@ -29,6 +29,7 @@ QHD_INIT_UNIFORM, QHD_INIT_USER = 0, 1
 QHD_OPT_TIME_PASSES = 0x1
 QHD_OPT_AUTOTUNE = 0x2
 QHD_OPT_NO_GRAPH = 0x4
+QHD_OPT_MFMA_DFT = 0x8
 
 
 class QHDError(RuntimeError):
@@ -110,6 +111,7 @@ class qhd_class_info(ctypes.Structure):
         ("grid_cap_row", ctypes.c_int32),
         ("grid_cap_col", ctypes.c_int32),
         ("tuned", ctypes.c_int32),
+        ("mfma_dft", ctypes.c_int32),
     ]
 
 
@@ -408,7 +410,8 @@ class Plan:
         cls, g = qhd_plan_info(self.handle)
         return dict(graph_steps=g, classes=[dict(ndim=c.ndim, n=tuple(c.n), members=c.members,
                                                  col_variant=c.col_variant, cap_row=c.grid_cap_row,
-                                                 cap_col=c.grid_cap_col, tuned=bool(c.tuned)) for c in cls])
+                                                 cap_col=c.grid_cap_col, tuned=bool(c.tuned),
+                                                 mfma_dft=bool(c.mfma_dft)) for c in cls])
 
     def kernel_timings(self) -> List[dict]:
         return [dict(name=t.name.decode(), launches=t.launches, total_ms=t.total_ms, points=t.points,
