@@ -20,6 +20,11 @@ Also reported on the same JSON line:
   plain         the same instances solved one at a time (single-instance
                 solver), per size, and the 256^2 x 10k-step single instance.
   parity        the GPU state against the oracle on a sample instance.
+  surrogate     the spectral neural-operator surrogate on the 128^2, T = 10,
+                dt = 0.01 dynamics: trained here on solver-generated pairs,
+                judged by the solver on held-out landscapes, and its inference
+                rate against the batched and the plain solver on the same
+                dynamics.
 """
 from __future__ import annotations
 
@@ -51,9 +56,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def build_plan(specs, q, flags=0, timing_stride=0):
+def build_plan(specs, q, flags=0, timing_stride=0, tune_cache=None):
     cspecs = [q.InstanceSpec(shape=s.shape, nsteps=s.nsteps, dt=s.dt) for s in specs]
-    return q.Plan(cspecs, flags=flags, timing_stride=timing_stride)
+    return q.Plan(cspecs, flags=flags, timing_stride=timing_stride, tune_cache=tune_cache or None)
 
 
 def main():
@@ -62,10 +67,22 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--count", type=int, default=768, help="instances in the batch")
+    ap.add_argument("--workload", choices=("batched2d", "3d"), default="batched2d",
+                    help="batched2d: the 768-instance 2-D batch (default); 3d: 16 instances of 128^3, "
+                         "T = 10, dt = 2e-3")
+    ap.add_argument("--mfma-dft", action="store_true",
+                    help="3d: line transforms as split-FP16 DFT products on the matrix cores")
     ap.add_argument("--cap-steps", type=int, default=0,
                     help="cap every instance's step count (profiling runs only; changes the workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--tune-cache", default="",
+                    help="launch tuning cache (read; classes without an entry are tuned and appended)")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-pairs", type=int, default=4096)
+    ap.add_argument("--surrogate-epochs", type=float, default=4.0)
+    ap.add_argument("--cpu-sample-steps", type=int, default=12000,
+                    help="oracle steps of the 256^2 CPU-baseline sample (about 10 s on 16 cores)")
     ap.add_argument("--timing-stride", type=int, default=16)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this size (counter calibration)")
@@ -83,9 +100,20 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     import qhd_inputs
+
+    # surrogate training potentials first: the worker processes are forked before
+    # anything touches the GPU
+    sur_f = None
+    if not args.no_surrogate and args.workload != "3d":
+        from paper_2303_01471_amd import screen
+        t0 = time.time()
+        sur_f = screen.make_landscapes(args.surrogate_pairs, 5_000_000, 128, workers=16)
+        log(f"surrogate landscapes: {len(sur_f)} x 128^2 in {time.time() - t0:.1f}s")
+
+    import torch
+
     from paper_2303_01471_amd import qhd as q
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -93,15 +121,22 @@ def main():
     q.load_library()
 
     if args.copy_calibration_mib > 0:
+        # one elementwise kernel that reads and writes the buffer once (the only
+        # torch elementwise launch of a counter run)
         n = args.copy_calibration_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        src = torch.empty(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-        log(f"copy calibration: {args.copy_calibration_mib} MiB device copy done")
+        log(f"copy calibration: {args.copy_calibration_mib} MiB read + written by one elementwise kernel")
 
-    specs = qhd_inputs.batched_2d(count=args.count)
+    if args.workload == "3d":
+        specs = qhd_inputs.batch_3d()
+        args.no_surrogate = True
+    else:
+        specs = qhd_inputs.batched_2d(count=args.count)
     if args.cap_steps > 0:
         for s in specs:
             s.nsteps = min(s.nsteps, args.cap_steps)
@@ -109,7 +144,9 @@ def main():
         pts = {}
         for s in specs:
             n = s.shape[0]
-            for fam in (f"row_pass_2d/n{n}", f"col_pass_2d/n{n}"):
+            fams = ((f"xpass_3d/n{n}", f"ypass_3d/n{n}", f"zpass_3d/n{n}") if len(s.shape) == 3
+                    else (f"row_pass_2d/n{n}", f"col_pass_2d/n{n}"))
+            for fam in fams:
                 pts[fam] = pts.get(fam, 0) + s.points
         with open(args.points_json, "w") as fh:
             json.dump(pts, fh)
@@ -117,7 +154,12 @@ def main():
     log(f"{len(specs)} instances, {sum(s.points for s in specs)/1e6:.1f} M points, "
         f"{total_gp:.3e} grid-point-steps per bench step")
 
-    plan = build_plan(specs, q, flags=q.QHD_OPT_TIME_PASSES, timing_stride=args.timing_stride)
+    extra = q.QHD_OPT_MFMA_DFT if args.mfma_dft else 0
+    plan = build_plan(specs, q, flags=q.QHD_OPT_TIME_PASSES | q.QHD_OPT_AUTOTUNE | extra,
+                      timing_stride=args.timing_stride, tune_cache=args.tune_cache)
+    tuned = plan.graph_info()["classes"]
+    log("launch configuration: " + "; ".join(
+        f"n{c['n'][0]}: col variant {c['col_variant']}, caps {c['cap_row']}/{c['cap_col']}" for c in tuned))
     t0 = time.time()
     grids = {}
     for i, s in enumerate(specs):
@@ -192,7 +234,7 @@ def main():
         for n, (i, f) in sorted(grids.items()):
             sp = specs[i]
             steps = 2000 if n <= 256 else 1000
-            p1 = build_plan([type(sp)(sp.seed, sp.shape, steps + 200, sp.dt, sp.n_terms, sp.kmax)], q)
+            p1 = build_plan([type(sp)(sp.seed, sp.shape, steps + 200, sp.dt, sp.n_terms, sp.kmax)], q, flags=extra)
             p1.set_potential(0, f)
             p1.evolve(200, stream)
             torch.cuda.synchronize()
@@ -204,37 +246,39 @@ def main():
             log(f"plain {n}x{n}: {rates[n] / 1e9:.2f} G gp-steps/s")
         plain_time = sum(s.points * s.nsteps / rates[s.shape[0]] for s in specs)
         plain_equiv = total_gp / plain_time
-        # the single-instance 256^2 x 10k-step configuration
-        c1 = qhd_inputs.single_2d(256)
-        p1 = build_plan([c1], q)
-        p1.set_potential(0, c1.grid())
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        p1.evolve(-1, stream)
-        r1, _, _, _ = p1.observe(stream)
-        torch.cuda.synchronize()
-        c1_rate = c1.points * c1.nsteps / (time.perf_counter() - t)
-        p1.close()
         plain = {"per_size_gp_steps_per_s": {str(k): round(v, 1) for k, v in rates.items()},
                  "batch_one_at_a_time_gp_steps_per_s": round(plain_equiv, 1),
-                 "batched_vs_plain": round(value / plain_equiv, 3),
-                 "single_256x256_10k_steps_gp_steps_per_s": round(c1_rate, 1),
-                 "single_256x256_norm_drift": abs(r1[0]["norm"] - 1.0),
+                 "batched_vs_plain": round(value / plain_equiv, 3)}
+        if args.workload != "3d":
+            # the single-instance 256^2 x 10k-step configuration
+            c1 = qhd_inputs.single_2d(256)
+            p1 = build_plan([c1], q)
+            p1.set_potential(0, c1.grid())
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            p1.evolve(-1, stream)
+            r1, _, _, _ = p1.observe(stream)
+            torch.cuda.synchronize()
+            c1_rate = c1.points * c1.nsteps / (time.perf_counter() - t)
+            p1.close()
+            plain["single_256x256_10k_steps_gp_steps_per_s"] = round(c1_rate, 1)
+            plain["single_256x256_norm_drift"] = abs(r1[0]["norm"] - 1.0)
+        plain.update({
                  "method": "per-size rates of the single-instance solver (one plan per instance, "
                            "2000/1000 steps after 200 warm steps), applied to the batch's own sizes "
-                           "and step counts"}
-        log(f"plain equivalent {plain_equiv / 1e9:.2f} G gp-steps/s; batched/plain "
-            f"{value / plain_equiv:.2f}x; single 256^2 10k: {c1_rate / 1e9:.2f} G gp-steps/s")
+                           "and step counts"})
+        log(f"plain equivalent {plain_equiv / 1e9:.2f} G gp-steps/s; batched/plain {value / plain_equiv:.2f}x")
 
     # ---- CPU baseline (FP64 oracle) and parity on a sample ----------------------------
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
         import oracle
-        n0 = 128 if 128 in grids else min(grids)
+        n0 = 256 if 256 in grids else min(grids)
         i0, f0 = grids[n0]
         sp = specs[i0]
-        sample_steps = 1500
+        # bounded sample: at most ~8e8 grid-point-steps (about 10 s on 16 cores)
+        sample_steps = max(1, min(args.cpu_sample_steps, sp.nsteps, int(8e8 // sp.points)))
         prob = oracle.Problem(shape=sp.shape, dt=sp.dt)
         psi = oracle.uniform_state(sp.shape)
         t = time.perf_counter()
@@ -243,20 +287,64 @@ def main():
         cpu_rate = sp.points * sample_steps / tcpu
         cpu = {"value": round(cpu_rate, 1), "unit": "grid-point-steps/s", "cores": oracle.max_threads(),
                "kind": "oracle",
-               "sample": f"instance {i0} of the batch ({n0}x{n0}), first {sample_steps} of its "
-                         f"{sp.nsteps} steps, FP64, {tcpu:.1f}s"}
+               "sample": f"instance {i0} of the batch ({'x'.join(map(str, sp.shape))}), first {sample_steps} "
+                         f"of its {sp.nsteps} steps, FP64, {tcpu:.1f}s"}
         log(f"cpu oracle: {cpu_rate / 1e6:.2f} M gp-steps/s on {cpu['cores']} threads ({tcpu:.1f}s)")
-        p1 = build_plan([type(sp)(sp.seed, sp.shape, sample_steps, sp.dt, sp.n_terms, sp.kmax)], q)
+        p1 = build_plan([type(sp)(sp.seed, sp.shape, sample_steps, sp.dt, sp.n_terms, sp.kmax)], q, flags=extra)
         p1.set_potential(0, f0)
         p1.evolve(-1, stream)
         r1, psig, _, _ = p1.observe(stream, want_psi=True)
         torch.cuda.synchronize()
         got = psig.cpu().numpy().reshape(sp.shape).astype(np.complex128)
         p1.close()
-        parity = {"sample": f"instance {i0} ({n0}x{n0}), {sample_steps} steps",
+        parity = {"sample": f"instance {i0} ({'x'.join(map(str, sp.shape))}), {sample_steps} steps"
+                            + (", split-FP16 MFMA DFT" if args.mfma_dft else ""),
                   "max_abs_dpsi": float(np.max(np.abs(got - psi))),
                   "norm_drift": abs(r1[0]["norm"] - 1.0), "tolerance": 1e-4}
         log(f"parity sample: max|dpsi| = {parity['max_abs_dpsi']:.3e}")
+
+    # ---- surrogate: trained here, judged by the solver, timed against it -------------
+    surrogate = None
+    if sur_f is not None:
+        from paper_2303_01471_amd import screen
+        from paper_2303_01471_amd.sno import Surrogate
+        f_dev = torch.from_numpy(sur_f).cuda()
+        rho_dev, succ, solve_s = screen.solve(f_dev, T=10.0, dt=0.01)
+        n_plain = 8
+        _, _, plain_s = screen.solve(f_dev[:n_plain], T=10.0, dt=0.01, chunk=1)
+        n_hold = max(64, len(sur_f) // 16)
+        n_train = len(sur_f) - n_hold
+        net = Surrogate(grid=128, width=32, modes=16, layers=4, max_batch=32, precision="bf16", train=True, seed=1)
+        hist = screen.train(net, f_dev[:n_train], rho_dev[:n_train], args.surrogate_epochs, 32, 2e-3)
+        params = net.get_params()
+        net.close()
+        inf = Surrogate(grid=128, width=32, modes=16, layers=4, max_batch=1024, precision="bf16", train=False)
+        inf.set_params(params)
+        pred = screen.predict(inf, f_dev[n_train:], min(1024, n_hold)).cpu().numpy().astype(np.float64)
+        rate = screen.throughput(inf, f_dev, min(1024, len(sur_f)))
+        inf.close()
+        ev = screen.evaluate(pred, rho_dev[n_train:].cpu().numpy().astype(np.float64), sur_f[n_train:],
+                             succ[n_train:], rho_dev[:n_train].mean(dim=0).cpu().numpy().astype(np.float64))
+        batched_rate, plain_rate = len(sur_f) / solve_s, n_plain / plain_s
+        surrogate = {"workload": "128x128, T=10, dt=0.01 (1000 steps), 8-term landscapes; width 32, 16 modes, "
+                                 "4 layers, BF16 weights/activations, FP32 accumulation",
+                     "train_pairs": n_train, "heldout": n_hold, "epochs": round(hist["epochs"], 2),
+                     "train_seconds": round(hist["seconds"], 2),
+                     "train_samples_per_s": round(hist["samples_per_s"], 1),
+                     "inference_landscapes_per_s": round(rate, 1), "inference_batch": 1024,
+                     "solver_batched_landscapes_per_s": round(batched_rate, 1),
+                     "solver_plain_landscapes_per_s": round(plain_rate, 1),
+                     "speedup_vs_batched_solver": round(rate / batched_rate, 2),
+                     "speedup_vs_plain_solver": round(rate / plain_rate, 2),
+                     "heldout_l1": round(ev["l1_mean"], 4),
+                     "heldout_l1_mean_density_baseline": round(ev["l1_baseline_mean_density"], 4),
+                     "heldout_success_mae": round(ev["success_mae"], 4),
+                     "heldout_success_spearman": round(ev["success_spearman"], 4),
+                     "heldout_top10pct_recall": round(ev["top_recall"], 3)}
+        log(f"surrogate: {rate:.0f} landscapes/s vs solver {batched_rate:.0f} (batched) / {plain_rate:.0f} "
+            f"(plain); held-out L1 {ev['l1_mean']:.3f} (mean-density {ev['l1_baseline_mean_density']:.3f}), "
+            f"success MAE {ev['success_mae']:.3f}, Spearman {ev['success_spearman']:.3f}")
+        del f_dev, rho_dev
 
     sizes = sorted({s.shape[0] for s in specs})
     line = {
@@ -272,8 +360,12 @@ def main():
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": f"batched-{len(specs)}: 2-D instances, n in {sizes}^2 (uniform), "
-                               f"T~U[5,20], dt=1e-3, Nesterov schedule, 8-24 cosine-term landscapes"
+        "config": {"workload": (f"batched-{len(specs)}: 2-D instances, n in {sizes}^2 (uniform), "
+                                f"T~U[5,20], dt=1e-3, Nesterov schedule, 8-24 cosine-term landscapes"
+                                if args.workload != "3d" else
+                                f"3-D: {len(specs)} instances of 128^3, T=10, dt=2e-3, Nesterov schedule, "
+                                f"16 cosine-term landscapes, transforms "
+                                + ("split-FP16 MFMA DFT" if args.mfma_dft else "FP32 Stockham FFT"))
                                + (f", steps capped at {args.cap_steps}" if args.cap_steps else ""),
                    "instances": len(specs), "grid_point_steps": total_gp,
                    "max_norm_drift": norm_drift},
@@ -281,6 +373,8 @@ def main():
         "cpu_baseline": cpu,
         "plain": plain,
         "parity": parity,
+        "surrogate": surrogate,
+        "launch_config": tuned,
         "kernels": kernels,
     }
     print(json.dumps(line), flush=True)

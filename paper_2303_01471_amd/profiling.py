@@ -7,8 +7,9 @@
         mean value per dispatch of every collected counter, per kernel
     python -m paper_2303_01471_amd.profiling traffic FETCH_DB WRITE_DB --copy-bytes B --source-hash H
         HBM bytes per grid point of every pass kernel from FETCH_SIZE and
-        WRITE_SIZE, each scaled by what the same counter reads for a plain copy
-        of B bytes in the same run; JSON (profiles/traffic.json format)
+        WRITE_SIZE, each scaled by what the same counter reads for one
+        elementwise kernel that reads and writes B bytes in the same run; JSON
+        (profiles/traffic.json format)
 
 Dispatch sizes (grid points per launch) come from the kernel arguments of the
 pass kernels as recorded by the benchmark (every instance active, steps capped).
@@ -67,12 +68,14 @@ _FAMILY = [
 
 def traffic(fetch_db: str, write_db: str, copy_bytes: float, points_per_dispatch: dict,
             source_hash: str) -> dict:
-    fe, _ = counter_means(fetch_db)
-    wr, _ = counter_means(write_db)
-    copy_k = [k for k in fe if "copy" in k.lower() or "elementwise" in k.lower()]
-    if not copy_k:
-        raise SystemExit("no copy kernel found for the calibration")
-    ck = max(copy_k, key=lambda k: fe[k].get("FETCH_SIZE", 0.0))
+    fe, nfe = counter_means(fetch_db)
+    wr, nwr = counter_means(write_db)
+    # the calibration kernel: the run's only torch elementwise launch, which reads and
+    # writes copy_bytes once
+    copy_k = [k for k in fe if "elementwise" in k.lower()]
+    if len(copy_k) != 1 or nfe[copy_k[0]] != 1 or nwr.get(copy_k[0]) != 1:
+        raise SystemExit(f"expected exactly one calibration dispatch, found {[(k, nfe[k]) for k in copy_k]}")
+    ck = copy_k[0]
     f_scale = copy_bytes / (fe[ck]["FETCH_SIZE"] * 1024.0)
     w_scale = copy_bytes / (wr[ck]["WRITE_SIZE"] * 1024.0)
     out = {"source_hash": source_hash, "copy_kernel": ck, "copy_bytes": copy_bytes,
