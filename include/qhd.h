@@ -89,7 +89,8 @@ typedef struct {
 } qhd_plan_opts;
 
 #define QHD_OPT_TIME_PASSES 0x1u /* record HIP events around sampled pass launches   */
-#define QHD_OPT_AUTOTUNE 0x2u    /* at plan creation, time the column-pass variants and
+#define QHD_OPT_AUTOTUNE 0x2u    /* at plan creation, time the row- and column-pass
+                                    variants (points per lane, staged / tile-wave) and
                                     the grid sizes of every 2-D shape class on its own
                                     batch and keep the fastest (a few ms per class)     */
 #define QHD_OPT_NO_GRAPH 0x4u    /* never replay captured step chunks (see qhd_evolve)  */
@@ -128,11 +129,13 @@ typedef struct {
 typedef struct {
   int32_t ndim, n[3];
   int32_t members;       /* instances in the class                                      */
-  int32_t col_variant;   /* 2-D column pass: 1 staged through LDS, 2 tile-wave          */
+  int32_t col_variant;   /* 2-D column pass: 1 staged through LDS (8 points per lane),
+                            2 tile-wave, 3 staged with 16 points per lane               */
   int32_t grid_cap_row;  /* workgroup caps of the row (x) and column passes             */
   int32_t grid_cap_col;
   int32_t tuned;         /* 1 if the autotuner chose them while creating this plan      */
   int32_t mfma_dft;      /* 1 if the class runs the matrix-core DFT passes              */
+  int32_t row_points_per_lane; /* 2-D row pass: 8 or 16 points of a line per lane       */
 } qhd_class_info;
 
 /* Create a plan for `batch` instances.  Validates every descriptor first (no

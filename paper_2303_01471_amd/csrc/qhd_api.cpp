@@ -112,6 +112,7 @@ struct ShapeClass {
   int fam_row = -1, fam_col = -1, fam_line = -1, fam_y = -1, fam_z = -1;
   // launch configuration (defaults, a tuning-cache entry, or the autotuner's choice)
   int col_variant = kColAuto;
+  int row_points = 8;  // points per lane of the row pass
   int cap_row = 2048, cap_col = 2048;
   bool tuned = false;
   bool mfma = false;  // 3-D 128^3 with QHD_OPT_MFMA_DFT
@@ -265,7 +266,7 @@ qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<
       } else if (c.ndim == 3) {
         HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
           return launch_row_pass_2d(c.nx, c.ny * c.nz, c.dev, nact, c.psi, c.f, c.tw_x, (int)s,
-                                    max_steps, p->grid_cap, stream);
+                                    max_steps, p->grid_cap, 8, stream);
         }));
         HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
           return launch_ypass_3d(c.nx, c.ny, c.nz, -1, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
@@ -282,7 +283,7 @@ qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<
       } else if (c.ndim == 2) {
         HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
           return launch_row_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, (int)s, max_steps,
-                                    c.cap_row, stream);
+                                    c.cap_row, c.row_points, stream);
         }));
         HIP_TRY(timed_launch(c.fam_col, pts, sample, [&] {
           return launch_col_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
@@ -302,7 +303,8 @@ qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<
 
 // ---- launch tuning ----------------------------------------------------------------
 
-// Tuning-cache lines: "qhd-tune 1 <arch> <nx> <ny> <members_pow2> <col_variant> <cap_row> <cap_col>"
+// Tuning-cache lines: "qhd-tune 1 <arch> <nx> <ny> <members_pow2> <col_variant> <cap_row> <cap_col>
+// [<row points per lane>]" (the last field is optional, 8 when absent)
 std::string tune_key(const std::string& arch, const ShapeClass& c) {
   int m = 1;
   while (m < (int)c.members.size()) m <<= 1;
@@ -319,12 +321,13 @@ bool tune_lookup(const std::string& path, const std::string& key, ShapeClass& c)
   while (fgets(line, sizeof line, fh)) {
     const size_t k = key.size();
     if (strncmp(line, key.c_str(), k) != 0 || line[k] != ' ') continue;
-    int v = 0, cr = 0, cc = 0;
-    if (sscanf(line + k, "%d %d %d", &v, &cr, &cc) == 3 && v >= kColAuto && v <= kColTileWave && cr >= 0 &&
-        cc >= 0) {
+    int v = 0, cr = 0, cc = 0, rp = 8;
+    const int got = sscanf(line + k, "%d %d %d %d", &v, &cr, &cc, &rp);
+    if (got >= 3 && v >= kColAuto && v <= kColStaged16 && cr >= 0 && cc >= 0 && (rp == 8 || rp == 16)) {
       c.col_variant = v;  // the last matching line wins
       c.cap_row = cr;
       c.cap_col = cc;
+      c.row_points = got == 4 ? rp : 8;
       found = true;
     }
   }
@@ -336,8 +339,8 @@ void tune_append(const std::string& path, const std::string& key, const ShapeCla
                  double us_col) {
   FILE* fh = fopen(path.c_str(), "a");
   if (!fh) return;
-  fprintf(fh, "%s %d %d %d  # row %.2f us, col %.2f us\n", key.c_str(), c.col_variant, c.cap_row, c.cap_col,
-          us_row, us_col);
+  fprintf(fh, "%s %d %d %d %d  # row %.2f us, col %.2f us\n", key.c_str(), c.col_variant, c.cap_row, c.cap_col,
+          c.row_points, us_row, us_col);
   fclose(fh);
 }
 
@@ -370,17 +373,21 @@ qhd_status autotune_class(qhd_plan p, ShapeClass& c, double& us_row, double& us_
   const int reps = 4;
   us_row = 1e30;
   us_col = 1e30;
-  int best_row = c.cap_row, best_col = c.cap_col, best_var = c.col_variant;
+  int best_row = c.cap_row, best_col = c.cap_col, best_var = c.col_variant, best_pts = c.row_points;
   bool ok = true;
-  for (int cap : caps) {
-    const double t = time_launches(p->internal, a, b, reps, [&] {
-      return launch_row_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.f, c.tw_x, 0, 1, cap, p->internal);
-    });
-    if (t < 0) ok = false;
-    else if (t < us_row) us_row = t, best_row = cap;
-  }
+  std::vector<int> row_pts = {8};
+  if (row_points_resolve(c.nx, 16) == 16 && c.nx < 1024) row_pts.push_back(16);
+  for (int rp : row_pts)
+    for (int cap : caps) {
+      const double t = time_launches(p->internal, a, b, reps, [&] {
+        return launch_row_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.f, c.tw_x, 0, 1, cap, rp, p->internal);
+      });
+      if (t < 0) ok = false;
+      else if (t < us_row) us_row = t, best_row = cap, best_pts = rp;
+    }
   std::vector<int> variants = {kColStaged};
   if (col_variant_resolve(c.ny, kColTileWave) == kColTileWave) variants.push_back(kColTileWave);
+  if (col_variant_resolve(c.ny, kColStaged16) == kColStaged16) variants.push_back(kColStaged16);
   for (int v : variants)
     for (int cap : caps) {
       const double t = time_launches(p->internal, a, b, reps, [&] {
@@ -395,6 +402,7 @@ qhd_status autotune_class(qhd_plan p, ShapeClass& c, double& us_row, double& us_
   c.cap_row = best_row;
   c.cap_col = best_col;
   c.col_variant = best_var;
+  c.row_points = best_pts;
   c.tuned = true;
   return QHD_OK;
 }
@@ -868,6 +876,7 @@ qhd_status qhd_plan_info(qhd_plan p, qhd_class_info* out, int32_t cap, int32_t* 
     o.grid_cap_col = c.cap_col;
     o.tuned = c.tuned ? 1 : 0;
     o.mfma_dft = c.mfma ? 1 : 0;
+    o.row_points_per_lane = c.ndim == 2 ? row_points_resolve(c.nx, c.row_points) : 0;
   }
   return QHD_OK;
 }

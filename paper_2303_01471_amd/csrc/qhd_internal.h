@@ -40,12 +40,14 @@ struct TimingSink {
 // hipSuccess or the launch error.  `nx`, `ny` are the class's mesh sizes.
 hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double* f, const double2* tw_nx, int s, long long max_steps,
-                              int grid_cap, hipStream_t stream);
-// column-pass variants: staged (tile column through LDS, one wavefront per line) or
-// tile-wave (8x8 tiles straight to registers, a line spread over TPL/8 wavefronts);
-// kColAuto takes the measured default for the size
-enum { kColAuto = 0, kColStaged = 1, kColTileWave = 2 };
+                              int grid_cap, int points_per_lane, hipStream_t stream);
+// column-pass variants: staged (tile column through LDS, one wavefront per line, 8
+// or 16 points per lane) or tile-wave (8x8 tiles straight to registers, a line spread
+// over TPL/8 wavefronts); kColAuto takes the measured default for the size
+enum { kColAuto = 0, kColStaged = 1, kColTileWave = 2, kColStaged16 = 3 };
 int col_variant_resolve(int ny, int variant);
+// points per lane of the row pass: 8, or 16 (chosen for 256 and 512; always at 1024)
+int row_points_resolve(int nx, int points_per_lane);
 hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double2* tw_ny, int s, long long max_steps, int grid_cap,
                               int variant, hipStream_t stream);
@@ -100,7 +102,7 @@ hipError_t launch_mfma_pass_3d(int axis, int dir, const InstDev* inst, int ninst
                                float2* psi, const double* f, int s, long long max_steps, int grid_cap,
                                hipStream_t stream);
 
-int pass_blocks_row_2d(int nx, int ny, int ninst, int grid_cap);
+int pass_blocks_row_2d(int nx, int ny, int ninst, int grid_cap, int points_per_lane);
 int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant);
 
 }  // namespace qhd

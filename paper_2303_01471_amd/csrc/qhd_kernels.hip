@@ -644,8 +644,14 @@ inline int blocks_for(long long items, int per_block, int cap) {
 
 }  // namespace
 
-int pass_blocks_row_2d(int nx, int ny, int ninst, int grid_cap) {
-  const int P = nx >= 1024 ? 16 : 8;
+int row_points_resolve(int nx, int points_per_lane) {
+  if (nx >= 1024) return 16;
+  if (points_per_lane == 16 && (nx == 256 || nx == 512)) return 16;
+  return 8;
+}
+
+int pass_blocks_row_2d(int nx, int ny, int ninst, int grid_cap, int points_per_lane) {
+  const int P = row_points_resolve(nx, points_per_lane);
   const int lpw = 256 / (nx / P);
   return blocks_for((long long)ninst * ny, lpw, grid_cap);
 }
@@ -669,16 +675,21 @@ hipError_t launch_col_tw(int blocks, int nx, const InstDev* inst, int ninst, flo
 int col_variant_resolve(int ny, int variant) {
   const bool tw_ok = ny >= 64 && ny <= 512;
   if (variant == kColTileWave && tw_ok) return kColTileWave;
+  if (variant == kColStaged16 && (ny == 256 || ny == 512)) return kColStaged16;
   if (variant == kColStaged) return kColStaged;
   return (ny >= 64 && ny <= 256) ? kColTileWave : kColStaged;  // measured defaults
 }
 
 int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant) {
   int items;
-  if (col_variant_resolve(ny, variant) == kColTileWave) {
+  const int v = col_variant_resolve(ny, variant);
+  if (v == kColTileWave) {
     const int P = 8;  // col_tw_p<N>() for every tile-wave size
     const int w = ny / P / 8;
     items = w >= 4 ? 1 : 4 / w;
+  } else if (v == kColStaged16) {
+    const int tpl = ny / 16;
+    items = (8 * tpl >= 256) ? 1 : 256 / (8 * tpl);
   } else {
     const int tpl = ny / 8;
     items = (8 * tpl >= 256) ? 1 : 256 / (8 * tpl);
@@ -688,8 +699,17 @@ int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant) {
 
 hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double* f, const double2* tw, int s, long long max_steps,
-                              int grid_cap, hipStream_t stream) {
-  const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap);
+                              int grid_cap, int points_per_lane, hipStream_t stream) {
+  const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap, points_per_lane);
+  if (row_points_resolve(nx, points_per_lane) == 16 && nx < 1024) {
+    if (nx == 256)
+      hipLaunchKernelGGL((k_row_pass_2d<256, 16>), dim3(blocks), dim3(256), 0, stream, inst, ninst, ilog2(ny), psi,
+                         f, tw, s, max_steps);
+    else
+      hipLaunchKernelGGL((k_row_pass_2d<512, 16>), dim3(blocks), dim3(256), 0, stream, inst, ninst, ilog2(ny), psi,
+                         f, tw, s, max_steps);
+    return hipGetLastError();
+  }
   QHD_SWITCH_N(nx, {
     constexpr int P_ = pts_per_lane<N_>();
     hipLaunchKernelGGL((k_row_pass_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
@@ -702,8 +722,18 @@ hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, fl
                               const double2* tw, int s, long long max_steps, int grid_cap,
                               int variant, hipStream_t stream) {
   const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap, variant);
-  if (col_variant_resolve(ny, variant) == kColTileWave) {
+  const int v = col_variant_resolve(ny, variant);
+  if (v == kColTileWave) {
     QHD_SWITCH_N(ny, { return launch_col_tw<N_>(blocks, nx, inst, ninst, psi, tw, s, max_steps, stream); });
+  }
+  if (v == kColStaged16) {
+    if (ny == 256)
+      hipLaunchKernelGGL((k_col_pass_2d<256, 16>), dim3(blocks), dim3(ColCfg<256, 16>::NT), 0, stream, inst, ninst,
+                         ilog2(nx), psi, tw, s, max_steps);
+    else
+      hipLaunchKernelGGL((k_col_pass_2d<512, 16>), dim3(blocks), dim3(ColCfg<512, 16>::NT), 0, stream, inst, ninst,
+                         ilog2(nx), psi, tw, s, max_steps);
+    return hipGetLastError();
   }
   switch (ny) {
     case 64: { hipLaunchKernelGGL((k_col_pass_2d<64, 8>), dim3(blocks), dim3(ColCfg<64, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }

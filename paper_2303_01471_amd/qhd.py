@@ -112,6 +112,7 @@ class qhd_class_info(ctypes.Structure):
         ("grid_cap_col", ctypes.c_int32),
         ("tuned", ctypes.c_int32),
         ("mfma_dft", ctypes.c_int32),
+        ("row_points_per_lane", ctypes.c_int32),
     ]
 
 
@@ -411,7 +412,8 @@ class Plan:
         return dict(graph_steps=g, classes=[dict(ndim=c.ndim, n=tuple(c.n), members=c.members,
                                                  col_variant=c.col_variant, cap_row=c.grid_cap_row,
                                                  cap_col=c.grid_cap_col, tuned=bool(c.tuned),
-                                                 mfma_dft=bool(c.mfma_dft)) for c in cls])
+                                                 mfma_dft=bool(c.mfma_dft),
+                                                 row_points=c.row_points_per_lane) for c in cls])
 
     def kernel_timings(self) -> List[dict]:
         return [dict(name=t.name.decode(), launches=t.launches, total_ms=t.total_ms, points=t.points,

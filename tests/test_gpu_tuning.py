@@ -73,19 +73,21 @@ def test_no_graph_for_uneven_plans():
     assert info["graph_steps"] == 0
 
 
-@pytest.mark.parametrize("n,variant,cap_row,cap_col", [(512, 2, 1024, 512), (256, 1, 4096, 8192),
-                                                       (128, 1, 512, 1024), (64, 2, 2048, 512)])
-def test_cached_launch_choice_matches_oracle(tmp_path, n, variant, cap_row, cap_col):
+@pytest.mark.parametrize("n,variant,cap_row,cap_col,row_pts", [(512, 2, 1024, 512, 8), (256, 1, 4096, 8192, 16),
+                                                               (128, 1, 512, 1024, 8), (64, 2, 2048, 512, 8),
+                                                               (512, 3, 2048, 4096, 16), (256, 3, 8192, 1024, 8)])
+def test_cached_launch_choice_matches_oracle(tmp_path, n, variant, cap_row, cap_col, row_pts):
     import torch
-    note(f"case: tuning-cache entry n={n} variant={variant} caps=({cap_row},{cap_col})")
+    note(f"case: tuning-cache entry n={n} variant={variant} caps=({cap_row},{cap_col}) row points {row_pts}")
     nsteps = 300 if n >= 512 else 600
     specs = [q.InstanceSpec(shape=(n, n), nsteps=nsteps, dt=1e-3) for _ in range(3)]
     fs = [qhd_inputs.landscape_grid(70 + k, (n, n)) for k in range(3)]
     arch = torch.cuda.get_device_properties(0).gcnArchName.replace(" ", "_").replace(":", "_")
     cache = tmp_path / "tune.txt"
-    cache.write_text(f"qhd-tune 1 {arch} {n} {n} 4 {variant} {cap_row} {cap_col}\n")
+    cache.write_text(f"qhd-tune 1 {arch} {n} {n} 4 {variant} {cap_row} {cap_col} {row_pts}\n")
     res, psis, _, info = _run(specs, fs, tune_cache=str(cache))
     assert info["classes"][0]["col_variant"] == variant
+    assert info["classes"][0]["row_points"] == row_pts
     assert info["classes"][0]["cap_row"] == cap_row and info["classes"][0]["cap_col"] == cap_col
     for i in (0, 2):
         ref, ro = run_oracle(specs[i], fs[i])
@@ -104,7 +106,7 @@ def test_autotune_writes_cache_that_a_later_plan_reads(tmp_path):
     assert text.startswith("qhd-tune 1 ") and info1["classes"][0]["tuned"]
     r2, p2, _, info2 = _run(specs, fs, tune_cache=cache)
     assert not info2["classes"][0]["tuned"]
-    for k in ("col_variant", "cap_row", "cap_col"):
+    for k in ("col_variant", "cap_row", "cap_col", "row_points"):
         assert info1["classes"][0][k] == info2["classes"][0][k]
     # same launch choice => bitwise the same result; the uniform state was restored
     for a, b in zip(p1, p2):
