@@ -15,6 +15,7 @@
 // B lane l -> column l%32, same k; D register r -> row 8(r/4)+4(l/32)+r%4,
 // column l%32.  Out-of-range rows, columns and k are zero-filled.
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 
 #include "sno_internal.h"
 
@@ -29,15 +30,54 @@ constexpr int BM = 64, BN = 64, BK = 32;
 
 template <typename T>
 struct Lds {
-  // row pitch in elements: 32 k values + padding (keeps 16-byte alignment for BF16)
-  static constexpr int PITCH = sizeof(T) == 2 ? BK + 8 : BK + 1;
+  // row pitch in elements: 32 k values + padding; rows stay 16-byte aligned for the
+  // vector stores of the staging
+  static constexpr int PITCH = sizeof(T) == 2 ? BK + 8 : BK + 4;
 };
 
 template <typename T, bool TRANS>
 __device__ __forceinline__ void stage(T* __restrict__ s, const T* __restrict__ g, int ld, int rows,
-                                      int K, int r0, int k0, bool negate) {
-  // stage rows [r0, r0+64) x k [k0, k0+32) of op(X) into s[row][k]
+                                      int K, int r0, int k0, bool negate, bool vec) {
+  // stage rows [r0, r0+64) x k [k0, k0+32) of op(X) into s[row][k]; with `vec` (16-byte
+  // aligned rows, ld a multiple of the vector length) whole 16-byte vectors are moved
   constexpr int P = Lds<T>::PITCH;
+  constexpr int V = 16 / sizeof(T);  // elements per 16-byte vector
+  typedef T vecT __attribute__((ext_vector_type(V)));
+  if (vec) {
+    if (!TRANS) {  // X stored [row][k]: vectors along k
+      for (int e = threadIdx.x; e < 64 * (32 / V); e += 256) {
+        const int r = e / (32 / V), kv = (e % (32 / V)) * V;
+        const int gr = r0 + r, gk = k0 + kv;
+        vecT v;
+        if (gr < rows && gk + V <= K) {
+          v = *reinterpret_cast<const vecT*>(g + (long long)gr * ld + gk);
+        } else {
+#pragma unroll
+          for (int i = 0; i < V; ++i) v[i] = (gr < rows && gk + i < K) ? g[(long long)gr * ld + gk + i] : (T)0.0f;
+        }
+        if (negate) {
+#pragma unroll
+          for (int i = 0; i < V; ++i) v[i] = (T)(-(float)v[i]);
+        }
+        *reinterpret_cast<vecT*>(s + r * P + kv) = v;
+      }
+    } else {  // X stored [k][row]: vectors along rows, scattered into [row][k]
+      for (int e = threadIdx.x; e < 32 * (64 / V); e += 256) {
+        const int k = e / (64 / V), rv = (e % (64 / V)) * V;
+        const int gr = r0 + rv, gk = k0 + k;
+        vecT v;
+        if (gk < K && gr + V <= rows) {
+          v = *reinterpret_cast<const vecT*>(g + (long long)gk * ld + gr);
+        } else {
+#pragma unroll
+          for (int i = 0; i < V; ++i) v[i] = (gk < K && gr + i < rows) ? g[(long long)gk * ld + gr + i] : (T)0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) s[(rv + i) * P + k] = negate ? (T)(-(float)v[i]) : v[i];
+      }
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < 64 * 32; e += 256) {
     int r, k;
     if (!TRANS) {  // X stored [row][k]: consecutive threads walk k
@@ -59,7 +99,8 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const T* __re
                                               long long sA, const T* __restrict__ B, int ldb,
                                               long long sB, TO* __restrict__ C, int ldc, long long sC,
                                               float alpha, float beta, const T* __restrict__ A2,
-                                              const T* __restrict__ B2, int neg2, int batch) {
+                                              const T* __restrict__ B2, int neg2, int batch, int vecA,
+                                              int vecB) {
   constexpr int P = Lds<T>::PITCH;
   __shared__ __attribute__((aligned(16))) T As[BM * P];
   __shared__ __attribute__((aligned(16))) T Bs[BN * P];
@@ -75,8 +116,8 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const T* __re
     const bool neg = pair == 1 && neg2;
     for (int k0 = 0; k0 < K; k0 += BK) {
       // op(A) is M x K ; op(B) is K x N, staged as [n][k]
-      stage<T, TA>(As, Ap, lda, M, K, m0, k0, neg);
-      stage<T, !TB>(Bs, Bp, ldb, N, K, n0, k0, false);
+      stage<T, TA>(As, Ap, lda, M, K, m0, k0, neg, vecA != 0);
+      stage<T, !TB>(Bs, Bp, ldb, N, K, n0, k0, false, vecB != 0);
       __syncthreads();
       if constexpr (sizeof(T) == 2) {
 #pragma unroll
@@ -121,9 +162,15 @@ hipError_t dispatch(bool ta, bool tb, const GemmArgs& g, hipStream_t stream) {
   const T* B2 = static_cast<const T*>(g.B2);
   const int neg2 = g.scale2 < 0.0f ? 1 : 0;
   if ((A2 == nullptr) != (B2 == nullptr)) return hipErrorInvalidValue;
+  // 16-byte vector staging when every row start of every batch entry is 16-byte aligned
+  constexpr int V = 16 / sizeof(T);
+  auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  const int vecA = (g.lda % V == 0 && g.sA % V == 0 && aligned(A) && (!A2 || aligned(A2))) ? 1 : 0;
+  const int vecB = (g.ldb % V == 0 && g.sB % V == 0 && aligned(B) && (!B2 || aligned(B2))) ? 1 : 0;
 #define QHD_GEMM(TA_, TB_)                                                                    \
   hipLaunchKernelGGL((k_gemm<T, TA_, TB_, TO>), grid, dim3(256), 0, stream, g.M, g.N, g.K, A, \
-                     g.lda, g.sA, B, g.ldb, g.sB, C, g.ldc, g.sC, g.alpha, g.beta, A2, B2, neg2, g.batch)
+                     g.lda, g.sA, B, g.ldb, g.sB, C, g.ldc, g.sC, g.alpha, g.beta, A2, B2, neg2, g.batch, \
+                     vecA, vecB)
   if (!ta && !tb) QHD_GEMM(false, false);
   else if (!ta && tb) QHD_GEMM(false, true);
   else if (ta && !tb) QHD_GEMM(true, false);
