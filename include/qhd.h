@@ -50,7 +50,7 @@ typedef enum {
   /* a = sched_p[0], b = sched_p[1] */
   QHD_SCHED_CONST = 1,
   /* per-step values: a_j = sched_table[2j], b_j = sched_table[2j+1], j = 0..nsteps-1,
-   * each applied over step j (the midpoint value of the step in the symmetric scheme) */
+   * each applied over step j as given, whatever the scheme */
   QHD_SCHED_TABLE = 2
 } qhd_sched_kind;
 
@@ -58,6 +58,16 @@ typedef enum {
   QHD_INIT_UNIFORM = 0, /* psi0 = N^{-1/2} at every mesh point (App. C.2.1 experiment) */
   QHD_INIT_USER = 1     /* qhd_set_state must be called before the first evolve       */
 } qhd_init_kind;
+
+/* Product formula of one step. */
+typedef enum {
+  /* symmetric: e^{-i dt/2 b V} F^{-1} e^{-i dt a L} F e^{-i dt/2 b V}, a and b at the step
+   * midpoint t_{j+1/2} = (j + 1/2) dt (second order) */
+  QHD_SCHEME_STRANG = 0,
+  /* the printed first-order product of App. C.2.1 eq. prod_qhd_fft / Algorithm 1:
+   * F^{-1} e^{-i dt a L} F e^{-i dt b V}, a and b at the left end t_j = j dt */
+  QHD_SCHEME_LIE = 1
+} qhd_scheme;
 
 /* One problem instance (Algorithm 1 of App. E.1). */
 typedef struct {
@@ -73,6 +83,7 @@ typedef struct {
                                 at plan creation; ignored otherwise                      */
   int32_t init_kind;    /* qhd_init_kind                                               */
   double success_radius;/* r > 0 of the success test |x - x*| < r (main text, fig. 2)  */
+  int32_t scheme;       /* qhd_scheme (0, the zero-initialised default: symmetric)     */
 } qhd_instance;
 
 /* Plan options.  Zero-initialise and set what you need. */

@@ -28,11 +28,38 @@ __device__ __forceinline__ void sched_ab(const InstDev& I, long long j, double& 
     a = I.sched_p0;
     b = I.sched_p1;
   } else {
-    const double t = ((double)j + 0.5) * I.dt;
+    // symmetric scheme: step midpoint; printed first-order product: left end
+    const double t = ((double)j + (I.scheme == kSchemeLie ? 0.0 : 0.5)) * I.dt;
     const double t3 = t * t * t;
     a = 2.0 / (I.sched_p0 + t3);
     b = 2.0 * t3;
   }
+}
+
+// Potential phase of the pass that applies V in step j, in turns per unit f.
+// Symmetric scheme: the leading half step of j merged with the trailing half step of
+// j-1 (only the leading half on the entry step, where nothing is pending).
+// First-order product: the full step dt b_j.
+__device__ __forceinline__ double potential_turns(const InstDev& I, long long j, bool entry) {
+  double a, b;
+  sched_ab(I, j, a, b);
+  if (I.scheme == kSchemeLie) return I.dt * b * kInv2Pi;
+  double beta = 0.5 * I.dt * b;
+  if (!entry && j > 0) {
+    double ap, bp;
+    sched_ab(I, j - 1, ap, bp);
+    beta += 0.5 * I.dt * bp;
+  }
+  return beta * kInv2Pi;
+}
+
+// Coefficient of the half step that closes a pending state at a readout (symmetric
+// scheme only: the first-order product leaves no potential factor pending).
+__device__ __forceinline__ double closing_turns(const InstDev& I) {
+  if (I.scheme == kSchemeLie) return 0.0;
+  double a, b;
+  sched_ab(I, I.steps_done - 1, a, b);
+  return 0.5 * I.dt * b * kInv2Pi;
 }
 
 __device__ __forceinline__ long long step_limit(const InstDev& I, long long max_steps) {

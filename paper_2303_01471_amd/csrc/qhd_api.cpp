@@ -76,6 +76,8 @@ qhd_status validate(const qhd_instance& d, int idx) {
     default:
       return fail(QHD_EINVAL, "instance %d: unknown sched_kind %d", idx, d.sched_kind);
   }
+  if (d.scheme != QHD_SCHEME_STRANG && d.scheme != QHD_SCHEME_LIE)
+    return fail(QHD_EINVAL, "instance %d: unknown scheme %d", idx, d.scheme);
   if (d.init_kind != QHD_INIT_UNIFORM && d.init_kind != QHD_INIT_USER)
     return fail(QHD_EINVAL, "instance %d: unknown init_kind %d", idx, d.init_kind);
   return QHD_OK;
@@ -575,6 +577,7 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
         }
       }
       I.sched = d.sched_kind;
+      I.scheme = d.scheme;
       I.sched_p0 = d.sched_p[0];
       I.sched_p1 = d.sched_p[1];
       I.r2 = d.success_radius * d.success_radius;

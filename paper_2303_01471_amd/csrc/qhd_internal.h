@@ -8,6 +8,7 @@
 namespace qhd {
 
 enum : int { kModeClean = 0, kModePending = 1 };
+enum : int { kSchemeStrang = 0, kSchemeLie = 1 };
 enum : int { kSchedNesterov = 0, kSchedConst = 1, kSchedTable = 2 };
 
 // Per-instance parameters as the kernels see them.  One array per shape class.
@@ -27,7 +28,7 @@ struct InstDev {
   int sched;
   int mode;              // kModeClean / kModePending
   int plan_index;        // position in the user's batch
-  int pad_;
+  int scheme;            // kSchemeStrang / kSchemeLie
 };
 
 // Sampled HIP-event timing of pass launches.

@@ -70,14 +70,7 @@ __global__ void __launch_bounds__(256) k_row_pass_2d(const InstDev* __restrict__
     const bool active = valid && s < step_limit(I, max_steps);
     const long long j = I.steps_done + s;
     const bool entry = (s == 0 && I.mode == kModeClean);
-    double a, b, bp;
-    sched_ab(I, j, a, b);
-    double beta = 0.5 * I.dt * b;
-    if (!entry && j > 0) {
-      sched_ab(I, j - 1, a, bp);
-      beta += 0.5 * I.dt * bp;
-    }
-    const double cpot = beta * kInv2Pi;
+    const double cpot = potential_turns(I, j, entry);
     float2* __restrict__ pl = psi + I.psi_off;
     const double* __restrict__ fl = f + I.psi_off;
     float2 reg[P];
@@ -323,14 +316,9 @@ __global__ void __launch_bounds__(256) k_line_pass_1d(const InstDev* __restrict_
     const bool active = valid && s < step_limit(I, max_steps);
     const long long j = I.steps_done + s;
     const bool entry = (s == 0 && I.mode == kModeClean);
-    double a, b, ap, bp;
+    double a, b;
     sched_ab(I, j, a, b);
-    double beta = 0.5 * I.dt * b;
-    if (!entry && j > 0) {
-      sched_ab(I, j - 1, ap, bp);
-      beta += 0.5 * I.dt * bp;
-    }
-    const double cpot = beta * kInv2Pi;
+    const double cpot = potential_turns(I, j, entry);
     const double ck = a * I.kin_turns[0];
     const double inv_n = 1.0 / (double)N;
     const long long base = I.psi_off;
@@ -424,12 +412,13 @@ __global__ void __launch_bounds__(256) k_observe_2d(const InstDev* __restrict__ 
 #pragma unroll
     for (int q = 0; q < P; ++q) fv[q] = f[base + tile_index(t + q * TPL, y, NX)];
     if (pending) {
-      double a, b;
-      sched_ab(I, I.steps_done - 1, a, b);
-      const double cpot = 0.5 * I.dt * b * kInv2Pi;
+      // back to position space; the symmetric scheme also owes the trailing half step
       line_fft<NX, P, +1>(reg, t, tw, my);
+      if (I.scheme != kSchemeLie) {
+        const double cpot = closing_turns(I);
 #pragma unroll
-      for (int q = 0; q < P; ++q) reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fv[q]));
+        for (int q = 0; q < P; ++q) reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fv[q]));
+      }
     }
     const long long rs = I.argmin / NX;
     const int xs = (int)(I.argmin % NX);
@@ -476,12 +465,10 @@ __global__ void __launch_bounds__(256) k_observe_1d(const InstDev* __restrict__ 
     const bool valid = L < ninst;
     const int i = (int)(valid ? L : ninst - 1);
     const InstDev& I = inst[i];
-    double cpot = 0.0;
-    if (I.mode == kModePending) {
-      double a, b;
-      sched_ab(I, I.steps_done - 1, a, b);
-      cpot = 0.5 * I.dt * b * kInv2Pi;
-    }
+    // the symmetric scheme leaves its trailing half step pending; the first-order
+    // product leaves nothing
+    const bool close = I.mode == kModePending && I.scheme != kSchemeLie;
+    const double cpot = close ? closing_turns(I) : 0.0;
     const int xs = (int)I.argmin;
     double sr = 0.0, sf = 0.0, sm = 0.0;
 #pragma unroll
@@ -490,7 +477,7 @@ __global__ void __launch_bounds__(256) k_observe_1d(const InstDev* __restrict__ 
       const long long p = I.psi_off + x;
       const double fv = f[p];
       float2 v = psi[p];
-      if (I.mode == kModePending) v = cmul_fd(v, phase_turns_d(cpot * fv));
+      if (close) v = cmul_fd(v, phase_turns_d(cpot * fv));
       const double rho = (double)v.x * v.x + (double)v.y * v.y;
       sr += rho;
       sf += fv * rho;

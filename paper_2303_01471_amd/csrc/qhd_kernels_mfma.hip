@@ -159,15 +159,7 @@ __global__ void __launch_bounds__(256) k_mfma_pass_3d(const InstDev* __restrict_
     double a, b;
     sched_ab(I, j, a, b);
     const bool entry = MODE == 1 && s == 0 && I.mode == kModeClean;
-    double cpot = 0.0;
-    if constexpr (MODE == 1) {
-      double beta = 0.5 * I.dt * b, a0, bp;
-      if (!entry && j > 0) {
-        sched_ab(I, j - 1, a0, bp);
-        beta += 0.5 * I.dt * bp;
-      }
-      cpot = beta * kInv2Pi;
-    }
+    const double cpot = MODE == 1 ? potential_turns(I, j, entry) : 0.0;
     float2* __restrict__ pl = psi + I.psi_off;
     const double* __restrict__ fl = f + I.psi_off;
     if (tid < 2 * kLines) smax[tid >> 5][tid & 31] = 0u;

@@ -26,6 +26,7 @@ STATUS_NAMES = {0: "QHD_OK", 1: "QHD_EINVAL", 2: "QHD_EUNSUPPORTED", 3: "QHD_ENO
                 4: "QHD_EDEVICE", 5: "QHD_ESTATE", 6: "QHD_ENUMERIC"}
 QHD_SCHED_NESTEROV, QHD_SCHED_CONST, QHD_SCHED_TABLE = 0, 1, 2
 QHD_INIT_UNIFORM, QHD_INIT_USER = 0, 1
+QHD_SCHEME_STRANG, QHD_SCHEME_LIE = 0, 1
 QHD_OPT_TIME_PASSES = 0x1
 QHD_OPT_AUTOTUNE = 0x2
 QHD_OPT_NO_GRAPH = 0x4
@@ -52,6 +53,7 @@ class qhd_instance(ctypes.Structure):
         ("sched_table", ctypes.POINTER(ctypes.c_double)),
         ("init_kind", ctypes.c_int32),
         ("success_radius", ctypes.c_double),
+        ("scheme", ctypes.c_int32),
     ]
 
 
@@ -301,6 +303,7 @@ class InstanceSpec:
     table: Optional[np.ndarray] = None
     init: int = QHD_INIT_UNIFORM
     radius: float = 0.1
+    scheme: int = QHD_SCHEME_STRANG
 
     def to_c(self, keep: list) -> qhd_instance:
         d = qhd_instance()
@@ -326,6 +329,7 @@ class InstanceSpec:
             d.sched_table = tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         d.init_kind = int(self.init)
         d.success_radius = float(self.radius)
+        d.scheme = int(self.scheme)
         return d
 
     @property

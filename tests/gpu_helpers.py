@@ -22,8 +22,9 @@ def note(msg: str):
 def oracle_problem(spec: q.InstanceSpec) -> oracle.Problem:
     sched = {q.QHD_SCHED_NESTEROV: oracle.SCHED_NESTEROV, q.QHD_SCHED_CONST: oracle.SCHED_CONST,
              q.QHD_SCHED_TABLE: oracle.SCHED_TABLE}[spec.sched]
+    scheme = oracle.SCHEME_LIE if spec.scheme == q.QHD_SCHEME_LIE else oracle.SCHEME_STRANG
     return oracle.Problem(shape=tuple(spec.shape), box=spec.box, dt=spec.dt, sched=sched,
-                          params=tuple(spec.sched_p), table=spec.table, radius=spec.radius)
+                          params=tuple(spec.sched_p), table=spec.table, radius=spec.radius, scheme=scheme)
 
 
 def run_gpu(specs: Sequence[q.InstanceSpec], fs: Sequence[np.ndarray], chunks: Optional[List[int]] = None,
