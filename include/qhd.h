@@ -183,6 +183,25 @@ qhd_status qhd_set_steps_done(qhd_plan plan, int32_t i, int64_t j);
  * captured (the passes are then launched directly into the caller's capture). */
 qhd_status qhd_evolve(qhd_plan plan, int64_t max_steps, void *stream);
 
+/* Lowest eigenpairs of the discrete Hamiltonian of 2-D instance i at time t,
+ *     H(t) = a(t) F^{-1} diag(|k|^2/2) F + b(t) diag(f)
+ * (the operator the split-operator step exponentiates, App. C.2.1 eq.
+ * prod_qhd_fft; its low-lying spectrum along the path is the subject of App. D),
+ * by the Lanczos iteration with full reorthogonalisation over `krylov` steps
+ * (nev < krylov <= min(400, points)), from a fixed pseudo-random start vector.
+ * a(t), b(t) follow the instance's schedule (TABLE: the entry of step floor(t/dt)).
+ * Writes the nev lowest Ritz values to energies[] (ascending); if residuals is not
+ * NULL, ||H phi - E phi|| of each unit Ritz vector; if overlaps is not NULL,
+ * |<phi_n|psi>|^2 / <psi|psi> for psi_dev, a device complex64 state of the instance
+ * in row-major order (x fastest; e.g. the instance's slice of qhd_observe's psi
+ * output).  Degenerate eigenvalues are found once (single-vector Krylov space).
+ * Matrix-vector products in FP32 on the GPU, scalars in FP64.  Allocates and frees
+ * (krylov + 4) vectors of the instance's size; synchronous on `stream`.  Not for
+ * stream capture.  QHD_EUNSUPPORTED for 1-D/3-D instances. */
+qhd_status qhd_spectrum(qhd_plan plan, int32_t i, double t, int32_t nev, int32_t krylov,
+                        const float *psi_dev, double *energies, double *overlaps, double *residuals,
+                        void *stream);
+
 /* Launch configuration: up to `cap` classes into out[], their number into
  * *n_classes, and the steps per captured graph chunk into *graph_steps (0: no
  * graph).  Host-only. */

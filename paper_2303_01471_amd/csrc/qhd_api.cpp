@@ -437,6 +437,28 @@ qhd_status build_step_graph(qhd_plan p, int k) {
 namespace qhd {
 // shared with the surrogate's entry points, which report through qhd_last_error()
 void set_error_message(const char* msg) { g_err = msg ? msg : ""; }
+
+// read-only view of one instance for the spectrum entry point
+qhd_status plan_instance_view(qhd_plan p, int i, InstanceView* v) {
+  if (!p || !v) return fail(QHD_EINVAL, "NULL argument");
+  if (i < 0 || i >= (int)p->inst.size()) return fail(QHD_EINVAL, "instance index %d out of range", i);
+  const ShapeClass& c = p->classes[p->cls_of[i]];
+  const int pos = p->pos_of[i];
+  const qhd_instance& d = p->inst[i];
+  v->ndim = c.ndim;
+  v->nx = c.nx;
+  v->ny = c.ny;
+  v->nz = c.nz;
+  v->f = c.f + c.host[pos].psi_off;
+  v->tw_x = c.tw_x;
+  v->tw_y = c.tw_y;
+  v->host = c.host[pos];
+  v->device = p->device;
+  v->potential_set = p->potential_set[i] != 0;
+  for (int a = 0; a < 3; ++a) v->length[a] = d.hi[a] - d.lo[a];
+  v->internal = p->internal;
+  return QHD_OK;
+}
 }  // namespace qhd
 
 extern "C" {

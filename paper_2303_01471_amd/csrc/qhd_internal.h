@@ -31,6 +31,19 @@ struct InstDev {
   int scheme;            // kSchemeStrang / kSchemeLie
 };
 
+// What the spectrum entry point (qhd_spectrum.cpp) reads of one plan instance.
+struct InstanceView {
+  int ndim, nx, ny, nz;
+  const double* f;        // the instance's tiled FP64 potential
+  const double2* tw_x;    // twiddle tables W_N^j of the x and y line lengths
+  const double2* tw_y;
+  InstDev host;           // host mirror of the instance parameters
+  int device;
+  bool potential_set;
+  double length[3];       // box lengths per axis
+  hipStream_t internal;   // the plan's own stream
+};
+
 // Sampled HIP-event timing of pass launches.
 struct TimingSink {
   hipEvent_t* ev;        // pairs (start, stop); nullptr when timing is off
@@ -105,5 +118,17 @@ hipError_t launch_mfma_pass_3d(int axis, int dir, const InstDev* inst, int ninst
 
 int pass_blocks_row_2d(int nx, int ny, int ninst, int grid_cap, int points_per_lane);
 int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant);
+
+// spectrum kernels (qhd_spectrum_kernels.hip); v is a plain row-major (x fastest)
+// complex64 vector of one nx x ny instance
+hipError_t spec_lines(int axis, int sign, float2* v, int nx, int ny, const double2* tw, hipStream_t st);
+hipError_t spec_kinetic(float2* v, int nx, int ny, double cx, double cy, double s, hipStream_t st);
+hipError_t spec_finish(float2* out, const float2* w, const float2* v, const double* f, double b, int nx, int ny,
+                       hipStream_t st);
+hipError_t spec_multidot(const float2* V, long long n, int count, const float2* w, double* partials, int nblk,
+                         hipStream_t st);
+hipError_t spec_multiaxpy(float2* w, const float2* V, long long n, int count, const double* c, double scale,
+                          hipStream_t st);
+hipError_t spec_random(float2* v, long long n, unsigned long long seed, hipStream_t st);
 
 }  // namespace qhd

@@ -135,6 +135,9 @@ _SIGNATURES = {
     "qhd_kernel_timings": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(qhd_kernel_timing),
                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "qhd_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "qhd_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]),
     "qhd_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(qhd_class_info), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "qhd_last_error": (ctypes.c_char_p, []),
@@ -241,6 +244,18 @@ def qhd_plan_info(plan: int, cap: int = 16):
     g = ctypes.c_int32()
     _check(load_library().qhd_plan_info(plan, arr, cap, ctypes.byref(n), ctypes.byref(g)))
     return [arr[k] for k in range(min(n.value, cap))], g.value
+
+
+def qhd_spectrum(plan: int, i: int, t: float, nev: int, krylov: int, psi_ptr: int = 0, stream: int = 0,
+                 want_overlaps: bool = False, want_residuals: bool = True):
+    """Returns (energies, overlaps or None, residuals or None) as numpy arrays."""
+    e = np.zeros(nev)
+    o = np.zeros(nev) if want_overlaps else None
+    r = np.zeros(nev) if want_residuals else None
+    _check(load_library().qhd_spectrum(plan, i, t, nev, krylov, psi_ptr or None, e.ctypes.data,
+                                       o.ctypes.data if o is not None else None,
+                                       r.ctypes.data if r is not None else None, stream))
+    return e, o, r
 
 
 def qhd_plan_destroy(plan: int):
@@ -409,6 +424,16 @@ class Plan:
     def psi_of(self, psi_flat, i: int):
         a, b = int(self.offsets[i]), int(self.offsets[i + 1])
         return psi_flat[a:b].reshape(tuple(self.specs[i].shape))
+
+    def spectrum(self, i: int, t: float, nev: int = 6, krylov: int = 200, psi=None, stream=None):
+        """Lowest nev eigenvalues of H(t) of instance i (2-D), residual norms and, if a
+        state psi (CUDA complex64, row-major) is given, the overlaps |<phi_n|psi>|^2."""
+        if psi is not None:
+            import torch
+            assert psi.dtype == torch.complex64 and psi.is_cuda and psi.is_contiguous()
+            assert psi.numel() == self.specs[i].points
+        return qhd_spectrum(self.handle, i, float(t), nev, krylov, psi.data_ptr() if psi is not None else 0,
+                            _stream_handle(stream), want_overlaps=psi is not None)
 
     def graph_info(self) -> dict:
         """Launch configuration chosen at plan creation (classes, graph chunk)."""

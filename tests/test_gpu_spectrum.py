@@ -1,0 +1,107 @@
+"""Lowest eigenpairs of H(t) (Lanczos on the GPU through qhd_spectrum) against
+the dense FP64 reference and the oscillator's closed form."""
+import math
+
+import numpy as np
+import pytest
+
+import qhd_inputs
+from gpu_helpers import note
+from oracle import spectrum_reference as sr
+from paper_2303_01471_amd import qhd as q
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    q.load_library()
+
+
+def _plan(spec, f):
+    plan = q.Plan([spec])
+    plan.set_potential(0, f)
+    return plan
+
+
+def test_lowest_levels_of_a_landscape_match_dense_reference():
+    import torch
+    spec = q.InstanceSpec(shape=(16, 32), nsteps=10, dt=1e-3, box=((0.0, 1.0), (-0.5, 1.5)))
+    f = qhd_inputs.evaluate(qhd_inputs.draw_landscape(7), spec.shape, spec.box)
+    t = 0.7
+    a, b = sr.nesterov_ab(t)
+    w, vecs = sr.lowest(f, spec.box, a, b, 8)
+    H = sr.hamiltonian(f, spec.box, a, b)
+    hnorm = np.max(np.abs(np.linalg.eigvalsh(H)))
+    plan = _plan(spec, f)
+    try:
+        # overlaps against the reference's third eigenvector
+        psi = torch.from_numpy(vecs[:, 2].astype(np.complex64)).cuda().contiguous()
+        e, ov, res = plan.spectrum(0, t, nev=6, krylov=400, psi=psi)
+    finally:
+        plan.close()
+    note(f"  E = {e}; dense {w[:6]}; ||H|| {hnorm:.1f}; residuals {res}; overlaps {ov}")
+    # FP32 matrix-vector products: errors of order 1e-7 ||H||
+    assert np.max(np.abs(e - w[:6])) < 2e-6 * hnorm
+    assert np.all(res < 2e-6 * hnorm)
+    assert ov[2] > 0.999 and np.sum(ov) - ov[2] < 1e-3
+
+
+def test_oscillator_levels_closed_form():
+    # a = b = 1 (CONST), f = (x^2 + 2 y^2)/2 on [-6, 6)^2, 128^2: E = (n1 + 1/2) + sqrt 2 (n2 + 1/2)
+    n, L = 128, 12.0
+    x = -L / 2 + np.arange(n) * (L / n)
+    f = 0.5 * (x[None, :] ** 2 + 2.0 * x[:, None] ** 2)
+    spec = q.InstanceSpec(shape=(n, n), nsteps=10, dt=1e-3, box=((-6.0, 6.0), (-6.0, 6.0)),
+                          sched=q.QHD_SCHED_CONST, sched_p=(1.0, 1.0))
+    plan = _plan(spec, f)
+    try:
+        e, _, res = plan.spectrum(0, 0.0, nev=5, krylov=300)
+    finally:
+        plan.close()
+    exact = np.array(sorted((i + 0.5) + math.sqrt(2.0) * (j + 0.5) for i in range(8) for j in range(8))[:5])
+    note(f"  oscillator E = {e}; exact {exact}; residuals {res}")
+    assert np.max(np.abs(e - exact)) < 2e-3
+
+
+def test_spectrum_errors():
+    spec3 = q.InstanceSpec(shape=(16, 16, 16), nsteps=1, dt=1e-3)
+    plan = q.Plan([spec3])
+    try:
+        plan.set_potential(0, np.zeros((16, 16, 16)))
+        with pytest.raises(q.QHDError) as e:
+            plan.spectrum(0, 1.0)
+        assert e.value.status == q.QHD_EUNSUPPORTED
+    finally:
+        plan.close()
+    plan = q.Plan([q.InstanceSpec(shape=(16, 16), nsteps=1, dt=1e-3)])
+    try:
+        with pytest.raises(q.QHDError) as e:
+            plan.spectrum(0, 1.0)
+        assert e.value.status == q.QHD_ESTATE
+        plan.set_potential(0, np.zeros((16, 16)))
+        with pytest.raises(q.QHDError) as e:
+            plan.spectrum(0, 1.0, nev=6, krylov=6)
+        assert e.value.status == q.QHD_EINVAL
+    finally:
+        plan.close()
+
+
+def test_trajectory_snapshots_match_oracle_and_weights_are_a_distribution():
+    from gpu_helpers import run_oracle
+    from paper_2303_01471_amd import trajectory
+    spec = q.InstanceSpec(shape=(64, 64), nsteps=300, dt=1e-2)
+    f = qhd_inputs.landscape_grid(1234, (64, 64))
+    snaps = trajectory.run(spec, f, times=(0.1, 0.5, 1.0, 3.0), nev=4, krylov=120)
+    for rec in snaps:
+        sub = q.InstanceSpec(shape=(64, 64), nsteps=rec["steps"], dt=1e-2)
+        _, ro = run_oracle(sub, f)
+        note(f"  t={rec['t']:.2f}: E[f] {rec['e_f']:.6f} (oracle {ro.e_f:.6f}) P {rec['success_mass']:.6f} "
+             f"levels {rec['energies']} weights {rec['weights']}")
+        assert abs(rec["e_f"] - ro.e_f) < 1e-4 and abs(rec["success_mass"] - ro.success) < 1e-4
+        assert np.all(rec["weights"] >= 0) and np.sum(rec["weights"]) <= 1 + 1e-5
+        assert np.all(np.diff(rec["energies"]) >= -1e-9)
