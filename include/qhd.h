@@ -51,8 +51,22 @@ typedef enum {
   QHD_SCHED_CONST = 1,
   /* per-step values: a_j = sched_table[2j], b_j = sched_table[2j+1], j = 0..nsteps-1,
    * each applied over step j as given, whatever the scheme */
-  QHD_SCHED_TABLE = 2
+  QHD_SCHED_TABLE = 2,
+  /* adiabatic interpolation g(t) = t / T, T = sched_p[0]: a = 1 - g, b = g (the
+   * baseline QAA's linear schedule, App. C.2 "Quantum Adiabatic Algorithm") */
+  QHD_SCHED_LINEAR = 3
 } qhd_sched_kind;
+
+/* Which Hamiltonian the instance evolves under: H = a(t) H_0 + b(t) diag(f). */
+typedef enum {
+  /* QHD: H_0 = -1/2 Laplacian on the periodic mesh (main text, App. C.2.1) */
+  QHD_MODEL_QHD = 0,
+  /* the baseline quantum adiabatic algorithm the paper compares with (App. C.2): each
+   * axis index written in radix 2 (log2 n qubits), H_0 = -sum_j sigma_x^(j) over all
+   * qubits, diagonal in the Walsh-Hadamard basis.  2-D only; use QHD_SCHED_LINEAR with
+   * T = nsteps * dt for the paper's setting.  The box only labels the mesh points. */
+  QHD_MODEL_QAA = 1
+} qhd_model;
 
 typedef enum {
   QHD_INIT_UNIFORM = 0, /* psi0 = N^{-1/2} at every mesh point (App. C.2.1 experiment) */
@@ -84,6 +98,7 @@ typedef struct {
   int32_t init_kind;    /* qhd_init_kind                                               */
   double success_radius;/* r > 0 of the success test |x - x*| < r (main text, fig. 2)  */
   int32_t scheme;       /* qhd_scheme (0, the zero-initialised default: symmetric)     */
+  int32_t model;        /* qhd_model (0, the zero-initialised default: QHD)            */
 } qhd_instance;
 
 /* Plan options.  Zero-initialise and set what you need. */

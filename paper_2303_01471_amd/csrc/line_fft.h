@@ -365,6 +365,37 @@ __device__ __forceinline__ void load_twiddles(TwiddlesLds<N, P>& tw, const doubl
 }
 
 // ---------------------------------------------------------------------------------
+// Walsh-Hadamard transform of one line (unnormalised, natural order):
+// X_u = sum_i (-1)^{popcount(u & i)} x_i.  Point i = t + q TPL: the bits of q are
+// combined in registers, the bits of t across the line's TPL consecutive lanes by
+// xor shuffles (a line never spans two wavefronts).  Additions only: exact up to
+// one rounding per butterfly.
+template <int N, int P>
+__device__ __forceinline__ void line_wht(float2 (&reg)[P], int t) {
+  constexpr int TPL = N / P;
+#pragma unroll
+  for (int h = 1; h < P; h <<= 1) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      if (!(q & h)) {
+        const float2 a = reg[q], b = reg[q | h];
+        reg[q] = fadd(a, b);
+        reg[q | h] = fsub(a, b);
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 1; h < TPL; h <<= 1) {
+    const bool upper = (t & h) != 0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const float2 o = make_float2(__shfl_xor(reg[q].x, h), __shfl_xor(reg[q].y, h));
+      reg[q] = upper ? fsub(o, reg[q]) : fadd(reg[q], o);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
 // unit phase factors
 
 // sin(2 pi r), cos(2 pi r) for |r| <= 1/2 (turns).

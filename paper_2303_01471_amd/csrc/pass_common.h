@@ -16,6 +16,9 @@ __device__ __forceinline__ long long tile_index(int x, int y, int nx) {
   return ((long long)((y >> 3) * (nx >> 3) + (x >> 3)) << 6) + ((y & 7) << 3) + (x & 7);
 }
 
+// integer frequency of FFT output index m on an axis of n points
+__device__ __forceinline__ int freq(int m, int n) { return m < (n >> 1) ? m : m - n; }
+
 // a_j, b_j of global step j (App. C.2.1, eq. nonconvex_QHD_h at the midpoint)
 __device__ __forceinline__ void sched_ab(const InstDev& I, long long j, double& a, double& b) {
   if (I.sched == kSchedTable) {
@@ -27,12 +30,33 @@ __device__ __forceinline__ void sched_ab(const InstDev& I, long long j, double& 
   } else if (I.sched == kSchedConst) {
     a = I.sched_p0;
     b = I.sched_p1;
+  } else if (I.sched == kSchedLinear) {
+    // adiabatic interpolation g = t / T: H0 weight 1 - g, problem weight g
+    const double t = ((double)j + (I.scheme == kSchemeLie ? 0.0 : 0.5)) * I.dt;
+    const double g = t / I.sched_p0;
+    a = 1.0 - g;
+    b = g;
   } else {
     // symmetric scheme: step midpoint; printed first-order product: left end
     const double t = ((double)j + (I.scheme == kSchemeLie ? 0.0 : 0.5)) * I.dt;
     const double t3 = t * t * t;
     a = 2.0 / (I.sched_p0 + t3);
     b = 2.0 * t3;
+  }
+}
+
+// Phase of the transformed-basis factor along one axis, in turns per unit of the
+// coefficient a: QHD, the kinetic term (pi dt / L^2) n^2 of frequency n (App. C.2.1);
+// QAA, the transverse field -sum sigma_x of the axis' qubits, whose eigenvalue in the
+// Walsh-Hadamard basis is 2 popcount(u) - bits, times dt / (2 pi).
+template <int MODEL>
+__device__ __forceinline__ double axis_turns(const InstDev& I, int axis, int idx, int n) {
+  if constexpr (MODEL == kModelQAA) {
+    const int bits = 31 - __builtin_clz(n);
+    return I.dt * kInv2Pi * (double)(2 * __builtin_popcount(idx) - bits);
+  } else {
+    const int m = freq(idx, n);
+    return I.kin_turns[axis] * (double)(m * m);
   }
 }
 
@@ -67,7 +91,6 @@ __device__ __forceinline__ long long step_limit(const InstDev& I, long long max_
   return (max_steps < 0 || max_steps > rem) ? rem : max_steps;
 }
 
-__device__ __forceinline__ int freq(int m, int n) { return m < (n >> 1) ? m : m - n; }
 
 // offset of slot q of lane t on tiled row y (x = t + q*TPL); compile-time stride
 // between slots once a slot spans whole tiles

@@ -68,6 +68,10 @@ qhd_status validate(const qhd_instance& d, int idx) {
       if (!std::isfinite(d.sched_p[0]) || !std::isfinite(d.sched_p[1]))
         return fail(QHD_EINVAL, "instance %d: CONST schedule needs finite a0, b0", idx);
       break;
+    case QHD_SCHED_LINEAR:
+      if (!std::isfinite(d.sched_p[0]) || !(d.sched_p[0] > 0.0))
+        return fail(QHD_EINVAL, "instance %d: LINEAR schedule needs T = sched_p[0] > 0", idx);
+      break;
     case QHD_SCHED_TABLE:
       if (d.nsteps > 0 && !d.sched_table) return fail(QHD_EINVAL, "instance %d: TABLE schedule needs sched_table", idx);
       for (int64_t j = 0; j < 2 * d.nsteps; ++j)
@@ -78,6 +82,10 @@ qhd_status validate(const qhd_instance& d, int idx) {
   }
   if (d.scheme != QHD_SCHEME_STRANG && d.scheme != QHD_SCHEME_LIE)
     return fail(QHD_EINVAL, "instance %d: unknown scheme %d", idx, d.scheme);
+  if (d.model != QHD_MODEL_QHD && d.model != QHD_MODEL_QAA)
+    return fail(QHD_EINVAL, "instance %d: unknown model %d", idx, d.model);
+  if (d.model == QHD_MODEL_QAA && d.ndim != 2)
+    return fail(QHD_EUNSUPPORTED, "instance %d: the QAA model is built for 2-D meshes", idx);
   if (d.init_kind != QHD_INIT_UNIFORM && d.init_kind != QHD_INIT_USER)
     return fail(QHD_EINVAL, "instance %d: unknown init_kind %d", idx, d.init_kind);
   return QHD_OK;
@@ -118,6 +126,7 @@ struct ShapeClass {
   int cap_row = 2048, cap_col = 2048;
   bool tuned = false;
   bool mfma = false;  // 3-D 128^3 with QHD_OPT_MFMA_DFT
+  int model = kModelQHD;
 };
 
 struct qhd_plan_s {
@@ -285,11 +294,11 @@ qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<
       } else if (c.ndim == 2) {
         HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
           return launch_row_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, (int)s, max_steps,
-                                    c.cap_row, c.row_points, stream);
+                                    c.cap_row, c.row_points, stream, c.model);
         }));
         HIP_TRY(timed_launch(c.fam_col, pts, sample, [&] {
           return launch_col_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
-                                    c.cap_col, c.col_variant, stream);
+                                    c.cap_col, c.col_variant, stream, c.model);
         }));
       } else {
         HIP_TRY(timed_launch(c.fam_line, pts, sample, [&] {
@@ -507,11 +516,11 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
   }
 
   // group into shape classes
-  std::map<std::tuple<int, int, int, int>, int> key2cls;
+  std::map<std::tuple<int, int, int, int, int>, int> key2cls;
   for (int i = 0; i < batch; ++i) {
     const qhd_instance& d = inst[i];
     const int nx = d.n[0], ny = d.ndim >= 2 ? d.n[1] : 1, nz = d.ndim >= 3 ? d.n[2] : 1;
-    auto key = std::make_tuple(d.ndim, nx, ny, nz);
+    auto key = std::make_tuple(d.ndim, nx, ny, nz, d.model);
     auto it = key2cls.find(key);
     int c;
     if (it == key2cls.end()) {
@@ -523,6 +532,7 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       sc.ny = ny;
       sc.nz = nz;
       sc.points = (long long)nx * ny * nz;
+      sc.model = d.model;
       p->classes.push_back(sc);
     } else {
       c = it->second;
@@ -600,6 +610,7 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       }
       I.sched = d.sched_kind;
       I.scheme = d.scheme;
+      I.model = d.model;
       I.sched_p0 = d.sched_p[0];
       I.sched_p1 = d.sched_p[1];
       I.r2 = d.success_radius * d.success_radius;
@@ -701,6 +712,7 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
     for (auto& c : p->classes) {
       c.cap_row = c.cap_col = p->grid_cap;
       if (c.ndim != 2) continue;
+      if (c.model == kModelQAA) continue;  // one fixed launch form (staged columns)
       if (!env_cap) {
         // measured defaults (uniform batches of 256 instances per size on MI355X)
         c.cap_row = c.nx >= 512 ? 8192 : (c.nx >= 256 ? 4096 : 1024);
@@ -941,7 +953,7 @@ qhd_status qhd_observe(qhd_plan p, void* stream_v, qhd_observables* out, float* 
     const int m = (int)c.members.size();
     if (c.ndim >= 2)
       HIP_TRY(launch_observe_2d(c.nx, c.ny * c.nz, c.ny, c.dev, m, c.psi, c.f, c.tw_x,
-                                reinterpret_cast<float2*>(psi_dev), rho_dev, c.partials, stream));
+                                reinterpret_cast<float2*>(psi_dev), rho_dev, c.partials, stream, c.model));
     else
       HIP_TRY(launch_observe_1d(c.nx, c.dev, m, c.psi, c.f, reinterpret_cast<float2*>(psi_dev),
                                 rho_dev, c.partials, stream));

@@ -9,7 +9,8 @@ namespace qhd {
 
 enum : int { kModeClean = 0, kModePending = 1 };
 enum : int { kSchemeStrang = 0, kSchemeLie = 1 };
-enum : int { kSchedNesterov = 0, kSchedConst = 1, kSchedTable = 2 };
+enum : int { kModelQHD = 0, kModelQAA = 1 };
+enum : int { kSchedNesterov = 0, kSchedConst = 1, kSchedTable = 2, kSchedLinear = 3 };
 
 // Per-instance parameters as the kernels see them.  One array per shape class.
 struct InstDev {
@@ -29,6 +30,8 @@ struct InstDev {
   int mode;              // kModeClean / kModePending
   int plan_index;        // position in the user's batch
   int scheme;            // kSchemeStrang / kSchemeLie
+  int model;             // kModelQHD / kModelQAA
+  int pad_;
 };
 
 // What the spectrum entry point (qhd_spectrum.cpp) reads of one plan instance.
@@ -54,7 +57,7 @@ struct TimingSink {
 // hipSuccess or the launch error.  `nx`, `ny` are the class's mesh sizes.
 hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double* f, const double2* tw_nx, int s, long long max_steps,
-                              int grid_cap, int points_per_lane, hipStream_t stream);
+                              int grid_cap, int points_per_lane, hipStream_t stream, int model = kModelQHD);
 // column-pass variants: staged (tile column through LDS, one wavefront per line, 8
 // or 16 points per lane) or tile-wave (8x8 tiles straight to registers, a line spread
 // over TPL/8 wavefronts); kColAuto takes the measured default for the size
@@ -64,7 +67,7 @@ int col_variant_resolve(int ny, int variant);
 int row_points_resolve(int nx, int points_per_lane);
 hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double2* tw_ny, int s, long long max_steps, int grid_cap,
-                              int variant, hipStream_t stream);
+                              int variant, hipStream_t stream, int model = kModelQHD);
 hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* psi, const double* f,
                                const double2* tw, int s, long long max_steps, int grid_cap,
                                hipStream_t stream);
@@ -87,7 +90,7 @@ hipError_t launch_zpass_3d(int nx, int ny, int nz, const InstDev* inst, int nins
 hipError_t launch_observe_2d(int nx, int rows, int ny, const InstDev* inst, int ninst,
                              const float2* psi, const double* f, const double2* tw_nx,
                              float2* out_psi, float* out_rho, double* partials,
-                             hipStream_t stream);
+                             hipStream_t stream, int model = kModelQHD);
 hipError_t launch_observe_1d(int n, const InstDev* inst, int ninst, const float2* psi,
                              const double* f, float2* out_psi, float* out_rho, double* partials,
                              hipStream_t stream);

@@ -40,10 +40,19 @@
 
 namespace qhd {
 
+// The line transform of a model: the DFT for QHD (kinetic term diagonal in Fourier
+// space), the Walsh-Hadamard transform for QAA (transverse field diagonal in the
+// Hadamard basis; its own inverse up to 1/N, so S is ignored).
+template <int MODEL, int N, int P, int S, typename TW>
+__device__ __forceinline__ void line_xform(float2 (&reg)[P], int t, const TW& tw, float2* lds) {
+  if constexpr (MODEL == kModelQAA) line_wht<N, P>(reg, t);
+  else line_fft<N, P, S>(reg, t, tw, lds);
+}
+
 // ------------------------------------------------------------------------------------
 // 2-D row pass: lines along x, one line per TPL lanes.
 
-template <int NX, int P>
+template <int NX, int P, int MODEL = kModelQHD>
 __global__ void __launch_bounds__(256) k_row_pass_2d(const InstDev* __restrict__ inst, int ninst,
                                                      int ny_log2, float2* __restrict__ psi,
                                                      const double* __restrict__ f,
@@ -76,10 +85,10 @@ __global__ void __launch_bounds__(256) k_row_pass_2d(const InstDev* __restrict__
     float2 reg[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) reg[q] = pl[row_slot<NX, TPL>(t, q, y)];
-    if (!entry) line_fft<NX, P, +1>(reg, t, tw, my);
+    if (!entry) line_xform<MODEL, NX, P, +1>(reg, t, tw, my);
 #pragma unroll
     for (int q = 0; q < P; ++q) reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fl[row_slot<NX, TPL>(t, q, y)]));
-    line_fft<NX, P, -1>(reg, t, tw, my);
+    line_xform<MODEL, NX, P, -1>(reg, t, tw, my);
     if (active) {
 #pragma unroll
       for (int q = 0; q < P; ++q) pl[row_slot<NX, TPL>(t, q, y)] = reg[q];
@@ -102,7 +111,7 @@ struct ColCfg {
   static constexpr int STRIDE = ((LineLds<NY>::kSlots + 13) / 16) * 16 + 2;
 };
 
-template <int NY, int P>
+template <int NY, int P, int MODEL = kModelQHD>
 __global__ void __launch_bounds__(256) k_col_pass_2d(
     const InstDev* __restrict__ inst, int ninst, int nx_log2, float2* __restrict__ psi,
     const double2* __restrict__ twtab, int s, long long max_steps) {
@@ -157,24 +166,36 @@ __global__ void __launch_bounds__(256) k_col_pass_2d(
       const int x = tc * 8 + (line & 7);
       double a, b;
       sched_ab(I, I.steps_done + s, a, b);
-      const double cy = a * I.kin_turns[1];
+      const double cy = a * (MODEL == kModelQAA ? I.dt : I.kin_turns[1]);
       if (cy != cached) {
-        // E_y(k_y) / (nx ny) for this lane's slots: computed once per distinct coefficient
+        // E_y / (nx ny) for this lane's slots: computed once per distinct coefficient
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-          const int nyf = freq(t + q * TPL, NY);
-          const double2 e = phase_turns_d(cy * (double)(nyf * nyf));
+          double arg;
+          if constexpr (MODEL == kModelQAA) {
+            arg = a * axis_turns<MODEL>(I, 1, t + q * TPL, NY);
+          } else {
+            const int nyf = freq(t + q * TPL, NY);
+            arg = cy * (double)(nyf * nyf);
+          }
+          const double2 e = phase_turns_d(arg);
           ey[q] = make_double2(e.x * inv_n, e.y * inv_n);
         }
         cached = cy;
       }
-      const int nxf = freq(x, nx);
-      const double2 ex = phase_turns_d(a * I.kin_turns[0] * (double)(nxf * nxf));
+      double xarg;
+      if constexpr (MODEL == kModelQAA) {
+        xarg = a * axis_turns<MODEL>(I, 0, x, nx);
+      } else {
+        const int nxf = freq(x, nx);
+        xarg = a * I.kin_turns[0] * (double)(nxf * nxf);
+      }
+      const double2 ex = phase_turns_d(xarg);
       float2 reg[P];
 #pragma unroll
       for (int q = 0; q < P; ++q) reg[q] = my[lds_slot(t + q * TPL)];
       wave_lds_sync();
-      line_fft<NY, P, -1>(reg, t, tw, my);
+      line_xform<MODEL, NY, P, -1>(reg, t, tw, my);
 #pragma unroll
       for (int q = 0; q < P; ++q) {
         // E_x E_y in FP64, rounded once: FP32 factors rounded separately gain a one-sided
@@ -182,7 +203,8 @@ __global__ void __launch_bounds__(256) k_col_pass_2d(
         const double2 k = make_double2(fma(ex.x, ey[q].x, -ex.y * ey[q].y), fma(ex.x, ey[q].y, ex.y * ey[q].x));
         reg[q] = cmul_ff(reg[q], make_float2((float)k.x, (float)k.y));
       }
-      line_fft<NY, P, +1>(reg, t, tw, my);
+      line_xform<MODEL, NY, P, +1>(reg, t, tw, my);
+      if constexpr (MODEL == kModelQAA) wave_lds_sync();  // the transform did not touch LDS
 #pragma unroll
       for (int q = 0; q < P; ++q) my[lds_slot(t + q * TPL)] = reg[q];
     }
@@ -379,7 +401,7 @@ __device__ __forceinline__ bool in_ball(int dxi, int dyi, int dzi, const InstDev
   return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz)) < I.r2;
 }
 
-template <int NX, int P>
+template <int NX, int P, int MODEL = kModelQHD>
 __global__ void __launch_bounds__(256) k_observe_2d(const InstDev* __restrict__ inst, int ninst,
                                                     int ny_log2, int slab_log2,
                                                     const float2* __restrict__ psi,
@@ -413,7 +435,7 @@ __global__ void __launch_bounds__(256) k_observe_2d(const InstDev* __restrict__ 
     for (int q = 0; q < P; ++q) fv[q] = f[base + tile_index(t + q * TPL, y, NX)];
     if (pending) {
       // back to position space; the symmetric scheme also owes the trailing half step
-      line_fft<NX, P, +1>(reg, t, tw, my);
+      line_xform<MODEL, NX, P, +1>(reg, t, tw, my);
       if (I.scheme != kSchemeLie) {
         const double cpot = closing_turns(I);
 #pragma unroll
@@ -686,7 +708,16 @@ int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant) {
 
 hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double* f, const double2* tw, int s, long long max_steps,
-                              int grid_cap, int points_per_lane, hipStream_t stream) {
+                              int grid_cap, int points_per_lane, hipStream_t stream, int model) {
+  if (model == kModelQAA) {
+    const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap, 8);
+    QHD_SWITCH_N(nx, {
+      constexpr int P_ = pts_per_lane<N_>();
+      hipLaunchKernelGGL((k_row_pass_2d<N_, P_, kModelQAA>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+                         ilog2(ny), psi, f, tw, s, max_steps);
+      return hipGetLastError();
+    });
+  }
   const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap, points_per_lane);
   if (row_points_resolve(nx, points_per_lane) == 16 && nx < 1024) {
     if (nx == 256)
@@ -707,7 +738,16 @@ hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, fl
 
 hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double2* tw, int s, long long max_steps, int grid_cap,
-                              int variant, hipStream_t stream) {
+                              int variant, hipStream_t stream, int model) {
+  if (model == kModelQAA) {  // staged form only: the Walsh-Hadamard lines use in-wave shuffles
+    const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap, kColStaged);
+    QHD_SWITCH_N(ny, {
+      constexpr int P_ = pts_per_lane<N_>();
+      hipLaunchKernelGGL((k_col_pass_2d<N_, P_, kModelQAA>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0, stream,
+                         inst, ninst, ilog2(nx), psi, tw, s, max_steps);
+      return hipGetLastError();
+    });
+  }
   const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap, variant);
   const int v = col_variant_resolve(ny, variant);
   if (v == kColTileWave) {
@@ -764,13 +804,17 @@ hipError_t launch_reset_inst(InstDev* inst, int ninst, hipStream_t stream) {
 hipError_t launch_observe_2d(int nx, int rows, int ny, const InstDev* inst, int ninst,
                              const float2* psi, const double* f, const double2* tw,
                              float2* out_psi, float* out_rho, double* partials,
-                             hipStream_t stream) {
+                             hipStream_t stream, int model) {
   QHD_SWITCH_N(nx, {
     constexpr int P_ = pts_per_lane<N_>();
     constexpr int LPW_ = 256 / (N_ / P_);
     const int blocks = blocks_for((long long)ninst * rows, LPW_, 4096);
-    hipLaunchKernelGGL((k_observe_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
-                       ilog2(rows), ilog2(ny), psi, f, tw, out_psi, out_rho, partials);
+    if (model == kModelQAA)
+      hipLaunchKernelGGL((k_observe_2d<N_, P_, kModelQAA>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+                         ilog2(rows), ilog2(ny), psi, f, tw, out_psi, out_rho, partials);
+    else
+      hipLaunchKernelGGL((k_observe_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+                         ilog2(rows), ilog2(ny), psi, f, tw, out_psi, out_rho, partials);
     return hipGetLastError();
   });
 }

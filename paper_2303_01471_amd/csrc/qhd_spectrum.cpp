@@ -200,6 +200,7 @@ extern "C" qhd_status qhd_spectrum(qhd_plan plan, int32_t i, double t, int32_t n
   qhd_status s = plan_instance_view(plan, i, &v);
   if (s != QHD_OK) return s;
   if (v.ndim != 2) return sfail(QHD_EUNSUPPORTED, "qhd_spectrum supports 2-D instances (instance %d is %d-D)", i, v.ndim);
+  if (v.host.model != kModelQHD) return sfail(QHD_EUNSUPPORTED, "qhd_spectrum is built for the QHD Hamiltonian");
   if (!v.potential_set) return sfail(QHD_ESTATE, "instance %d: qhd_set_potential was not called", i);
   const long long n = (long long)v.nx * v.ny;
   if (nev < 1) return sfail(QHD_EINVAL, "nev must be >= 1");

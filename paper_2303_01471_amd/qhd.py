@@ -24,7 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libqhd.so")
 QHD_OK, QHD_EINVAL, QHD_EUNSUPPORTED, QHD_ENOMEM, QHD_EDEVICE, QHD_ESTATE, QHD_ENUMERIC = range(7)
 STATUS_NAMES = {0: "QHD_OK", 1: "QHD_EINVAL", 2: "QHD_EUNSUPPORTED", 3: "QHD_ENOMEM",
                 4: "QHD_EDEVICE", 5: "QHD_ESTATE", 6: "QHD_ENUMERIC"}
-QHD_SCHED_NESTEROV, QHD_SCHED_CONST, QHD_SCHED_TABLE = 0, 1, 2
+QHD_SCHED_NESTEROV, QHD_SCHED_CONST, QHD_SCHED_TABLE, QHD_SCHED_LINEAR = 0, 1, 2, 3
+QHD_MODEL_QHD, QHD_MODEL_QAA = 0, 1
 QHD_INIT_UNIFORM, QHD_INIT_USER = 0, 1
 QHD_SCHEME_STRANG, QHD_SCHEME_LIE = 0, 1
 QHD_OPT_TIME_PASSES = 0x1
@@ -54,6 +55,7 @@ class qhd_instance(ctypes.Structure):
         ("init_kind", ctypes.c_int32),
         ("success_radius", ctypes.c_double),
         ("scheme", ctypes.c_int32),
+        ("model", ctypes.c_int32),
     ]
 
 
@@ -319,6 +321,7 @@ class InstanceSpec:
     init: int = QHD_INIT_UNIFORM
     radius: float = 0.1
     scheme: int = QHD_SCHEME_STRANG
+    model: int = QHD_MODEL_QHD
 
     def to_c(self, keep: list) -> qhd_instance:
         d = qhd_instance()
@@ -345,6 +348,7 @@ class InstanceSpec:
         d.init_kind = int(self.init)
         d.success_radius = float(self.radius)
         d.scheme = int(self.scheme)
+        d.model = int(self.model)
         return d
 
     @property

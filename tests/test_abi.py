@@ -60,6 +60,9 @@ def _inst(**kw):
     (lambda d: setattr(d, "sched_kind", q.QHD_SCHED_TABLE), q.QHD_EINVAL),  # NULL table
     (lambda d: setattr(d, "init_kind", 5), q.QHD_EINVAL),
     (lambda d: setattr(d, "scheme", 2), q.QHD_EINVAL),
+    (lambda d: setattr(d, "model", 2), q.QHD_EINVAL),
+    (lambda d: (setattr(d, "model", q.QHD_MODEL_QAA), setattr(d, "ndim", 1)), q.QHD_EUNSUPPORTED),
+    (lambda d: (setattr(d, "sched_kind", q.QHD_SCHED_LINEAR), d.sched_p.__setitem__(0, 0.0)), q.QHD_EINVAL),
 ])
 def test_invalid_descriptor_rejected_before_device_work(mutate, status):
     good = _inst()

@@ -1,0 +1,61 @@
+"""The baseline quantum adiabatic algorithm (QAA) the paper compares with, on
+the GPU (Walsh-Hadamard passes), against the FP64 split-step reference, at the
+paper's resolutions 64^2 and 128^2 with T = 10."""
+import numpy as np
+import pytest
+
+import qhd_inputs
+from gpu_helpers import PSI_TOL, compare, note, run_gpu, run_oracle
+from paper_2303_01471_amd import qhd as q
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    q.load_library()
+
+
+def _qaa(n, nsteps=1000, dt=0.01):
+    return q.InstanceSpec(shape=(n, n), nsteps=nsteps, dt=dt, model=q.QHD_MODEL_QAA,
+                          sched=q.QHD_SCHED_LINEAR, sched_p=(nsteps * dt, 0.0))
+
+
+def test_qaa_against_reference_at_the_papers_resolutions():
+    specs = [_qaa(64), _qaa(128)]
+    fs = [qhd_inputs.landscape_grid(1234, s.shape) for s in specs]
+    note("case: QAA 64^2 and 128^2, T = 10, dt = 0.01")
+    res, psis, _, st = run_gpu(specs, fs)
+    assert st == q.QHD_OK
+    for i, (spec, f) in enumerate(zip(specs, fs)):
+        ref, ro = run_oracle(spec, f)
+        err, nd, d_ef, d_p = compare(spec, f, res[i], psis[i], ref, ro, f"qaa[{i}]")
+        assert err <= PSI_TOL and abs(res[i]["norm"] - ro.norm) <= 1e-5 and d_p <= 1e-4
+
+
+def test_qaa_and_qhd_in_one_plan_and_chunked_equals_one_shot():
+    qaa, qhd = _qaa(128, nsteps=300), q.InstanceSpec(shape=(128, 128), nsteps=300, dt=1e-3)
+    f = qhd_inputs.landscape_grid(77, (128, 128))
+    res, psis, _, _ = run_gpu([qaa, qhd], [f, f])
+    for i, spec in enumerate((qaa, qhd)):
+        ref, ro = run_oracle(spec, f)
+        err, *_ = compare(spec, f, res[i], psis[i], ref, ro, f"mixed[{i}]")
+        assert err <= PSI_TOL
+    _, p2, _, _ = run_gpu([qaa], [f], chunks=[17, 100], flags=q.QHD_OPT_NO_GRAPH)
+    _, p3, _, _ = run_gpu([qaa], [f])
+    assert np.array_equal(p2[0], p3[0])
+    assert np.array_equal(p3[0], psis[0])
+
+
+def test_qaa_readouts_at_the_end_of_the_schedule():
+    # the paper's comparison: at T = 10 QAA concentrates far less mass near the minimiser
+    # than QHD on the same landscape (a property of the methods; the value is reported)
+    f = qhd_inputs.landscape_grid(1234, (128, 128))
+    rq, _, _, _ = run_gpu([_qaa(128)], [f])
+    rh, _, _, _ = run_gpu([q.InstanceSpec(shape=(128, 128), nsteps=10000, dt=1e-3)], [f])
+    note(f"  success mass at T=10, 128^2: QAA {rq[0]['success_mass']:.4f}, QHD {rh[0]['success_mass']:.4f}")
+    assert 0.0 <= rq[0]["success_mass"] <= 1.0
