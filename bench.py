@@ -56,9 +56,87 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def build_plan(specs, q, flags=0, timing_stride=0, tune_cache=None):
-    cspecs = [q.InstanceSpec(shape=s.shape, nsteps=s.nsteps, dt=s.dt) for s in specs]
+def build_plan(specs, q, flags=0, timing_stride=0, tune_cache=None, qaa=False):
+    """Plan over the specs: QHD with the Nesterov-type schedule, or (qaa) the baseline
+    QAA with the linear schedule g = t / T, T = nsteps * dt."""
+    if qaa:
+        cspecs = [q.InstanceSpec(shape=s.shape, nsteps=s.nsteps, dt=s.dt, sched=q.QHD_SCHED_LINEAR,
+                                 sched_p=(s.nsteps * s.dt, 0.0), model=q.QHD_MODEL_QAA) for s in specs]
+    else:
+        cspecs = [q.InstanceSpec(shape=s.shape, nsteps=s.nsteps, dt=s.dt) for s in specs]
     return q.Plan(cspecs, flags=flags, timing_stride=timing_stride, tune_cache=tune_cache or None)
+
+
+def kernel_table(kt):
+    out = []
+    for t in kt:
+        gbs = t["points"] * t["bytes_per_point"] / (t["total_ms"] * 1e-3) / 1e9
+        out.append(dict(name=t["name"], sampled_launches=t["launches"],
+                        mean_us=round(t["total_ms"] * 1e3 / t["launches"], 2),
+                        achieved_GBps=round(gbs, 1), bytes_per_point=t["bytes_per_point"]))
+    return out
+
+
+def roofline_of(kt):
+    """Dominant kernel family (largest summed time): algorithmic bytes per mean launch /
+    mean HIP-event duration, and the counter-measured HBM bytes of a mean launch when the
+    committed counter summary matches the kernel sources."""
+    dom = max(kt, key=lambda t: t["total_ms"]) if kt else None
+    if dom is None:
+        return None
+    achieved = dom["points"] * dom["bytes_per_point"] / (dom["total_ms"] * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            tj = json.load(open(TRAFFIC_FILE))
+            ent = tj.get("kernels", {}).get(dom["name"])
+            if tj.get("source_hash") == kernel_source_hash() and ent:
+                traffic = round(ent["hbm_bytes_per_point"] * dom["points"] / dom["launches"], 1)
+        except Exception:
+            traffic = None
+    return {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "algorithmic_bytes_per_point": dom["bytes_per_point"],
+            "mean_launch_us": round(dom["total_ms"] * 1e3 / dom["launches"], 2)}
+
+
+def upload(plan, specs, label):
+    t0 = time.time()
+    grids = {}
+    for i, s in enumerate(specs):
+        f = s.grid()
+        plan.set_potential(i, f)
+        grids.setdefault(s.shape[0], (i, f))
+        if (i + 1) % 128 == 0:
+            log(f"  {label} potentials uploaded: {i + 1}/{len(specs)} ({time.time() - t0:.1f}s)")
+    return grids
+
+
+def timed_runs(plan, steps, warmup, stream, label):
+    """warmup + steps whole runs (reset, evolve to the end, observe); returns
+    (seconds of the timed runs, last readouts, status)."""
+    import torch
+
+    def one():
+        plan.reset(stream)
+        plan.evolve(-1, stream)
+        res, _, _, st = plan.observe(stream)
+        return res, st
+
+    for w in range(warmup):
+        t = time.time()
+        one()
+        torch.cuda.synchronize()
+        log(f"{label} warmup {w + 1}/{warmup}: {time.time() - t:.2f}s")
+    plan.kernel_timings()  # drop warmup samples
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for k in range(steps):
+        last = one()
+        log(f"{label} timed step {k + 1}/{steps} issued")
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, last[0], last[1]
 
 
 def main():
@@ -67,9 +145,12 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--count", type=int, default=768, help="instances in the batch")
-    ap.add_argument("--workload", choices=("batched2d", "3d"), default="batched2d",
+    ap.add_argument("--workload", choices=("batched2d", "3d", "qaa"), default="batched2d",
                     help="batched2d: the 768-instance 2-D batch (default); 3d: 16 instances of 128^3, "
-                         "T = 10, dt = 2e-3")
+                         "T = 10, dt = 2e-3; qaa: the baseline QAA on 512 instances of 64^2 / 128^2, "
+                         "T = 10, dt = 1e-3, with QHD on the same landscapes beside it")
+    ap.add_argument("--no-qaa-summary", action="store_true",
+                    help="batched2d: skip the short baseline-QAA leg reported beside the main line")
     ap.add_argument("--mfma-dft", action="store_true",
                     help="3d: line transforms as split-FP16 DFT products on the matrix cores")
     ap.add_argument("--cap-steps", type=int, default=0,
@@ -106,7 +187,7 @@ def main():
     # surrogate training potentials first: the worker processes are forked before
     # anything touches the GPU
     sur_f = None
-    if not args.no_surrogate and args.workload != "3d":
+    if not args.no_surrogate and args.workload == "batched2d":
         from paper_2303_01471_amd import screen
         t0 = time.time()
         sur_f = screen.make_landscapes(args.surrogate_pairs, 5_000_000, 128, workers=16)
@@ -132,8 +213,12 @@ def main():
         del src, dst
         log(f"copy calibration: {args.copy_calibration_mib} MiB read + written by one elementwise kernel")
 
+    qaa = args.workload == "qaa"
     if args.workload == "3d":
         specs = qhd_inputs.batch_3d()
+        args.no_surrogate = True
+    elif qaa:
+        specs = qhd_inputs.qaa_batch()
         args.no_surrogate = True
     else:
         specs = qhd_inputs.batched_2d(count=args.count)
@@ -141,13 +226,19 @@ def main():
         for s in specs:
             s.nsteps = min(s.nsteps, args.cap_steps)
     if args.points_json:
+        # grid points per dispatch of every pass family with all members active (the
+        # short baseline-QAA leg of the default run included)
         pts = {}
-        for s in specs:
-            n = s.shape[0]
-            fams = ((f"xpass_3d/n{n}", f"ypass_3d/n{n}", f"zpass_3d/n{n}") if len(s.shape) == 3
-                    else (f"row_pass_2d/n{n}", f"col_pass_2d/n{n}"))
-            for fam in fams:
-                pts[fam] = pts.get(fam, 0) + s.points
+        legs = [(specs, "_qaa" if qaa else "")]
+        if args.workload == "batched2d" and not args.no_qaa_summary:
+            legs.append((qhd_inputs.qaa_batch(count=256), "_qaa"))
+        for leg, tag in legs:
+            for s in leg:
+                n = s.shape[0]
+                fams = ((f"xpass_3d/n{n}", f"ypass_3d/n{n}", f"zpass_3d/n{n}") if len(s.shape) == 3
+                        else (f"row_pass_2d{tag}/n{n}", f"col_pass_2d{tag}/n{n}"))
+                for fam in fams:
+                    pts[fam] = pts.get(fam, 0) + s.points
         with open(args.points_json, "w") as fh:
             json.dump(pts, fh)
     total_gp = float(sum(s.points * s.nsteps for s in specs))
@@ -156,43 +247,14 @@ def main():
 
     extra = q.QHD_OPT_MFMA_DFT if args.mfma_dft else 0
     plan = build_plan(specs, q, flags=q.QHD_OPT_TIME_PASSES | q.QHD_OPT_AUTOTUNE | extra,
-                      timing_stride=args.timing_stride, tune_cache=args.tune_cache)
+                      timing_stride=args.timing_stride, tune_cache=args.tune_cache, qaa=qaa)
     tuned = plan.graph_info()["classes"]
     log("launch configuration: " + "; ".join(
         f"n{c['n'][0]}: col variant {c['col_variant']}, caps {c['cap_row']}/{c['cap_col']}" for c in tuned))
-    t0 = time.time()
-    grids = {}
-    for i, s in enumerate(specs):
-        f = s.grid()
-        plan.set_potential(i, f)
-        if i < 8 or s.shape[0] not in grids:
-            grids.setdefault(s.shape[0], (i, f))
-        if (i + 1) % 128 == 0:
-            log(f"  potentials uploaded: {i + 1}/{len(specs)} ({time.time() - t0:.1f}s)")
+    grids = upload(plan, specs, "main")
     stream = torch.cuda.current_stream()
 
-    def one_step():
-        plan.reset(stream)
-        plan.evolve(-1, stream)
-        res, _, _, st = plan.observe(stream)
-        return res, st
-
-    for w in range(args.warmup):
-        t = time.time()
-        one_step()
-        torch.cuda.synchronize()
-        log(f"warmup {w + 1}/{args.warmup}: {time.time() - t:.2f}s")
-    plan.kernel_timings()  # drop warmup samples
-
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    last = None
-    for k in range(args.steps):
-        last = one_step()
-        log(f"timed step {k + 1}/{args.steps} issued")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    res, st = last
+    elapsed, res, st = timed_runs(plan, args.steps, args.warmup, stream, "main")
     ms_per_step = elapsed * 1e3 / args.steps
     value = total_gp * args.steps / elapsed
     norm_drift = max(abs(r["norm"] - 1.0) for r in res)
@@ -200,32 +262,74 @@ def main():
         f"max |norm-1| = {norm_drift:.2e}, status {st}")
 
     kt = [t for t in plan.kernel_timings() if t["launches"] > 0]
-    kernels = []
-    for t in kt:
-        gbs = t["points"] * t["bytes_per_point"] / (t["total_ms"] * 1e-3) / 1e9
-        kernels.append(dict(name=t["name"], sampled_launches=t["launches"],
-                            mean_us=round(t["total_ms"] * 1e3 / t["launches"], 2),
-                            achieved_GBps=round(gbs, 1), bytes_per_point=t["bytes_per_point"]))
-    dom = max(kt, key=lambda t: t["total_ms"]) if kt else None
-    roofline = None
-    if dom is not None:
-        achieved = dom["points"] * dom["bytes_per_point"] / (dom["total_ms"] * 1e-3) / 1e9
-        traffic = None
-        src_hash = kernel_source_hash()
-        if os.path.exists(TRAFFIC_FILE):
-            try:
-                tj = json.load(open(TRAFFIC_FILE))
-                ent = tj.get("kernels", {}).get(dom["name"])
-                if tj.get("source_hash") == src_hash and ent:
-                    # HBM bytes of one mean launch, like `achieved`
-                    traffic = round(ent["hbm_bytes_per_point"] * dom["points"] / dom["launches"], 1)
-            except Exception:
-                traffic = None
-        roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic, "algorithmic_bytes_per_point": dom["bytes_per_point"],
-                    "mean_launch_us": round(dom["total_ms"] * 1e3 / dom["launches"], 2)}
+    kernels = kernel_table(kt)
+    roofline = roofline_of(kt)
     plan.close()
+
+    # ---- QAA workload: QHD on the very same landscapes, sizes and T beside it ---------
+    comparison = None
+    if qaa:
+        pq = build_plan(specs, q, flags=q.QHD_OPT_AUTOTUNE, tune_cache=args.tune_cache)
+        upload(pq, specs, "qhd")
+        el_q, res_q, _ = timed_runs(pq, 1, 1, stream, "qhd")
+        pq.close()
+        sm_a = np.array([r["success_mass"] for r in res])
+        sm_q = np.array([r["success_mass"] for r in res_q])
+        comparison = {"qhd_same_instances_gp_steps_per_s": round(total_gp / el_q, 1),
+                      "qaa_mean_success_mass": round(float(sm_a.mean()), 4),
+                      "qhd_mean_success_mass": round(float(sm_q.mean()), 4),
+                      "qhd_better_fraction": round(float(np.mean(sm_q > sm_a)), 3),
+                      "success_ball": "radius 0.1 around the grid argmin (unit box)"}
+        log(f"QHD on the same instances: {total_gp / el_q / 1e9:.2f} G gp-steps/s; mean success "
+            f"QAA {sm_a.mean():.4f} vs QHD {sm_q.mean():.4f}")
+
+    # ---- batched2d: a short baseline-QAA leg (its own batch) beside the main line ----
+    qaa_summary = None
+    if args.workload == "batched2d" and not args.no_qaa_summary:
+        qs = qhd_inputs.qaa_batch(count=256)
+        if args.cap_steps > 0:
+            for s_ in qs:
+                s_.nsteps = min(s_.nsteps, args.cap_steps)
+        gp_q = float(sum(s_.points * s_.nsteps for s_ in qs))
+        pa = build_plan(qs, q, flags=q.QHD_OPT_TIME_PASSES, timing_stride=args.timing_stride, qaa=True)
+        upload(pa, qs, "qaa")
+        el_a, res_a, st_a = timed_runs(pa, 1, 1, stream, "qaa")
+        kt_a = [t for t in pa.kernel_timings() if t["launches"] > 0]
+        pa.close()
+        qaa_summary = {"workload": f"baseline QAA, {len(qs)} instances of 64^2 / 128^2 (radix-2 qubits), "
+                                   f"T=10, dt=1e-3, linear schedule g=t/T",
+                       "gp_steps_per_s": round(gp_q / el_a, 1), "grid_point_steps": gp_q,
+                       "max_norm_drift": max(abs(r["norm"] - 1.0) for r in res_a),
+                       "mean_success_mass": round(float(np.mean([r["success_mass"] for r in res_a])), 4),
+                       "roofline": roofline_of(kt_a), "kernels": kernel_table(kt_a)}
+        log(f"qaa leg: {gp_q / el_a / 1e9:.2f} G gp-steps/s")
+
+    # ---- batched2d: the energy spectrum of H(t) (Lanczos, FFT matrix-vector products) --
+    spectrum = None
+    if args.workload == "batched2d" and not args.no_qaa_summary:
+        sp0 = qhd_inputs.single_2d(128)
+        ps = build_plan([sp0], q)
+        ps.set_potential(0, sp0.grid())
+        rows = []
+        # |H| bound for the relative residual: a |k|max^2 / 2 + b max|f| on the unit box
+        kmax2 = 2.0 * (2.0 * np.pi * (sp0.shape[0] // 2)) ** 2
+        fmax = float(np.max(np.abs(sp0.grid())))
+        for t_s in (1.0, 10.0):
+            ps.spectrum(0, t_s, nev=6, krylov=400)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, _, r = ps.spectrum(0, t_s, nev=6, krylov=400)
+            torch.cuda.synchronize()
+            a_t, b_t = 2.0 / (1e-3 + t_s ** 3), 2.0 * t_s ** 3
+            rows.append({"t": t_s, "ms": round((time.perf_counter() - t0) * 1e3, 2),
+                         "e0": float(e[0]), "e1": float(e[1]),
+                         "max_residual_rel": float(max(r)) / (0.5 * a_t * kmax2 + b_t * fmax)})
+        ps.close()
+        spectrum = {"workload": "lowest 6 levels of H(t) on one 128^2 instance, Lanczos with 400 Krylov "
+                                "vectors (full reorthogonalisation), FFT matrix-vector products; residual "
+                                "relative to a bound on |H|",
+                    "solves": rows}
+        log("spectrum: " + ", ".join(f"t={r_['t']}: {r_['ms']} ms" for r_ in rows))
 
     # ---- plain: the single-instance solver on the same GPU ---------------------------
     plain = None
@@ -234,7 +338,8 @@ def main():
         for n, (i, f) in sorted(grids.items()):
             sp = specs[i]
             steps = 2000 if n <= 256 else 1000
-            p1 = build_plan([type(sp)(sp.seed, sp.shape, steps + 200, sp.dt, sp.n_terms, sp.kmax)], q, flags=extra)
+            p1 = build_plan([type(sp)(sp.seed, sp.shape, steps + 200, sp.dt, sp.n_terms, sp.kmax)], q, flags=extra,
+                            qaa=qaa)
             p1.set_potential(0, f)
             p1.evolve(200, stream)
             torch.cuda.synchronize()
@@ -249,7 +354,7 @@ def main():
         plain = {"per_size_gp_steps_per_s": {str(k): round(v, 1) for k, v in rates.items()},
                  "batch_one_at_a_time_gp_steps_per_s": round(plain_equiv, 1),
                  "batched_vs_plain": round(value / plain_equiv, 3)}
-        if args.workload != "3d":
+        if args.workload == "batched2d":
             # the single-instance 256^2 x 10k-step configuration
             c1 = qhd_inputs.single_2d(256)
             p1 = build_plan([c1], q)
@@ -272,7 +377,39 @@ def main():
     # ---- CPU baseline (FP64 oracle) and parity on a sample ----------------------------
     cpu = None
     parity = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and qaa:
+        # the FP64 split-step QAA reference on one instance of the batch
+        import threadpoolctl
+
+        from oracle import qaa_reference
+        n0 = 128 if 128 in grids else min(grids)
+        i0, f0 = grids[n0]
+        sp = specs[i0]
+        sample_steps = max(1, min(args.cpu_sample_steps, sp.nsteps))
+        T = sp.nsteps * sp.dt
+        t = time.perf_counter()
+        psi = qaa_reference.evolve(f0, qaa_reference.uniform(sp.shape), sp.dt, sample_steps, T)
+        tcpu = time.perf_counter() - t
+        cpu_rate = sp.points * sample_steps / tcpu
+        blas = [p_["num_threads"] for p_ in threadpoolctl.threadpool_info() if p_.get("user_api") == "blas"]
+        cpu = {"value": round(cpu_rate, 1), "unit": "grid-point-steps/s", "cores": max(blas) if blas else 1,
+               "kind": "oracle",
+               "sample": f"instance {i0} of the batch ({'x'.join(map(str, sp.shape))}), first {sample_steps} "
+                         f"of its {sp.nsteps} steps, FP64 split-step QAA reference, {tcpu:.1f}s"}
+        log(f"cpu QAA reference: {cpu_rate / 1e6:.2f} M gp-steps/s ({tcpu:.1f}s)")
+        p1 = q.Plan([q.InstanceSpec(shape=sp.shape, nsteps=sample_steps, dt=sp.dt, sched=q.QHD_SCHED_LINEAR,
+                                    sched_p=(T, 0.0), model=q.QHD_MODEL_QAA)])
+        p1.set_potential(0, f0)
+        p1.evolve(-1, stream)
+        r1, psig, _, _ = p1.observe(stream, want_psi=True)
+        torch.cuda.synchronize()
+        got = psig.cpu().numpy().reshape(sp.shape).astype(np.complex128)
+        p1.close()
+        parity = {"sample": f"instance {i0} ({'x'.join(map(str, sp.shape))}), {sample_steps} steps, QAA",
+                  "max_abs_dpsi": float(np.max(np.abs(got - psi))),
+                  "norm_drift": abs(r1[0]["norm"] - 1.0), "tolerance": 1e-4}
+        log(f"parity sample: max|dpsi| = {parity['max_abs_dpsi']:.3e}")
+    elif not args.no_cpu_baseline:
         import oracle
         n0 = 256 if 256 in grids else min(grids)
         i0, f0 = grids[n0]
@@ -362,7 +499,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"batched-{len(specs)}: 2-D instances, n in {sizes}^2 (uniform), "
                                 f"T~U[5,20], dt=1e-3, Nesterov schedule, 8-24 cosine-term landscapes"
-                                if args.workload != "3d" else
+                                if args.workload == "batched2d" else
+                                f"baseline QAA: {len(specs)} 2-D instances, n in {sizes}^2 (radix-2 qubits, "
+                                f"H0 = -sum sigma_x), T=10, dt=1e-3, linear schedule, 8-24 cosine-term landscapes"
+                                if qaa else
                                 f"3-D: {len(specs)} instances of 128^3, T=10, dt=2e-3, Nesterov schedule, "
                                 f"16 cosine-term landscapes, transforms "
                                 + ("split-FP16 MFMA DFT" if args.mfma_dft else "FP32 Stockham FFT"))
@@ -374,6 +514,8 @@ def main():
         "plain": plain,
         "parity": parity,
         "surrogate": surrogate,
+        "qaa": qaa_summary if not qaa else comparison,
+        "spectrum": spectrum,
         "launch_config": tuned,
         "kernels": kernels,
     }

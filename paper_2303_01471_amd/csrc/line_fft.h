@@ -36,27 +36,44 @@ namespace qhd {
 
 __device__ __forceinline__ float2 fadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 fsub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 fadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 fsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
 // z * w with z in FP32 and w in FP64: one rounding per component
 __device__ __forceinline__ float2 cmul_fd(float2 z, double2 w) {
   const double zr = (double)z.x, zi = (double)z.y;
   return make_float2((float)fma(zr, w.x, -zi * w.y), (float)fma(zr, w.y, zi * w.x));
 }
+// both in FP64
+__device__ __forceinline__ double2 cmul_fd(double2 z, double2 w) {
+  return make_double2(fma(z.x, w.x, -z.y * w.y), fma(z.x, w.y, z.y * w.x));
+}
 __device__ __forceinline__ float2 cmul_fd_conj(float2 z, double2 w) {
   const double zr = (double)z.x, zi = (double)z.y;
   return make_float2((float)fma(zr, w.x, zi * w.y), (float)fma(zi, w.x, -zr * w.y));
 }
-
-// z * w, both FP32 (used for unit phase factors; random, unbiased rounding)
-__device__ __forceinline__ float2 cmul_ff(float2 z, float2 w) {
-  return make_float2(fmaf(z.x, w.x, -z.y * w.y), fmaf(z.x, w.y, z.y * w.x));
+__device__ __forceinline__ double2 cmul_fd_conj(double2 z, double2 w) {
+  return make_double2(fma(z.x, w.x, z.y * w.y), fma(z.y, w.x, -z.x * w.y));
 }
 
+// conversions between the FP32 storage type and a line's working type
+__device__ __forceinline__ void assign(float2& d, float2 v) { d = v; }
+__device__ __forceinline__ void assign(double2& d, float2 v) { d = make_double2(v.x, v.y); }
+__device__ __forceinline__ void assign(float2& d, double2 v) { d = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ void assign(double2& d, double2 v) { d = v; }
+
 // multiply by S*i (S = -1: -i z, S = +1: +i z), exact
-template <int S>
-__device__ __forceinline__ float2 mul_si(float2 z) {
-  if constexpr (S < 0) return make_float2(z.y, -z.x);
-  else return make_float2(-z.y, z.x);
+template <int S, typename W>
+__device__ __forceinline__ W mul_si(W z) {
+  W r;
+  if constexpr (S < 0) {
+    r.x = z.y;
+    r.y = -z.x;
+  } else {
+    r.x = -z.y;
+    r.y = z.x;
+  }
+  return r;
 }
 
 // cos, sin of k pi / 8 as FP64, and their FP32 hi+lo splits
@@ -75,12 +92,16 @@ __host__ __device__ constexpr float lo32(double v) { return (float)(v - (double)
 
 // z * e^{S 2 pi i K / 16}: exact for multiples of pi/2; otherwise an FP32 product
 // with a hi+lo constant (the small cross terms first, the large ones last)
-template <int S, int K>
-__device__ __forceinline__ float2 rot16(float2 z) {
+template <int S, int K, typename W>
+__device__ __forceinline__ W rot16(W z) {
   if constexpr (K == 0) {
     return z;
   } else if constexpr (K == 4) {
     return mul_si<S>(z);
+  } else if constexpr (std::is_same<W, double2>::value) {
+    // FP64 working type: the constant itself carries enough precision
+    constexpr double c = c16d(K), sn = S * s16d(K);
+    return make_double2(fma(z.x, c, -z.y * sn), fma(z.x, sn, z.y * c));
   } else if constexpr (K == 2 || K == 6) {
     // (1/sqrt2) (z.x - S z.y, S z.x + z.y) for K=2 ; (1/sqrt2)(-z.x - S z.y, S z.x - z.y) for K=6
     constexpr float ch = hi32(0.70710678118654752440), cl = lo32(0.70710678118654752440);
@@ -99,27 +120,27 @@ __device__ __forceinline__ float2 rot16(float2 z) {
 // ---------------------------------------------------------------------------------
 // small DFTs on registers: X_k = sum_m x_m e^{S 2 pi i m k / R}, in place, natural order
 
-template <int S>
-__device__ __forceinline__ void dft2(float2 (&u)[2]) {
-  const float2 a = u[0], b = u[1];
+template <int S, typename W>
+__device__ __forceinline__ void dft2(W (&u)[2]) {
+  const W a = u[0], b = u[1];
   u[0] = fadd(a, b);
   u[1] = fsub(a, b);
 }
 
-template <int S>
-__device__ __forceinline__ void dft4(float2 (&u)[4]) {
-  const float2 s02 = fadd(u[0], u[2]), d02 = fsub(u[0], u[2]);
-  const float2 s13 = fadd(u[1], u[3]), d13 = mul_si<S>(fsub(u[1], u[3]));
+template <int S, typename W>
+__device__ __forceinline__ void dft4(W (&u)[4]) {
+  const W s02 = fadd(u[0], u[2]), d02 = fsub(u[0], u[2]);
+  const W s13 = fadd(u[1], u[3]), d13 = mul_si<S>(fsub(u[1], u[3]));
   u[0] = fadd(s02, s13);
   u[2] = fsub(s02, s13);
   u[1] = fadd(d02, d13);
   u[3] = fsub(d02, d13);
 }
 
-template <int S>
-__device__ __forceinline__ void dft8(float2 (&u)[8]) {
-  float2 e[4] = {u[0], u[2], u[4], u[6]};
-  float2 o[4] = {u[1], u[3], u[5], u[7]};
+template <int S, typename W>
+__device__ __forceinline__ void dft8(W (&u)[8]) {
+  W e[4] = {u[0], u[2], u[4], u[6]};
+  W o[4] = {u[1], u[3], u[5], u[7]};
   dft4<S>(e);
   dft4<S>(o);
   o[1] = rot16<S, 2>(o[1]);
@@ -132,9 +153,9 @@ __device__ __forceinline__ void dft8(float2 (&u)[8]) {
   }
 }
 
-template <int S>
-__device__ __forceinline__ void dft16(float2 (&u)[16]) {
-  float2 e[8], o[8];
+template <int S, typename W>
+__device__ __forceinline__ void dft16(W (&u)[16]) {
+  W e[8], o[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     e[k] = u[2 * k];
@@ -156,8 +177,8 @@ __device__ __forceinline__ void dft16(float2 (&u)[16]) {
   }
 }
 
-template <int R, int S>
-__device__ __forceinline__ void dft(float2 (&u)[R]) {
+template <int R, int S, typename W>
+__device__ __forceinline__ void dft(W (&u)[R]) {
   if constexpr (R == 2) dft2<S>(u);
   else if constexpr (R == 4) dft4<S>(u);
   else if constexpr (R == 8) dft8<S>(u);
@@ -343,6 +364,84 @@ __device__ __forceinline__ void line_fft(float2 (&reg)[P], int t, const TW& tw, 
   line_fft_from<N, P, S, BLOCK_SYNC, 0>(reg, t, tw, lds);
 }
 
+// ---------------------------------------------------------------------------------
+// Mixed-precision form: the first stage computes in the type of the input array and
+// the last stage in the type of the output array; the stages between, and every LDS
+// exchange, are FP32.  A transform of a near-uniform line concentrates its mass into
+// a few coefficients in the last stage (and an inverse transform starts from them in
+// the first), where every FP32 rounding moves the norm by up to ~1e-7 of the whole
+// line; with those two stages in FP64 (and the diagonal factor between two transforms
+// applied in FP64 too) the concentrated values are rounded once, when they are
+// stored.  FP64 adds and FMAs issue at the FP32 (unpacked) rate on CDNA, and the FP64
+// stages need no widening around their twiddle products.
+
+template <int N, int P, int S, int STAGE, bool BLOCK_SYNC, typename W, typename A, typename B, typename TW>
+__device__ __forceinline__ void fft_stage_io(const A (&src)[P], B (&dst)[P], int t, const TW& tw,
+                                             float2* __restrict__ lds) {
+  using SP = StagePlan<N, P>;
+  constexpr int NS = SP::ns(STAGE);
+  constexpr int R = SP::radix(STAGE);
+  constexpr int NB = P / R;
+  constexpr int TPL = N / P;
+  constexpr bool LAST = (STAGE == SP::count() - 1);
+  static_assert(LAST || std::is_same<B, float2>::value, "an exchanged stage writes FP32");
+#pragma unroll
+  for (int m = 0; m < NB; ++m) {
+    W u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) assign(u[r], src[m + r * NB]);
+    if constexpr (STAGE > 0) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const double2 w = tw.template get<STAGE>(m * (R - 1) + (r - 1));
+        u[r] = S < 0 ? cmul_fd(u[r], w) : cmul_fd_conj(u[r], w);
+      }
+    }
+    dft<R, S>(u);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) assign(dst[m + r * NB], u[r]);
+    } else {
+      const int v = t + m * TPL;
+      const int base = (v / NS) * NS * R + (v % NS);
+#pragma unroll
+      for (int r = 0; r < R; ++r) assign(lds[lds_slot(base + r * NS)], u[r]);
+    }
+  }
+  if constexpr (!LAST) {
+    line_lds_sync<BLOCK_SYNC>();
+#pragma unroll
+    for (int q = 0; q < P; ++q) dst[q] = lds[lds_slot(t + q * TPL)];
+    line_lds_sync<BLOCK_SYNC>();
+  }
+}
+
+template <int N, int P, int S, bool BLOCK_SYNC, int STAGE, typename TW>
+__device__ __forceinline__ void fft_mid_stages(float2 (&reg)[P], int t, const TW& tw, float2* __restrict__ lds) {
+  if constexpr (STAGE < StagePlan<N, P>::count() - 1) {
+    fft_stage_io<N, P, S, STAGE, BLOCK_SYNC, float2>(reg, reg, t, tw, lds);
+    fft_mid_stages<N, P, S, BLOCK_SYNC, STAGE + 1>(reg, t, tw, lds);
+  }
+}
+
+// Full unnormalised transform of one line from `in` (float2 or double2) to `out`
+// (float2 or double2), same layout as line_fft.
+template <int N, int P, int S, bool BLOCK_SYNC = false, typename TIN, typename TOUT, typename TW>
+__device__ __forceinline__ void line_fft_io(TIN (&in)[P], TOUT (&out)[P], int t, const TW& tw,
+                                            float2* __restrict__ lds) {
+  constexpr int C = StagePlan<N, P>::count();
+  if constexpr (C == 1) {
+    using W = typename std::conditional<std::is_same<TIN, double2>::value || std::is_same<TOUT, double2>::value,
+                                        double2, float2>::type;
+    fft_stage_io<N, P, S, 0, BLOCK_SYNC, W>(in, out, t, tw, lds);
+  } else {
+    float2 mid[P];
+    fft_stage_io<N, P, S, 0, BLOCK_SYNC, TIN>(in, mid, t, tw, lds);
+    fft_mid_stages<N, P, S, BLOCK_SYNC, 1>(mid, t, tw, lds);
+    fft_stage_io<N, P, S, C - 1, BLOCK_SYNC, TOUT>(mid, out, t, tw, lds);
+  }
+}
+
 // Twiddle storage per line length: an LDS table for the long lines (register
 // pressure), per-lane registers for the short ones.
 template <int N, int P>
@@ -369,16 +468,16 @@ __device__ __forceinline__ void load_twiddles(TwiddlesLds<N, P>& tw, const doubl
 // X_u = sum_i (-1)^{popcount(u & i)} x_i.  Point i = t + q TPL: the bits of q are
 // combined in registers, the bits of t across the line's TPL consecutive lanes by
 // xor shuffles (a line never spans two wavefronts).  Additions only: exact up to
-// one rounding per butterfly.
-template <int N, int P>
-__device__ __forceinline__ void line_wht(float2 (&reg)[P], int t) {
+// one rounding per butterfly.  T is float2 or double2.
+template <int N, int P, typename T>
+__device__ __forceinline__ void line_wht(T (&reg)[P], int t) {
   constexpr int TPL = N / P;
 #pragma unroll
   for (int h = 1; h < P; h <<= 1) {
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       if (!(q & h)) {
-        const float2 a = reg[q], b = reg[q | h];
+        const T a = reg[q], b = reg[q | h];
         reg[q] = fadd(a, b);
         reg[q | h] = fsub(a, b);
       }
@@ -389,7 +488,9 @@ __device__ __forceinline__ void line_wht(float2 (&reg)[P], int t) {
     const bool upper = (t & h) != 0;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      const float2 o = make_float2(__shfl_xor(reg[q].x, h), __shfl_xor(reg[q].y, h));
+      T o;
+      o.x = __shfl_xor(reg[q].x, h);
+      o.y = __shfl_xor(reg[q].y, h);
       reg[q] = upper ? fsub(o, reg[q]) : fadd(reg[q], o);
     }
   }

@@ -666,9 +666,10 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       snprintf(name, sizeof name, "zpass_3d/n%d", c.nz);
       c.fam_z = family_index(p, name, 16.0);
     } else if (c.ndim == 2) {
-      snprintf(name, sizeof name, "row_pass_2d/n%d", c.nx);
+      const char* tag = c.model == kModelQAA ? "_qaa" : "";
+      snprintf(name, sizeof name, "row_pass_2d%s/n%d", tag, c.nx);
       c.fam_row = family_index(p, name, 24.0);
-      snprintf(name, sizeof name, "col_pass_2d/n%d", c.ny);
+      snprintf(name, sizeof name, "col_pass_2d%s/n%d", tag, c.ny);
       c.fam_col = family_index(p, name, 16.0);
     } else {
       snprintf(name, sizeof name, "line_pass_1d/n%d", c.nx);

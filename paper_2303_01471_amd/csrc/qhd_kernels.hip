@@ -40,14 +40,20 @@
 
 namespace qhd {
 
-// The line transform of a model: the DFT for QHD (kinetic term diagonal in Fourier
+// Line transforms of a model: the DFT for QHD (kinetic term diagonal in Fourier
 // space), the Walsh-Hadamard transform for QAA (transverse field diagonal in the
-// Hadamard basis; its own inverse up to 1/N, so S is ignored).
-template <int MODEL, int N, int P, int S, typename TW>
-__device__ __forceinline__ void line_xform(float2 (&reg)[P], int t, const TW& tw, float2* lds) {
-  if constexpr (MODEL == kModelQAA) line_wht<N, P>(reg, t);
-  else line_fft<N, P, S>(reg, t, tw, lds);
-}
+// Hadamard basis; its own inverse up to 1/N).
+//
+// Working precision in registers.  A near-uniform state (QHD starts uniform; the QAA
+// state stays close to the ground state of the transverse field) is concentrated in
+// the transformed basis, and every FP32 rounding of its few large coefficients moves
+// the norm by up to ~1e-7, a random walk over the steps.  The column pass is where the
+// whole mesh concentrates into one coefficient: there the last stage of the forward
+// transform, the diagonal factor and the first stage of the inverse run in FP64
+// (line_fft_io), so those coefficients are not rounded between them.  The row pass
+// concentrates each row separately (one coefficient per row) and stays FP32, which
+// measured the same drift.  QAA lines need no LDS and run in FP64 throughout
+// (additions and xor shuffles; FP64 adds issue at the unpacked FP32 rate).
 
 // ------------------------------------------------------------------------------------
 // 2-D row pass: lines along x, one line per TPL lanes.
@@ -82,16 +88,30 @@ __global__ void __launch_bounds__(256) k_row_pass_2d(const InstDev* __restrict__
     const double cpot = potential_turns(I, j, entry);
     float2* __restrict__ pl = psi + I.psi_off;
     const double* __restrict__ fl = f + I.psi_off;
-    float2 reg[P];
+    if constexpr (MODEL == kModelQAA) {
+      double2 reg[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) reg[q] = pl[row_slot<NX, TPL>(t, q, y)];
-    if (!entry) line_xform<MODEL, NX, P, +1>(reg, t, tw, my);
+      for (int q = 0; q < P; ++q) assign(reg[q], pl[row_slot<NX, TPL>(t, q, y)]);
+      if (!entry) line_wht<NX, P>(reg, t);
 #pragma unroll
-    for (int q = 0; q < P; ++q) reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fl[row_slot<NX, TPL>(t, q, y)]));
-    line_xform<MODEL, NX, P, -1>(reg, t, tw, my);
-    if (active) {
+      for (int q = 0; q < P; ++q) reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fl[row_slot<NX, TPL>(t, q, y)]));
+      line_wht<NX, P>(reg, t);
+      if (active) {
 #pragma unroll
-      for (int q = 0; q < P; ++q) pl[row_slot<NX, TPL>(t, q, y)] = reg[q];
+        for (int q = 0; q < P; ++q) assign(pl[row_slot<NX, TPL>(t, q, y)], reg[q]);
+      }
+    } else {
+      float2 reg[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) reg[q] = pl[row_slot<NX, TPL>(t, q, y)];
+      if (!entry) line_fft<NX, P, +1>(reg, t, tw, my);
+#pragma unroll
+      for (int q = 0; q < P; ++q) reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fl[row_slot<NX, TPL>(t, q, y)]));
+      line_fft<NX, P, -1>(reg, t, tw, my);
+      if (active) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) pl[row_slot<NX, TPL>(t, q, y)] = reg[q];
+      }
     }
   }
 }
@@ -105,6 +125,9 @@ struct ColCfg {
   static constexpr int TPL = NY / P;
   static constexpr int NT = 256;                                          // threads per block
   static constexpr int ITEMS = (8 * TPL >= NT) ? 1 : NT / (8 * TPL);     // tile columns per block
+  // waves per SIMD the register budget must allow: the LDS of a block (line buffers,
+  // twiddle table) lets three blocks share a CU when 8 points per lane
+  static constexpr int MIN_WAVES = P == 8 ? 3 : 1;
   static constexpr int LINES = ITEMS * 8;                                 // columns per block
   static constexpr int SUBS = (LINES * TPL) / NT;                         // column rounds per item
   // line stride in LDS slots, = 2 (mod 16) so the tile scatter hits distinct banks
@@ -112,7 +135,7 @@ struct ColCfg {
 };
 
 template <int NY, int P, int MODEL = kModelQHD>
-__global__ void __launch_bounds__(256) k_col_pass_2d(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColCfg<NY, P>::MIN_WAVES))) k_col_pass_2d(
     const InstDev* __restrict__ inst, int ninst, int nx_log2, float2* __restrict__ psi,
     const double2* __restrict__ twtab, int s, long long max_steps) {
   using C = ColCfg<NY, P>;
@@ -195,16 +218,30 @@ __global__ void __launch_bounds__(256) k_col_pass_2d(
 #pragma unroll
       for (int q = 0; q < P; ++q) reg[q] = my[lds_slot(t + q * TPL)];
       wave_lds_sync();
-      line_xform<MODEL, NY, P, -1>(reg, t, tw, my);
+      double2 kd[P];
+      if constexpr (MODEL == kModelQAA) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) assign(kd[q], reg[q]);
+        line_wht<NY, P>(kd, t);
+      } else {
+        line_fft_io<NY, P, -1>(reg, kd, t, tw, my);
+      }
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        // E_x E_y in FP64, rounded once: FP32 factors rounded separately gain a one-sided
-        // magnitude error where the phase is tiny (cos rounds to 1, sin does not)
+        // E_x E_y and its product with psi in FP64: a factor rounded to FP32 has a
+        // one-sided magnitude error where the phase is tiny (cos rounds to 1, sin does
+        // not), and that error repeats every step
         const double2 k = make_double2(fma(ex.x, ey[q].x, -ex.y * ey[q].y), fma(ex.x, ey[q].y, ex.y * ey[q].x));
-        reg[q] = cmul_ff(reg[q], make_float2((float)k.x, (float)k.y));
+        kd[q] = cmul_fd(kd[q], k);
       }
-      line_xform<MODEL, NY, P, +1>(reg, t, tw, my);
-      if constexpr (MODEL == kModelQAA) wave_lds_sync();  // the transform did not touch LDS
+      if constexpr (MODEL == kModelQAA) {
+        line_wht<NY, P>(kd, t);
+#pragma unroll
+        for (int q = 0; q < P; ++q) assign(reg[q], kd[q]);
+        wave_lds_sync();  // the transforms did not touch LDS
+      } else {
+        line_fft_io<NY, P, +1>(kd, reg, t, tw, my);
+      }
 #pragma unroll
       for (int q = 0; q < P; ++q) my[lds_slot(t + q * TPL)] = reg[q];
     }
@@ -298,13 +335,14 @@ __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
     float2 reg[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) reg[q] = base[(long long)q * W * tcols * 64];
-    line_fft<NY, P, -1, (W > 1)>(reg, t, tw, my);
+    double2 kd[P];
+    line_fft_io<NY, P, -1, (W > 1)>(reg, kd, t, tw, my);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       const double2 k = make_double2(fma(ex.x, ey[q].x, -ex.y * ey[q].y), fma(ex.x, ey[q].y, ex.y * ey[q].x));
-      reg[q] = cmul_ff(reg[q], make_float2((float)k.x, (float)k.y));
+      kd[q] = cmul_fd(kd[q], k);
     }
-    line_fft<NY, P, +1, (W > 1)>(reg, t, tw, my);
+    line_fft_io<NY, P, +1, (W > 1)>(kd, reg, t, tw, my);
     if (active) {
 #pragma unroll
       for (int q = 0; q < P; ++q) base[(long long)q * W * tcols * 64] = reg[q];
@@ -350,14 +388,15 @@ __global__ void __launch_bounds__(256) k_line_pass_1d(const InstDev* __restrict_
       const long long p = base + t + q * TPL;
       reg[q] = cmul_fd(psi[p], phase_turns_d(cpot * f[p]));
     }
-    line_fft<N, P, -1>(reg, t, tw, my);
+    double2 kd[P];
+    line_fft_io<N, P, -1>(reg, kd, t, tw, my);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       const int nf = freq(t + q * TPL, N);
       const double2 w = phase_turns_d(ck * (double)(nf * nf));
-      reg[q] = cmul_ff(reg[q], make_float2((float)(w.x * inv_n), (float)(w.y * inv_n)));
+      kd[q] = cmul_fd(kd[q], make_double2(w.x * inv_n, w.y * inv_n));
     }
-    line_fft<N, P, +1>(reg, t, tw, my);
+    line_fft_io<N, P, +1>(kd, reg, t, tw, my);
     if (active) {
 #pragma unroll
       for (int q = 0; q < P; ++q) psi[base + t + q * TPL] = reg[q];
@@ -435,7 +474,16 @@ __global__ void __launch_bounds__(256) k_observe_2d(const InstDev* __restrict__ 
     for (int q = 0; q < P; ++q) fv[q] = f[base + tile_index(t + q * TPL, y, NX)];
     if (pending) {
       // back to position space; the symmetric scheme also owes the trailing half step
-      line_xform<MODEL, NX, P, +1>(reg, t, tw, my);
+      double2 in[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) assign(in[q], reg[q]);
+      if constexpr (MODEL == kModelQAA) {
+        line_wht<NX, P>(in, t);
+#pragma unroll
+        for (int q = 0; q < P; ++q) assign(reg[q], in[q]);
+      } else {
+        line_fft_io<NX, P, +1>(in, reg, t, tw, my);
+      }
       if (I.scheme != kSchemeLie) {
         const double cpot = closing_turns(I);
 #pragma unroll

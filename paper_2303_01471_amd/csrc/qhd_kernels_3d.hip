@@ -63,13 +63,15 @@ __global__ void __launch_bounds__((YCfg<NY>::NT)) k_ypass_3d(
     const InstDev& I = inst[i];
     const bool active = valid && s < step_limit(I, max_steps);
     float2* __restrict__ base = psi + I.psi_off + (long long)z * slab + ((long long)(wv * tcols + tc) << 6) + lane;
-    float2 reg[P];
+    // first and last stages in FP64 (a forward transform ends, an inverse one starts,
+    // in the concentrated coefficients)
+    double2 in[P], out[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) reg[q] = base[(long long)q * W * tcols * 64];
-    line_fft<NY, P, DIR, (W > 1)>(reg, t, tw, my);
+    for (int q = 0; q < P; ++q) assign(in[q], base[(long long)q * W * tcols * 64]);
+    line_fft_io<NY, P, DIR, (W > 1)>(in, out, t, tw, my);
     if (active) {
 #pragma unroll
-      for (int q = 0; q < P; ++q) base[(long long)q * W * tcols * 64] = reg[q];
+      for (int q = 0; q < P; ++q) assign(base[(long long)q * W * tcols * 64], out[q]);
     }
     if constexpr (W == 1) wave_lds_sync();
   }
@@ -125,14 +127,15 @@ __global__ void __launch_bounds__((ZCfg<NZ>::NT)) k_zpass_3d(
     float2 reg[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) reg[q] = base[(long long)q * W * slab];
-    line_fft<NZ, P, -1, (W > 1)>(reg, t, tw, my);
+    double2 kd[P];
+    line_fft_io<NZ, P, -1, (W > 1)>(reg, kd, t, tw, my);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       const int nzf = freq(t + q * W, NZ);
       const double2 k = phase_turns_d(fma(cz, (double)(nzf * nzf), cxy));
-      reg[q] = cmul_ff(reg[q], make_float2((float)(k.x * inv_n), (float)(k.y * inv_n)));
+      kd[q] = cmul_fd(kd[q], make_double2(k.x * inv_n, k.y * inv_n));
     }
-    line_fft<NZ, P, +1, (W > 1)>(reg, t, tw, my);
+    line_fft_io<NZ, P, +1, (W > 1)>(kd, reg, t, tw, my);
     if (active) {
 #pragma unroll
       for (int q = 0; q < P; ++q) base[(long long)q * W * slab] = reg[q];

@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(256) k_mfma_pass_3d(const InstDev* __restrict_
           const int nzf = freq(acc_row(wave, lane, r), kN);
           const double2 kf = phase_turns_d(fma(cz, (double)(nzf * nzf), cxy));
           const float2 y2 = make_float2(ldexpf(ar[r], e_acc), ldexpf(ai[r], e_acc));
-          const float2 z = cmul_ff(y2, make_float2((float)(kf.x * inv_n), (float)(kf.y * inv_n)));
+          const float2 z = cmul_fd(y2, make_double2(kf.x * inv_n, kf.y * inv_n));
           ar[r] = z.x;
           ai[r] = z.y;
           mm = fmaxf(mm, fmaxf(fabsf(z.x), fabsf(z.y)));

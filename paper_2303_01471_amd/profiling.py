@@ -58,12 +58,18 @@ def counter_means(db: str):
         {k: len(v) for k, v in disp.items()}
 
 
-# pass kernel -> (family name used by the library's timing, algorithmic bytes per point)
+# pass kernel -> (family name used by the library's timing, algorithmic bytes per point);
+# the 2-D kernels' last template argument is the model (0 QHD, 1 QAA)
 _FAMILY = [
-    (re.compile(r"k_row_pass_2d<(\d+),"), "row_pass_2d/n{}", 24.0),
-    (re.compile(r"k_col_pass_(?:2d|tw)<(\d+),"), "col_pass_2d/n{}", 16.0),
-    (re.compile(r"k_line_pass_1d<(\d+),"), "line_pass_1d/n{}", 24.0),
+    (re.compile(r"k_row_pass_2d<(\d+), \d+(?:, (\d+))?>"), "row_pass_2d{}/n{}", 24.0),
+    (re.compile(r"k_col_pass_(?:2d|tw)<(\d+), \d+(?:, (\d+))?>"), "col_pass_2d{}/n{}", 16.0),
+    (re.compile(r"k_line_pass_1d<(\d+),"), "line_pass_1d{}/n{}", 24.0),
 ]
+
+
+def _family_name(fam: str, m) -> str:
+    model = m.group(2) if m.re.groups >= 2 else None
+    return fam.format("_qaa" if model == "1" else "", m.group(1))
 
 
 def traffic(fetch_db: str, write_db: str, copy_bytes: float, points_per_dispatch: dict,
@@ -85,7 +91,7 @@ def traffic(fetch_db: str, write_db: str, copy_bytes: float, points_per_dispatch
             m = rx.search(k)
             if not m:
                 continue
-            name = fam.format(m.group(1))
+            name = _family_name(fam, m)
             pts = points_per_dispatch.get(name)
             if not pts:
                 continue

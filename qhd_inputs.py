@@ -141,3 +141,18 @@ def batch_3d(count: int = 16, n: int = 128, seed_base: int = 3030, dt: float = 2
              T: float = 10.0, n_terms: int = 16) -> List[InstanceSpec]:
     return [InstanceSpec(seed_base + i, (n, n, n), int(round(T / dt)), dt, n_terms, 4)
             for i in range(count)]
+
+
+def qaa_batch(count: int = 512, seed_base: int = 19820301, sizes=(64, 128), T: float = 10.0,
+              dt: float = 1e-3, terms=(8, 24)) -> List[InstanceSpec]:
+    """Batch for the baseline-QAA comparison at the paper's QAA resolutions (64 and 128
+    points per axis, App. C.2.2) and its evolution time T = 10: per instance, from
+    PCG64(seed_base + i), the grid size uniformly from ``sizes`` and the number of
+    cosine terms uniformly in [terms[0], terms[1]]; every instance runs T / dt steps."""
+    out = []
+    for i in range(count):
+        rng = np.random.Generator(np.random.PCG64(seed_base + i))
+        n = int(sizes[int(rng.integers(0, len(sizes)))])
+        m = int(rng.integers(terms[0], terms[1] + 1))
+        out.append(InstanceSpec(seed_base + 1_000_000 + i, (n, n), int(round(T / dt)), dt, m, 6))
+    return out

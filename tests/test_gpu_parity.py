@@ -230,3 +230,17 @@ def test_batched_launch_sampled_against_oracle():
     idx = sorted(picked.values())
     _check([specs[i] for i in idx], [fs[i] for i in idx], [res[i] for i in idx],
            [psis[i] for i in idx], "batch")
+
+
+def test_batch_norm_drift_over_ten_thousand_steps():
+    """The benchmark's landscape recipe at 128^2 and 256^2 with T = 10 (10^4 steps of
+    dt = 1e-3, the paper's experiment length): the norm of every instance stays within
+    1e-5 of 1.  The state starts uniform, i.e. concentrated in the Fourier basis, where
+    FP32 rounding of the few large coefficients would random-walk the norm."""
+    specs_in = qhd_inputs.batched_2d(count=256, sizes=(128, 256), t_range=(10.0, 10.0))
+    specs = [q.InstanceSpec(shape=s.shape, nsteps=s.nsteps, dt=s.dt) for s in specs_in]
+    note(f"case: QHD batch, {len(specs)} instances of 128^2 / 256^2, 10k steps")
+    res, _, _, st = run_gpu(specs, [s.grid() for s in specs_in])
+    drift = [abs(r["norm"] - 1.0) for r in res]
+    note(f"  |norm - 1| over the batch: max {max(drift):.3e}, median {float(np.median(drift)):.3e}")
+    assert st == q.QHD_OK and max(drift) <= 1e-5

@@ -59,3 +59,16 @@ def test_qaa_readouts_at_the_end_of_the_schedule():
     rh, _, _, _ = run_gpu([q.InstanceSpec(shape=(128, 128), nsteps=10000, dt=1e-3)], [f])
     note(f"  success mass at T=10, 128^2: QAA {rq[0]['success_mass']:.4f}, QHD {rh[0]['success_mass']:.4f}")
     assert 0.0 <= rq[0]["success_mass"] <= 1.0
+
+
+def test_qaa_batch_norm_drift_over_ten_thousand_steps():
+    # the QAA batch of the benchmark (512 landscapes at 64^2 / 128^2, T = 10, dt = 1e-3):
+    # near the end of the linear schedule the transverse-field phases are tiny, where a
+    # factor rounded to FP32 would gain magnitude every step; the bar is 1e-5 per 1e4 steps
+    specs_in = qhd_inputs.qaa_batch()
+    specs = [_qaa(s.shape[0], nsteps=s.nsteps, dt=s.dt) for s in specs_in]
+    note(f"case: QAA batch, {len(specs)} instances, 10k steps")
+    res, _, _, st = run_gpu(specs, [s.grid() for s in specs_in])
+    drift = max(abs(r["norm"] - 1.0) for r in res)
+    note(f"  max |norm - 1| over the batch: {drift:.3e}")
+    assert st == q.QHD_OK and drift <= 1e-5
