@@ -80,7 +80,12 @@ typedef enum {
   QHD_SCHEME_STRANG = 0,
   /* the printed first-order product of App. C.2.1 eq. prod_qhd_fft / Algorithm 1:
    * F^{-1} e^{-i dt a L} F e^{-i dt b V}, a and b at the left end t_j = j dt */
-  QHD_SCHEME_LIE = 1
+  QHD_SCHEME_LIE = 1,
+  /* fourth order: the symmetric step composed as a triple jump (Yoshida 1990), three
+   * symmetric stages of lengths w1 dt, w0 dt, w1 dt with w1 = 1/(2 - 2^{1/3}),
+   * w0 = 1 - 2 w1, each with a and b at its own midpoint; three times the passes of
+   * QHD_SCHEME_STRANG per step.  Not with QHD_SCHED_TABLE (QHD_EUNSUPPORTED). */
+  QHD_SCHEME_YOSHIDA4 = 2
 } qhd_scheme;
 
 /* One problem instance (Algorithm 1 of App. E.1). */

@@ -24,7 +24,7 @@ _SRC = os.path.join(_HERE, "qhd_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 SCHED_NESTEROV, SCHED_CONST, SCHED_TABLE = 0, 1, 2
-SCHEME_STRANG, SCHEME_LIE = 0, 1
+SCHEME_STRANG, SCHEME_LIE, SCHEME_YOSHIDA4 = 0, 1, 2
 
 # planted mistakes (tests only); must match the MUT_* codes in qhd_oracle.c
 MUTATIONS = {

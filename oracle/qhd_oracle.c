@@ -32,6 +32,10 @@
  *     with a, b evaluated at the step midpoint t_{j+1/2} = (j + 1/2) dt, t computed
  *     from the integer j.  SCHEME_LIE is the paper's printed first-order formula:
  *     V(dt) first, then the kinetic factor, coefficients at the left end t_j = j dt.
+ *     SCHEME_YOSHIDA4 composes the symmetric step as a fourth-order triple jump
+ *     (Yoshida, Phys. Lett. A 150, 262 (1990)): three symmetric steps of lengths
+ *     w1 dt, w0 dt, w1 dt with w1 = 1 / (2 - 2^{1/3}) and w0 = 1 - 2 w1, each with
+ *     a, b at its own midpoint (time advances with the stages).
  *   * The shifted Fourier transform only re-orders frequencies; |k|^2 is what
  *     enters, so a plain DFT with n in {0..N/2-1, -N/2..-1} is used.
  *   * x* = argmin of f on the mesh, ties to the lowest flat index; the success
@@ -59,6 +63,7 @@
 
 #define ORACLE_SCHEME_STRANG 0
 #define ORACLE_SCHEME_LIE 1
+#define ORACLE_SCHEME_YOSHIDA4 2
 
 /* planted mistakes, test use only */
 #define MUT_NONE 0
@@ -182,6 +187,18 @@ static void fft_nd(const oracle_desc *d, double *psi, int sign) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* a(t), b(t) of eq. nonconvex_QHD_h (or the constants) at time t. */
+static void coefficients_at(const oracle_desc *d, double t, double *a, double *b) {
+  if (d->sched == ORACLE_SCHED_CONST) {
+    *a = d->p[0];
+    *b = d->p[1];
+    return;
+  }
+  const double t3 = t * t * t;
+  *a = 2.0 / (d->p[0] + t3);
+  *b = 2.0 * t3;
+}
+
 /* Schedule: a(t), b(t) of the Hamiltonian for global step j. */
 static void coefficients(const oracle_desc *d, int64_t j, double *a, double *b) {
   if (d->sched == ORACLE_SCHED_TABLE) {
@@ -282,12 +299,31 @@ int oracle_fft(const oracle_desc *d, double *psi, int sign) {
 int oracle_evolve(const oracle_desc *d, const double *f, double *psi, int64_t j0, int64_t nsteps) {
   if (check_desc(d) || !f || !psi || nsteps < 0 || j0 < 0) return -1;
   if (d->sched == ORACLE_SCHED_TABLE && (!d->table || j0 + nsteps > d->table_len)) return -1;
+  if (d->scheme == ORACLE_SCHEME_YOSHIDA4 && d->sched == ORACLE_SCHED_TABLE) return -1;
 #ifdef _OPENMP
   if (d->threads > 0) omp_set_num_threads(d->threads);
 #endif
   const double dt = d->dt;
   for (int64_t j = j0; j < j0 + nsteps; ++j) {
     double a, b;
+    if (d->scheme == ORACLE_SCHEME_YOSHIDA4) {
+      /* three symmetric steps; stage k starts at j dt + c_k dt, lasts w_k dt */
+      const double w1 = 1.0 / (2.0 - cbrt(2.0)), w0 = 1.0 - 2.0 * w1;
+      const double w[3] = {w1, w0, w1};
+      double start = (double)j * dt;
+      for (int k = 0; k < 3; ++k) {
+        const double h = w[k] * dt;
+        coefficients_at(d, start + 0.5 * h, &a, &b);
+        potential_phase(d, psi, f, 0.5 * h * b);
+        fft_nd(d, psi, -1);
+        kinetic_phase(d, psi, h * a);
+        fft_nd(d, psi, +1);
+        inverse_scale(d, psi);
+        potential_phase(d, psi, f, 0.5 * h * b);
+        start += h;
+      }
+      continue;
+    }
     coefficients(d, j, &a, &b);
     if (d->scheme == ORACLE_SCHEME_LIE) {
       /* eq. prod_qhd_fft: psi_{j+1} = F^{-1} e^{-i s a_j L} F e^{-i s b_j f} psi_j

@@ -19,8 +19,40 @@ __device__ __forceinline__ long long tile_index(int x, int y, int nx) {
 // integer frequency of FFT output index m on an axis of n points
 __device__ __forceinline__ int freq(int m, int n) { return m < (n >> 1) ? m : m - n; }
 
-// a_j, b_j of global step j (App. C.2.1, eq. nonconvex_QHD_h at the midpoint)
+// Fourth-order triple jump (Yoshida 1990): a step of length dt is three symmetric
+// stages of lengths w1 dt, w0 dt, w1 dt, with w1 = 1 / (2 - 2^{1/3}) and
+// w0 = 1 - 2 w1 = -2^{1/3} / (2 - 2^{1/3}).
+constexpr double kYoshidaW1 = 1.3512071919596576340;
+constexpr double kYoshidaW0 = -1.7024143839193152681;
+
+// Coefficients of stage j (App. C.2.1, eq. nonconvex_QHD_h), multiplied by the
+// stage's length in units of dt: every phase of a stage is then (coefficient) x dt.
+// Strang and the fourth-order composition take a and b at the stage midpoint; the
+// printed first-order product at the left end of the step.  One stage per step
+// except for the fourth-order scheme (stage j is stage j mod 3 of step j / 3).
 __device__ __forceinline__ void sched_ab(const InstDev& I, long long j, double& a, double& b) {
+  if (I.scheme == kSchemeYoshida4) {
+    const long long step = j / 3;
+    const int k = (int)(j - 3 * step);
+    const double w = k == 1 ? kYoshidaW0 : kYoshidaW1;
+    const double start = k == 0 ? 0.0 : (k == 1 ? kYoshidaW1 : kYoshidaW1 + kYoshidaW0);
+    if (I.sched == kSchedConst) {
+      a = I.sched_p0 * w;
+      b = I.sched_p1 * w;
+      return;
+    }
+    const double t = ((double)step + start + 0.5 * w) * I.dt;
+    if (I.sched == kSchedLinear) {
+      const double g = t / I.sched_p0;
+      a = (1.0 - g) * w;
+      b = g * w;
+    } else {
+      const double t3 = t * t * t;
+      a = 2.0 / (I.sched_p0 + t3) * w;
+      b = 2.0 * t3 * w;
+    }
+    return;
+  }
   if (I.sched == kSchedTable) {
     // lines of finished instances still evaluate (and discard) their step: never
     // read outside the table
@@ -86,9 +118,11 @@ __device__ __forceinline__ double closing_turns(const InstDev& I) {
   return 0.5 * I.dt * b * kInv2Pi;
 }
 
+// stages instance I takes in an evolve call capped at max_steps steps (< 0: no cap)
 __device__ __forceinline__ long long step_limit(const InstDev& I, long long max_steps) {
   const long long rem = I.nsteps - I.steps_done;
-  return (max_steps < 0 || max_steps > rem) ? rem : max_steps;
+  const long long cap = max_steps * I.stages;
+  return (max_steps < 0 || cap > rem) ? rem : cap;
 }
 
 

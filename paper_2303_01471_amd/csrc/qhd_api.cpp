@@ -45,6 +45,9 @@ qhd_status fail(qhd_status st, const char* fmt, ...) {
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // Host-only validation of one descriptor (no device work).
+// stages of one step: the fourth-order composition runs three symmetric stages
+int stages_per_step(const qhd_instance& d) { return d.scheme == QHD_SCHEME_YOSHIDA4 ? 3 : 1; }
+
 qhd_status validate(const qhd_instance& d, int idx) {
   if (d.ndim < 1 || d.ndim > 3) return fail(QHD_EINVAL, "instance %d: ndim must be 1, 2 or 3 (got %d)", idx, d.ndim);
   for (int a = 0; a < d.ndim; ++a) {
@@ -80,12 +83,17 @@ qhd_status validate(const qhd_instance& d, int idx) {
     default:
       return fail(QHD_EINVAL, "instance %d: unknown sched_kind %d", idx, d.sched_kind);
   }
-  if (d.scheme != QHD_SCHEME_STRANG && d.scheme != QHD_SCHEME_LIE)
+  if (d.scheme != QHD_SCHEME_STRANG && d.scheme != QHD_SCHEME_LIE && d.scheme != QHD_SCHEME_YOSHIDA4)
     return fail(QHD_EINVAL, "instance %d: unknown scheme %d", idx, d.scheme);
+  if (d.scheme == QHD_SCHEME_YOSHIDA4 && d.sched_kind == QHD_SCHED_TABLE)
+    return fail(QHD_EUNSUPPORTED, "instance %d: the fourth-order scheme evaluates the schedule between table "
+                                  "points; use NESTEROV, CONST or LINEAR", idx);
   if (d.model != QHD_MODEL_QHD && d.model != QHD_MODEL_QAA)
     return fail(QHD_EINVAL, "instance %d: unknown model %d", idx, d.model);
   if (d.model == QHD_MODEL_QAA && d.ndim != 2)
     return fail(QHD_EUNSUPPORTED, "instance %d: the QAA model is built for 2-D meshes", idx);
+  if (d.model == QHD_MODEL_QAA && d.scheme != QHD_SCHEME_STRANG)
+    return fail(QHD_EUNSUPPORTED, "instance %d: the QAA model runs the symmetric scheme", idx);
   if (d.init_kind != QHD_INIT_UNIFORM && d.init_kind != QHD_INIT_USER)
     return fail(QHD_EINVAL, "instance %d: unknown init_kind %d", idx, d.init_kind);
   return QHD_OK;
@@ -154,7 +162,8 @@ struct qhd_plan_s {
   // a chunk of graph_k steps of every class, captured at plan creation (see qhd_evolve)
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  int graph_k = 0;
+  int graph_k = 0;    // stages per replay
+  int graph_sps = 1;  // stages per step of every instance of a graph plan
   // timing
   std::vector<Family> families;
   std::vector<Pending> pending;
@@ -418,12 +427,13 @@ qhd_status autotune_class(qhd_plan p, ShapeClass& c, double& us_row, double& us_
   return QHD_OK;
 }
 
-// Capture graph_k steps of every class (all members active) plus the commit.
-qhd_status build_step_graph(qhd_plan p, int k) {
+// Capture k steps (k * sps stages) of every class (all members active) plus the commit;
+// every instance takes sps stages per step.
+qhd_status build_step_graph(qhd_plan p, int k, int sps) {
   std::vector<std::vector<long long>> lim(p->classes.size());
-  for (size_t ci = 0; ci < p->classes.size(); ++ci) lim[ci].assign(p->classes[ci].members.size(), k);
+  for (size_t ci = 0; ci < p->classes.size(); ++ci) lim[ci].assign(p->classes[ci].members.size(), (long long)k * sps);
   HIP_TRY(hipStreamBeginCapture(p->internal, hipStreamCaptureModeThreadLocal));
-  qhd_status st = enqueue_steps(p, k, lim, k, p->internal, false);
+  qhd_status st = enqueue_steps(p, (long long)k * sps, lim, k, p->internal, false);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(p->internal, &g);
   if (st != QHD_OK) {
@@ -437,7 +447,8 @@ qhd_status build_step_graph(qhd_plan p, int k) {
     return fail(QHD_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
   }
   p->graph = g;
-  p->graph_k = k;
+  p->graph_k = k * sps;
+  p->graph_sps = sps;
   return QHD_OK;
 }
 
@@ -585,7 +596,8 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
   for (size_t ci = 0; ci < p->classes.size(); ++ci) {
     ShapeClass& c = p->classes[ci];
     std::stable_sort(c.members.begin(), c.members.end(),
-                     [&](int a, int b) { return inst[a].nsteps > inst[b].nsteps; });
+                     [&](int a, int b) { return inst[a].nsteps * stages_per_step(inst[a]) >
+                                                inst[b].nsteps * stages_per_step(inst[b]); });
     const int m = (int)c.members.size();
     max_pts = std::max(max_pts, c.points);
     max_members = std::max(max_members, (size_t)m);
@@ -614,7 +626,8 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       I.sched_p0 = d.sched_p[0];
       I.sched_p1 = d.sched_p[1];
       I.r2 = d.success_radius * d.success_radius;
-      I.nsteps = d.nsteps;
+      I.stages = stages_per_step(d);
+      I.nsteps = d.nsteps * I.stages;
       I.steps_done = 0;
       I.mode = kModeClean;
       I.plan_index = i;
@@ -739,14 +752,16 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       }
     }
   }
-  // step-chunk graph for plans whose instances all take the same number of steps
+  // step-chunk graph for plans whose instances all take the same number of steps of
+  // the same number of stages
   {
-    long long n0 = inst[0].nsteps;
+    const long long n0 = inst[0].nsteps;
+    const int sps = stages_per_step(inst[0]);
     bool same = true;
-    for (int i = 1; i < batch; ++i) same = same && inst[i].nsteps == n0;
-    const int k = (int)std::min<long long>(64, n0);
+    for (int i = 1; i < batch; ++i) same = same && inst[i].nsteps == n0 && stages_per_step(inst[i]) == sps;
+    const int k = (int)std::min<long long>(64 / sps, n0);
     if (same && k >= 8 && !(p->opts.flags & (QHD_OPT_NO_GRAPH | QHD_OPT_TIME_PASSES))) {
-      qhd_status st = build_step_graph(p, k);
+      qhd_status st = build_step_graph(p, k, sps);
       if (st != QHD_OK) return bail(st);
     }
   }
@@ -833,7 +848,7 @@ qhd_status qhd_set_steps_done(qhd_plan p, int32_t i, int64_t j) {
   InstDev& I = c.host[p->pos_of[i]];
   if (I.mode != kModeClean)
     return fail(QHD_ESTATE, "instance %d: set_steps_done needs a clean state (call qhd_set_state first)", i);
-  I.steps_done = j;
+  I.steps_done = j * I.stages;
   return push_inst(p, i);
 }
 
@@ -855,8 +870,10 @@ qhd_status qhd_evolve(qhd_plan p, int64_t max_steps, void* stream_v) {
     ShapeClass& c = p->classes[ci];
     lim[ci].resize(c.members.size());
     for (size_t k = 0; k < c.members.size(); ++k) {
+      // in stages, like the kernels' step_limit
       const long long rem = c.host[k].nsteps - c.host[k].steps_done;
-      const long long l = (max_steps < 0 || max_steps > rem) ? rem : max_steps;
+      const long long cap = max_steps * c.host[k].stages;
+      const long long l = (max_steps < 0 || cap > rem) ? rem : cap;
       lim[ci][k] = l;
       S = std::max(S, l);
     }
@@ -878,7 +895,9 @@ qhd_status qhd_evolve(qhd_plan p, int64_t max_steps, void* stream_v) {
     std::vector<std::vector<long long>> rest(lim);
     for (auto& v : rest)
       for (auto& l : v) l -= done;
-    qhd_status st = enqueue_steps(p, S - done, rest, done > 0 ? S - done : max_steps, stream, timing);
+    // after whole graph chunks every instance has (S - done) / graph_sps steps left
+    qhd_status st = enqueue_steps(p, S - done, rest, done > 0 ? (S - done) / p->graph_sps : max_steps, stream,
+                                  timing);
     if (st != QHD_OK) return st;
   }
   for (size_t ci = 0; ci < p->classes.size(); ++ci) {
@@ -900,7 +919,7 @@ qhd_status qhd_plan_info(qhd_plan p, qhd_class_info* out, int32_t cap, int32_t* 
   g_err.clear();
   if (!p || !n_classes || !graph_steps || (cap > 0 && !out)) return fail(QHD_EINVAL, "NULL argument");
   *n_classes = (int32_t)p->classes.size();
-  *graph_steps = p->graph_exec ? p->graph_k : 0;
+  *graph_steps = p->graph_exec ? p->graph_k / p->graph_sps : 0;
   for (int k = 0; k < cap && k < (int)p->classes.size(); ++k) {
     const ShapeClass& c = p->classes[k];
     qhd_class_info& o = out[k];
@@ -970,8 +989,8 @@ qhd_status qhd_observe(qhd_plan p, void* stream_v, qhd_observables* out, float* 
       o.success_mass = r[2] / r[0];
       o.f_min = I.f_min;
       o.argmin_index = I.argmin;
-      o.steps_done = I.steps_done;
-      o.t = (double)I.steps_done * I.dt;
+      o.steps_done = I.steps_done / I.stages;
+      o.t = (double)o.steps_done * I.dt;
       if (!std::isfinite(o.norm) || !std::isfinite(o.e_f) || !std::isfinite(o.success_mass)) {
         if (status == QHD_OK) status = fail(QHD_ENUMERIC, "instance %d: non-finite observable", I.plan_index);
       } else if (std::fabs(o.norm - 1.0) > p->opts.norm_tolerance) {

@@ -8,7 +8,7 @@
 namespace qhd {
 
 enum : int { kModeClean = 0, kModePending = 1 };
-enum : int { kSchemeStrang = 0, kSchemeLie = 1 };
+enum : int { kSchemeStrang = 0, kSchemeLie = 1, kSchemeYoshida4 = 2 };
 enum : int { kModelQHD = 0, kModelQAA = 1 };
 enum : int { kSchedNesterov = 0, kSchedConst = 1, kSchedTable = 2, kSchedLinear = 3 };
 
@@ -21,17 +21,17 @@ struct InstDev {
   const double* table;   // device copy of (a_j, b_j) pairs, kSchedTable only
   double r2;             // success radius squared
   double f_min;          // f(x*)
-  long long nsteps;
-  long long steps_done;  // authoritative device copy (updated by the commit kernel)
+  long long nsteps;      // in stages (steps x stages)
+  long long steps_done;  // in stages; authoritative device copy (updated by the commit kernel)
   long long psi_off;     // element offset of the instance in its class buffers
   long long out_off;     // element offset in plan-wide concatenated outputs
   long long argmin;      // flat index of x*
   int sched;
   int mode;              // kModeClean / kModePending
   int plan_index;        // position in the user's batch
-  int scheme;            // kSchemeStrang / kSchemeLie
+  int scheme;            // kSchemeStrang / kSchemeLie / kSchemeYoshida4
   int model;             // kModelQHD / kModelQAA
-  int pad_;
+  int stages;            // stages per step: 3 for kSchemeYoshida4, else 1
 };
 
 // What the spectrum entry point (qhd_spectrum.cpp) reads of one plan instance.

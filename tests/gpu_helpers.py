@@ -22,7 +22,8 @@ def note(msg: str):
 def oracle_problem(spec: q.InstanceSpec) -> oracle.Problem:
     sched = {q.QHD_SCHED_NESTEROV: oracle.SCHED_NESTEROV, q.QHD_SCHED_CONST: oracle.SCHED_CONST,
              q.QHD_SCHED_TABLE: oracle.SCHED_TABLE}[spec.sched]
-    scheme = oracle.SCHEME_LIE if spec.scheme == q.QHD_SCHEME_LIE else oracle.SCHEME_STRANG
+    scheme = {q.QHD_SCHEME_STRANG: oracle.SCHEME_STRANG, q.QHD_SCHEME_LIE: oracle.SCHEME_LIE,
+              q.QHD_SCHEME_YOSHIDA4: oracle.SCHEME_YOSHIDA4}[spec.scheme]
     return oracle.Problem(shape=tuple(spec.shape), box=spec.box, dt=spec.dt, sched=sched,
                           params=tuple(spec.sched_p), table=spec.table, radius=spec.radius, scheme=scheme)
 

@@ -16,7 +16,7 @@ import scipy.linalg
 from scipy.integrate import solve_ivp
 
 import oracle
-from oracle import Problem, SCHED_CONST, SCHED_NESTEROV, SCHED_TABLE, SCHEME_LIE, SCHEME_STRANG
+from oracle import Problem, SCHED_CONST, SCHED_NESTEROV, SCHED_TABLE, SCHEME_LIE, SCHEME_STRANG, SCHEME_YOSHIDA4
 
 
 # ----------------------------------------------------------------------------------------
@@ -177,6 +177,75 @@ def pin_time_order(mutation=0, seed=2, scheme=SCHEME_STRANG):
     want = 4.0 if scheme == SCHEME_STRANG else 2.0
     ok = all(abs(r - want) < 0.1 * want for r in (r1, r2))
     return ok, (errs, r1, r2)
+
+
+# ---- the fourth-order composition (triple jump, Yoshida 1990) ------------------------
+# w1 = 1 / (2 - 2^{1/3}), w0 = 1 - 2 w1: S(w1 h) S(w0 h) S(w1 h) of a symmetric
+# second-order step S is fourth order (the odd error terms cancel by symmetry and
+# 2 w1^3 + w0^3 = 0 removes the third-order one).
+
+def yoshida_weights():
+    w1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+    return (w1, 1.0 - 2.0 * w1, w1)
+
+
+def pin_yoshida_one_step(seed=11):
+    """One fourth-order step equals the product of three dense symmetric steps of
+    lengths w1 dt, w0 dt, w1 dt, each with a, b at its own midpoint (time advancing
+    with the stages), built from matrix exponentials of the discretised operators."""
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for shape, box in [((32,), [(0.0, 2.0)]), ((8, 8), [(0.0, 1.0), (0.0, 1.0)]),
+                       ((4, 16), [(-1.0, 2.0), (0.5, 1.25)])]:
+        f = rng.uniform(-1, 3, size=shape)
+        psi0 = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+        psi0 /= np.linalg.norm(psi0)
+        for sched, params in [(SCHED_CONST, (0.7, 1.3)), (SCHED_NESTEROV, (1e-3, 0.0))]:
+            dt, j = 0.02, 17
+            prob = Problem(shape=shape, box=box, dt=dt, sched=sched, params=params, scheme=SCHEME_YOSHIDA4)
+            got = oracle.evolve(prob, f, psi0, j0=j, nsteps=1)
+            ref, start = psi0, j * dt
+            for w in yoshida_weights():
+                h = w * dt
+                a, b = params if sched == SCHED_CONST else nesterov_ab(start + 0.5 * h, params[0])
+                ref = one_step_dense(shape, box, f, ref, h, a, b)
+                start += h
+            worst = max(worst, float(np.max(np.abs(got - ref))))
+    return worst < 1e-12, worst
+
+
+def pin_yoshida_order(seed=2):
+    """Global error of the fourth-order composition against the exact time-ordered
+    evolution (same problem as pin_time_order) shrinks like dt^4."""
+    rng = np.random.default_rng(seed)
+    shape, box = (8, 8), [(0.0, 6.0), (0.0, 8.0)]
+    f = rng.uniform(0, 2, size=shape)
+    psi0 = oracle.uniform_state(shape)
+    eps, T = 1.0, 1.0
+    K = dense_kinetic(shape, box)
+    ref = exact_propagate(K, f.reshape(-1), lambda t: nesterov_ab(t, eps), 0.0, T, psi0).reshape(shape)
+    errs = []
+    for nst in (16, 32, 64):
+        prob = Problem(shape=shape, box=box, dt=T / nst, sched=SCHED_NESTEROV, params=(eps, 0.0),
+                       scheme=SCHEME_YOSHIDA4)
+        errs.append(float(np.max(np.abs(oracle.evolve(prob, f, psi0, 0, nst) - ref))))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    ok = all(abs(r - 16.0) < 1.6 for r in (r1, r2))
+    return ok, (errs, r1, r2)
+
+
+def pin_yoshida_reversal(seed=12):
+    """The composition is symmetric: with constant coefficients, n steps of -dt undo
+    n steps of dt."""
+    from qhd_inputs import landscape_grid
+    shape = (16, 32)
+    f = landscape_grid(seed, shape)
+    fwd = Problem(shape=shape, dt=2e-3, sched=SCHED_CONST, params=(0.8, 5.0), scheme=SCHEME_YOSHIDA4)
+    bwd = Problem(shape=shape, dt=-2e-3, sched=SCHED_CONST, params=(0.8, 5.0), scheme=SCHEME_YOSHIDA4)
+    psi0 = oracle.uniform_state(shape)
+    back = oracle.evolve(bwd, f, oracle.evolve(fwd, f, psi0, 0, 150), 0, 150)
+    err = float(np.max(np.abs(back - psi0)))
+    return err < 1e-12, err
 
 
 def pin_norm(mutation=0, seed=3, nsteps=10000):

@@ -59,9 +59,10 @@ def _inst(**kw):
     (lambda d: d.sched_p.__setitem__(0, 0.0), q.QHD_EINVAL),
     (lambda d: setattr(d, "sched_kind", q.QHD_SCHED_TABLE), q.QHD_EINVAL),  # NULL table
     (lambda d: setattr(d, "init_kind", 5), q.QHD_EINVAL),
-    (lambda d: setattr(d, "scheme", 2), q.QHD_EINVAL),
+    (lambda d: setattr(d, "scheme", 3), q.QHD_EINVAL),
     (lambda d: setattr(d, "model", 2), q.QHD_EINVAL),
     (lambda d: (setattr(d, "model", q.QHD_MODEL_QAA), setattr(d, "ndim", 1)), q.QHD_EUNSUPPORTED),
+    (lambda d: (setattr(d, "model", q.QHD_MODEL_QAA), setattr(d, "scheme", q.QHD_SCHEME_LIE)), q.QHD_EUNSUPPORTED),
     (lambda d: (setattr(d, "sched_kind", q.QHD_SCHED_LINEAR), d.sched_p.__setitem__(0, 0.0)), q.QHD_EINVAL),
 ])
 def test_invalid_descriptor_rejected_before_device_work(mutate, status):
@@ -72,6 +73,17 @@ def test_invalid_descriptor_rejected_before_device_work(mutate, status):
         q.qhd_plan_create([good, bad])
     assert ei.value.status == status
     assert "instance 1" in ei.value.message
+
+
+def test_fourth_order_scheme_with_table_schedule_unsupported():
+    # the composition evaluates the schedule between the table's per-step values
+    keep = []
+    good = _inst()
+    bad = q.InstanceSpec(shape=(64, 64), nsteps=10, dt=1e-2, sched=q.QHD_SCHED_TABLE,
+                         table=np.ones((10, 2)), scheme=q.QHD_SCHEME_YOSHIDA4).to_c(keep)
+    with pytest.raises(q.QHDError) as ei:
+        q.qhd_plan_create([good, bad])
+    assert ei.value.status == q.QHD_EUNSUPPORTED and "instance 1" in ei.value.message
 
 
 def test_table_with_nan_rejected():

@@ -30,6 +30,22 @@ def test_pin_paper_first_order_formula():
     assert ok, detail
 
 
+@pytest.mark.parametrize("pin", [P.pin_yoshida_one_step, P.pin_yoshida_order, P.pin_yoshida_reversal])
+def test_pin_fourth_order_composition(pin):
+    ok, detail = pin()
+    assert ok, detail
+
+
+def test_fourth_order_pins_catch_a_wrong_weight(monkeypatch):
+    """A plausible mistake in the composition (w0 = 1 - w1, i.e. stages that do not
+    sum to dt) planted in the pins' own weights makes the one-step pin fail."""
+    monkeypatch.setattr(P, "yoshida_weights", lambda: (1.0 / (2.0 - 2.0 ** (1.0 / 3.0)),
+                                                      1.0 - 1.0 / (2.0 - 2.0 ** (1.0 / 3.0)),
+                                                      1.0 / (2.0 - 2.0 ** (1.0 / 3.0))))
+    ok, _ = P.pin_yoshida_one_step()
+    assert not ok
+
+
 @pytest.mark.parametrize("mutation", sorted(oracle.MUTATIONS))
 def test_planted_mistake_is_caught(mutation):
     code = oracle.MUTATIONS[mutation]
