@@ -10,8 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqhd.so")
 
-SOURCES = ["qhd_api.cpp", "qhd_kernels.hip", "qhd_kernels_3d.hip", "qhd_kernels_mfma.hip", "qhd_spectrum.cpp", "qhd_spectrum_kernels.hip", "sno.cpp", "sno_gemm.hip", "sno_kernels.hip"]
-HEADERS = ["line_fft.h", "qhd_internal.h", "pass_common.h", "sno_internal.h"]
+SOURCES = ["qhd_api.cpp", "qhd_kernels.hip", "qhd_kernels_3d.hip", "qhd_kernels_mfma.hip", "qhd_spectrum.cpp", "qhd_spectrum_kernels.hip", "sno.cpp", "sno_gemm.hip", "sno_kernels.hip", "rqp.cpp", "rqp_kernels.hip"]
+HEADERS = ["line_fft.h", "qhd_internal.h", "pass_common.h", "sno_internal.h", "rqp_internal.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -32,7 +32,7 @@ def stale() -> bool:
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
-    deps = sources() + [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(ROOT, "include", h) for h in ("qhd.h", "qhd_sno.h")]
+    deps = sources() + [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(ROOT, "include", h) for h in ("qhd.h", "qhd_sno.h", "qhd_rqp.h")]
     return any(os.path.getmtime(d) > t for d in deps)
 
 

@@ -106,6 +106,31 @@ class qhd_sno_desc(ctypes.Structure):
     ]
 
 
+class qhd_rqp_desc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("r", ctypes.c_int32),
+        ("dt", ctypes.c_double),
+        ("nsteps", ctypes.c_int64),
+        ("sched_kind", ctypes.c_int32),
+        ("sched_p", ctypes.c_double * 2),
+        ("sched_table", ctypes.POINTER(ctypes.c_double)),
+        ("min_tol", ctypes.c_double),
+    ]
+
+
+class qhd_rqp_obs(ctypes.Structure):
+    _fields_ = [
+        ("norm", ctypes.c_double),
+        ("e_f", ctypes.c_double),
+        ("p_min", ctypes.c_double),
+        ("f_min", ctypes.c_double),
+        ("argmin_index", ctypes.c_int64),
+        ("steps_done", ctypes.c_int64),
+        ("t", ctypes.c_double),
+    ]
+
+
 class qhd_class_info(ctypes.Structure):
     _fields_ = [
         ("ndim", ctypes.c_int32),
@@ -122,7 +147,8 @@ class qhd_class_info(ctypes.Structure):
 
 _lib = None
 
-# every entry point declared in include/qhd.h and include/qhd_sno.h, with its ctypes signature
+# every entry point declared in include/qhd.h, include/qhd_sno.h and include/qhd_rqp.h,
+# with its ctypes signature
 _SIGNATURES = {
     "qhd_plan_create": (ctypes.c_int, [ctypes.POINTER(qhd_instance), ctypes.c_int32,
                                        ctypes.POINTER(qhd_plan_opts), ctypes.POINTER(ctypes.c_void_p)]),
@@ -154,6 +180,14 @@ _SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p]),
     "qhd_sno_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
     "qhd_sno_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "qhd_rqp_create": (ctypes.c_int, [ctypes.POINTER(qhd_rqp_desc), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "qhd_rqp_set_objective": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "qhd_rqp_evolve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "qhd_rqp_observe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(qhd_rqp_obs),
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "qhd_rqp_reset": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "qhd_rqp_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "qhd_rqp_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 
@@ -302,6 +336,41 @@ def qhd_sno_step(sno: int, lr: float, stream: int):
 
 def qhd_sno_destroy(sno: int):
     _check(load_library().qhd_sno_destroy(sno))
+
+
+def qhd_rqp_create(desc: qhd_rqp_desc, batch: int) -> int:
+    h = ctypes.c_void_p()
+    _check(load_library().qhd_rqp_create(ctypes.byref(desc), batch, ctypes.byref(h)))
+    return h.value
+
+
+def qhd_rqp_set_objective(h: int, i: int, Q_ptr: int, b_ptr: int):
+    _check(load_library().qhd_rqp_set_objective(h, i, Q_ptr, b_ptr))
+
+
+def qhd_rqp_evolve(h: int, max_steps: int, stream: int):
+    _check(load_library().qhd_rqp_evolve(h, max_steps, stream))
+
+
+def qhd_rqp_observe(h: int, stream: int, out, marginals_ptr: int, prob_ptr: int) -> int:
+    st = load_library().qhd_rqp_observe(h, stream, out, marginals_ptr or None, prob_ptr or None)
+    if st not in (QHD_OK, QHD_ENUMERIC):
+        _check(st)
+    return st
+
+
+def qhd_rqp_reset(h: int, stream: int):
+    _check(load_library().qhd_rqp_reset(h, stream))
+
+
+def qhd_rqp_points(h: int) -> int:
+    n = ctypes.c_int64()
+    _check(load_library().qhd_rqp_points(h, ctypes.byref(n)))
+    return n.value
+
+
+def qhd_rqp_destroy(h: int):
+    _check(load_library().qhd_rqp_destroy(h))
 
 
 # ------------------------------------------------------------------------------------

@@ -156,3 +156,18 @@ def qaa_batch(count: int = 512, seed_base: int = 19820301, sizes=(64, 128), T: f
         m = int(rng.integers(terms[0], terms[1] + 1))
         out.append(InstanceSpec(seed_base + 1_000_000 + i, (n, n), int(round(T / dt)), dt, m, 6))
     return out
+
+
+def qp_instances(count: int, dim: int = 5, seed_base: int = 5050) -> List[Tuple[np.ndarray, np.ndarray]]:
+    """Box-constrained QP instances (App. G.1 recipe for the dense 5-dimensional group):
+    the Hessian Q symmetric with entries uniform in [-1, 1] (upper triangle drawn,
+    mirrored), the linear term b uniform in [-1, 1]; from PCG64(seed_base + i), draw
+    order Q then b."""
+    out = []
+    for i in range(count):
+        rng = np.random.Generator(np.random.PCG64(seed_base + i))
+        U = rng.uniform(-1.0, 1.0, size=(dim, dim))
+        Q = np.triu(U) + np.triu(U, 1).T
+        b = rng.uniform(-1.0, 1.0, size=dim)
+        out.append((Q, b))
+    return out

@@ -1,5 +1,5 @@
 """C-ABI library checks that need no GPU: it loads, exports every symbol that
-include/qhd.h and include/qhd_sno.h declare, and rejects invalid descriptors in
+include/qhd.h, include/qhd_sno.h and include/qhd_rqp.h declare, and rejects invalid descriptors in
 its host-only validation layer before touching any device."""
 import ctypes
 import os
@@ -11,7 +11,7 @@ import pytest
 from paper_2303_01471_amd import qhd as q
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("qhd.h", "qhd_sno.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("qhd.h", "qhd_sno.h", "qhd_rqp.h")]
 
 
 def declared_symbols():
@@ -27,6 +27,7 @@ def test_library_exports_every_declared_symbol():
     syms = declared_symbols()
     assert "qhd_plan_create" in syms and "qhd_evolve" in syms and "qhd_observe" in syms
     assert "qhd_sno_forward" in syms and "qhd_sno_backward" in syms
+    assert "qhd_rqp_create" in syms and "qhd_rqp_evolve" in syms and "qhd_rqp_observe" in syms
     for s in syms:
         assert hasattr(lib, s), f"libqhd.so does not export {s}"
         assert s in q._SIGNATURES, f"binding has no signature for {s}"
@@ -112,3 +113,33 @@ def test_null_arguments():
     n = ctypes.c_int64()
     assert lib.qhd_plan_points(None, ctypes.byref(n)) == q.QHD_EINVAL
     assert lib.qhd_plan_destroy(None) == q.QHD_OK
+
+
+def _rqp_desc(**kw):
+    d = q.qhd_rqp_desc()
+    d.dim, d.r, d.dt, d.nsteps = 5, 8, 1e-2, 10
+    d.sched_kind = q.QHD_SCHED_NESTEROV
+    d.sched_p[0], d.sched_p[1] = 1e-3, 0.0
+    d.min_tol = 1e-9
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("kw,batch,status", [
+    (dict(dim=0), 1, q.QHD_EINVAL),
+    (dict(dim=9), 1, q.QHD_EINVAL),
+    (dict(r=0), 1, q.QHD_EINVAL),
+    (dict(r=16), 1, q.QHD_EINVAL),
+    (dict(dt=0.0), 1, q.QHD_EINVAL),
+    (dict(nsteps=-1), 1, q.QHD_EINVAL),
+    (dict(min_tol=-1.0), 1, q.QHD_EINVAL),
+    (dict(sched_kind=9), 1, q.QHD_EINVAL),
+    (dict(sched_kind=q.QHD_SCHED_TABLE), 1, q.QHD_EINVAL),  # NULL table
+    (dict(dim=8, r=15), 1, q.QHD_EUNSUPPORTED),             # 16^8 points
+    (dict(), 0, q.QHD_EINVAL),
+])
+def test_relaxed_qp_descriptor_rejected_before_device_work(kw, batch, status):
+    with pytest.raises(q.QHDError) as ei:
+        q.qhd_rqp_create(_rqp_desc(**kw), batch)
+    assert ei.value.status == status
