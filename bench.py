@@ -139,16 +139,119 @@ def timed_runs(plan, steps, warmup, stream, label):
     return time.perf_counter() - t0, last[0], last[1]
 
 
+RQP_BYTES_PER_POINT_STEP = lambda d: 16.0 * d + 8.0  # d axis passes (read + write c64) + f once
+
+
+def rqp_run(q, probs, r, dt, nsteps, steps, warmup, stream, label):
+    """Relaxed-QP batch: warmup + timed whole runs (reset, evolve, observe); returns
+    (seconds per run measured with HIP events on the stream, readouts)."""
+    import torch
+    from paper_2303_01471_amd.rqp import RelaxedQP
+    d = len(probs[0][1])
+    h = RelaxedQP(d, r, len(probs), dt, nsteps)
+    try:
+        for i, (Q, b) in enumerate(probs):
+            h.set_objective(i, Q, b)
+        for w in range(warmup):
+            h.reset(stream)
+            h.evolve(-1, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(steps):
+            h.reset(stream)
+            h.evolve(-1, stream)
+        e1.record(stream)
+        res, _, _, _ = h.observe(stream)
+        torch.cuda.synchronize()
+        secs = e0.elapsed_time(e1) * 1e-3 / steps
+        log(f"{label}: {secs * 1e3:.1f} ms per run")
+        return secs, res, h.points
+    finally:
+        h.close()
+
+
+def rqp_summary(secs, res, points, probs, nsteps, r):
+    import numpy as np
+    d = len(probs[0][1])
+    gp = float(points) * len(probs) * nsteps
+    rate = gp / secs
+    achieved = rate * RQP_BYTES_PER_POINT_STEP(d) / 1e9
+    return {"gp_steps_per_s": round(rate, 1), "grid_point_steps": gp,
+            "roofline": {"bound": "hbm", "kernel": f"relaxed-QP step ({d} axis passes, r+1={r + 1})",
+                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "algorithmic_bytes_per_point": RQP_BYTES_PER_POINT_STEP(d),
+                         "mean_step_us": round(secs / nsteps * 1e6, 2)},
+            "max_norm_drift": max(abs(x["norm"] - 1.0) for x in res),
+            "mean_p_min": round(float(np.mean([x["p_min"] for x in res])), 4),
+            "mean_gap_e_f_minus_f_min": round(float(np.mean([x["e_f"] - x["f_min"] for x in res])), 4)}
+
+
+def main_rqp(args, q, np, torch, qhd_inputs):
+    """--workload rqp: the relaxed-QP batch is the measured workload."""
+    probs = qhd_inputs.qp_instances(256, 5)
+    r, dt, nsteps = 8, 1e-2, 1000
+    if args.cap_steps > 0:
+        nsteps = min(nsteps, args.cap_steps)
+    stream = torch.cuda.current_stream()
+    secs, res, pts = rqp_run(q, probs, r, dt, nsteps, args.steps, args.warmup, stream, "relaxed-QP")
+    summ = rqp_summary(secs, res, pts, probs, nsteps, r)
+    cpu = parity = None
+    if not args.no_cpu_baseline:
+        # the FP64 reference on the batch's first instance for a bounded number of steps
+        import threadpoolctl
+
+        from oracle import rqp_reference as rq
+        from paper_2303_01471_amd.rqp import RelaxedQP
+        Q0, b0 = probs[0]
+        ns = min(nsteps, 200)
+        f0 = rq.objective(Q0, b0, r)
+        ab = lambda t: rq.nesterov_ab(t, 1e-3)
+        t0 = time.perf_counter()
+        psi = rq.evolve(f0, rq.initial_state(5, r), r, dt, ns, ab)
+        tcpu = time.perf_counter() - t0
+        blas = [p_["num_threads"] for p_ in threadpoolctl.threadpool_info() if p_.get("user_api") == "blas"]
+        cpu = {"value": round(pts * ns / tcpu, 1), "unit": "grid-point-steps/s", "cores": max(blas) if blas else 1,
+               "kind": "oracle", "sample": f"instance 0 of the batch (9^5 lattice), first {ns} of its {nsteps} "
+                                           f"steps, FP64 relaxed-QP reference, {tcpu:.1f}s"}
+        h = RelaxedQP(5, r, 1, dt, ns)
+        h.set_objective(0, Q0, b0)
+        h.evolve(-1, stream)
+        r1, _, prob, _ = h.observe(stream, want_prob=True)
+        torch.cuda.synchronize()
+        h.close()
+        parity = {"sample": f"instance 0 (9^5 lattice), {ns} steps, |phi|^2 per lattice point",
+                  "max_abs_drho": float(np.max(np.abs(prob.cpu().numpy()[0] - (np.abs(psi) ** 2).reshape(-1)))),
+                  "norm_drift": abs(r1[0]["norm"] - 1.0), "tolerance": 1e-5}
+        log(f"relaxed-QP cpu reference {cpu['value'] / 1e6:.2f} M gp-steps/s; parity {parity['max_abs_drho']:.2e}")
+    line = {
+        "metric": "grid-point-steps/s of the relaxed-QHD box-QP batch (1 GPU)",
+        "value": summ["gp_steps_per_s"], "unit": "grid-point-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(secs * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "relaxed QHD for box-constrained QP: 256 instances of the 5-D recipe, r = 8 "
+                               "(9^5 lattice), T = 10, dt = 1e-2, Nesterov schedule"
+                               + (f", steps capped at {args.cap_steps}" if args.cap_steps else ""),
+                   "instances": len(probs), "grid_point_steps": summ["grid_point_steps"],
+                   "max_norm_drift": summ["max_norm_drift"]},
+        "roofline": summ["roofline"], "cpu_baseline": cpu, "parity": parity,
+        "relaxed_qp": {k: v for k, v in summ.items() if k not in ("roofline",)},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--count", type=int, default=768, help="instances in the batch")
-    ap.add_argument("--workload", choices=("batched2d", "3d", "qaa"), default="batched2d",
+    ap.add_argument("--workload", choices=("batched2d", "3d", "qaa", "rqp"), default="batched2d",
                     help="batched2d: the 768-instance 2-D batch (default); 3d: 16 instances of 128^3, "
                          "T = 10, dt = 2e-3; qaa: the baseline QAA on 512 instances of 64^2 / 128^2, "
-                         "T = 10, dt = 1e-3, with QHD on the same landscapes beside it")
+                         "T = 10, dt = 1e-3, with QHD on the same landscapes beside it; rqp: the relaxed "
+                         "QHD for box-constrained QP, 256 instances of the 5-D recipe, r = 8, T = 10, dt = 1e-2")
     ap.add_argument("--no-qaa-summary", action="store_true",
                     help="batched2d: skip the short baseline-QAA leg reported beside the main line")
     ap.add_argument("--mfma-dft", action="store_true",
@@ -200,6 +303,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     q.load_library()
+    if args.workload == "rqp":
+        return main_rqp(args, q, np, torch, qhd_inputs)
 
     if args.copy_calibration_mib > 0:
         # one elementwise kernel that reads and writes the buffer once (the only
@@ -330,6 +435,16 @@ def main():
                                 "relative to a bound on |H|",
                     "solves": rows}
         log("spectrum: " + ", ".join(f"t={r_['t']}: {r_['ms']} ms" for r_ in rows))
+
+    # ---- batched2d: a short relaxed-QP leg (box-constrained QP, 5-D, r = 8) ---------
+    rqp = None
+    if args.workload == "batched2d" and not args.no_qaa_summary:
+        probs = qhd_inputs.qp_instances(256, 5)
+        nst = min(1000, args.cap_steps) if args.cap_steps > 0 else 1000
+        secs, res_r, pts_r = rqp_run(q, probs, 8, 1e-2, nst, 1, 1, stream, "relaxed-QP leg")
+        rqp = {"workload": "relaxed QHD for box-constrained QP: 256 instances of the 5-D recipe (Q, b uniform "
+                           "in [-1, 1]), r = 8 (9^5 lattice), T = 10, dt = 1e-2, Nesterov schedule"}
+        rqp.update(rqp_summary(secs, res_r, pts_r, probs, nst, 8))
 
     # ---- plain: the single-instance solver on the same GPU ---------------------------
     plain = None
@@ -516,6 +631,7 @@ def main():
         "surrogate": surrogate,
         "qaa": qaa_summary if not qaa else comparison,
         "spectrum": spectrum,
+        "relaxed_qp": rqp,
         "launch_config": tuned,
         "kernels": kernels,
     }
