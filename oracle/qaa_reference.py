@@ -95,3 +95,30 @@ def dense_h0(shape) -> np.ndarray:
         return -op
 
     return np.kron(axis_op(ny), np.eye(nx)) + np.kron(np.eye(ny), axis_op(nx))
+
+
+# ---- the paper's integrator: leapfrog (App. C.2, "Quantum Adiabatic Algorithm") ------
+# With psi = R + i I and H(t) = (1 - g) H0 + g H1 real symmetric, i psi' = H psi reads
+# R' = H I, I' = -H R: a separable Hamiltonian system (R as position, I as momentum).
+# The kick-drift-kick leapfrog step from t_n to t_{n+1}:
+#     I <- I - dt/2 H(t_n) R;   R <- R + dt H(t_{n+1/2}) I;   I <- I - dt/2 H(t_{n+1}) R
+# (time-reversible and symplectic, second order; stable for dt |H| < 2).
+
+def apply_h(f: np.ndarray, v: np.ndarray, g: float) -> np.ndarray:
+    """H v for a real field v: (1 - g) W^{-1} D0 W v + g f v (W the 2-D Walsh-Hadamard
+    transform, W^{-1} = W / N)."""
+    N = v.size
+    return (1.0 - g) * wht2(d0(v.shape) * wht2(v)) / N + g * f * v
+
+
+def evolve_leapfrog(f: np.ndarray, psi: np.ndarray, dt: float, nsteps: int, T: float, j0: int = 0) -> np.ndarray:
+    """Leapfrog steps j0 .. j0+nsteps-1 (FP64), g(t) = t / T."""
+    f = np.asarray(f, dtype=np.float64)
+    psi = np.asarray(psi, dtype=np.complex128)
+    R, I = psi.real.copy(), psi.imag.copy()
+    for j in range(j0, j0 + nsteps):
+        t0, th, t1 = j * dt, (j + 0.5) * dt, (j + 1) * dt
+        I = I - 0.5 * dt * apply_h(f, R, t0 / T)
+        R = R + dt * apply_h(f, I, th / T)
+        I = I - 0.5 * dt * apply_h(f, R, t1 / T)
+    return R + 1j * I

@@ -107,3 +107,59 @@ def test_planted_mistake_sign_of_transverse_field_is_caught(monkeypatch):
     want = (U @ psi.reshape(-1)).reshape(shape)
     monkeypatch.setattr(qa, "d0", lambda s: -qa.d0_axis(s[0])[:, None] - qa.d0_axis(s[1])[None, :])
     assert np.max(np.abs(qa.evolve(f, psi, dt, 1, T) - want)) > 1e-3
+
+
+# ---- leapfrog (the paper's QAA integrator) ---------------------------------------------
+
+def test_leapfrog_h_application_matches_dense_operator():
+    shape, g = (8, 4), 0.3
+    f = _landscape(shape, 21)
+    rng = np.random.Generator(np.random.PCG64(22))
+    v = rng.standard_normal(shape)
+    H = (1 - g) * qa.dense_h0(shape) + g * np.diag(f.reshape(-1))
+    assert np.max(np.abs(qa.apply_h(f, v, g).reshape(-1) - H @ v.reshape(-1))) < 1e-12
+
+
+def test_leapfrog_step_is_kick_drift_kick_with_dense_operators():
+    shape, dt, T, j = (4, 4), 0.05, 2.0, 3
+    f = _landscape(shape, 23)
+    rng = np.random.Generator(np.random.PCG64(24))
+    psi = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    H = lambda t: (1 - t / T) * qa.dense_h0(shape) + (t / T) * np.diag(f.reshape(-1))
+    R, I = psi.real.reshape(-1), psi.imag.reshape(-1)
+    I = I - 0.5 * dt * H(j * dt) @ R
+    R = R + dt * H((j + 0.5) * dt) @ I
+    I = I - 0.5 * dt * H((j + 1) * dt) @ R
+    got = qa.evolve_leapfrog(f, psi, dt, 1, T, j0=j).reshape(-1)
+    assert np.max(np.abs(got - (R + 1j * I))) < 1e-12
+
+
+def test_leapfrog_second_order_convergence_and_time_reversal():
+    shape, T = (4, 8), 2.0
+    f = _landscape(shape, 25)
+    psi0 = qa.uniform(shape)
+    ref = _exact(f, psi0, T, T)
+    errs = [np.max(np.abs(qa.evolve_leapfrog(f, psi0, T / n, n, T) - ref)) for n in (80, 160, 320)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.6 < r1 < 4.4 and 3.6 < r2 < 4.4, errs
+    # reversibility: steps n-1 .. 0 with -dt (kicks and drift at the same times) undo the run
+    n, dt = 40, 0.05
+    fwd = qa.evolve_leapfrog(f, psi0, dt, n, T)
+    R, I = fwd.real.copy(), fwd.imag.copy()
+    for j in reversed(range(n)):
+        I = I + 0.5 * dt * qa.apply_h(f, R, (j + 1) * dt / T)
+        R = R - dt * qa.apply_h(f, I, (j + 0.5) * dt / T)
+        I = I + 0.5 * dt * qa.apply_h(f, R, j * dt / T)
+    assert np.max(np.abs(R + 1j * I - psi0)) < 1e-12
+
+
+def test_leapfrog_planted_mistake_swapped_schedule_weights_is_caught(monkeypatch):
+    # H0 weighted by g and H1 by 1 - g: the convergence check against the exact
+    # evolution fails
+    shape, T = (4, 8), 2.0
+    f = _landscape(shape, 25)
+    psi0 = qa.uniform(shape)
+    ref = _exact(f, psi0, T, T)
+    orig = qa.apply_h
+    monkeypatch.setattr(qa, "apply_h", lambda f_, v, g: orig(f_, v, 1.0 - g))
+    assert np.max(np.abs(qa.evolve_leapfrog(f, psi0, T / 160, 160, T) - ref)) > 1e-3
