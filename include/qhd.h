@@ -85,7 +85,12 @@ typedef enum {
    * symmetric stages of lengths w1 dt, w0 dt, w1 dt with w1 = 1/(2 - 2^{1/3}),
    * w0 = 1 - 2 w1, each with a and b at its own midpoint; three times the passes of
    * QHD_SCHEME_STRANG per step.  Not with QHD_SCHED_TABLE (QHD_EUNSUPPORTED). */
-  QHD_SCHEME_YOSHIDA4 = 2
+  QHD_SCHEME_YOSHIDA4 = 2,
+  /* QHD_MODEL_QAA only: the leapfrog integrator the paper uses for its baseline QAA
+   * (App. C.2): with psi = R + i I, kick I -= dt/2 H(t_j) R, drift R += dt H(t_{j+1/2}) I,
+   * kick I -= dt/2 H(t_{j+1}) R (second order, time-reversible, stable for dt |H| < 2;
+   * the norm is not exactly conserved).  Not with QHD_SCHED_TABLE. */
+  QHD_SCHEME_LEAPFROG = 3
 } qhd_scheme;
 
 /* One problem instance (Algorithm 1 of App. E.1). */

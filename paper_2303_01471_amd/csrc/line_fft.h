@@ -496,6 +496,32 @@ __device__ __forceinline__ void line_wht(T (&reg)[P], int t) {
   }
 }
 
+// The same transform of a real line (FP64 values).
+template <int N, int P>
+__device__ __forceinline__ void line_wht_real(double (&reg)[P], int t) {
+  constexpr int TPL = N / P;
+#pragma unroll
+  for (int h = 1; h < P; h <<= 1) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      if (!(q & h)) {
+        const double a = reg[q], b = reg[q | h];
+        reg[q] = a + b;
+        reg[q | h] = a - b;
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 1; h < TPL; h <<= 1) {
+    const bool upper = (t & h) != 0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const double o = __shfl_xor(reg[q], h);
+      reg[q] = upper ? o - reg[q] : reg[q] + o;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------
 // unit phase factors
 

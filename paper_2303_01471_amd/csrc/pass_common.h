@@ -10,6 +10,8 @@ namespace qhd {
 
 constexpr double kInv2Pi = 0.15915494309189533577;
 
+__host__ __device__ constexpr int ilog2_c(int n) { return n <= 1 ? 0 : 1 + ilog2_c(n >> 1); }
+
 // 8x8-tiled index of mesh point (x, y) on an nx-wide slab (rows y may run over
 // several z slabs: row = y + ny z)
 __device__ __forceinline__ long long tile_index(int x, int y, int nx) {
@@ -30,27 +32,31 @@ constexpr double kYoshidaW0 = -1.7024143839193152681;
 // Strang and the fourth-order composition take a and b at the stage midpoint; the
 // printed first-order product at the left end of the step.  One stage per step
 // except for the fourth-order scheme (stage j is stage j mod 3 of step j / 3).
+// a(t), b(t) of the closed-form schedules (not kSchedTable)
+__device__ __forceinline__ void sched_at_time(const InstDev& I, double t, double& a, double& b) {
+  if (I.sched == kSchedConst) {
+    a = I.sched_p0;
+    b = I.sched_p1;
+  } else if (I.sched == kSchedLinear) {
+    const double g = t / I.sched_p0;
+    a = 1.0 - g;
+    b = g;
+  } else {
+    const double t3 = t * t * t;
+    a = 2.0 / (I.sched_p0 + t3);
+    b = 2.0 * t3;
+  }
+}
+
 __device__ __forceinline__ void sched_ab(const InstDev& I, long long j, double& a, double& b) {
   if (I.scheme == kSchemeYoshida4) {
     const long long step = j / 3;
     const int k = (int)(j - 3 * step);
     const double w = k == 1 ? kYoshidaW0 : kYoshidaW1;
     const double start = k == 0 ? 0.0 : (k == 1 ? kYoshidaW1 : kYoshidaW1 + kYoshidaW0);
-    if (I.sched == kSchedConst) {
-      a = I.sched_p0 * w;
-      b = I.sched_p1 * w;
-      return;
-    }
-    const double t = ((double)step + start + 0.5 * w) * I.dt;
-    if (I.sched == kSchedLinear) {
-      const double g = t / I.sched_p0;
-      a = (1.0 - g) * w;
-      b = g * w;
-    } else {
-      const double t3 = t * t * t;
-      a = 2.0 / (I.sched_p0 + t3) * w;
-      b = 2.0 * t3 * w;
-    }
+    sched_at_time(I, ((double)step + start + 0.5 * w) * I.dt, a, b);
+    a *= w;
+    b *= w;
     return;
   }
   if (I.sched == kSchedTable) {
@@ -116,6 +122,19 @@ __device__ __forceinline__ double closing_turns(const InstDev& I) {
   double a, b;
   sched_ab(I, I.steps_done - 1, a, b);
   return 0.5 * I.dt * b * kInv2Pi;
+}
+
+// Leapfrog stage j of the QAA model (the paper's integrator for its baseline QAA):
+// with psi = R + i I, stage 0 of step n kicks I by -dt/2 H(t_n) R, stage 1 drifts R by
+// +dt H(t_{n+1/2}) I, stage 2 kicks I by -dt/2 H(t_{n+1}) R.  Returns a, b of H at
+// that time, the coefficient c and whether the stage is a kick (source R, target I).
+__device__ __forceinline__ void leapfrog_stage(const InstDev& I, long long j, double& a, double& b, double& c,
+                                               bool& kick) {
+  const long long step = j / 3;
+  const int k = (int)(j - 3 * step);
+  kick = k != 1;
+  c = kick ? -0.5 * I.dt : I.dt;
+  sched_at_time(I, ((double)step + 0.5 * k) * I.dt, a, b);
 }
 
 // stages instance I takes in an evolve call capped at max_steps steps (< 0: no cap)

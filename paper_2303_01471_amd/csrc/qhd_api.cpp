@@ -45,8 +45,11 @@ qhd_status fail(qhd_status st, const char* fmt, ...) {
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // Host-only validation of one descriptor (no device work).
-// stages of one step: the fourth-order composition runs three symmetric stages
-int stages_per_step(const qhd_instance& d) { return d.scheme == QHD_SCHEME_YOSHIDA4 ? 3 : 1; }
+// stages of one step: the fourth-order composition runs three symmetric stages, the
+// leapfrog step kick, drift and kick
+int stages_per_step(const qhd_instance& d) {
+  return (d.scheme == QHD_SCHEME_YOSHIDA4 || d.scheme == QHD_SCHEME_LEAPFROG) ? 3 : 1;
+}
 
 qhd_status validate(const qhd_instance& d, int idx) {
   if (d.ndim < 1 || d.ndim > 3) return fail(QHD_EINVAL, "instance %d: ndim must be 1, 2 or 3 (got %d)", idx, d.ndim);
@@ -83,7 +86,8 @@ qhd_status validate(const qhd_instance& d, int idx) {
     default:
       return fail(QHD_EINVAL, "instance %d: unknown sched_kind %d", idx, d.sched_kind);
   }
-  if (d.scheme != QHD_SCHEME_STRANG && d.scheme != QHD_SCHEME_LIE && d.scheme != QHD_SCHEME_YOSHIDA4)
+  if (d.scheme != QHD_SCHEME_STRANG && d.scheme != QHD_SCHEME_LIE && d.scheme != QHD_SCHEME_YOSHIDA4 &&
+      d.scheme != QHD_SCHEME_LEAPFROG)
     return fail(QHD_EINVAL, "instance %d: unknown scheme %d", idx, d.scheme);
   if (d.scheme == QHD_SCHEME_YOSHIDA4 && d.sched_kind == QHD_SCHED_TABLE)
     return fail(QHD_EUNSUPPORTED, "instance %d: the fourth-order scheme evaluates the schedule between table "
@@ -92,8 +96,12 @@ qhd_status validate(const qhd_instance& d, int idx) {
     return fail(QHD_EINVAL, "instance %d: unknown model %d", idx, d.model);
   if (d.model == QHD_MODEL_QAA && d.ndim != 2)
     return fail(QHD_EUNSUPPORTED, "instance %d: the QAA model is built for 2-D meshes", idx);
-  if (d.model == QHD_MODEL_QAA && d.scheme != QHD_SCHEME_STRANG)
-    return fail(QHD_EUNSUPPORTED, "instance %d: the QAA model runs the symmetric scheme", idx);
+  if (d.scheme == QHD_SCHEME_LEAPFROG && d.model != QHD_MODEL_QAA)
+    return fail(QHD_EUNSUPPORTED, "instance %d: the leapfrog integrator is built for the QAA model", idx);
+  if (d.model == QHD_MODEL_QAA && d.scheme != QHD_SCHEME_STRANG && d.scheme != QHD_SCHEME_LEAPFROG)
+    return fail(QHD_EUNSUPPORTED, "instance %d: the QAA model runs the symmetric scheme or leapfrog", idx);
+  if (d.scheme == QHD_SCHEME_LEAPFROG && d.sched_kind == QHD_SCHED_TABLE)
+    return fail(QHD_EUNSUPPORTED, "instance %d: leapfrog evaluates the schedule between table points", idx);
   if (d.init_kind != QHD_INIT_UNIFORM && d.init_kind != QHD_INIT_USER)
     return fail(QHD_EINVAL, "instance %d: unknown init_kind %d", idx, d.init_kind);
   return QHD_OK;
@@ -135,6 +143,8 @@ struct ShapeClass {
   bool tuned = false;
   bool mfma = false;  // 3-D 128^3 with QHD_OPT_MFMA_DFT
   int model = kModelQHD;
+  bool leapfrog = false;           // QAA members integrated by leapfrog stages
+  float* scratch = nullptr;        // leapfrog: partial H v between the row and column passes
 };
 
 struct qhd_plan_s {
@@ -181,6 +191,7 @@ void free_plan(qhd_plan p) {
     (void)hipFree(c.dev);
     (void)hipFree(c.psi);
     (void)hipFree(c.f);
+    (void)hipFree(c.scratch);
     (void)hipFree(c.partials);
     (void)hipFree(c.results);
   }
@@ -299,6 +310,14 @@ qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<
         HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
           return launch_ypass_3d(c.nx, c.ny, c.nz, +1, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
                                  p->grid_cap, stream);
+        }));
+      } else if (c.ndim == 2 && c.leapfrog) {
+        HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
+          return launch_lf_row_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.scratch, (int)s, max_steps, c.cap_row,
+                                  stream);
+        }));
+        HIP_TRY(timed_launch(c.fam_col, pts, sample, [&] {
+          return launch_lf_col_2d(c.nx, c.ny, c.dev, nact, c.psi, c.scratch, (int)s, max_steps, c.cap_col, stream);
         }));
       } else if (c.ndim == 2) {
         HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
@@ -527,11 +546,12 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
   }
 
   // group into shape classes
-  std::map<std::tuple<int, int, int, int, int>, int> key2cls;
+  std::map<std::tuple<int, int, int, int, int, int>, int> key2cls;
   for (int i = 0; i < batch; ++i) {
     const qhd_instance& d = inst[i];
     const int nx = d.n[0], ny = d.ndim >= 2 ? d.n[1] : 1, nz = d.ndim >= 3 ? d.n[2] : 1;
-    auto key = std::make_tuple(d.ndim, nx, ny, nz, d.model);
+    const bool lf = d.scheme == QHD_SCHEME_LEAPFROG;
+    auto key = std::make_tuple(d.ndim, nx, ny, nz, d.model, (int)lf);
     auto it = key2cls.find(key);
     int c;
     if (it == key2cls.end()) {
@@ -544,6 +564,7 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       sc.nz = nz;
       sc.points = (long long)nx * ny * nz;
       sc.model = d.model;
+      sc.leapfrog = lf;
       p->classes.push_back(sc);
     } else {
       c = it->second;
@@ -651,6 +672,7 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
     const size_t pts = (size_t)m * (size_t)c.points;
     e = hipMalloc(&c.dev, sizeof(InstDev) * m);
     if (e == hipSuccess) e = hipMalloc(&c.psi, sizeof(float2) * pts);
+    if (e == hipSuccess && c.leapfrog) e = hipMalloc(&c.scratch, sizeof(float) * pts);
     if (e == hipSuccess) e = hipMalloc(&c.f, sizeof(double) * pts);
     if (e == hipSuccess) e = hipMalloc(&c.partials, sizeof(double) * 3 * (size_t)m * c.lines);
     if (e == hipSuccess) e = hipMalloc(&c.results, sizeof(double) * 3 * (size_t)m);
@@ -679,7 +701,7 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       snprintf(name, sizeof name, "zpass_3d/n%d", c.nz);
       c.fam_z = family_index(p, name, 16.0);
     } else if (c.ndim == 2) {
-      const char* tag = c.model == kModelQAA ? "_qaa" : "";
+      const char* tag = c.leapfrog ? "_qaa_lf" : (c.model == kModelQAA ? "_qaa" : "");
       snprintf(name, sizeof name, "row_pass_2d%s/n%d", tag, c.nx);
       c.fam_row = family_index(p, name, 24.0);
       snprintf(name, sizeof name, "col_pass_2d%s/n%d", tag, c.ny);

@@ -8,7 +8,7 @@
 namespace qhd {
 
 enum : int { kModeClean = 0, kModePending = 1 };
-enum : int { kSchemeStrang = 0, kSchemeLie = 1, kSchemeYoshida4 = 2 };
+enum : int { kSchemeStrang = 0, kSchemeLie = 1, kSchemeYoshida4 = 2, kSchemeLeapfrog = 3 };
 enum : int { kModelQHD = 0, kModelQAA = 1 };
 enum : int { kSchedNesterov = 0, kSchedConst = 1, kSchedTable = 2, kSchedLinear = 3 };
 
@@ -65,6 +65,12 @@ enum { kColAuto = 0, kColStaged = 1, kColTileWave = 2, kColStaged16 = 3 };
 int col_variant_resolve(int ny, int variant);
 // points per lane of the row pass: 8, or 16 (chosen for 256 and 512; always at 1024)
 int row_points_resolve(int nx, int points_per_lane);
+// leapfrog stages of the QAA model: the row pass writes the partial H v into scratch
+// (float per point, psi's layout), the column pass completes H v and updates psi
+hipError_t launch_lf_row_2d(int nx, int ny, const InstDev* inst, int ninst, const float2* psi, const double* f,
+                            float* scratch, int s, long long max_steps, int grid_cap, hipStream_t stream);
+hipError_t launch_lf_col_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi, const float* scratch, int s,
+                            long long max_steps, int grid_cap, hipStream_t stream);
 hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double2* tw_ny, int s, long long max_steps, int grid_cap,
                               int variant, hipStream_t stream, int model = kModelQHD);

@@ -351,6 +351,168 @@ __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
 }
 
 // ------------------------------------------------------------------------------------
+// Leapfrog stages of the QAA model (the paper's integrator for its baseline QAA).  The
+// state stays in position space, R = psi.x, I = psi.y.  A stage applies
+//     H v = a W^{-1} D0 W v + b f v,   D0 = d_x(u) + d_y(v), d(u) = 2 popcount(u) - bits,
+// to its source component v and adds c H v to its target component, in two passes that
+// use the separability of D0: the row pass stores u = a W_x^{-1} d_x W_x v + b f v into
+// the class scratch buffer (same tiled layout as psi); the column pass adds
+// a W_y^{-1} d_y W_y v and updates the target.  Lines in FP64.
+
+template <int NX, int P>
+__global__ void __launch_bounds__(256) k_lf_row_2d(const InstDev* __restrict__ inst, int ninst, int ny_log2,
+                                                   const float2* __restrict__ psi, const double* __restrict__ f,
+                                                   float* __restrict__ scratch, int s, long long max_steps) {
+  constexpr int TPL = NX / P;
+  constexpr int LPW = 256 / TPL;
+  constexpr int BITS = ilog2_c(NX);
+  const int ll = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const long long total = (long long)ninst << ny_log2;
+  long long begin, end;
+  block_share(total, LPW, begin, end);
+  for (long long l0 = begin; l0 < end; l0 += LPW) {
+    const long long L = l0 + ll;
+    const bool valid = L < end;
+    const long long Lc = valid ? L : end - 1;
+    const int i = (int)(Lc >> ny_log2), y = (int)(Lc & ((1 << ny_log2) - 1));
+    const InstDev& I = inst[i];
+    const bool active = valid && s < step_limit(I, max_steps);
+    double a, b, c;
+    bool kick;
+    leapfrog_stage(I, I.steps_done + s, a, b, c, kick);
+    const float2* __restrict__ pl = psi + I.psi_off;
+    double v[P], h[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const float2 z = pl[row_slot<NX, TPL>(t, q, y)];
+      v[q] = kick ? z.x : z.y;
+      h[q] = v[q];
+    }
+    line_wht_real<NX, P>(h, t);
+#pragma unroll
+    for (int q = 0; q < P; ++q) h[q] *= (double)(2 * __builtin_popcount(t + q * TPL) - BITS);
+    line_wht_real<NX, P>(h, t);
+    if (active) {
+      const double* __restrict__ fl = f + I.psi_off;
+      float* __restrict__ ul = scratch + I.psi_off;
+      constexpr double kInvN = 1.0 / NX;
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const long long o = row_slot<NX, TPL>(t, q, y);
+        ul[o] = (float)fma(a * kInvN, h[q], b * fl[o] * v[q]);
+      }
+    }
+  }
+}
+
+template <int NY, int P>
+__global__ void __launch_bounds__(256) k_lf_col_2d(const InstDev* __restrict__ inst, int ninst, int nx_log2,
+                                                   float2* __restrict__ psi, const float* __restrict__ scratch, int s,
+                                                   long long max_steps) {
+  using C = ColCfg<NY, P>;
+  constexpr int TPL = C::TPL, ITEMS = C::ITEMS, NT = C::NT, STRIDE = C::STRIDE, SUBS = C::SUBS;
+  constexpr int TILES = NY / 8;
+  constexpr int BITS = ilog2_c(NY);
+  __shared__ float2 lds[C::LINES * STRIDE];
+  __shared__ float ulds[C::LINES * STRIDE];
+  const int tid = threadIdx.x;
+  const int line0 = tid / TPL, t = tid % TPL;
+  const int nx = 1 << nx_log2, tc_log2 = nx_log2 - 3, tcols = nx >> 3;
+  const long long total = (long long)ninst << tc_log2;
+  long long begin, end;
+  block_share(total, ITEMS, begin, end);
+  for (long long g0 = begin; g0 < end; g0 += ITEMS) {
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const long long g = g0 + it;
+      if (g < end) {
+        const int i = (int)(g >> tc_log2), tc = (int)(g & (tcols - 1));
+        const InstDev& I = inst[i];
+        if (s < step_limit(I, max_steps)) {
+          const float4* __restrict__ src = reinterpret_cast<const float4*>(psi + I.psi_off) + tc * 32;
+          const float4* __restrict__ srcu = reinterpret_cast<const float4*>(scratch + I.psi_off) + tc * 16;
+          float2* __restrict__ dst = lds + it * 8 * STRIDE;
+          float* __restrict__ dstu = ulds + it * 8 * STRIDE;
+#pragma unroll
+          for (int e = tid; e < TILES * 32; e += NT) {
+            const int ty = e >> 5, w = e & 31;
+            const float4 v = src[(long long)ty * tcols * 32 + w];
+            const int y = ty * 8 + (w >> 2), xx = (w & 3) << 1;
+            dst[xx * STRIDE + lds_slot(y)] = make_float2(v.x, v.y);
+            dst[(xx + 1) * STRIDE + lds_slot(y)] = make_float2(v.z, v.w);
+          }
+#pragma unroll
+          for (int e = tid; e < TILES * 16; e += NT) {
+            const int ty = e >> 4, w = e & 15;
+            const float4 v = srcu[(long long)ty * tcols * 16 + w];
+            const int y = ty * 8 + (w >> 1), xx = (w & 1) << 2;
+            dstu[xx * STRIDE + lds_slot(y)] = v.x;
+            dstu[(xx + 1) * STRIDE + lds_slot(y)] = v.y;
+            dstu[(xx + 2) * STRIDE + lds_slot(y)] = v.z;
+            dstu[(xx + 3) * STRIDE + lds_slot(y)] = v.w;
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sub = 0; sub < SUBS; ++sub) {
+      const int line = line0 + sub * (NT / TPL);
+      float2* my = lds + line * STRIDE;
+      const float* myu = ulds + line * STRIDE;
+      const long long g = g0 + line / 8;
+      const long long gc = g < end ? g : end - 1;
+      const InstDev& I = inst[(int)(gc >> tc_log2)];
+      double a, b, c;
+      bool kick;
+      leapfrog_stage(I, I.steps_done + s, a, b, c, kick);
+      double h[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const float2 z = my[lds_slot(t + q * TPL)];
+        h[q] = kick ? z.x : z.y;
+      }
+      line_wht_real<NY, P>(h, t);
+#pragma unroll
+      for (int q = 0; q < P; ++q) h[q] *= (double)(2 * __builtin_popcount(t + q * TPL) - BITS);
+      line_wht_real<NY, P>(h, t);
+      constexpr double kInvN = 1.0 / NY;
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const int slot = lds_slot(t + q * TPL);
+        const double w = fma(a * kInvN, h[q], (double)myu[slot]);
+        float2 z = my[slot];
+        if (kick) z.y = (float)fma(c, w, (double)z.y);
+        else z.x = (float)fma(c, w, (double)z.x);
+        my[slot] = z;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const long long g = g0 + it;
+      if (g < end) {
+        const int i = (int)(g >> tc_log2), tc = (int)(g & (tcols - 1));
+        const InstDev& I = inst[i];
+        if (s < step_limit(I, max_steps)) {
+          float4* __restrict__ dstg = reinterpret_cast<float4*>(psi + I.psi_off) + tc * 32;
+          const float2* __restrict__ srcl = lds + it * 8 * STRIDE;
+#pragma unroll
+          for (int e = tid; e < TILES * 32; e += NT) {
+            const int ty = e >> 5, w = e & 31;
+            const int y = ty * 8 + (w >> 2), xx = (w & 3) << 1;
+            const float2 p0 = srcl[xx * STRIDE + lds_slot(y)];
+            const float2 p1 = srcl[(xx + 1) * STRIDE + lds_slot(y)];
+            dstg[(long long)ty * tcols * 32 + w] = make_float4(p0.x, p0.y, p1.x, p1.y);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // 1-D pass: V (merged halves) . F . K . F^{-1}, the state stays in position space
 // with the trailing half step of the last step pending.
 
@@ -464,7 +626,8 @@ __global__ void __launch_bounds__(256) k_observe_2d(const InstDev* __restrict__ 
     const long long Lc = valid ? L : total - 1;
     const int i = (int)(Lc >> ny_log2), y = (int)(Lc & ((1 << ny_log2) - 1));
     const InstDev& I = inst[i];
-    const bool pending = (I.mode == kModePending);
+    // leapfrog keeps the state in position space, in step with the clock
+    const bool pending = (I.mode == kModePending) && I.scheme != kSchemeLeapfrog;
     const long long base = I.psi_off;
     float2 reg[P];
 #pragma unroll
@@ -822,6 +985,28 @@ hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, fl
     default: break;
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_lf_row_2d(int nx, int ny, const InstDev* inst, int ninst, const float2* psi, const double* f,
+                            float* scratch, int s, long long max_steps, int grid_cap, hipStream_t stream) {
+  const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap, 8);
+  QHD_SWITCH_N(nx, {
+    constexpr int P_ = pts_per_lane<N_>();
+    hipLaunchKernelGGL((k_lf_row_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst, ilog2(ny), psi, f,
+                       scratch, s, max_steps);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_lf_col_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi, const float* scratch, int s,
+                            long long max_steps, int grid_cap, hipStream_t stream) {
+  const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap, kColStaged);
+  QHD_SWITCH_N(ny, {
+    constexpr int P_ = pts_per_lane<N_>();
+    hipLaunchKernelGGL((k_lf_col_2d<N_, P_>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0, stream, inst, ninst,
+                       ilog2(nx), psi, scratch, s, max_steps);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* psi, const double* f,

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "QHD_OK", 1: "QHD_EINVAL", 2: "QHD_EUNSUPPORTED", 3: "QHD_ENO
 QHD_SCHED_NESTEROV, QHD_SCHED_CONST, QHD_SCHED_TABLE, QHD_SCHED_LINEAR = 0, 1, 2, 3
 QHD_MODEL_QHD, QHD_MODEL_QAA = 0, 1
 QHD_INIT_UNIFORM, QHD_INIT_USER = 0, 1
-QHD_SCHEME_STRANG, QHD_SCHEME_LIE, QHD_SCHEME_YOSHIDA4 = 0, 1, 2
+QHD_SCHEME_STRANG, QHD_SCHEME_LIE, QHD_SCHEME_YOSHIDA4, QHD_SCHEME_LEAPFROG = 0, 1, 2, 3
 QHD_OPT_TIME_PASSES = 0x1
 QHD_OPT_AUTOTUNE = 0x2
 QHD_OPT_NO_GRAPH = 0x4

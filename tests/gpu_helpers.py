@@ -56,9 +56,11 @@ def run_oracle(spec: q.InstanceSpec, f: np.ndarray, psi0=None, j0: int = 0):
     if spec.model == q.QHD_MODEL_QAA:
         # split-step QAA reference (numpy FP64); readouts by the C oracle on the same mesh
         from oracle import qaa_reference as qa
-        assert spec.sched == q.QHD_SCHED_LINEAR and spec.scheme == q.QHD_SCHEME_STRANG
+        assert spec.sched == q.QHD_SCHED_LINEAR
+        assert spec.scheme in (q.QHD_SCHEME_STRANG, q.QHD_SCHEME_LEAPFROG)
         psi = qa.uniform(spec.shape) if psi0 is None else np.asarray(psi0, np.complex128)
-        psi = qa.evolve(f, psi, spec.dt, spec.nsteps - j0, spec.sched_p[0], j0=j0)
+        step = qa.evolve_leapfrog if spec.scheme == q.QHD_SCHEME_LEAPFROG else qa.evolve
+        psi = step(f, psi, spec.dt, spec.nsteps - j0, spec.sched_p[0], j0=j0)
         prob = oracle.Problem(shape=tuple(spec.shape), box=spec.box, dt=spec.dt, radius=spec.radius)
         return psi, oracle.readout(prob, f, psi)
     prob = oracle_problem(spec)

@@ -60,7 +60,8 @@ def _inst(**kw):
     (lambda d: d.sched_p.__setitem__(0, 0.0), q.QHD_EINVAL),
     (lambda d: setattr(d, "sched_kind", q.QHD_SCHED_TABLE), q.QHD_EINVAL),  # NULL table
     (lambda d: setattr(d, "init_kind", 5), q.QHD_EINVAL),
-    (lambda d: setattr(d, "scheme", 3), q.QHD_EINVAL),
+    (lambda d: setattr(d, "scheme", 4), q.QHD_EINVAL),
+    (lambda d: setattr(d, "scheme", q.QHD_SCHEME_LEAPFROG), q.QHD_EUNSUPPORTED),  # QHD model
     (lambda d: setattr(d, "model", 2), q.QHD_EINVAL),
     (lambda d: (setattr(d, "model", q.QHD_MODEL_QAA), setattr(d, "ndim", 1)), q.QHD_EUNSUPPORTED),
     (lambda d: (setattr(d, "model", q.QHD_MODEL_QAA), setattr(d, "scheme", q.QHD_SCHEME_LIE)), q.QHD_EUNSUPPORTED),

@@ -20,9 +20,12 @@ def _gpu():
     q.load_library()
 
 
-def _qaa(n, nsteps=1000, dt=0.01):
+def _qaa(n, nsteps=1000, dt=0.01, scheme=q.QHD_SCHEME_STRANG):
     return q.InstanceSpec(shape=(n, n), nsteps=nsteps, dt=dt, model=q.QHD_MODEL_QAA,
-                          sched=q.QHD_SCHED_LINEAR, sched_p=(nsteps * dt, 0.0))
+                          sched=q.QHD_SCHED_LINEAR, sched_p=(nsteps * dt, 0.0), scheme=scheme)
+
+
+LF = q.QHD_SCHEME_LEAPFROG
 
 
 def test_qaa_against_reference_at_the_papers_resolutions():
@@ -72,3 +75,36 @@ def test_qaa_batch_norm_drift_over_ten_thousand_steps():
     drift = max(abs(r["norm"] - 1.0) for r in res)
     note(f"  max |norm - 1| over the batch: {drift:.3e}")
     assert st == q.QHD_OK and drift <= 1e-5
+
+
+
+def test_leapfrog_against_reference_at_the_papers_resolutions():
+    # the paper's QAA integrator; the leapfrog norm is not conserved exactly (O(dt^2):
+    # ~2e-3 at dt = 0.01, above the plan's default readout tolerance), so the step is
+    # 0.005 and the norm is compared with the reference's own
+    specs = [_qaa(64, nsteps=2000, dt=0.005, scheme=LF), _qaa(128, nsteps=2000, dt=0.005, scheme=LF),
+             _qaa(32, nsteps=600, dt=0.005, scheme=LF)]
+    fs = [qhd_inputs.landscape_grid(1234 + k, s_.shape) for k, s_ in enumerate(specs)]
+    note("case: leapfrog QAA 64^2 / 128^2 (T = 10, dt = 0.005), 32^2")
+    res, psis, _, st = run_gpu(specs, fs)
+    assert st == q.QHD_OK
+    for i, (spec, f) in enumerate(zip(specs, fs)):
+        ref, ro = run_oracle(spec, f)
+        err, nd, d_ef, d_p = compare(spec, f, res[i], psis[i], ref, ro, f"lf[{i}]")
+        assert err <= PSI_TOL and abs(res[i]["norm"] - ro.norm) <= 1e-5 and d_p <= 1e-4
+
+
+def test_leapfrog_mixed_plan_chunks_and_agreement_with_split_step():
+    lf, ss = _qaa(128, nsteps=400, dt=1e-3, scheme=LF), _qaa(128, nsteps=400, dt=1e-3)
+    qhd_spec = q.InstanceSpec(shape=(128, 128), nsteps=400, dt=1e-3)
+    f = qhd_inputs.landscape_grid(78, (128, 128))
+    res, psis, _, _ = run_gpu([lf, ss, qhd_spec], [f, f, f])
+    for i, spec in enumerate((lf, ss, qhd_spec)):
+        ref, ro = run_oracle(spec, f)
+        err, *_ = compare(spec, f, res[i], psis[i], ref, ro, f"lfmix[{i}]")
+        assert err <= PSI_TOL
+    # both integrators approximate the same evolution at second order
+    assert np.max(np.abs(psis[0] - psis[1])) < 1e-4
+    _, p2, _, _ = run_gpu([lf], [f], chunks=[1, 50, 77], flags=q.QHD_OPT_NO_GRAPH)
+    _, p3, _, _ = run_gpu([lf], [f])
+    assert np.array_equal(p2[0], p3[0]) and np.array_equal(p3[0], psis[0])
