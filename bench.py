@@ -56,12 +56,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def build_plan(specs, q, flags=0, timing_stride=0, tune_cache=None, qaa=False):
+def build_plan(specs, q, flags=0, timing_stride=0, tune_cache=None, qaa=False, scheme=0):
     """Plan over the specs: QHD with the Nesterov-type schedule, or (qaa) the baseline
-    QAA with the linear schedule g = t / T, T = nsteps * dt."""
+    QAA with the linear schedule g = t / T, T = nsteps * dt (scheme: split step or leapfrog)."""
     if qaa:
         cspecs = [q.InstanceSpec(shape=s.shape, nsteps=s.nsteps, dt=s.dt, sched=q.QHD_SCHED_LINEAR,
-                                 sched_p=(s.nsteps * s.dt, 0.0), model=q.QHD_MODEL_QAA) for s in specs]
+                                 sched_p=(s.nsteps * s.dt, 0.0), model=q.QHD_MODEL_QAA, scheme=scheme)
+                  for s in specs]
     else:
         cspecs = [q.InstanceSpec(shape=s.shape, nsteps=s.nsteps, dt=s.dt) for s in specs]
     return q.Plan(cspecs, flags=flags, timing_stride=timing_stride, tune_cache=tune_cache or None)
@@ -378,12 +379,21 @@ def main():
         upload(pq, specs, "qhd")
         el_q, res_q, _ = timed_runs(pq, 1, 1, stream, "qhd")
         pq.close()
+        # the paper's integrator for QAA on the same instances
+        pl = build_plan(specs, q, qaa=True, scheme=q.QHD_SCHEME_LEAPFROG)
+        upload(pl, specs, "qaa-leapfrog")
+        el_l, res_l, _ = timed_runs(pl, 1, 1, stream, "qaa-leapfrog")
+        pl.close()
+        sm_l = np.array([r["success_mass"] for r in res_l])
         sm_a = np.array([r["success_mass"] for r in res])
         sm_q = np.array([r["success_mass"] for r in res_q])
         comparison = {"qhd_same_instances_gp_steps_per_s": round(total_gp / el_q, 1),
                       "qaa_mean_success_mass": round(float(sm_a.mean()), 4),
                       "qhd_mean_success_mass": round(float(sm_q.mean()), 4),
                       "qhd_better_fraction": round(float(np.mean(sm_q > sm_a)), 3),
+                      "qaa_leapfrog_gp_steps_per_s": round(total_gp / el_l, 1),
+                      "qaa_leapfrog_mean_success_mass": round(float(sm_l.mean()), 4),
+                      "qaa_leapfrog_max_norm_deviation": max(abs(r["norm"] - 1.0) for r in res_l),
                       "success_ball": "radius 0.1 around the grid argmin (unit box)"}
         log(f"QHD on the same instances: {total_gp / el_q / 1e9:.2f} G gp-steps/s; mean success "
             f"QAA {sm_a.mean():.4f} vs QHD {sm_q.mean():.4f}")
