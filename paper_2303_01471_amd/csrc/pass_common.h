@@ -27,12 +27,8 @@ __device__ __forceinline__ int freq(int m, int n) { return m < (n >> 1) ? m : m 
 constexpr double kYoshidaW1 = 1.3512071919596576340;
 constexpr double kYoshidaW0 = -1.7024143839193152681;
 
-// Coefficients of stage j (App. C.2.1, eq. nonconvex_QHD_h), multiplied by the
-// stage's length in units of dt: every phase of a stage is then (coefficient) x dt.
-// Strang and the fourth-order composition take a and b at the stage midpoint; the
-// printed first-order product at the left end of the step.  One stage per step
-// except for the fourth-order scheme (stage j is stage j mod 3 of step j / 3).
-// a(t), b(t) of the closed-form schedules (not kSchedTable)
+// a(t), b(t) of the closed-form schedules (not kSchedTable; App. C.2.1, eq.
+// nonconvex_QHD_h, constants, or the adiabatic interpolation)
 __device__ __forceinline__ void sched_at_time(const InstDev& I, double t, double& a, double& b) {
   if (I.sched == kSchedConst) {
     a = I.sched_p0;
@@ -48,39 +44,38 @@ __device__ __forceinline__ void sched_at_time(const InstDev& I, double t, double
   }
 }
 
+// Coefficients of stage j, multiplied by the stage's length in units of dt: every
+// phase of a stage is then (coefficient) x dt.  Strang and the fourth-order
+// composition take a and b at the stage midpoint; the printed first-order product at
+// the left end of the step; TABLE schedules give them per step.  One stage per step
+// except for the fourth-order scheme (stage j is stage j mod 3 of step j / 3).
+// Y4 = false compiles the stage arithmetic of the fourth-order scheme out (kernels of
+// shape classes without such members: fewer live registers in the hot passes).
+template <bool Y4 = true>
 __device__ __forceinline__ void sched_ab(const InstDev& I, long long j, double& a, double& b) {
-  if (I.scheme == kSchemeYoshida4) {
-    const long long step = j / 3;
-    const int k = (int)(j - 3 * step);
-    const double w = k == 1 ? kYoshidaW0 : kYoshidaW1;
-    const double start = k == 0 ? 0.0 : (k == 1 ? kYoshidaW1 : kYoshidaW1 + kYoshidaW0);
-    sched_at_time(I, ((double)step + start + 0.5 * w) * I.dt, a, b);
-    a *= w;
-    b *= w;
-    return;
-  }
   if (I.sched == kSchedTable) {
     // lines of finished instances still evaluate (and discard) their step: never
     // read outside the table
     const bool in = (j >= 0 && j < I.nsteps);
     a = in ? I.table[2 * j] : 0.0;
     b = in ? I.table[2 * j + 1] : 0.0;
-  } else if (I.sched == kSchedConst) {
-    a = I.sched_p0;
-    b = I.sched_p1;
-  } else if (I.sched == kSchedLinear) {
-    // adiabatic interpolation g = t / T: H0 weight 1 - g, problem weight g
-    const double t = ((double)j + (I.scheme == kSchemeLie ? 0.0 : 0.5)) * I.dt;
-    const double g = t / I.sched_p0;
-    a = 1.0 - g;
-    b = g;
+    return;
+  }
+  double t, w = 1.0;
+  if (Y4 && I.scheme == kSchemeYoshida4) {
+    // stage counts stay below 2^31 (checked at plan creation): 32-bit division
+    const int step = (int)j / 3;
+    const int k = (int)j - 3 * step;
+    w = k == 1 ? kYoshidaW0 : kYoshidaW1;
+    const double start = k == 0 ? 0.0 : (k == 1 ? kYoshidaW1 : kYoshidaW1 + kYoshidaW0);
+    t = ((double)step + start + 0.5 * w) * I.dt;
   } else {
     // symmetric scheme: step midpoint; printed first-order product: left end
-    const double t = ((double)j + (I.scheme == kSchemeLie ? 0.0 : 0.5)) * I.dt;
-    const double t3 = t * t * t;
-    a = 2.0 / (I.sched_p0 + t3);
-    b = 2.0 * t3;
+    t = ((double)j + (I.scheme == kSchemeLie ? 0.0 : 0.5)) * I.dt;
   }
+  sched_at_time(I, t, a, b);
+  a *= w;
+  b *= w;
 }
 
 // Phase of the transformed-basis factor along one axis, in turns per unit of the
@@ -102,14 +97,15 @@ __device__ __forceinline__ double axis_turns(const InstDev& I, int axis, int idx
 // Symmetric scheme: the leading half step of j merged with the trailing half step of
 // j-1 (only the leading half on the entry step, where nothing is pending).
 // First-order product: the full step dt b_j.
+template <bool Y4 = true>
 __device__ __forceinline__ double potential_turns(const InstDev& I, long long j, bool entry) {
   double a, b;
-  sched_ab(I, j, a, b);
+  sched_ab<Y4>(I, j, a, b);
   if (I.scheme == kSchemeLie) return I.dt * b * kInv2Pi;
   double beta = 0.5 * I.dt * b;
   if (!entry && j > 0) {
     double ap, bp;
-    sched_ab(I, j - 1, ap, bp);
+    sched_ab<Y4>(I, j - 1, ap, bp);
     beta += 0.5 * I.dt * bp;
   }
   return beta * kInv2Pi;
@@ -130,8 +126,8 @@ __device__ __forceinline__ double closing_turns(const InstDev& I) {
 // that time, the coefficient c and whether the stage is a kick (source R, target I).
 __device__ __forceinline__ void leapfrog_stage(const InstDev& I, long long j, double& a, double& b, double& c,
                                                bool& kick) {
-  const long long step = j / 3;
-  const int k = (int)(j - 3 * step);
+  const int step = (int)j / 3;
+  const int k = (int)j - 3 * step;
   kick = k != 1;
   c = kick ? -0.5 * I.dt : I.dt;
   sched_at_time(I, ((double)step + 0.5 * k) * I.dt, a, b);

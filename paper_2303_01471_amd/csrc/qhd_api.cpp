@@ -63,6 +63,7 @@ qhd_status validate(const qhd_instance& d, int idx) {
   }
   if (!std::isfinite(d.dt) || !(d.dt > 0.0)) return fail(QHD_EINVAL, "instance %d: dt must be finite and > 0", idx);
   if (d.nsteps < 0) return fail(QHD_EINVAL, "instance %d: nsteps must be >= 0", idx);
+  if (d.nsteps > (int64_t)600000000) return fail(QHD_EINVAL, "instance %d: nsteps must be <= 6e8", idx);
   if (!(d.success_radius > 0.0) || !std::isfinite(d.success_radius))
     return fail(QHD_EINVAL, "instance %d: success_radius must be finite and > 0", idx);
   switch (d.sched_kind) {
@@ -144,6 +145,7 @@ struct ShapeClass {
   bool mfma = false;  // 3-D 128^3 with QHD_OPT_MFMA_DFT
   int model = kModelQHD;
   bool leapfrog = false;           // QAA members integrated by leapfrog stages
+  bool y4 = false;                 // some member runs the fourth-order scheme
   float* scratch = nullptr;        // leapfrog: partial H v between the row and column passes
 };
 
@@ -322,11 +324,11 @@ qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<
       } else if (c.ndim == 2) {
         HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
           return launch_row_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, (int)s, max_steps,
-                                    c.cap_row, c.row_points, stream, c.model);
+                                    c.cap_row, c.row_points, stream, c.model, c.y4);
         }));
         HIP_TRY(timed_launch(c.fam_col, pts, sample, [&] {
           return launch_col_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
-                                    c.cap_col, c.col_variant, stream, c.model);
+                                    c.cap_col, c.col_variant, stream, c.model, c.y4);
         }));
       } else {
         HIP_TRY(timed_launch(c.fam_line, pts, sample, [&] {
@@ -419,7 +421,8 @@ qhd_status autotune_class(qhd_plan p, ShapeClass& c, double& us_row, double& us_
   for (int rp : row_pts)
     for (int cap : caps) {
       const double t = time_launches(p->internal, a, b, reps, [&] {
-        return launch_row_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.f, c.tw_x, 0, 1, cap, rp, p->internal);
+        return launch_row_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.f, c.tw_x, 0, 1, cap, rp, p->internal, c.model,
+                                  c.y4);
       });
       if (t < 0) ok = false;
       else if (t < us_row) us_row = t, best_row = cap, best_pts = rp;
@@ -430,7 +433,7 @@ qhd_status autotune_class(qhd_plan p, ShapeClass& c, double& us_row, double& us_
   for (int v : variants)
     for (int cap : caps) {
       const double t = time_launches(p->internal, a, b, reps, [&] {
-        return launch_col_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.tw_y, 0, 1, cap, v, p->internal);
+        return launch_col_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.tw_y, 0, 1, cap, v, p->internal, c.model, c.y4);
       });
       if (t < 0) ok = false;
       else if (t < us_col) us_col = t, best_col = cap, best_var = v;
@@ -570,6 +573,7 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       c = it->second;
     }
     p->classes[c].members.push_back(i);
+    p->classes[c].y4 = p->classes[c].y4 || d.scheme == QHD_SCHEME_YOSHIDA4;
     p->cls_of[i] = c;
   }
   // twiddle tables W_N^j = exp(-2 pi i j / N) for every line length in use

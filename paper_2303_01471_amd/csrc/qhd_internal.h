@@ -57,7 +57,8 @@ struct TimingSink {
 // hipSuccess or the launch error.  `nx`, `ny` are the class's mesh sizes.
 hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double* f, const double2* tw_nx, int s, long long max_steps,
-                              int grid_cap, int points_per_lane, hipStream_t stream, int model = kModelQHD);
+                              int grid_cap, int points_per_lane, hipStream_t stream, int model = kModelQHD,
+                              bool y4 = true);
 // column-pass variants: staged (tile column through LDS, one wavefront per line, 8
 // or 16 points per lane) or tile-wave (8x8 tiles straight to registers, a line spread
 // over TPL/8 wavefronts); kColAuto takes the measured default for the size
@@ -73,7 +74,7 @@ hipError_t launch_lf_col_2d(int nx, int ny, const InstDev* inst, int ninst, floa
                             long long max_steps, int grid_cap, hipStream_t stream);
 hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double2* tw_ny, int s, long long max_steps, int grid_cap,
-                              int variant, hipStream_t stream, int model = kModelQHD);
+                              int variant, hipStream_t stream, int model = kModelQHD, bool y4 = true);
 hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* psi, const double* f,
                                const double2* tw, int s, long long max_steps, int grid_cap,
                                hipStream_t stream);

@@ -58,8 +58,11 @@ namespace qhd {
 // ------------------------------------------------------------------------------------
 // 2-D row pass: lines along x, one line per TPL lanes.
 
-template <int NX, int P, int MODEL = kModelQHD>
-__global__ void __launch_bounds__(256) k_row_pass_2d(const InstDev* __restrict__ inst, int ninst,
+// (512 points with 16 per lane: the LDS of a block admits three waves per SIMD, so the
+// register budget is held to that.)
+template <int NX, int P, int MODEL = kModelQHD, bool Y4 = true>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((P == 16 && NX == 512) ? 3 : 1)))
+k_row_pass_2d(const InstDev* __restrict__ inst, int ninst,
                                                      int ny_log2, float2* __restrict__ psi,
                                                      const double* __restrict__ f,
                                                      const double2* __restrict__ twtab, int s,
@@ -85,7 +88,7 @@ __global__ void __launch_bounds__(256) k_row_pass_2d(const InstDev* __restrict__
     const bool active = valid && s < step_limit(I, max_steps);
     const long long j = I.steps_done + s;
     const bool entry = (s == 0 && I.mode == kModeClean);
-    const double cpot = potential_turns(I, j, entry);
+    const double cpot = potential_turns<Y4>(I, j, entry);
     float2* __restrict__ pl = psi + I.psi_off;
     const double* __restrict__ fl = f + I.psi_off;
     if constexpr (MODEL == kModelQAA) {
@@ -134,7 +137,7 @@ struct ColCfg {
   static constexpr int STRIDE = ((LineLds<NY>::kSlots + 13) / 16) * 16 + 2;
 };
 
-template <int NY, int P, int MODEL = kModelQHD>
+template <int NY, int P, int MODEL = kModelQHD, bool Y4 = true>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColCfg<NY, P>::MIN_WAVES))) k_col_pass_2d(
     const InstDev* __restrict__ inst, int ninst, int nx_log2, float2* __restrict__ psi,
     const double2* __restrict__ twtab, int s, long long max_steps) {
@@ -188,7 +191,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColCfg
       const InstDev& I = inst[i];
       const int x = tc * 8 + (line & 7);
       double a, b;
-      sched_ab(I, I.steps_done + s, a, b);
+      sched_ab<Y4>(I, I.steps_done + s, a, b);
       const double cy = a * (MODEL == kModelQAA ? I.dt : I.kin_turns[1]);
       if (cy != cached) {
         // E_y / (nx ny) for this lane's slots: computed once per distinct coefficient
@@ -288,7 +291,7 @@ struct ColTwCfg {
   static_assert(TPL % 8 == 0, "tile-wave column pass needs TPL multiple of 8");
 };
 
-template <int NY, int P>
+template <int NY, int P, bool Y4 = true>
 __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
     const InstDev* __restrict__ inst, int ninst, int nx_log2, float2* __restrict__ psi,
     const double2* __restrict__ twtab, int s, long long max_steps) {
@@ -318,7 +321,7 @@ __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
     const InstDev& I = inst[i];
     const bool active = valid && s < step_limit(I, max_steps);
     double a, b;
-    sched_ab(I, I.steps_done + s, a, b);
+    sched_ab<Y4>(I, I.steps_done + s, a, b);
     const double cy = a * I.kin_turns[1];
     if (cy != cached) {
 #pragma unroll
@@ -879,12 +882,12 @@ int pass_blocks_row_2d(int nx, int ny, int ninst, int grid_cap, int points_per_l
 template <int N>
 constexpr int col_tw_p() { return N >= 1024 ? 16 : 8; }
 
-template <int N>
+template <int N, bool Y4>
 hipError_t launch_col_tw(int blocks, int nx, const InstDev* inst, int ninst, float2* psi,
                          const double2* tw, int s, long long max_steps, hipStream_t stream) {
   if constexpr (N >= 64 && N <= 512) {
     constexpr int P_ = col_tw_p<N>();
-    hipLaunchKernelGGL((k_col_pass_tw<N, P_>), dim3(blocks), dim3(ColTwCfg<N, P_>::NT), 0, stream,
+    hipLaunchKernelGGL((k_col_pass_tw<N, P_, Y4>), dim3(blocks), dim3(ColTwCfg<N, P_>::NT), 0, stream,
                        inst, ninst, ilog2(nx), psi, tw, s, max_steps);
     return hipGetLastError();
   } else {
@@ -917,74 +920,83 @@ int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant) {
   return blocks_for((long long)ninst * (nx / 8), items, grid_cap);
 }
 
-hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
-                              const double* f, const double2* tw, int s, long long max_steps,
-                              int grid_cap, int points_per_lane, hipStream_t stream, int model) {
-  if (model == kModelQAA) {
-    const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap, 8);
-    QHD_SWITCH_N(nx, {
-      constexpr int P_ = pts_per_lane<N_>();
-      hipLaunchKernelGGL((k_row_pass_2d<N_, P_, kModelQAA>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
-                         ilog2(ny), psi, f, tw, s, max_steps);
-      return hipGetLastError();
-    });
-  }
+template <bool Y4>
+hipError_t row_pass_qhd(int nx, int ny, const InstDev* inst, int ninst, float2* psi, const double* f,
+                        const double2* tw, int s, long long max_steps, int grid_cap, int points_per_lane,
+                        hipStream_t stream) {
   const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap, points_per_lane);
   if (row_points_resolve(nx, points_per_lane) == 16 && nx < 1024) {
     if (nx == 256)
-      hipLaunchKernelGGL((k_row_pass_2d<256, 16>), dim3(blocks), dim3(256), 0, stream, inst, ninst, ilog2(ny), psi,
-                         f, tw, s, max_steps);
+      hipLaunchKernelGGL((k_row_pass_2d<256, 16, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+                         ilog2(ny), psi, f, tw, s, max_steps);
     else
-      hipLaunchKernelGGL((k_row_pass_2d<512, 16>), dim3(blocks), dim3(256), 0, stream, inst, ninst, ilog2(ny), psi,
-                         f, tw, s, max_steps);
+      hipLaunchKernelGGL((k_row_pass_2d<512, 16, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+                         ilog2(ny), psi, f, tw, s, max_steps);
     return hipGetLastError();
   }
   QHD_SWITCH_N(nx, {
     constexpr int P_ = pts_per_lane<N_>();
-    hipLaunchKernelGGL((k_row_pass_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+    hipLaunchKernelGGL((k_row_pass_2d<N_, P_, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
                        ilog2(ny), psi, f, tw, s, max_steps);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
+                              const double* f, const double2* tw, int s, long long max_steps,
+                              int grid_cap, int points_per_lane, hipStream_t stream, int model, bool y4) {
+  if (model == kModelQAA) {  // the QAA model runs the symmetric scheme or leapfrog
+    const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap, 8);
+    QHD_SWITCH_N(nx, {
+      constexpr int P_ = pts_per_lane<N_>();
+      hipLaunchKernelGGL((k_row_pass_2d<N_, P_, kModelQAA, false>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+                         ilog2(ny), psi, f, tw, s, max_steps);
+      return hipGetLastError();
+    });
+  }
+  return y4 ? row_pass_qhd<true>(nx, ny, inst, ninst, psi, f, tw, s, max_steps, grid_cap, points_per_lane, stream)
+            : row_pass_qhd<false>(nx, ny, inst, ninst, psi, f, tw, s, max_steps, grid_cap, points_per_lane, stream);
+}
+
+template <bool Y4>
+hipError_t col_pass_qhd(int nx, int ny, const InstDev* inst, int ninst, float2* psi, const double2* tw, int s,
+                        long long max_steps, int grid_cap, int variant, hipStream_t stream) {
+  const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap, variant);
+  const int v = col_variant_resolve(ny, variant);
+  if (v == kColTileWave) {
+    QHD_SWITCH_N(ny, { return (launch_col_tw<N_, Y4>)(blocks, nx, inst, ninst, psi, tw, s, max_steps, stream); });
+  }
+  if (v == kColStaged16) {
+    if (ny == 256)
+      hipLaunchKernelGGL((k_col_pass_2d<256, 16, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<256, 16>::NT), 0, stream,
+                         inst, ninst, ilog2(nx), psi, tw, s, max_steps);
+    else
+      hipLaunchKernelGGL((k_col_pass_2d<512, 16, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<512, 16>::NT), 0, stream,
+                         inst, ninst, ilog2(nx), psi, tw, s, max_steps);
+    return hipGetLastError();
+  }
+  QHD_SWITCH_N(ny, {
+    constexpr int P_ = pts_per_lane<N_>();
+    hipLaunchKernelGGL((k_col_pass_2d<N_, P_, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0, stream,
+                       inst, ninst, ilog2(nx), psi, tw, s, max_steps);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
                               const double2* tw, int s, long long max_steps, int grid_cap,
-                              int variant, hipStream_t stream, int model) {
+                              int variant, hipStream_t stream, int model, bool y4) {
   if (model == kModelQAA) {  // staged form only: the Walsh-Hadamard lines use in-wave shuffles
     const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap, kColStaged);
     QHD_SWITCH_N(ny, {
       constexpr int P_ = pts_per_lane<N_>();
-      hipLaunchKernelGGL((k_col_pass_2d<N_, P_, kModelQAA>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0, stream,
-                         inst, ninst, ilog2(nx), psi, tw, s, max_steps);
+      hipLaunchKernelGGL((k_col_pass_2d<N_, P_, kModelQAA, false>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0,
+                         stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps);
       return hipGetLastError();
     });
   }
-  const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap, variant);
-  const int v = col_variant_resolve(ny, variant);
-  if (v == kColTileWave) {
-    QHD_SWITCH_N(ny, { return launch_col_tw<N_>(blocks, nx, inst, ninst, psi, tw, s, max_steps, stream); });
-  }
-  if (v == kColStaged16) {
-    if (ny == 256)
-      hipLaunchKernelGGL((k_col_pass_2d<256, 16>), dim3(blocks), dim3(ColCfg<256, 16>::NT), 0, stream, inst, ninst,
-                         ilog2(nx), psi, tw, s, max_steps);
-    else
-      hipLaunchKernelGGL((k_col_pass_2d<512, 16>), dim3(blocks), dim3(ColCfg<512, 16>::NT), 0, stream, inst, ninst,
-                         ilog2(nx), psi, tw, s, max_steps);
-    return hipGetLastError();
-  }
-  switch (ny) {
-    case 64: { hipLaunchKernelGGL((k_col_pass_2d<64, 8>), dim3(blocks), dim3(ColCfg<64, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
-    case 128: { hipLaunchKernelGGL((k_col_pass_2d<128, 8>), dim3(blocks), dim3(ColCfg<128, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
-    case 256: { hipLaunchKernelGGL((k_col_pass_2d<256, 8>), dim3(blocks), dim3(ColCfg<256, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
-    case 512: { hipLaunchKernelGGL((k_col_pass_2d<512, 8>), dim3(blocks), dim3(ColCfg<512, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
-    case 1024: { hipLaunchKernelGGL((k_col_pass_2d<1024, 16>), dim3(blocks), dim3(ColCfg<1024, 16>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
-    case 8: { hipLaunchKernelGGL((k_col_pass_2d<8, 8>), dim3(blocks), dim3(ColCfg<8, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
-    case 16: { hipLaunchKernelGGL((k_col_pass_2d<16, 8>), dim3(blocks), dim3(ColCfg<16, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
-    case 32: { hipLaunchKernelGGL((k_col_pass_2d<32, 8>), dim3(blocks), dim3(ColCfg<32, 8>::NT), 0, stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps); return hipGetLastError(); }
-    default: break;
-  }
-  return hipErrorInvalidValue;
+  return y4 ? col_pass_qhd<true>(nx, ny, inst, ninst, psi, tw, s, max_steps, grid_cap, variant, stream)
+            : col_pass_qhd<false>(nx, ny, inst, ninst, psi, tw, s, max_steps, grid_cap, variant, stream);
 }
 
 hipError_t launch_lf_row_2d(int nx, int ny, const InstDev* inst, int ninst, const float2* psi, const double* f,
