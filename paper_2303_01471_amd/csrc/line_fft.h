@@ -466,60 +466,75 @@ __device__ __forceinline__ void load_twiddles(TwiddlesLds<N, P>& tw, const doubl
 // ---------------------------------------------------------------------------------
 // Walsh-Hadamard transform of one line (unnormalised, natural order):
 // X_u = sum_i (-1)^{popcount(u & i)} x_i.  Point i = t + q TPL: the bits of q are
-// combined in registers, the bits of t across the line's TPL consecutive lanes by
-// xor shuffles (a line never spans two wavefronts).  Additions only: exact up to
-// one rounding per butterfly.  T is float2 or double2.
+// combined in registers, the bits of t across the line's TPL consecutive lanes (a line
+// never spans two wavefronts, and its first lane is a multiple of TPL).  Additions
+// only: exact up to one rounding per butterfly.
+//
+// Lane exchanges (partner lane ^ H) without LDS where the pattern allows: H = 1, 2 are
+// DPP quad permutations, H = 8 a DPP rotation by 8 within a row of 16 lanes, H = 4 and
+// 16 ds_swizzle in bitmask mode (no LDS memory access); H = 32 a permute through LDS.
+template <int H>
+__device__ __forceinline__ int lane_xor(int v) {
+  if constexpr (H == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+  else if constexpr (H == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+  else if constexpr (H == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);  // row_ror:8
+  else if constexpr (H == 4 || H == 16) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (H << 10));
+  else return __shfl_xor(v, H);
+}
+
+template <int H>
+__device__ __forceinline__ double lane_xor(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = lane_xor<H>((int)(u & 0xffffffffLL)), hi = lane_xor<H>((int)(u >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int H>
+__device__ __forceinline__ double2 lane_xor(double2 v) {
+  return make_double2(lane_xor<H>(v.x), lane_xor<H>(v.y));
+}
+
+template <int H>
+__device__ __forceinline__ float2 lane_xor(float2 v) {
+  return make_float2(__int_as_float(lane_xor<H>(__float_as_int(v.x))), __int_as_float(lane_xor<H>(__float_as_int(v.y))));
+}
+
+__device__ __forceinline__ double wadd(double a, double b) { return a + b; }
+__device__ __forceinline__ double wsub(double a, double b) { return a - b; }
+template <typename T>
+__device__ __forceinline__ T wadd(T a, T b) { return fadd(a, b); }
+template <typename T>
+__device__ __forceinline__ T wsub(T a, T b) { return fsub(a, b); }
+
+// butterflies over the lane bits H, 2H, ... < TPL
+template <int H, int TPL, int P, typename T>
+__device__ __forceinline__ void wht_lanes(T (&reg)[P], int t) {
+  if constexpr (H < TPL) {
+    const bool upper = (t & H) != 0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const T o = lane_xor<H>(reg[q]);
+      reg[q] = upper ? wsub(o, reg[q]) : wadd(reg[q], o);
+    }
+    wht_lanes<2 * H, TPL, P>(reg, t);
+  }
+}
+
+// T: double (a real line), float2 or double2 (a complex line)
 template <int N, int P, typename T>
 __device__ __forceinline__ void line_wht(T (&reg)[P], int t) {
-  constexpr int TPL = N / P;
 #pragma unroll
   for (int h = 1; h < P; h <<= 1) {
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       if (!(q & h)) {
         const T a = reg[q], b = reg[q | h];
-        reg[q] = fadd(a, b);
-        reg[q | h] = fsub(a, b);
+        reg[q] = wadd(a, b);
+        reg[q | h] = wsub(a, b);
       }
     }
   }
-#pragma unroll
-  for (int h = 1; h < TPL; h <<= 1) {
-    const bool upper = (t & h) != 0;
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      T o;
-      o.x = __shfl_xor(reg[q].x, h);
-      o.y = __shfl_xor(reg[q].y, h);
-      reg[q] = upper ? fsub(o, reg[q]) : fadd(reg[q], o);
-    }
-  }
-}
-
-// The same transform of a real line (FP64 values).
-template <int N, int P>
-__device__ __forceinline__ void line_wht_real(double (&reg)[P], int t) {
-  constexpr int TPL = N / P;
-#pragma unroll
-  for (int h = 1; h < P; h <<= 1) {
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      if (!(q & h)) {
-        const double a = reg[q], b = reg[q | h];
-        reg[q] = a + b;
-        reg[q | h] = a - b;
-      }
-    }
-  }
-#pragma unroll
-  for (int h = 1; h < TPL; h <<= 1) {
-    const bool upper = (t & h) != 0;
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      const double o = __shfl_xor(reg[q], h);
-      reg[q] = upper ? o - reg[q] : reg[q] + o;
-    }
-  }
+  wht_lanes<1, N / P, P>(reg, t);
 }
 
 // ---------------------------------------------------------------------------------

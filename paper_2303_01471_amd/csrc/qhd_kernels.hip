@@ -391,10 +391,10 @@ __global__ void __launch_bounds__(256) k_lf_row_2d(const InstDev* __restrict__ i
       v[q] = kick ? z.x : z.y;
       h[q] = v[q];
     }
-    line_wht_real<NX, P>(h, t);
+    line_wht<NX, P>(h, t);
 #pragma unroll
     for (int q = 0; q < P; ++q) h[q] *= (double)(2 * __builtin_popcount(t + q * TPL) - BITS);
-    line_wht_real<NX, P>(h, t);
+    line_wht<NX, P>(h, t);
     if (active) {
       const double* __restrict__ fl = f + I.psi_off;
       float* __restrict__ ul = scratch + I.psi_off;
@@ -475,10 +475,10 @@ __global__ void __launch_bounds__(256) k_lf_col_2d(const InstDev* __restrict__ i
         const float2 z = my[lds_slot(t + q * TPL)];
         h[q] = kick ? z.x : z.y;
       }
-      line_wht_real<NY, P>(h, t);
+      line_wht<NY, P>(h, t);
 #pragma unroll
       for (int q = 0; q < P; ++q) h[q] *= (double)(2 * __builtin_popcount(t + q * TPL) - BITS);
-      line_wht_real<NY, P>(h, t);
+      line_wht<NY, P>(h, t);
       constexpr double kInvN = 1.0 / NY;
 #pragma unroll
       for (int q = 0; q < P; ++q) {
