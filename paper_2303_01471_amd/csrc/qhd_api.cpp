@@ -705,11 +705,13 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       snprintf(name, sizeof name, "zpass_3d/n%d", c.nz);
       c.fam_z = family_index(p, name, 16.0);
     } else if (c.ndim == 2) {
+      // leapfrog stages: the row pass reads psi and f and writes the partial H v (4 B),
+      // the column pass reads psi and it and writes psi
       const char* tag = c.leapfrog ? "_qaa_lf" : (c.model == kModelQAA ? "_qaa" : "");
       snprintf(name, sizeof name, "row_pass_2d%s/n%d", tag, c.nx);
-      c.fam_row = family_index(p, name, 24.0);
+      c.fam_row = family_index(p, name, c.leapfrog ? 20.0 : 24.0);
       snprintf(name, sizeof name, "col_pass_2d%s/n%d", tag, c.ny);
-      c.fam_col = family_index(p, name, 16.0);
+      c.fam_col = family_index(p, name, c.leapfrog ? 20.0 : 16.0);
     } else {
       snprintf(name, sizeof name, "line_pass_1d/n%d", c.nx);
       c.fam_line = family_index(p, name, 24.0);

@@ -59,10 +59,13 @@ def counter_means(db: str):
 
 
 # pass kernel -> (family name used by the library's timing, algorithmic bytes per point);
-# the 2-D kernels' last template argument is the model (0 QHD, 1 QAA)
+# the 2-D kernels' third template argument is the model (0 QHD, 1 QAA), a last boolean
+# one whether the fourth-order stage arithmetic is compiled in
 _FAMILY = [
-    (re.compile(r"k_row_pass_2d<(\d+), \d+(?:, (\d+))?>"), "row_pass_2d{}/n{}", 24.0),
-    (re.compile(r"k_col_pass_(?:2d|tw)<(\d+), \d+(?:, (\d+))?>"), "col_pass_2d{}/n{}", 16.0),
+    (re.compile(r"k_row_pass_2d<(\d+), \d+(?:, (\d+))?(?:, (?:true|false))?>"), "row_pass_2d{}/n{}", 24.0),
+    (re.compile(r"k_col_pass_(?:2d|tw)<(\d+), \d+(?:, (\d+))?(?:, (?:true|false))?>"), "col_pass_2d{}/n{}", 16.0),
+    (re.compile(r"k_lf_row_2d<(\d+), \d+>()"), "row_pass_2d_qaa_lf{}/n{}", 20.0),
+    (re.compile(r"k_lf_col_2d<(\d+), \d+>()"), "col_pass_2d_qaa_lf{}/n{}", 20.0),
     (re.compile(r"k_line_pass_1d<(\d+),"), "line_pass_1d{}/n{}", 24.0),
 ]
 
@@ -70,6 +73,15 @@ _FAMILY = [
 def _family_name(fam: str, m) -> str:
     model = m.group(2) if m.re.groups >= 2 else None
     return fam.format("_qaa" if model == "1" else "", m.group(1))
+
+
+def family_of(kernel: str):
+    """(family name, algorithmic bytes per point) of a pass kernel, or None."""
+    for rx, fam, bpp in _FAMILY:
+        m = rx.search(kernel)
+        if m:
+            return _family_name(fam, m), bpp
+    return None
 
 
 def traffic(fetch_db: str, write_db: str, copy_bytes: float, points_per_dispatch: dict,
@@ -87,11 +99,9 @@ def traffic(fetch_db: str, write_db: str, copy_bytes: float, points_per_dispatch
     out = {"source_hash": source_hash, "copy_kernel": ck, "copy_bytes": copy_bytes,
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
     for k, v in fe.items():
-        for rx, fam, bpp in _FAMILY:
-            m = rx.search(k)
-            if not m:
-                continue
-            name = _family_name(fam, m)
+        fb = family_of(k)
+        if fb:
+            name, bpp = fb
             pts = points_per_dispatch.get(name)
             if not pts:
                 continue
