@@ -32,6 +32,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -48,11 +49,14 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the pass kernels' code (comments and whitespace removed): the key under
+    which HBM counter readings are kept."""
     h = hashlib.sha256()
     for rel in ("paper_2303_01471_amd/csrc/qhd_kernels.hip", "paper_2303_01471_amd/csrc/line_fft.h",
                 "paper_2303_01471_amd/csrc/pass_common.h", "paper_2303_01471_amd/csrc/qhd_internal.h"):
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
+            code = re.sub(r"/\*.*?\*/|//[^\n]*", " ", fh.read(), flags=re.S)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 

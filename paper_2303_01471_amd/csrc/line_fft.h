@@ -372,8 +372,11 @@ __device__ __forceinline__ void line_fft(float2 (&reg)[P], int t, const TW& tw, 
 // the first), where every FP32 rounding moves the norm by up to ~1e-7 of the whole
 // line; with those two stages in FP64 (and the diagonal factor between two transforms
 // applied in FP64 too) the concentrated values are rounded once, when they are
-// stored.  FP64 adds and FMAs issue at the FP32 (unpacked) rate on CDNA, and the FP64
-// stages need no widening around their twiddle products.
+// stored.  The FP64 stages need no widening around their twiddle products.  (On
+// gfx950 FP64 arithmetic and FP32<->FP64 conversions issue at half the unpacked FP32
+// rate, measured 37 vs 74 T lane-operations/s; the passes are not issue-bound, and
+// twiddle products moved to FP32 hi+lo pairs were measured to gain nothing at 512^2
+// and 1-2 % at 128^2 / 256^2.)
 
 template <int N, int P, int S, int STAGE, bool BLOCK_SYNC, typename W, typename A, typename B, typename TW>
 __device__ __forceinline__ void fft_stage_io(const A (&src)[P], B (&dst)[P], int t, const TW& tw,
