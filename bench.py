@@ -460,6 +460,38 @@ def main():
                            "in [-1, 1]), r = 8 (9^5 lattice), T = 10, dt = 1e-2, Nesterov schedule"}
         rqp.update(rqp_summary(secs, res_r, pts_r, probs, nst, 8))
 
+    # ---- batched2d: resident steps (psi held in LDS) against streaming passes ---------
+    resident = None
+    if args.workload == "batched2d" and not args.no_qaa_summary:
+        def rate_of(rspecs, rfs, flags):
+            pr = build_plan(rspecs, q, flags=flags, tune_cache=args.tune_cache)
+            for k, fr in enumerate(rfs):
+                pr.set_potential(k, fr)
+            pr.evolve(-1, stream)
+            torch.cuda.synchronize()
+            pr.reset(stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pr.evolve(-1, stream)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            rr, _, _, _ = pr.observe(stream)
+            pr.close()
+            return sum(x.points * x.nsteps for x in rspecs) / el, max(abs(x["norm"] - 1.0) for x in rr)
+        rows = []
+        for n, count in ((128, 512), (64, 1024), (64, 1), (128, 1)):
+            rs = qhd_inputs.batched_2d(count=count, sizes=(n,), t_range=(2.0, 2.0))
+            rfs = [x.grid() for x in rs]
+            r_s, _ = rate_of(rs, rfs, q.QHD_OPT_AUTOTUNE)
+            r_r, d_r = rate_of(rs, rfs, q.QHD_OPT_RESIDENT)
+            rows.append({"instances": count, "n": n, "steps": rs[0].nsteps,
+                         "streaming_gp_steps_per_s": round(r_s, 1), "resident_gp_steps_per_s": round(r_r, 1),
+                         "resident_vs_streaming": round(r_r / r_s, 3), "resident_max_norm_drift": d_r})
+            log(f"resident: {count} x {n}^2: {r_r / 1e9:.1f} G vs streaming {r_s / 1e9:.1f} G gp-steps/s")
+        resident = {"workload": "QHD_OPT_RESIDENT (psi in LDS for a whole evolve call, one workgroup per "
+                                "instance) vs the streaming passes, landscape recipe, T=2, dt=1e-3",
+                    "cases": rows}
+
     # ---- plain: the single-instance solver on the same GPU ---------------------------
     plain = None
     if not args.no_plain:
@@ -646,6 +678,7 @@ def main():
         "qaa": qaa_summary if not qaa else comparison,
         "spectrum": spectrum,
         "relaxed_qp": rqp,
+        "resident": resident,
         "launch_config": tuned,
         "kernels": kernels,
     }

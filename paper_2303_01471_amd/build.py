@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqhd.so")
 
-SOURCES = ["qhd_api.cpp", "qhd_kernels.hip", "qhd_kernels_3d.hip", "qhd_kernels_mfma.hip", "qhd_spectrum.cpp", "qhd_spectrum_kernels.hip", "sno.cpp", "sno_gemm.hip", "sno_kernels.hip", "rqp.cpp", "rqp_kernels.hip"]
+SOURCES = ["qhd_api.cpp", "qhd_kernels.hip", "qhd_kernels_3d.hip", "qhd_kernels_mfma.hip", "qhd_kernels_resident.hip", "qhd_spectrum.cpp", "qhd_spectrum_kernels.hip", "sno.cpp", "sno_gemm.hip", "sno_kernels.hip", "rqp.cpp", "rqp_kernels.hip"]
 HEADERS = ["line_fft.h", "qhd_internal.h", "pass_common.h", "sno_internal.h", "rqp_internal.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

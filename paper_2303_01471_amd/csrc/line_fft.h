@@ -208,6 +208,17 @@ struct StagePlan {
 
 // LDS slot of line position i: one pad entry after every 8
 __host__ __device__ constexpr int lds_slot(int i) { return i + (i >> 3); }
+
+// Where a line keeps position i of its LDS exchange buffer, relative to the line's base
+// pointer: the padded contiguous layout (default), or a fixed stride (a column of a
+// row-major array in LDS, exchanged in place).
+struct SlotIx {
+  __device__ static constexpr int at(int i) { return lds_slot(i); }
+};
+template <int STRIDE>
+struct StrideIx {
+  __device__ static constexpr int at(int i) { return i * STRIDE; }
+};
 template <int N>
 struct LineLds {
   static constexpr int kSlots = N + N / 8;
@@ -310,7 +321,7 @@ __device__ __forceinline__ void line_lds_sync() {
   else wave_lds_sync();
 }
 
-template <int N, int P, int S, int STAGE, bool BLOCK_SYNC = false, typename TW>
+template <int N, int P, int S, int STAGE, bool BLOCK_SYNC = false, typename IX = SlotIx, typename TW>
 __device__ __forceinline__ void fft_stage(float2 (&reg)[P], int t, const TW& tw, float2* __restrict__ lds) {
   using SP = StagePlan<N, P>;
   constexpr int NS = SP::ns(STAGE);
@@ -338,30 +349,30 @@ __device__ __forceinline__ void fft_stage(float2 (&reg)[P], int t, const TW& tw,
       const int v = t + m * TPL;
       const int base = (v / NS) * NS * R + (v % NS);
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[lds_slot(base + r * NS)] = u[r];
+      for (int r = 0; r < R; ++r) lds[IX::at(base + r * NS)] = u[r];
     }
   }
   if constexpr (!LAST) {
     line_lds_sync<BLOCK_SYNC>();
 #pragma unroll
-    for (int q = 0; q < P; ++q) reg[q] = lds[lds_slot(t + q * TPL)];
+    for (int q = 0; q < P; ++q) reg[q] = lds[IX::at(t + q * TPL)];
     line_lds_sync<BLOCK_SYNC>();
   }
 }
 
-template <int N, int P, int S, bool BLOCK_SYNC, int STAGE = 0, typename TW>
+template <int N, int P, int S, bool BLOCK_SYNC, int STAGE = 0, typename IX = SlotIx, typename TW>
 __device__ __forceinline__ void line_fft_from(float2 (&reg)[P], int t, const TW& tw, float2* __restrict__ lds) {
   if constexpr (STAGE < StagePlan<N, P>::count()) {
-    fft_stage<N, P, S, STAGE, BLOCK_SYNC>(reg, t, tw, lds);
-    line_fft_from<N, P, S, BLOCK_SYNC, STAGE + 1>(reg, t, tw, lds);
+    fft_stage<N, P, S, STAGE, BLOCK_SYNC, IX>(reg, t, tw, lds);
+    line_fft_from<N, P, S, BLOCK_SYNC, STAGE + 1, IX>(reg, t, tw, lds);
   }
 }
 
 // Full unnormalised transform of one line, X_k = sum_m x_m e^{S 2 pi i m k / N};
-// TW is Twiddles<N, P> or TwiddlesLds<N, P>.
-template <int N, int P, int S, bool BLOCK_SYNC = false, typename TW>
+// TW is Twiddles<N, P> or TwiddlesLds<N, P>; IX places the exchange buffer's positions.
+template <int N, int P, int S, bool BLOCK_SYNC = false, typename IX = SlotIx, typename TW>
 __device__ __forceinline__ void line_fft(float2 (&reg)[P], int t, const TW& tw, float2* __restrict__ lds) {
-  line_fft_from<N, P, S, BLOCK_SYNC, 0>(reg, t, tw, lds);
+  line_fft_from<N, P, S, BLOCK_SYNC, 0, IX>(reg, t, tw, lds);
 }
 
 // ---------------------------------------------------------------------------------
@@ -378,7 +389,8 @@ __device__ __forceinline__ void line_fft(float2 (&reg)[P], int t, const TW& tw, 
 // twiddle products moved to FP32 hi+lo pairs were measured to gain nothing at 512^2
 // and 1-2 % at 128^2 / 256^2.)
 
-template <int N, int P, int S, int STAGE, bool BLOCK_SYNC, typename W, typename A, typename B, typename TW>
+template <int N, int P, int S, int STAGE, bool BLOCK_SYNC, typename W, typename IX, typename A, typename B,
+          typename TW>
 __device__ __forceinline__ void fft_stage_io(const A (&src)[P], B (&dst)[P], int t, const TW& tw,
                                              float2* __restrict__ lds) {
   using SP = StagePlan<N, P>;
@@ -408,40 +420,41 @@ __device__ __forceinline__ void fft_stage_io(const A (&src)[P], B (&dst)[P], int
       const int v = t + m * TPL;
       const int base = (v / NS) * NS * R + (v % NS);
 #pragma unroll
-      for (int r = 0; r < R; ++r) assign(lds[lds_slot(base + r * NS)], u[r]);
+      for (int r = 0; r < R; ++r) assign(lds[IX::at(base + r * NS)], u[r]);
     }
   }
   if constexpr (!LAST) {
     line_lds_sync<BLOCK_SYNC>();
 #pragma unroll
-    for (int q = 0; q < P; ++q) dst[q] = lds[lds_slot(t + q * TPL)];
+    for (int q = 0; q < P; ++q) dst[q] = lds[IX::at(t + q * TPL)];
     line_lds_sync<BLOCK_SYNC>();
   }
 }
 
-template <int N, int P, int S, bool BLOCK_SYNC, int STAGE, typename TW>
+template <int N, int P, int S, bool BLOCK_SYNC, int STAGE, typename IX, typename TW>
 __device__ __forceinline__ void fft_mid_stages(float2 (&reg)[P], int t, const TW& tw, float2* __restrict__ lds) {
   if constexpr (STAGE < StagePlan<N, P>::count() - 1) {
-    fft_stage_io<N, P, S, STAGE, BLOCK_SYNC, float2>(reg, reg, t, tw, lds);
-    fft_mid_stages<N, P, S, BLOCK_SYNC, STAGE + 1>(reg, t, tw, lds);
+    fft_stage_io<N, P, S, STAGE, BLOCK_SYNC, float2, IX>(reg, reg, t, tw, lds);
+    fft_mid_stages<N, P, S, BLOCK_SYNC, STAGE + 1, IX>(reg, t, tw, lds);
   }
 }
 
 // Full unnormalised transform of one line from `in` (float2 or double2) to `out`
 // (float2 or double2), same layout as line_fft.
-template <int N, int P, int S, bool BLOCK_SYNC = false, typename TIN, typename TOUT, typename TW>
+template <int N, int P, int S, bool BLOCK_SYNC = false, typename IX = SlotIx, typename TIN, typename TOUT,
+          typename TW>
 __device__ __forceinline__ void line_fft_io(TIN (&in)[P], TOUT (&out)[P], int t, const TW& tw,
                                             float2* __restrict__ lds) {
   constexpr int C = StagePlan<N, P>::count();
   if constexpr (C == 1) {
     using W = typename std::conditional<std::is_same<TIN, double2>::value || std::is_same<TOUT, double2>::value,
                                         double2, float2>::type;
-    fft_stage_io<N, P, S, 0, BLOCK_SYNC, W>(in, out, t, tw, lds);
+    fft_stage_io<N, P, S, 0, BLOCK_SYNC, W, IX>(in, out, t, tw, lds);
   } else {
     float2 mid[P];
-    fft_stage_io<N, P, S, 0, BLOCK_SYNC, TIN>(in, mid, t, tw, lds);
-    fft_mid_stages<N, P, S, BLOCK_SYNC, 1>(mid, t, tw, lds);
-    fft_stage_io<N, P, S, C - 1, BLOCK_SYNC, TOUT>(mid, out, t, tw, lds);
+    fft_stage_io<N, P, S, 0, BLOCK_SYNC, TIN, IX>(in, mid, t, tw, lds);
+    fft_mid_stages<N, P, S, BLOCK_SYNC, 1, IX>(mid, t, tw, lds);
+    fft_stage_io<N, P, S, C - 1, BLOCK_SYNC, TOUT, IX>(mid, out, t, tw, lds);
   }
 }
 

@@ -147,6 +147,8 @@ struct ShapeClass {
   bool leapfrog = false;           // QAA members integrated by leapfrog stages
   bool y4 = false;                 // some member runs the fourth-order scheme
   float* scratch = nullptr;        // leapfrog: partial H v between the row and column passes
+  bool resident = false;           // QHD_OPT_RESIDENT: all steps of a call in one launch, psi in LDS
+  int fam_res = -1;
 };
 
 struct qhd_plan_s {
@@ -278,6 +280,17 @@ qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<
       for (size_t k = 0; k < c.members.size(); ++k)
         if (lim[ci][k] > s) nact = (int)k + 1;
       if (nact == 0) continue;
+      if (c.resident) {
+        // every sub-step of the call in one launch (timed as a whole: its points are
+        // the call's grid-point stages)
+        if (s != 0) continue;
+        double gps = 0.0;
+        for (size_t k = 0; k < c.members.size(); ++k) gps += (double)lim[ci][k] * (double)c.points;
+        HIP_TRY(timed_launch(c.fam_res, gps, timing, [&] {
+          return launch_resident_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, c.tw_y, max_steps, c.y4, stream);
+        }));
+        continue;
+      }
       const double pts = (double)nact * (double)c.points;
       if (c.ndim == 3 && c.mfma) {
         HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
@@ -704,6 +717,12 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       c.fam_y = family_index(p, name, 16.0);
       snprintf(name, sizeof name, "zpass_3d/n%d", c.nz);
       c.fam_z = family_index(p, name, 16.0);
+    } else if (c.ndim == 2 && (p->opts.flags & QHD_OPT_RESIDENT) && c.model == kModelQHD && !c.leapfrog &&
+               resident_supported(c.nx, c.ny)) {
+      // psi stays in LDS; per grid-point step only f (8 B, FP64) is read, from the caches
+      c.resident = true;
+      snprintf(name, sizeof name, "resident_2d/n%d", c.nx);
+      c.fam_res = family_index(p, name, 8.0);
     } else if (c.ndim == 2) {
       // leapfrog stages: the row pass reads psi and f and writes the partial H v (4 B),
       // the column pass reads psi and it and writes psi
@@ -754,7 +773,7 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
     for (auto& c : p->classes) {
       c.cap_row = c.cap_col = p->grid_cap;
       if (c.ndim != 2) continue;
-      if (c.model == kModelQAA) continue;  // one fixed launch form (staged columns)
+      if (c.model == kModelQAA || c.resident) continue;  // one fixed launch form each
       if (!env_cap) {
         // measured defaults (uniform batches of 256 instances per size on MI355X)
         c.cap_row = c.nx >= 512 ? 8192 : (c.nx >= 256 ? 4096 : 1024);
@@ -956,12 +975,13 @@ qhd_status qhd_plan_info(qhd_plan p, qhd_class_info* out, int32_t cap, int32_t* 
     o.n[1] = c.ny;
     o.n[2] = c.nz;
     o.members = (int32_t)c.members.size();
-    o.col_variant = c.ndim == 2 ? col_variant_resolve(c.ny, c.col_variant) : 0;
+    o.col_variant = c.ndim == 2 && !c.resident ? col_variant_resolve(c.ny, c.col_variant) : 0;
     o.grid_cap_row = c.cap_row;
     o.grid_cap_col = c.cap_col;
     o.tuned = c.tuned ? 1 : 0;
     o.mfma_dft = c.mfma ? 1 : 0;
-    o.row_points_per_lane = c.ndim == 2 ? row_points_resolve(c.nx, c.row_points) : 0;
+    o.row_points_per_lane = c.ndim == 2 && !c.resident ? row_points_resolve(c.nx, c.row_points) : 0;
+    o.resident = c.resident ? 1 : 0;
   }
   return QHD_OK;
 }

@@ -53,7 +53,7 @@ namespace qhd {
 // (line_fft_io), so those coefficients are not rounded between them.  The row pass
 // concentrates each row separately (one coefficient per row) and stays FP32, which
 // measured the same drift.  QAA lines need no LDS and run in FP64 throughout
-// (additions and xor shuffles; FP64 adds issue at the unpacked FP32 rate).
+// (additions and xor shuffles).
 
 // ------------------------------------------------------------------------------------
 // 2-D row pass: lines along x, one line per TPL lanes.

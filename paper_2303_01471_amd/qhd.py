@@ -32,6 +32,7 @@ QHD_OPT_TIME_PASSES = 0x1
 QHD_OPT_AUTOTUNE = 0x2
 QHD_OPT_NO_GRAPH = 0x4
 QHD_OPT_MFMA_DFT = 0x8
+QHD_OPT_RESIDENT = 0x10
 
 
 class QHDError(RuntimeError):
@@ -142,6 +143,7 @@ class qhd_class_info(ctypes.Structure):
         ("tuned", ctypes.c_int32),
         ("mfma_dft", ctypes.c_int32),
         ("row_points_per_lane", ctypes.c_int32),
+        ("resident", ctypes.c_int32),
     ]
 
 
@@ -515,7 +517,8 @@ class Plan:
                                                  col_variant=c.col_variant, cap_row=c.grid_cap_row,
                                                  cap_col=c.grid_cap_col, tuned=bool(c.tuned),
                                                  mfma_dft=bool(c.mfma_dft),
-                                                 row_points=c.row_points_per_lane) for c in cls])
+                                                 row_points=c.row_points_per_lane,
+                                                 resident=bool(c.resident)) for c in cls])
 
     def kernel_timings(self) -> List[dict]:
         return [dict(name=t.name.decode(), launches=t.launches, total_ms=t.total_ms, points=t.points,

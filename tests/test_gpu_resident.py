@@ -1,0 +1,150 @@
+"""Resident 2-D steps (QHD_OPT_RESIDENT): one workgroup per instance keeps psi in LDS
+for a whole evolve call.  Checked against the streaming passes (same arithmetic, so
+the same values) and against the FP64 oracle, over every supported shape, the three
+schemes, uneven step counts, chunked calls, graph replay, resume and a plan that
+mixes resident and streaming classes."""
+import numpy as np
+import pytest
+
+import qhd_inputs
+from gpu_helpers import NORM_TOL, PSI_TOL, compare, note, run_gpu, run_oracle
+from paper_2303_01471_amd import qhd as q
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(32, 32), (64, 64), (128, 128), (128, 64), (64, 128), (32, 128), (128, 32), (64, 32)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    q.load_library()
+
+
+def _landscapes(shapes, seed):
+    out = []
+    for k, sh in enumerate(shapes):
+        out.append(qhd_inputs.landscape_grid(seed + k, sh))
+    return out
+
+
+def _classes(specs, flags):
+    plan = q.Plan(specs, flags=flags)
+    try:
+        return plan.graph_info()["classes"]
+    finally:
+        plan.close()
+
+
+def _oracle_check(specs, fs, res, psis, label):
+    for i, (spec, f) in enumerate(zip(specs, fs)):
+        ref, ro = run_oracle(spec, f)
+        err, nd, d_ef, d_p = compare(spec, f, res[i], psis[i], ref, ro, f"{label}[{i}]")
+        assert err <= PSI_TOL
+        assert abs(res[i]["norm"] - ro.norm) <= NORM_TOL * max(1.0, spec.nsteps / 1e4)
+        assert d_ef <= 1e-3 and d_p <= 1e-4
+        assert res[i]["argmin_index"] == ro.argmin and res[i]["f_min"] == ro.f_min
+        assert res[i]["steps_done"] == spec.nsteps
+
+
+def test_every_shape_matches_streaming_and_oracle():
+    note("case: resident vs streaming vs oracle, shapes " + str(SHAPES))
+    specs = [q.InstanceSpec(shape=sh, nsteps=60 + 37 * k, dt=1e-3) for k, sh in enumerate(SHAPES)]
+    fs = _landscapes(SHAPES, 700)
+    cls = _classes(specs, q.QHD_OPT_RESIDENT)
+    assert all(c["resident"] for c in cls), cls
+    res_r, psi_r, _, st_r = run_gpu(specs, fs, flags=q.QHD_OPT_RESIDENT)
+    res_s, psi_s, _, st_s = run_gpu(specs, fs)
+    assert st_r == q.QHD_OK and st_s == q.QHD_OK
+    for i in range(len(specs)):
+        d = float(np.max(np.abs(psi_r[i] - psi_s[i])))
+        note(f"  {SHAPES[i]}: resident vs streaming max|dpsi| = {d:.3e}")
+        assert np.array_equal(psi_r[i], psi_s[i])
+    _oracle_check(specs, fs, res_r, psi_r, "resident")
+
+
+def test_schemes_and_schedules_against_oracle():
+    note("case: resident, first-order and fourth-order schemes, constant and table schedules")
+    shapes = [(64, 32), (32, 64), (64, 64), (32, 32)]
+    t = (np.arange(90) + 0.5) * 2e-3
+    table = np.stack([1.0 + 0.5 * np.cos(t), 2.0 * t], axis=1)
+    specs = [q.InstanceSpec(shape=shapes[0], nsteps=120, dt=2e-3, scheme=q.QHD_SCHEME_LIE),
+             q.InstanceSpec(shape=shapes[1], nsteps=80, dt=2e-3, scheme=q.QHD_SCHEME_YOSHIDA4),
+             q.InstanceSpec(shape=shapes[2], nsteps=100, dt=2e-3, sched=q.QHD_SCHED_CONST, sched_p=(0.7, 1.3)),
+             q.InstanceSpec(shape=shapes[3], nsteps=90, dt=2e-3, sched=q.QHD_SCHED_TABLE, table=table)]
+    fs = _landscapes(shapes, 720)
+    res, psis, _, st = run_gpu(specs, fs, flags=q.QHD_OPT_RESIDENT)
+    assert st == q.QHD_OK
+    _oracle_check(specs, fs, res, psis, "schemes")
+
+
+def test_config0_and_128_against_oracle():
+    note("case: resident 64^2 dt=0.01 1000 steps and 128^2 dt=1e-3 2000 steps")
+    specs = [q.InstanceSpec(shape=(64, 64), nsteps=1000, dt=1e-2),
+             q.InstanceSpec(shape=(128, 128), nsteps=2000, dt=1e-3)]
+    fs = _landscapes([(64, 64), (128, 128)], 740)
+    res, psis, _, st = run_gpu(specs, fs, flags=q.QHD_OPT_RESIDENT)
+    assert st == q.QHD_OK
+    _oracle_check(specs, fs, res, psis, "c0")
+
+
+def test_chunked_calls_graph_replay_and_resume():
+    note("case: resident chunked evolve vs one shot; graph replay; resume from a checkpoint")
+    import torch
+    shapes = [(128, 128), (64, 64), (64, 64)]
+    specs = [q.InstanceSpec(shape=sh, nsteps=400, dt=1e-3) for sh in shapes]
+    fs = _landscapes(shapes, 760)
+    _, one, _, _ = run_gpu(specs, fs, flags=q.QHD_OPT_RESIDENT | q.QHD_OPT_NO_GRAPH)
+    plan = q.Plan(specs, flags=q.QHD_OPT_RESIDENT)
+    try:
+        assert plan.graph_info()["graph_steps"] > 0
+        for i, f in enumerate(fs):
+            plan.set_potential(i, f)
+        for c in (1, 13, 130, 64):
+            plan.evolve(c)
+            plan.observe()  # readouts between calls leave the state untouched
+        plan.evolve()
+        _, psi, _, st = plan.observe(want_psi=True)
+        torch.cuda.synchronize()
+        assert st == q.QHD_OK
+        for i in range(len(specs)):
+            assert np.array_equal(plan.psi_of(psi, i).cpu().numpy(), one[i])
+    finally:
+        plan.close()
+    # checkpoint at step 150 (closed state), resumed in a new resident plan
+    half = [q.InstanceSpec(shape=sh, nsteps=150, dt=1e-3) for sh in shapes]
+    _, mid, _, _ = run_gpu(half, fs, flags=q.QHD_OPT_RESIDENT)
+    user = [q.InstanceSpec(shape=sh, nsteps=400, dt=1e-3, init=q.QHD_INIT_USER) for sh in shapes]
+    res, psis, _, st = run_gpu(user, fs, states={i: mid[i] for i in range(3)},
+                               steps_done={i: 150 for i in range(3)}, flags=q.QHD_OPT_RESIDENT)
+    assert st == q.QHD_OK
+    for i, (spec, f) in enumerate(zip(user, fs)):
+        ref, ro = run_oracle(spec, f, mid[i], 150)
+        err, nd, d_ef, d_p = compare(spec, f, res[i], psis[i], ref, ro, f"resume[{i}]")
+        assert err <= PSI_TOL and d_ef <= 1e-3 and d_p <= 1e-4
+
+
+def test_mixed_plan_resident_and_streaming_classes():
+    note("case: one plan with resident 128^2 / 64^2 classes and a streaming 256^2 class")
+    shapes = [(256, 256), (128, 128), (64, 64), (128, 128)]
+    specs = [q.InstanceSpec(shape=sh, nsteps=n, dt=1e-3) for sh, n in zip(shapes, (200, 260, 90, 140))]
+    fs = _landscapes(shapes, 780)
+    cls = {tuple(c["n"][:2]): c["resident"] for c in _classes(specs, q.QHD_OPT_RESIDENT)}
+    assert cls[(256, 256)] is False and cls[(128, 128)] is True and cls[(64, 64)] is True
+    res, psis, _, st = run_gpu(specs, fs, chunks=[50, 75], flags=q.QHD_OPT_RESIDENT)
+    assert st == q.QHD_OK
+    _oracle_check(specs, fs, res, psis, "mixed")
+
+
+def test_batch_norm_drift_resident():
+    """The benchmark recipe at 128^2 for 10^4 steps, resident: every norm within 1e-5."""
+    specs_in = qhd_inputs.batched_2d(count=64, sizes=(128,), t_range=(10.0, 10.0))
+    specs = [q.InstanceSpec(shape=s.shape, nsteps=s.nsteps, dt=s.dt) for s in specs_in]
+    note(f"case: resident batch, {len(specs)} instances of 128^2, 10k steps")
+    res, _, _, st = run_gpu(specs, [s.grid() for s in specs_in], flags=q.QHD_OPT_RESIDENT)
+    drift = [abs(r["norm"] - 1.0) for r in res]
+    note(f"  |norm - 1|: max {max(drift):.3e}, median {float(np.median(drift)):.3e}")
+    assert st == q.QHD_OK and max(drift) <= 1e-5
