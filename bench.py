@@ -268,6 +268,8 @@ def main():
     ap.add_argument("--tune-cache", default="",
                     help="launch tuning cache (read; classes without an entry are tuned and appended)")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-resident", action="store_true",
+                    help="skip the resident-vs-streaming leg (it reuses the 64^2/128^2 pass kernels)")
     ap.add_argument("--surrogate-pairs", type=int, default=4096)
     ap.add_argument("--surrogate-epochs", type=float, default=4.0)
     ap.add_argument("--cpu-sample-steps", type=int, default=12000,
@@ -388,6 +390,15 @@ def main():
         upload(pl, specs, "qaa-leapfrog")
         el_l, res_l, _ = timed_runs(pl, 1, 1, stream, "qaa-leapfrog")
         pl.close()
+        # both models with resident steps (psi in LDS for the whole call)
+        prq = build_plan(specs, q, flags=q.QHD_OPT_RESIDENT, qaa=True)
+        upload(prq, specs, "qaa-resident")
+        el_rq, res_rq, _ = timed_runs(prq, 1, 1, stream, "qaa-resident")
+        prq.close()
+        prh = build_plan(specs, q, flags=q.QHD_OPT_RESIDENT)
+        upload(prh, specs, "qhd-resident")
+        el_rh, _, _ = timed_runs(prh, 1, 1, stream, "qhd-resident")
+        prh.close()
         sm_l = np.array([r["success_mass"] for r in res_l])
         sm_a = np.array([r["success_mass"] for r in res])
         sm_q = np.array([r["success_mass"] for r in res_q])
@@ -398,6 +409,9 @@ def main():
                       "qaa_leapfrog_gp_steps_per_s": round(total_gp / el_l, 1),
                       "qaa_leapfrog_mean_success_mass": round(float(sm_l.mean()), 4),
                       "qaa_leapfrog_max_norm_deviation": max(abs(r["norm"] - 1.0) for r in res_l),
+                      "qaa_resident_gp_steps_per_s": round(total_gp / el_rq, 1),
+                      "qaa_resident_max_norm_drift": max(abs(r["norm"] - 1.0) for r in res_rq),
+                      "qhd_resident_same_instances_gp_steps_per_s": round(total_gp / el_rh, 1),
                       "success_ball": "radius 0.1 around the grid argmin (unit box)"}
         log(f"QHD on the same instances: {total_gp / el_q / 1e9:.2f} G gp-steps/s; mean success "
             f"QAA {sm_a.mean():.4f} vs QHD {sm_q.mean():.4f}")
@@ -462,7 +476,7 @@ def main():
 
     # ---- batched2d: resident steps (psi held in LDS) against streaming passes ---------
     resident = None
-    if args.workload == "batched2d" and not args.no_qaa_summary:
+    if args.workload == "batched2d" and not args.no_qaa_summary and not args.no_resident:
         def rate_of(rspecs, rfs, flags):
             pr = build_plan(rspecs, q, flags=flags, tune_cache=args.tune_cache)
             for k, fr in enumerate(rfs):
@@ -481,6 +495,9 @@ def main():
         rows = []
         for n, count in ((128, 512), (64, 1024), (64, 1), (128, 1)):
             rs = qhd_inputs.batched_2d(count=count, sizes=(n,), t_range=(2.0, 2.0))
+            if args.cap_steps > 0:
+                for x in rs:
+                    x.nsteps = min(x.nsteps, args.cap_steps)
             rfs = [x.grid() for x in rs]
             r_s, _ = rate_of(rs, rfs, q.QHD_OPT_AUTOTUNE)
             r_r, d_r = rate_of(rs, rfs, q.QHD_OPT_RESIDENT)

@@ -136,15 +136,17 @@ typedef struct {
                                     FP32 accumulation (relative error ~2^-22 per
                                     transform, against ~2^-24 for the FP32 FFT); other
                                     instances are unaffected                            */
-#define QHD_OPT_RESIDENT 0x10u   /* 2-D QHD instances with n_x, n_y in {32, 64, 128} and
-                                    any scheme: all the steps of an evolve call run in
+#define QHD_OPT_RESIDENT 0x10u   /* 2-D instances with n_x, n_y in {32, 64, 128} (QHD
+                                    with any scheme, or QAA integrated by the split step):
+                                    all the steps of an evolve call run in
                                     one launch, one workgroup per instance holding psi
                                     in LDS (n_y (9 n_x / 8 + 1) 8 bytes, ~148 KB and one
                                     instance per CU at 128^2), so psi crosses HBM only
                                     at the start and the end of the call (the scope's
                                     resident mode of the two-pass step, App. C.2.1).
                                     Same arithmetic as the streaming passes with 8
-                                    points per lane.  QAA and other shapes unaffected   */
+                                    points per lane.  Leapfrog QAA and other shapes
+                                    unaffected                                          */
 
 typedef struct qhd_plan_s *qhd_plan;
 

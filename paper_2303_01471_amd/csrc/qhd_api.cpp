@@ -287,7 +287,8 @@ qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<
         double gps = 0.0;
         for (size_t k = 0; k < c.members.size(); ++k) gps += (double)lim[ci][k] * (double)c.points;
         HIP_TRY(timed_launch(c.fam_res, gps, timing, [&] {
-          return launch_resident_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, c.tw_y, max_steps, c.y4, stream);
+          return launch_resident_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, c.tw_y, max_steps, c.model, c.y4,
+                                    stream);
         }));
         continue;
       }
@@ -717,11 +718,10 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       c.fam_y = family_index(p, name, 16.0);
       snprintf(name, sizeof name, "zpass_3d/n%d", c.nz);
       c.fam_z = family_index(p, name, 16.0);
-    } else if (c.ndim == 2 && (p->opts.flags & QHD_OPT_RESIDENT) && c.model == kModelQHD && !c.leapfrog &&
-               resident_supported(c.nx, c.ny)) {
+    } else if (c.ndim == 2 && (p->opts.flags & QHD_OPT_RESIDENT) && !c.leapfrog && resident_supported(c.nx, c.ny)) {
       // psi stays in LDS; per grid-point step only f (8 B, FP64) is read, from the caches
       c.resident = true;
-      snprintf(name, sizeof name, "resident_2d/n%d", c.nx);
+      snprintf(name, sizeof name, "resident_2d%s/n%d", c.model == kModelQAA ? "_qaa" : "", c.nx);
       c.fam_res = family_index(p, name, 8.0);
     } else if (c.ndim == 2) {
       // leapfrog stages: the row pass reads psi and f and writes the partial H v (4 B),

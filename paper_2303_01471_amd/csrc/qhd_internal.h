@@ -85,8 +85,8 @@ hipError_t launch_commit(InstDev* inst, int ninst, long long max_steps, hipStrea
 // tiled HBM state once.  nx, ny in {32, 64, 128}.
 bool resident_supported(int nx, int ny);
 hipError_t launch_resident_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi, const double* f,
-                              const double2* tw_nx, const double2* tw_ny, long long max_steps, bool y4,
-                              hipStream_t stream);
+                              const double2* tw_nx, const double2* tw_ny, long long max_steps, int model,
+                              bool y4, hipStream_t stream);
 
 // 3-D (qhd_kernels_3d.hip): y-lines (dir -1 forward, +1 inverse) and the z-pass
 // with the kinetic factor.  The x-pass is launch_row_pass_2d with rows = ny*nz.

@@ -17,19 +17,21 @@
 // its points into registers, and its own storage then serves as the exchange buffer
 // of its transforms.  Every arithmetic step (line transforms, twiddles, phases, the
 // FP64 kinetic factor and the FP64 ends of the column transforms) is the one of the
-// streaming passes with 8 points per lane, so both paths give the same values.
+// streaming passes with 8 points per lane, so both paths give the same values.  The
+// QAA model (App. E.2's baseline) runs the same two phases with FP64 Walsh-Hadamard
+// lines, which need no LDS exchange.
 #include "line_fft.h"
 #include "pass_common.h"
 #include "qhd_internal.h"
 
 namespace qhd {
 
-template <int NX, int NY>
+template <int NX, int NY, int MODEL = kModelQHD>
 struct ResCfg {
   static constexpr int P = 8;
   static constexpr int TX = NX / P, TY = NY / P;               // lanes per row / column line
   // 1024 threads (four waves per SIMD) where the registers fit in 128 per lane
-  static constexpr int MAXT = (NX == 128 && NY == 64) ? 512 : 1024;
+  static constexpr int MAXT = ((NX == 128 && NY == 64) || (MODEL == kModelQAA && NX * NY == 16384)) ? 512 : 1024;
   static constexpr int NT = (NX * NY / P) < MAXT ? (NX * NY / P) : MAXT;
   static constexpr int RS = ((NX + NX / 8) | 1);               // row stride in slots (odd)
   static constexpr int ROWS_PER_IT = NT / TX, COLS_PER_IT = NT / TY;
@@ -37,14 +39,14 @@ struct ResCfg {
   static_assert(NY % ROWS_PER_IT == 0 && NX % COLS_PER_IT == 0, "whole line rounds");
 };
 
-template <int NX, int NY, bool Y4>
-__global__ void __launch_bounds__((ResCfg<NX, NY>::NT)) k_resident_2d(const InstDev* __restrict__ inst, int ninst,
+template <int NX, int NY, int MODEL, bool Y4>
+__global__ void __launch_bounds__((ResCfg<NX, NY, MODEL>::NT)) k_resident_2d(const InstDev* __restrict__ inst, int ninst,
                                                                      float2* __restrict__ psi,
                                                                      const double* __restrict__ f,
                                                                      const double2* __restrict__ twx,
                                                                      const double2* __restrict__ twy,
                                                                      long long max_steps) {
-  using C = ResCfg<NX, NY>;
+  using C = ResCfg<NX, NY, MODEL>;
   constexpr int P = C::P, TX = C::TX, TY = C::TY, NT = C::NT, RS = C::RS;
   __shared__ float2 st[NY * RS];
   __shared__ double2 twlx[TwLdsSize<NX, P>::value];
@@ -81,8 +83,14 @@ __global__ void __launch_bounds__((ResCfg<NX, NY>::NT)) k_resident_2d(const Inst
       const double cx = a * I.kin_turns[0];
       if (tid < NY) {
         // read in the column phase, after the barrier that ends the row phase
-        const int nyf = freq(tid, NY);
-        const double2 e = phase_turns_d(a * I.kin_turns[1] * (double)(nyf * nyf));
+        double arg;
+        if constexpr (MODEL == kModelQAA) {
+          arg = a * axis_turns<MODEL>(I, 1, tid, NY);
+        } else {
+          const int nyf = freq(tid, NY);
+          arg = a * I.kin_turns[1] * (double)(nyf * nyf);
+        }
+        const double2 e = phase_turns_d(arg);
         eyl[tid] = make_double2(e.x * inv_n, e.y * inv_n);
       }
       // row phase: [F_x^{-1}] . merged potential half steps . F_x
@@ -90,17 +98,30 @@ __global__ void __launch_bounds__((ResCfg<NX, NY>::NT)) k_resident_2d(const Inst
 #pragma unroll 1
       for (int y = rl; y < NY; y += C::ROWS_PER_IT) {
         float2* my = st + y * RS;
-        float2 reg[P];
+        if constexpr (MODEL == kModelQAA) {
+          double2 reg[P];
 #pragma unroll
-        for (int q = 0; q < P; ++q) reg[q] = my[lds_slot(rt + q * TX)];
-        wave_lds_sync();
-        if (!entry) line_fft<NX, P, +1>(reg, rt, tx, my);
+          for (int q = 0; q < P; ++q) assign(reg[q], my[lds_slot(rt + q * TX)]);
+          if (!entry) line_wht<NX, P>(reg, rt);
 #pragma unroll
-        for (int q = 0; q < P; ++q)
-          reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fg[tile_index(rt + q * TX, y, NX)]));
-        line_fft<NX, P, -1>(reg, rt, tx, my);
+          for (int q = 0; q < P; ++q)
+            reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fg[tile_index(rt + q * TX, y, NX)]));
+          line_wht<NX, P>(reg, rt);
 #pragma unroll
-        for (int q = 0; q < P; ++q) my[lds_slot(rt + q * TX)] = reg[q];
+          for (int q = 0; q < P; ++q) assign(my[lds_slot(rt + q * TX)], reg[q]);
+        } else {
+          float2 reg[P];
+#pragma unroll
+          for (int q = 0; q < P; ++q) reg[q] = my[lds_slot(rt + q * TX)];
+          wave_lds_sync();
+          if (!entry) line_fft<NX, P, +1>(reg, rt, tx, my);
+#pragma unroll
+          for (int q = 0; q < P; ++q)
+            reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fg[tile_index(rt + q * TX, y, NX)]));
+          line_fft<NX, P, -1>(reg, rt, tx, my);
+#pragma unroll
+          for (int q = 0; q < P; ++q) my[lds_slot(rt + q * TX)] = reg[q];
+        }
       }
       __syncthreads();
       // column phase: F_y . K . F_y^{-1} with K = E_x E_y / (nx ny) in FP64
@@ -110,18 +131,33 @@ __global__ void __launch_bounds__((ResCfg<NX, NY>::NT)) k_resident_2d(const Inst
         float2 reg[P];
 #pragma unroll
         for (int q = 0; q < P; ++q) reg[q] = my[(ct + q * TY) * RS];
-        wave_lds_sync();
         double2 kd[P];
-        line_fft_io<NY, P, -1, false, StrideIx<RS>>(reg, kd, ct, ty, my);
-        const int nxf = freq(x, NX);
-        const double2 ex = phase_turns_d(cx * (double)(nxf * nxf));
+        double xarg;
+        if constexpr (MODEL == kModelQAA) {
+#pragma unroll
+          for (int q = 0; q < P; ++q) assign(kd[q], reg[q]);
+          line_wht<NY, P>(kd, ct);
+          xarg = a * axis_turns<MODEL>(I, 0, x, NX);
+        } else {
+          wave_lds_sync();
+          line_fft_io<NY, P, -1, false, StrideIx<RS>>(reg, kd, ct, ty, my);
+          const int nxf = freq(x, NX);
+          xarg = cx * (double)(nxf * nxf);
+        }
+        const double2 ex = phase_turns_d(xarg);
 #pragma unroll
         for (int q = 0; q < P; ++q) {
           const double2 ey = eyl[ct + q * TY];
           const double2 k = make_double2(fma(ex.x, ey.x, -ex.y * ey.y), fma(ex.x, ey.y, ex.y * ey.x));
           kd[q] = cmul_fd(kd[q], k);
         }
-        line_fft_io<NY, P, +1, false, StrideIx<RS>>(kd, reg, ct, ty, my);
+        if constexpr (MODEL == kModelQAA) {
+          line_wht<NY, P>(kd, ct);
+#pragma unroll
+          for (int q = 0; q < P; ++q) assign(reg[q], kd[q]);
+        } else {
+          line_fft_io<NY, P, +1, false, StrideIx<RS>>(kd, reg, ct, ty, my);
+        }
 #pragma unroll
         for (int q = 0; q < P; ++q) my[(ct + q * TY) * RS] = reg[q];
       }
@@ -144,18 +180,22 @@ bool resident_supported(int nx, int ny) {
 }
 
 hipError_t launch_resident_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi, const double* f,
-                              const double2* tw_nx, const double2* tw_ny, long long max_steps, bool y4,
-                              hipStream_t stream) {
+                              const double2* tw_nx, const double2* tw_ny, long long max_steps, int model,
+                              bool y4, hipStream_t stream) {
   if (ninst <= 0) return hipSuccess;
   if (!resident_supported(nx, ny)) return hipErrorInvalidValue;
 #define QHD_RES_LAUNCH(NX_, NY_)                                                                              \
   if (nx == NX_ && ny == NY_) {                                                                               \
-    if (y4)                                                                                                   \
-      hipLaunchKernelGGL((k_resident_2d<NX_, NY_, true>), dim3(ninst), dim3(ResCfg<NX_, NY_>::NT), 0, stream, \
+    constexpr int NT_ = ResCfg<NX_, NY_>::NT, NTQ_ = ResCfg<NX_, NY_, kModelQAA>::NT;                         \
+    if (model == kModelQAA)                                                                                   \
+      hipLaunchKernelGGL((k_resident_2d<NX_, NY_, kModelQAA, false>), dim3(ninst), dim3(NTQ_), 0, stream,     \
+                         inst, ninst, psi, f, tw_nx, tw_ny, max_steps);                                       \
+    else if (y4)                                                                                              \
+      hipLaunchKernelGGL((k_resident_2d<NX_, NY_, kModelQHD, true>), dim3(ninst), dim3(NT_), 0, stream,       \
                          inst, ninst, psi, f, tw_nx, tw_ny, max_steps);                                       \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_resident_2d<NX_, NY_, false>), dim3(ninst), dim3(ResCfg<NX_, NY_>::NT), 0,        \
-                         stream, inst, ninst, psi, f, tw_nx, tw_ny, max_steps);                               \
+      hipLaunchKernelGGL((k_resident_2d<NX_, NY_, kModelQHD, false>), dim3(ninst), dim3(NT_), 0, stream,      \
+                         inst, ninst, psi, f, tw_nx, tw_ny, max_steps);                                       \
     return hipGetLastError();                                                                                 \
   }
   QHD_RES_LAUNCH(32, 32)

@@ -98,9 +98,16 @@ def traffic(fetch_db: str, write_db: str, copy_bytes: float, points_per_dispatch
     w_scale = copy_bytes / (wr[ck]["WRITE_SIZE"] * 1024.0)
     out = {"source_hash": source_hash, "copy_kernel": ck, "copy_bytes": copy_bytes,
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
+    # a family's kernel is its most-dispatched instantiation (the one the workload runs;
+    # other variants are autotuning trials)
+    best = {}
+    for k in fe:
+        fb = family_of(k)
+        if fb and (fb[0] not in best or nfe[k] > nfe[best[fb[0]]]):
+            best[fb[0]] = k
     for k, v in fe.items():
         fb = family_of(k)
-        if fb:
+        if fb and best[fb[0]] == k:
             name, bpp = fb
             pts = points_per_dispatch.get(name)
             if not pts:

@@ -148,3 +148,31 @@ def test_batch_norm_drift_resident():
     drift = [abs(r["norm"] - 1.0) for r in res]
     note(f"  |norm - 1|: max {max(drift):.3e}, median {float(np.median(drift)):.3e}")
     assert st == q.QHD_OK and max(drift) <= 1e-5
+
+
+def _qaa(shape, nsteps, dt, scheme=q.QHD_SCHEME_STRANG):
+    return q.InstanceSpec(shape=shape, nsteps=nsteps, dt=dt, model=q.QHD_MODEL_QAA, sched=q.QHD_SCHED_LINEAR,
+                          sched_p=(nsteps * dt, 0.0), scheme=scheme)
+
+
+def test_qaa_resident_matches_streaming_and_reference():
+    note("case: resident QAA (split step) vs streaming QAA vs the FP64 QAA reference")
+    shapes = [(64, 64), (128, 128), (128, 64), (32, 64)]
+    specs = [_qaa(sh, n, 1e-2) for sh, n in zip(shapes, (400, 300, 250, 500))]
+    fs = _landscapes(shapes, 800)
+    cls = _classes(specs, q.QHD_OPT_RESIDENT)
+    assert all(c["resident"] for c in cls), cls
+    res_r, psi_r, _, st_r = run_gpu(specs, fs, chunks=[7, 60], flags=q.QHD_OPT_RESIDENT)
+    _, psi_s, _, st_s = run_gpu(specs, fs, chunks=[7, 60])
+    assert st_r == q.QHD_OK and st_s == q.QHD_OK
+    for i in range(len(specs)):
+        d = float(np.max(np.abs(psi_r[i] - psi_s[i])))
+        note(f"  QAA {shapes[i]}: resident vs streaming max|dpsi| = {d:.3e}")
+        assert np.array_equal(psi_r[i], psi_s[i])
+    _oracle_check(specs, fs, res_r, psi_r, "qaa-resident")
+
+
+def test_leapfrog_classes_stay_streaming():
+    specs = [_qaa((64, 64), 100, 5e-3, q.QHD_SCHEME_LEAPFROG), _qaa((128, 128), 100, 1e-2)]
+    cls = {tuple(c["n"][:2]): c["resident"] for c in _classes(specs, q.QHD_OPT_RESIDENT)}
+    assert cls[(64, 64)] is False and cls[(128, 128)] is True

@@ -1,0 +1,46 @@
+"""Host logic of the profile summaries (paper_2303_01471_amd/profiling.py): kernel-name
+families and the counter-to-traffic mapping, on small synthetic counter databases of
+the rocprofv3 layout."""
+import sqlite3
+
+from paper_2303_01471_amd import profiling
+
+
+def test_families_of_the_pass_kernels():
+    f = profiling.family_of
+    assert f("void qhd::k_row_pass_2d<512, 16, 0, false>(qhd::InstDev const*)") == ("row_pass_2d/n512", 24.0)
+    assert f("k_col_pass_2d<128, 8, 1, false>") == ("col_pass_2d_qaa/n128", 16.0)
+    assert f("k_col_pass_tw<256, 8, true>") == ("col_pass_2d/n256", 16.0)
+    assert f("k_lf_row_2d<64, 8>") == ("row_pass_2d_qaa_lf/n64", 20.0)
+    assert f("k_argmin") is None
+
+
+def _db(path, rows):
+    con = sqlite3.connect(path)
+    con.execute("create table counters_collection (kernel_name text, counter_name text, value real, "
+                "dispatch_id integer)")
+    con.executemany("insert into counters_collection values (?, ?, ?, ?)", rows)
+    con.commit()
+    con.close()
+
+
+def test_traffic_scales_by_the_copy_kernel_and_takes_the_main_instantiation(tmp_path):
+    copy = "at::native::vectorized_elementwise_kernel<4, MulFunctor>"
+    main, trial = "k_col_pass_2d<512, 8, 0, false>", "k_col_pass_2d<512, 16, 0, false>"
+    pts = 1 << 20
+    # the copy kernel moves 1 MiB each way; its FETCH_SIZE reads half of that (KiB units)
+    fe = [(copy, "FETCH_SIZE", 512.0, 1)]
+    wr = [(copy, "WRITE_SIZE", 1024.0, 1)]
+    for d in range(10):  # 10 launches of the kernel the workload runs: 8 + 8 B per point
+        fe.append((main, "FETCH_SIZE", pts * 8 / 1024 / 2, 100 + d))
+        wr.append((main, "WRITE_SIZE", pts * 8 / 1024, 100 + d))
+    fe.append((trial, "FETCH_SIZE", 1.0, 999))  # one autotuning trial of another variant
+    wr.append((trial, "WRITE_SIZE", 0.0, 999))
+    _db(tmp_path / "fe.db", fe)
+    _db(tmp_path / "wr.db", wr)
+    out = profiling.traffic(str(tmp_path / "fe.db"), str(tmp_path / "wr.db"), float(1 << 20),
+                            {"col_pass_2d/n512": pts}, "h")
+    assert abs(out["fetch_scale"] - 2.0) < 1e-12 and abs(out["write_scale"] - 1.0) < 1e-12
+    k = out["kernels"]["col_pass_2d/n512"]
+    assert k["kernel"] == main
+    assert abs(k["hbm_bytes_per_point"] - 16.0) < 1e-9 and k["algorithmic_bytes_per_point"] == 16.0
