@@ -85,7 +85,9 @@ def kernel_table(kt):
 def roofline_of(kt):
     """Dominant kernel family (largest summed time): algorithmic bytes per mean launch /
     mean HIP-event duration, and the counter-measured HBM bytes of a mean launch when the
-    committed counter summary matches the kernel sources."""
+    committed counter summary matches the kernel sources.  Resident launches (psi in LDS
+    for a whole call, no HBM bytes per step) are listed in the kernel table only."""
+    kt = [t for t in kt if not t["name"].startswith("resident")]
     dom = max(kt, key=lambda t: t["total_ms"]) if kt else None
     if dom is None:
         return None
@@ -268,6 +270,9 @@ def main():
     ap.add_argument("--tune-cache", default="",
                     help="launch tuning cache (read; classes without an entry are tuned and appended)")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--streaming-only", action="store_true",
+                    help="batched2d: run every class with the streaming passes (by default classes of at "
+                         "most 128^2 run resident steps, QHD_OPT_RESIDENT)")
     ap.add_argument("--no-resident", action="store_true",
                     help="skip the resident-vs-streaming leg (it reuses the 64^2/128^2 pass kernels)")
     ap.add_argument("--surrogate-pairs", type=int, default=4096)
@@ -358,7 +363,10 @@ def main():
         f"{total_gp:.3e} grid-point-steps per bench step")
 
     extra = q.QHD_OPT_MFMA_DFT if args.mfma_dft else 0
-    plan = build_plan(specs, q, flags=q.QHD_OPT_TIME_PASSES | q.QHD_OPT_AUTOTUNE | extra,
+    # the batch's small classes run resident steps beside the streaming passes of the large
+    # ones (bitwise the same results); the plain and parity legs keep the streaming passes
+    main_flags = extra | (q.QHD_OPT_RESIDENT if args.workload == "batched2d" and not args.streaming_only else 0)
+    plan = build_plan(specs, q, flags=q.QHD_OPT_TIME_PASSES | q.QHD_OPT_AUTOTUNE | main_flags,
                       timing_stride=args.timing_stride, tune_cache=args.tune_cache, qaa=qaa)
     tuned = plan.graph_info()["classes"]
     log("launch configuration: " + "; ".join(
@@ -677,6 +685,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"batched-{len(specs)}: 2-D instances, n in {sizes}^2 (uniform), "
                                 f"T~U[5,20], dt=1e-3, Nesterov schedule, 8-24 cosine-term landscapes"
+                                + ("" if args.streaming_only else "; 128^2 class with resident steps")
                                 if args.workload == "batched2d" else
                                 f"baseline QAA: {len(specs)} 2-D instances, n in {sizes}^2 (radix-2 qubits, "
                                 f"H0 = -sum sigma_x), T=10, dt=1e-3, linear schedule, 8-24 cosine-term landscapes"

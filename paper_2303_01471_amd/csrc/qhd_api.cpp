@@ -149,6 +149,7 @@ struct ShapeClass {
   float* scratch = nullptr;        // leapfrog: partial H v between the row and column passes
   bool resident = false;           // QHD_OPT_RESIDENT: all steps of a call in one launch, psi in LDS
   int fam_res = -1;
+  int res_slot = -1;               // its stream and join event in the plan
 };
 
 struct qhd_plan_s {
@@ -182,6 +183,11 @@ struct qhd_plan_s {
   std::vector<Family> families;
   std::vector<Pending> pending;
   std::vector<hipEvent_t> free_events;
+  // resident classes run on streams of their own, forked from the caller's stream and
+  // joined back before the step commit (default priority)
+  std::vector<hipStream_t> res_streams;
+  std::vector<hipEvent_t> res_join;
+  hipEvent_t res_fork = nullptr;
 };
 
 namespace {
@@ -191,6 +197,10 @@ void free_plan(qhd_plan p) {
   (void)hipSetDevice(p->device);
   if (p->internal) (void)hipStreamSynchronize(p->internal);
   if (p->last_stream_valid) (void)hipStreamSynchronize(p->last_stream);
+  for (auto st : p->res_streams) (void)hipStreamSynchronize(st);
+  for (auto ev : p->res_join) (void)hipEventDestroy(ev);
+  if (p->res_fork) (void)hipEventDestroy(p->res_fork);
+  for (auto st : p->res_streams) (void)hipStreamDestroy(st);
   for (auto& c : p->classes) {
     (void)hipFree(c.dev);
     (void)hipFree(c.psi);
@@ -258,20 +268,46 @@ qhd_status push_inst(qhd_plan p, int i) {
 qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<long long>>& lim,
                          long long max_steps, hipStream_t stream, bool timing) {
   const int stride = p->opts.timing_stride;
-  auto timed_launch = [&](int fam, double points, bool sample, auto&& fn) -> hipError_t {
+  auto timed_on = [&](hipStream_t st, int fam, double points, bool sample, auto&& fn) -> hipError_t {
     hipEvent_t a = nullptr, b = nullptr;
     if (sample) {
       a = take_event(p);
       b = take_event(p);
-      if (a && b) (void)hipEventRecord(a, stream);
+      if (a && b) (void)hipEventRecord(a, st);
     }
     hipError_t r = fn();
     if (sample && a && b) {
-      (void)hipEventRecord(b, stream);
+      (void)hipEventRecord(b, st);
       p->pending.push_back({a, b, fam, points});
     }
     return r;
   };
+  auto timed_launch = [&](int fam, double points, bool sample, auto&& fn) -> hipError_t {
+    return timed_on(stream, fam, points, sample, fn);
+  };
+  // resident classes: every sub-step of the call in one launch each, on the class's own
+  // stream, so that CUs left idle by one class (its last wave of workgroups) serve the
+  // others; timed as a whole (points = the call's grid-point stages)
+  std::vector<int> joined;
+  for (size_t ci = 0; ci < p->classes.size(); ++ci) {
+    ShapeClass& c = p->classes[ci];
+    if (!c.resident) continue;
+    int nact = 0;
+    double gps = 0.0;
+    for (size_t k = 0; k < c.members.size(); ++k) {
+      if (lim[ci][k] > 0) nact = (int)k + 1;
+      gps += (double)lim[ci][k] * (double)c.points;
+    }
+    if (nact == 0) continue;
+    if (joined.empty()) HIP_TRY(hipEventRecord(p->res_fork, stream));
+    hipStream_t rs = p->res_streams[c.res_slot];
+    HIP_TRY(hipStreamWaitEvent(rs, p->res_fork, 0));
+    HIP_TRY(timed_on(rs, c.fam_res, gps, timing, [&] {
+      return launch_resident_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, c.tw_y, max_steps, c.model, c.y4, rs);
+    }));
+    HIP_TRY(hipEventRecord(p->res_join[c.res_slot], rs));
+    joined.push_back(c.res_slot);
+  }
   for (long long s = 0; s < S; ++s) {
     const bool sample = timing && (s % stride == 0);
     for (size_t ci = 0; ci < p->classes.size(); ++ci) {
@@ -279,19 +315,7 @@ qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<
       int nact = 0;
       for (size_t k = 0; k < c.members.size(); ++k)
         if (lim[ci][k] > s) nact = (int)k + 1;
-      if (nact == 0) continue;
-      if (c.resident) {
-        // every sub-step of the call in one launch (timed as a whole: its points are
-        // the call's grid-point stages)
-        if (s != 0) continue;
-        double gps = 0.0;
-        for (size_t k = 0; k < c.members.size(); ++k) gps += (double)lim[ci][k] * (double)c.points;
-        HIP_TRY(timed_launch(c.fam_res, gps, timing, [&] {
-          return launch_resident_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, c.tw_y, max_steps, c.model, c.y4,
-                                    stream);
-        }));
-        continue;
-      }
+      if (nact == 0 || c.resident) continue;
       const double pts = (double)nact * (double)c.points;
       if (c.ndim == 3 && c.mfma) {
         HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
@@ -352,6 +376,7 @@ qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<
       }
     }
   }
+  for (int k : joined) HIP_TRY(hipStreamWaitEvent(stream, p->res_join[k], 0));
   for (auto& c : p->classes) HIP_TRY(launch_commit(c.dev, (int)c.members.size(), max_steps, stream));
   return QHD_OK;
 }
@@ -797,6 +822,26 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
           return bail(QHD_EDEVICE);
         }
       }
+    }
+  }
+  // a stream and a join event per resident class, one fork event
+  for (auto& c : p->classes) {
+    if (!c.resident) continue;
+    hipStream_t rs = nullptr;
+    hipEvent_t ev = nullptr;
+    e = hipStreamCreateWithFlags(&rs, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+      p->res_streams.push_back(rs);
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    }
+    if (e == hipSuccess) {
+      p->res_join.push_back(ev);
+      c.res_slot = (int)p->res_join.size() - 1;
+    }
+    if (e == hipSuccess && !p->res_fork) e = hipEventCreateWithFlags(&p->res_fork, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      fail(QHD_EDEVICE, "resident stream: %s", hipGetErrorString(e));
+      return bail(QHD_EDEVICE);
     }
   }
   // step-chunk graph for plans whose instances all take the same number of steps of
