@@ -270,9 +270,9 @@ def main():
     ap.add_argument("--tune-cache", default="",
                     help="launch tuning cache (read; classes without an entry are tuned and appended)")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--streaming-only", action="store_true",
-                    help="batched2d: run every class with the streaming passes (by default classes of at "
-                         "most 128^2 run resident steps, QHD_OPT_RESIDENT)")
+    ap.add_argument("--resident-classes", action="store_true",
+                    help="batched2d: time the main batch with its classes of at most 128^2 on resident "
+                         "steps (QHD_OPT_RESIDENT); by default that configuration is timed separately")
     ap.add_argument("--no-resident", action="store_true",
                     help="skip the resident-vs-streaming leg (it reuses the 64^2/128^2 pass kernels)")
     ap.add_argument("--surrogate-pairs", type=int, default=4096)
@@ -363,9 +363,10 @@ def main():
         f"{total_gp:.3e} grid-point-steps per bench step")
 
     extra = q.QHD_OPT_MFMA_DFT if args.mfma_dft else 0
-    # the batch's small classes run resident steps beside the streaming passes of the large
-    # ones (bitwise the same results); the plain and parity legs keep the streaming passes
-    main_flags = extra | (q.QHD_OPT_RESIDENT if args.workload == "batched2d" and not args.streaming_only else 0)
+    # by default every class streams, so that the sampled pass durations (the roofline) are
+    # not stretched by resident workgroups holding CUs; the mixed configuration is timed
+    # on its own below
+    main_flags = extra | (q.QHD_OPT_RESIDENT if args.workload == "batched2d" and args.resident_classes else 0)
     plan = build_plan(specs, q, flags=q.QHD_OPT_TIME_PASSES | q.QHD_OPT_AUTOTUNE | main_flags,
                       timing_stride=args.timing_stride, tune_cache=args.tune_cache, qaa=qaa)
     tuned = plan.graph_info()["classes"]
@@ -485,6 +486,18 @@ def main():
     # ---- batched2d: resident steps (psi held in LDS) against streaming passes ---------
     resident = None
     if args.workload == "batched2d" and not args.no_qaa_summary and not args.no_resident:
+        # the benchmark batch itself with its 128^2 class resident, beside the streaming
+        # passes of the 256^2 / 512^2 classes (bitwise the same results)
+        mixed = None
+        if not args.resident_classes:
+            pm = build_plan(specs, q, flags=q.QHD_OPT_AUTOTUNE | extra | q.QHD_OPT_RESIDENT,
+                            tune_cache=args.tune_cache)
+            upload(pm, specs, "mixed")
+            el_m, res_m, _ = timed_runs(pm, 1, 1, stream, "mixed-resident")
+            pm.close()
+            mixed = {"gp_steps_per_s": round(total_gp / el_m, 1), "vs_all_streaming": round(total_gp / el_m / value, 3),
+                     "max_norm_drift": max(abs(r["norm"] - 1.0) for r in res_m)}
+            log(f"batch with the 128^2 class resident: {total_gp / el_m / 1e9:.2f} G gp-steps/s")
         def rate_of(rspecs, rfs, flags):
             pr = build_plan(rspecs, q, flags=flags, tune_cache=args.tune_cache)
             for k, fr in enumerate(rfs):
@@ -515,7 +528,7 @@ def main():
             log(f"resident: {count} x {n}^2: {r_r / 1e9:.1f} G vs streaming {r_s / 1e9:.1f} G gp-steps/s")
         resident = {"workload": "QHD_OPT_RESIDENT (psi in LDS for a whole evolve call, one workgroup per "
                                 "instance) vs the streaming passes, landscape recipe, T=2, dt=1e-3",
-                    "cases": rows}
+                    "cases": rows, "benchmark_batch_with_128_resident": mixed}
 
     # ---- plain: the single-instance solver on the same GPU ---------------------------
     plain = None
@@ -685,7 +698,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"batched-{len(specs)}: 2-D instances, n in {sizes}^2 (uniform), "
                                 f"T~U[5,20], dt=1e-3, Nesterov schedule, 8-24 cosine-term landscapes"
-                                + ("" if args.streaming_only else "; 128^2 class with resident steps")
+                                + ("; 128^2 class with resident steps" if args.resident_classes else "")
                                 if args.workload == "batched2d" else
                                 f"baseline QAA: {len(specs)} 2-D instances, n in {sizes}^2 (radix-2 qubits, "
                                 f"H0 = -sum sigma_x), T=10, dt=1e-3, linear schedule, 8-24 cosine-term landscapes"

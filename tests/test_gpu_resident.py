@@ -176,3 +176,40 @@ def test_leapfrog_classes_stay_streaming():
     specs = [_qaa((64, 64), 100, 5e-3, q.QHD_SCHEME_LEAPFROG), _qaa((128, 128), 100, 1e-2)]
     cls = {tuple(c["n"][:2]): c["resident"] for c in _classes(specs, q.QHD_OPT_RESIDENT)}
     assert cls[(64, 64)] is False and cls[(128, 128)] is True
+
+
+def test_user_graph_capture_with_resident_and_streaming_classes():
+    """qhd_evolve captured into the caller's graph (the resident launches fork to their
+    own streams inside the capture and join back): every replay, with eager readouts and
+    synchronisations between replays, equals the eager run bitwise."""
+    import torch
+    note("case: evolve(40) captured in a torch CUDA graph, replayed 3 times; resident + streaming classes")
+    shapes = [(128, 128), (64, 64), (256, 256)]
+    specs = [q.InstanceSpec(shape=sh, nsteps=200, dt=1e-3) for sh in shapes]
+    fs = _landscapes(shapes, 820)
+    eager = q.Plan(specs, flags=q.QHD_OPT_RESIDENT)
+    cap = q.Plan(specs, flags=q.QHD_OPT_RESIDENT)
+    try:
+        for i, f in enumerate(fs):
+            eager.set_potential(i, f)
+            cap.set_potential(i, f)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            cap.evolve(40, stream=side)
+        torch.cuda.synchronize()
+        for r in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            eager.evolve(40)
+            _, pe, _, st_e = eager.observe(want_psi=True)
+            _, pc, _, st_c = cap.observe(want_psi=True)
+            torch.cuda.synchronize()
+            assert st_e == q.QHD_OK and st_c == q.QHD_OK
+            for i in range(len(specs)):
+                assert torch.equal(eager.psi_of(pe, i), cap.psi_of(pc, i)), (r, i)
+        del g
+    finally:
+        eager.close()
+        cap.close()
