@@ -146,7 +146,25 @@ def timed_runs(plan, steps, warmup, stream, label):
     return time.perf_counter() - t0, last[0], last[1]
 
 
-RQP_BYTES_PER_POINT_STEP = lambda d: 16.0 * d + 8.0  # d axis passes (read + write c64) + f once
+RQP_FUSED_POINTS = 6561  # the library's LDS run of the fused leading-axes pass
+
+
+def rqp_fused_axes(d, np_):
+    """Leading axes the library applies in one LDS pass: the largest K <= d with
+    np_^K <= RQP_FUSED_POINTS."""
+    k, chunk = 0, np_
+    while k < d and chunk <= RQP_FUSED_POINTS:
+        k, chunk = k + 1, chunk * np_
+    return k
+
+
+def RQP_BYTES_PER_POINT_STEP(d, np_):
+    """HBM bytes per lattice point and step: the fused pass reads f once and reads and
+    writes the state (24 B), every other axis pass reads and writes it (16 B)."""
+    return 16.0 * (d - rqp_fused_axes(d, np_)) + 24.0
+
+
+FP64_PEAK_TFLOPS = 78.6
 
 
 def rqp_run(q, probs, r, dt, nsteps, steps, warmup, stream, label):
@@ -180,15 +198,23 @@ def rqp_run(q, probs, r, dt, nsteps, steps, warmup, stream, label):
 
 def rqp_summary(secs, res, points, probs, nsteps, r):
     import numpy as np
-    d = len(probs[0][1])
+    d, np_ = len(probs[0][1]), r + 1
     gp = float(points) * len(probs) * nsteps
     rate = gp / secs
-    achieved = rate * RQP_BYTES_PER_POINT_STEP(d) / 1e9
+    bpp = RQP_BYTES_PER_POINT_STEP(d, np_)
+    achieved = rate * bpp / 1e9
+    flops = 8.0 * np_ * d  # every axis: np_ complex multiply-adds per point in FP64
+    k = rqp_fused_axes(d, np_)
     return {"gp_steps_per_s": round(rate, 1), "grid_point_steps": gp,
-            "roofline": {"bound": "hbm", "kernel": f"relaxed-QP step ({d} axis passes, r+1={r + 1})",
+            "roofline": {"bound": "hbm",
+                         "kernel": f"relaxed-QP step (axes 1-{k} fused in one LDS pass, {d - k} more axis "
+                                   f"passes, r+1={np_})",
                          "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                         "algorithmic_bytes_per_point": RQP_BYTES_PER_POINT_STEP(d),
+                         "algorithmic_bytes_per_point": bpp,
+                         "fp64_flop_per_point": flops,
+                         "fp64_achieved_tflops": round(rate * flops / 1e12, 2),
+                         "fp64_frac": round(rate * flops / 1e12 / FP64_PEAK_TFLOPS, 4),
                          "mean_step_us": round(secs / nsteps * 1e6, 2)},
             "max_norm_drift": max(abs(x["norm"] - 1.0) for x in res),
             "mean_p_min": round(float(np.mean([x["p_min"] for x in res])), 4),

@@ -78,7 +78,10 @@ qhd_status qhd_rqp_set_objective(qhd_rqp h, int32_t i, const double *Q, const do
 
 /* Advance every instance by min(max_steps, remaining) steps (max_steps < 0: to the
  * end).  Asynchronous on `stream`; allocates nothing.  QHD_ESTATE if an objective is
- * missing. */
+ * missing.  The leading axes whose (r+1)^K points fit 6561 run as one pass through
+ * LDS (the 9^5 lattice: axes 1-4 fused, axis 5 alone), with the values of K separate
+ * passes; the environment variable QHD_RQP_UNFUSED=1, read at creation, keeps one pass
+ * per axis. */
 qhd_status qhd_rqp_evolve(qhd_rqp h, int64_t max_steps, void *stream);
 
 /* Readouts of every instance into host `out` (batch entries); optional device outputs:

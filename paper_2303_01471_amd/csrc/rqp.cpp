@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -32,6 +33,7 @@ struct qhd_rqp_s {
   double* Qb = nullptr;     // per instance [Q (d x d), b (d)]
   double* U = nullptr;      // eigenvectors of A' (columns), row-major NP x NP
   double* lam = nullptr;    // eigenvalues of A'
+  double2* M = nullptr;     // kinetic factor of one axis for the current step (NP x NP)
   double* amp = nullptr;    // discrete Gaussian amplitudes of one axis
   double* fmin = nullptr;
   long long* amin = nullptr;
@@ -42,6 +44,7 @@ struct qhd_rqp_s {
   std::vector<char> has_obj;
   long long steps_done = 0;
   bool pending = false;     // the trailing potential half step of the last step is owed
+  int fused_axes = 0;       // axes 1..K run as one LDS pass (0: every axis its own pass)
 };
 
 namespace {
@@ -141,7 +144,7 @@ void schedule(const qhd_rqp_s* h, long long j, double& a, double& b) {
 void release(qhd_rqp h) {
   if (!h) return;
   (void)hipSetDevice(h->device);
-  for (void* p : {(void*)h->psi, (void*)h->f, (void*)h->Qb, (void*)h->U, (void*)h->lam, (void*)h->amp,
+  for (void* p : {(void*)h->psi, (void*)h->f, (void*)h->Qb, (void*)h->U, (void*)h->lam, (void*)h->M, (void*)h->amp,
                   (void*)h->fmin, (void*)h->amin, (void*)h->sums})
     if (p) (void)hipFree(p);
   if (h->host_sums) (void)hipHostFree(h->host_sums);
@@ -200,6 +203,13 @@ qhd_status qhd_rqp_create(const qhd_rqp_desc* desc, int32_t batch, qhd_rqp* out)
   h->NP = desc->r + 1;
   h->N = 1;
   for (int k = 0; k < desc->dim; ++k) h->N *= h->NP;
+  // the most leading axes whose chunk fits the fused pass's LDS run (QHD_RQP_UNFUSED=1:
+  // one pass per axis, the reference form of the same arithmetic)
+  const char* unfused = std::getenv("QHD_RQP_UNFUSED");
+  if (!(unfused && std::strcmp(unfused, "1") == 0)) {
+    long long chunk = h->NP;
+    for (int k = 1; k <= desc->dim && chunk <= kFusedPoints; ++k, chunk *= h->NP) h->fused_axes = k;
+  }
   h->fmin_h.assign(batch, 0.0);
   h->amin_h.assign(batch, 0);
   h->has_obj.assign(batch, 0);
@@ -211,6 +221,7 @@ qhd_status qhd_rqp_create(const qhd_rqp_desc* desc, int32_t batch, qhd_rqp* out)
   if (e == hipSuccess) e = hipMalloc(&h->Qb, sizeof(double) * (size_t)batch * (d * d + d));
   if (e == hipSuccess) e = hipMalloc(&h->U, sizeof(double) * NP * NP);
   if (e == hipSuccess) e = hipMalloc(&h->lam, sizeof(double) * NP);
+  if (e == hipSuccess) e = hipMalloc(&h->M, sizeof(double2) * NP * NP);
   if (e == hipSuccess) e = hipMalloc(&h->amp, sizeof(double) * NP);
   if (e == hipSuccess) e = hipMalloc(&h->fmin, sizeof(double) * batch);
   if (e == hipSuccess) e = hipMalloc(&h->amin, sizeof(long long) * batch);
@@ -292,9 +303,16 @@ qhd_status qhd_rqp_evolve(qhd_rqp h, int64_t max_steps, void* stream_v) {
     }
     const double theta = 0.5 * d.dt * a * r2;
     long long stride = 1;
-    for (int k = 0; k < d.dim; ++k) {
-      RQP_TRY(rqp_axis_pass(h->NP, h->psi, h->f, total, (int)stride, h->U, h->lam, theta, k == 0,
-                            beta * 0.15915494309189533577, st));
+    int k = 0;
+    RQP_TRY(rqp_matrix(h->NP, h->U, h->lam, theta, h->M, st));
+    if (h->fused_axes > 0) {
+      // axes 1..K in one pass through LDS, the rest one pass each
+      RQP_TRY(rqp_fused_pass(h->NP, h->psi, h->f, total, h->fused_axes, h->M, beta * 0.15915494309189533577, st));
+      for (; k < h->fused_axes; ++k) stride *= h->NP;
+    }
+    for (; k < d.dim; ++k) {
+      RQP_TRY(rqp_axis_pass(h->NP, h->psi, h->f, total, (int)stride, h->M, k == 0, beta * 0.15915494309189533577,
+                            st));
       stride *= h->NP;
     }
   }

@@ -8,8 +8,10 @@
 // the exact kinetic factor exp(+i theta A') of one axis (A' = U diag(lambda) U^T);
 // the factors of different axes commute, so their product is the kinetic factor of
 // A'_d.  The first pass also applies the potential factor exp(-i beta f) (the merged
-// half steps) to each point before its line is transformed.  Every block forms M in
-// FP64 in LDS from U and lambda; lines accumulate in FP64 and round once on store.
+// half steps) to each point before its line is transformed.  M is formed in FP64 once
+// per step by a one-block kernel into a small global buffer; the passes read it with
+// wave-uniform (scalar) loads, so the matrix costs no LDS or VGPR bandwidth, and lines
+// accumulate in FP64 and round once on store.
 //
 // Lines of stride s < 64 (axes 1, 2 and, for small NP, a few more) are staged through
 // LDS so that global accesses are contiguous; lines of stride >= 64 are read directly
@@ -28,10 +30,11 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// M[m][n] = sum_k U[m][k] e^{i theta lam_k} U[n][k] into LDS (all threads call)
+// M[m][n] = sum_k U[m][k] e^{i theta lam_k} U[n][k] into global memory (one block)
 template <int NP>
-__device__ __forceinline__ void form_matrix(const double* __restrict__ U, const double* __restrict__ lam,
-                                            double theta, double2* Ml, double2* ph) {
+__global__ void __launch_bounds__(kThreads) k_rqp_matrix(const double* __restrict__ U, const double* __restrict__ lam,
+                                                        double theta, double2* __restrict__ M) {
+  __shared__ double2 ph[NP];
   if (threadIdx.x < NP) {
     double s, c;
     sincos(theta * lam[threadIdx.x], &s, &c);
@@ -47,20 +50,30 @@ __device__ __forceinline__ void form_matrix(const double* __restrict__ U, const 
       re = fma(w, ph[k].x, re);
       im = fma(w, ph[k].y, im);
     }
-    Ml[e] = make_double2(re, im);
+    M[e] = make_double2(re, im);
   }
-  __syncthreads();
 }
 
-// y = M x for one line, FP64
+// A wave-uniform zero the compiler cannot see through (no memory access).  Offsetting
+// the matrix by it once per line keeps the matrix reads (scalar loads, the same entry for
+// every lane) inside the line loops: hoisted out of them, the NP^2 FP64 complex entries
+// would sit in vector registers (~400 VGPRs and 140 AGPRs at NP = 9, one wave per SIMD).
+__device__ __forceinline__ int opaque_zero() {
+  int z;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+  return z;
+}
+
+// y = M x for one line, FP64; M in global memory, read wave-uniformly
 template <int NP>
-__device__ __forceinline__ void line_apply(const double2* Ml, const double2 (&x)[NP], double2 (&y)[NP]) {
+__device__ __forceinline__ void line_apply(const double2* __restrict__ Mg, const double2 (&x)[NP], double2 (&y)[NP]) {
+  const double2* __restrict__ M = Mg + opaque_zero();
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
     double re = 0.0, im = 0.0;
 #pragma unroll
     for (int n = 0; n < NP; ++n) {
-      const double2 w = Ml[m * NP + n];
+      const double2 w = M[m * NP + n];
       re = fma(w.x, x[n].x, fma(-w.y, x[n].y, re));
       im = fma(w.x, x[n].y, fma(w.y, x[n].x, im));
     }
@@ -73,13 +86,8 @@ __device__ __forceinline__ void line_apply(const double2* Ml, const double2 (&x)
 template <int NP, bool FUSE_V>
 __global__ void __launch_bounds__(kThreads) k_rqp_axis_staged(float2* __restrict__ psi, const double* __restrict__ f,
                                                              long long total_points, int s, int LB,
-                                                             const double* __restrict__ U,
-                                                             const double* __restrict__ lam, double theta,
-                                                             double beta_turns) {
-  __shared__ double2 Ml[NP * NP];
-  __shared__ double2 ph[NP];
+                                                             const double2* __restrict__ Ml, double beta_turns) {
   __shared__ float2 seg[kThreads * NP];
-  form_matrix<NP>(U, lam, theta, Ml, ph);
   const long long p0 = (long long)blockIdx.x * LB * NP;
   const int npts = (int)((total_points - p0 < (long long)LB * NP) ? total_points - p0 : (long long)LB * NP);
   for (int e = threadIdx.x; e < npts; e += kThreads) {
@@ -104,14 +112,49 @@ __global__ void __launch_bounds__(kThreads) k_rqp_axis_staged(float2* __restrict
   for (int e = threadIdx.x; e < npts; e += kThreads) psi[p0 + e] = seg[e];
 }
 
+// Fused pass: axes 1..K at once.  A chunk is the NP^K contiguous points that share the
+// indices of axes K+1..d; a block holds a run of whole chunks in LDS (at most
+// kFusedPoints points), applies the potential factor on load, then the matrix along
+// axis 1, 2, ..., K with a barrier between axes, and stores once.  Each axis rounds to
+// FP32 on its LDS store exactly as a separate pass rounds on its HBM store, so the
+// values are those of K separate passes, for 16 B of HBM traffic per point instead of
+// 16 K.  (9^4 points: 52.5 KB, three blocks per CU.)
+template <int NP>
+__global__ void __launch_bounds__(kThreads) k_rqp_fused(float2* __restrict__ psi, const double* __restrict__ f,
+                                                       long long total_points, int K, int run,
+                                                       const double2* __restrict__ Ml, double beta_turns) {
+  __shared__ float2 seg[kFusedPoints];
+  for (long long p0 = (long long)blockIdx.x * run; p0 < total_points; p0 += (long long)gridDim.x * run) {
+    // total_points and run are whole numbers of chunks, so every run holds whole lines
+    const int npts = (int)((total_points - p0 < (long long)run) ? total_points - p0 : (long long)run);
+    for (int e = threadIdx.x; e < npts; e += kThreads)
+      seg[e] = cmul_fd(psi[p0 + e], phase_turns_d(beta_turns * f[p0 + e]));
+    __syncthreads();
+    const int lines = npts / NP;
+    int s = 1;
+    for (int k = 0; k < K; ++k) {
+      for (int line = threadIdx.x; line < lines; line += kThreads) {
+        const int outer = line / s, inner = line - outer * s;
+        const int base = outer * s * NP + inner;
+        double2 x[NP], y[NP];
+#pragma unroll
+        for (int m = 0; m < NP; ++m) assign(x[m], seg[base + m * s]);
+        line_apply<NP>(Ml, x, y);
+#pragma unroll
+        for (int m = 0; m < NP; ++m) assign(seg[base + m * s], y[m]);
+      }
+      __syncthreads();
+      s *= NP;
+    }
+    for (int e = threadIdx.x; e < npts; e += kThreads) psi[p0 + e] = seg[e];
+    __syncthreads();  // the next run reuses the LDS
+  }
+}
+
 // Direct pass for strides >= 64: thread = line.
 template <int NP>
 __global__ void __launch_bounds__(kThreads) k_rqp_axis_direct(float2* __restrict__ psi, long long total_lines, int s,
-                                                             const double* __restrict__ U,
-                                                             const double* __restrict__ lam, double theta) {
-  __shared__ double2 Ml[NP * NP];
-  __shared__ double2 ph[NP];
-  form_matrix<NP>(U, lam, theta, Ml, ph);
+                                                             const double2* __restrict__ Ml) {
   for (long long L = (long long)blockIdx.x * kThreads + threadIdx.x; L < total_lines;
        L += (long long)gridDim.x * kThreads) {
     const long long outer = L / s, inner = L - outer * s;
@@ -265,26 +308,39 @@ __global__ void __launch_bounds__(kThreads) k_rqp_marginals(const float2* __rest
 }
 
 template <int NP>
-hipError_t axis_pass_np(float2* psi, const double* f, long long total_points, int s, const double* U,
-                        const double* lam, double theta, bool fuse_v, double beta_turns, hipStream_t st) {
+hipError_t axis_pass_np(float2* psi, const double* f, long long total_points, int s, const double2* M, bool fuse_v,
+                        double beta_turns, hipStream_t st) {
   if (s < 64) {
     const int LB = (kThreads / s) * s;
     const long long lines = total_points / NP;
     const unsigned blocks = (unsigned)((lines + LB - 1) / LB);
     if (fuse_v)
       hipLaunchKernelGGL((k_rqp_axis_staged<NP, true>), dim3(blocks), dim3(kThreads), 0, st, psi, f, total_points, s,
-                         LB, U, lam, theta, beta_turns);
+                         LB, M, beta_turns);
     else
       hipLaunchKernelGGL((k_rqp_axis_staged<NP, false>), dim3(blocks), dim3(kThreads), 0, st, psi, f, total_points,
-                         s, LB, U, lam, theta, beta_turns);
+                         s, LB, M, beta_turns);
   } else {
     if (fuse_v) return hipErrorInvalidValue;  // the potential is fused into the axis-1 pass only
     const long long lines = total_points / NP;
     long long b = (lines + kThreads - 1) / kThreads;
     if (b > 65536) b = 65536;
-    hipLaunchKernelGGL((k_rqp_axis_direct<NP>), dim3((unsigned)b), dim3(kThreads), 0, st, psi, lines, s, U, lam,
-                       theta);
+    hipLaunchKernelGGL((k_rqp_axis_direct<NP>), dim3((unsigned)b), dim3(kThreads), 0, st, psi, lines, s, M);
   }
+  return hipGetLastError();
+}
+
+template <int NP>
+hipError_t fused_np(float2* psi, const double* f, long long total_points, int K, const double2* M, double beta_turns,
+                    hipStream_t st) {
+  long long chunk = 1;
+  for (int k = 0; k < K; ++k) chunk *= NP;
+  if (K < 1 || chunk > kFusedPoints || total_points % chunk != 0) return hipErrorInvalidValue;
+  const int run = (int)((kFusedPoints / chunk) * chunk);
+  long long blocks = (total_points + run - 1) / run;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL((k_rqp_fused<NP>), dim3((unsigned)blocks), dim3(kThreads), 0, st, psi, f, total_points, K, run,
+                     M, beta_turns);
   return hipGetLastError();
 }
 
@@ -298,13 +354,38 @@ hipError_t marginals_np(const float2* psi, long long N, int d, int batch, float*
 
 #define QHD_RQP_NP_CASES(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
-hipError_t rqp_axis_pass(int NP, float2* psi, const double* f, long long total_points, int stride,
-                         const double* U, const double* lam, double theta, bool fuse_v, double beta_turns,
-                         hipStream_t st) {
+hipError_t rqp_matrix(int NP, const double* U, const double* lam, double theta, double2* M, hipStream_t st) {
+  switch (NP) {
+#define QHD_RQP_CASE(n)                                                                        \
+  case n:                                                                                      \
+    hipLaunchKernelGGL((k_rqp_matrix<n>), dim3(1), dim3(kThreads), 0, st, U, lam, theta, M); \
+    return hipGetLastError();
+    QHD_RQP_NP_CASES(QHD_RQP_CASE)
+#undef QHD_RQP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t rqp_axis_pass(int NP, float2* psi, const double* f, long long total_points, int stride, const double2* M,
+                         bool fuse_v, double beta_turns, hipStream_t st) {
   switch (NP) {
 #define QHD_RQP_CASE(n) \
   case n:               \
-    return axis_pass_np<n>(psi, f, total_points, stride, U, lam, theta, fuse_v, beta_turns, st);
+    return axis_pass_np<n>(psi, f, total_points, stride, M, fuse_v, beta_turns, st);
+    QHD_RQP_NP_CASES(QHD_RQP_CASE)
+#undef QHD_RQP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t rqp_fused_pass(int NP, float2* psi, const double* f, long long total_points, int K, const double2* M,
+                          double beta_turns, hipStream_t st) {
+  switch (NP) {
+#define QHD_RQP_CASE(n) \
+  case n:               \
+    return fused_np<n>(psi, f, total_points, K, M, beta_turns, st);
     QHD_RQP_NP_CASES(QHD_RQP_CASE)
 #undef QHD_RQP_CASE
     default:

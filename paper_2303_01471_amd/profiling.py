@@ -25,7 +25,7 @@ import sys
 
 
 def _short(name: str) -> str:
-    n = name.split("(")[0]
+    n = name.replace("(anonymous namespace)::", "").split("(")[0]
     for pre in ("void ", "qhd::"):
         n = n.replace(pre, "")
     return n.strip()

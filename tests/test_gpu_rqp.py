@@ -130,3 +130,20 @@ def test_norm_drift_over_two_thousand_steps():
     drift = max(abs(r["norm"] - 1.0) for r in res)
     note(f"  relaxed QHD 9^5, 2000 steps: max |norm - 1| = {drift:.2e}")
     assert drift <= 1e-5
+
+
+def test_fused_leading_axes_equal_one_pass_per_axis(monkeypatch):
+    """The leading axes whose lattice fits one LDS run are applied in one pass; each axis
+    rounds to FP32 on its LDS store as a separate pass does on its HBM store, so the
+    states are bitwise equal (9^5: axes 1-4 fused; 16^3 and 2^8: every axis fused)."""
+    cases = [(5, 8, qhd_inputs.qp_instances(4, 5, 15), 1e-2, 120),
+             (3, 15, qhd_inputs.qp_instances(2, 3, 16), 5e-3, 60),
+             (8, 1, qhd_inputs.qp_instances(2, 8, 17), 2e-2, 60),
+             (2, 9, qhd_inputs.qp_instances(3, 2, 18), 1e-2, 50)]
+    for dim, r, probs, dt, n in cases:
+        monkeypatch.delenv("QHD_RQP_UNFUSED", raising=False)
+        _, _, fused, _ = _run(dim, r, probs, dt, n, chunks=[7])
+        monkeypatch.setenv("QHD_RQP_UNFUSED", "1")
+        _, _, sep, _ = _run(dim, r, probs, dt, n, chunks=[7])
+        note(f"  d={dim} r={r}: fused vs per-axis max|drho| = {float(np.max(np.abs(fused - sep))):.2e}")
+        assert np.array_equal(fused, sep)

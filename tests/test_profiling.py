@@ -13,6 +13,8 @@ def test_families_of_the_pass_kernels():
     assert f("k_col_pass_tw<256, 8, true>") == ("col_pass_2d/n256", 16.0)
     assert f("k_lf_row_2d<64, 8>") == ("row_pass_2d_qaa_lf/n64", 20.0)
     assert f("k_argmin") is None
+    assert profiling._short("void qhd::(anonymous namespace)::k_rqp_fused<9>(HIP_vector_type<float, 2u>*, "
+                            "double const*)") == "k_rqp_fused<9>"
 
 
 def _db(path, rows):
