@@ -145,7 +145,12 @@ typedef struct {
                                     at the start and the end of the call (the scope's
                                     resident mode of the two-pass step, App. C.2.1).
                                     Same arithmetic as the streaming passes with 8
-                                    points per lane.  Leapfrog QAA and other shapes
+                                    points per lane.  With QHD_OPT_AUTOTUNE as well,
+                                    each such class keeps resident steps only if 16 of
+                                    them beat 16 streaming steps on its own batch (one
+                                    CU per 128^2 instance loses against the whole GPU
+                                    for a lone instance); the choice is kept in the
+                                    tuning cache.  Leapfrog QAA and other shapes
                                     unaffected                                          */
 
 typedef struct qhd_plan_s *qhd_plan;

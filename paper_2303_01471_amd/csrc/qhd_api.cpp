@@ -488,6 +488,71 @@ qhd_status autotune_class(qhd_plan p, ShapeClass& c, double& us_row, double& us_
   return QHD_OK;
 }
 
+// Tuning-cache lines of the resident-or-streaming choice: "qhd-resident 1 <arch> <nx> <ny>
+// <members_pow2> <model> <1 resident | 0 streaming>"
+std::string resident_key(const std::string& arch, const ShapeClass& c) {
+  int m = 1;
+  while (m < (int)c.members.size()) m <<= 1;
+  char buf[160];
+  snprintf(buf, sizeof buf, "qhd-resident 1 %s %d %d %d %d", arch.c_str(), c.nx, c.ny, m, c.model);
+  return buf;
+}
+
+int resident_lookup(const std::string& path, const std::string& key) {
+  FILE* fh = fopen(path.c_str(), "r");
+  if (!fh) return -1;
+  char line[256];
+  int dec = -1;
+  while (fgets(line, sizeof line, fh)) {
+    const size_t k = key.size();
+    if (strncmp(line, key.c_str(), k) != 0 || line[k] != ' ') continue;
+    int v = -1;
+    if (sscanf(line + k, "%d", &v) == 1 && (v == 0 || v == 1)) dec = v;  // the last matching line wins
+  }
+  fclose(fh);
+  return dec;
+}
+
+void resident_append(const std::string& path, const std::string& key, int dec, double us_res, double us_str) {
+  FILE* fh = fopen(path.c_str(), "a");
+  if (!fh) return;
+  fprintf(fh, "%s %d  # 16 steps: resident %.2f us, streaming %.2f us\n", key.c_str(), dec, us_res, us_str);
+  fclose(fh);
+}
+
+// Time 16 steps of the class (every member) as one resident launch and as streaming
+// passes with the class's launch configuration.  The state is overwritten; the caller
+// restores it.
+qhd_status compare_resident(qhd_plan p, ShapeClass& c, double& us_res, double& us_str) {
+  const int m = (int)c.members.size();
+  const int k = 16;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(QHD_EDEVICE, "hipEventCreate failed");
+  }
+  us_res = time_launches(p->internal, a, b, 2, [&] {
+    return launch_resident_2d(c.nx, c.ny, c.dev, m, c.psi, c.f, c.tw_x, c.tw_y, k, c.model, c.y4, p->internal);
+  });
+  us_str = time_launches(p->internal, a, b, 2, [&] {
+    hipError_t r = hipSuccess;
+    for (int s = 0; s < k && r == hipSuccess; ++s) {
+      r = launch_row_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.f, c.tw_x, s, k, c.cap_row, c.row_points, p->internal,
+                             c.model, c.y4);
+      if (r == hipSuccess)
+        r = launch_col_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.tw_y, s, k, c.cap_col, c.col_variant, p->internal,
+                               c.model, c.y4);
+    }
+    return r;
+  });
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (us_res < 0 || us_str < 0)
+    return fail(QHD_EDEVICE, "resident comparison launch failed: %s", hipGetErrorString(hipGetLastError()));
+  return QHD_OK;
+}
+
 // Capture k steps (k * sps stages) of every class (all members active) plus the commit;
 // every instance takes sps stages per step.
 qhd_status build_step_graph(qhd_plan p, int k, int sps) {
@@ -743,12 +808,14 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       c.fam_y = family_index(p, name, 16.0);
       snprintf(name, sizeof name, "zpass_3d/n%d", c.nz);
       c.fam_z = family_index(p, name, 16.0);
-    } else if (c.ndim == 2 && (p->opts.flags & QHD_OPT_RESIDENT) && !c.leapfrog && resident_supported(c.nx, c.ny)) {
-      // psi stays in LDS; per grid-point step only f (8 B, FP64) is read, from the caches
-      c.resident = true;
-      snprintf(name, sizeof name, "resident_2d%s/n%d", c.model == kModelQAA ? "_qaa" : "", c.nx);
-      c.fam_res = family_index(p, name, 8.0);
     } else if (c.ndim == 2) {
+      if ((p->opts.flags & QHD_OPT_RESIDENT) && !c.leapfrog && resident_supported(c.nx, c.ny)) {
+        // psi stays in LDS; per grid-point step only f (8 B, FP64) is read, from the caches.
+        // The streaming families below are kept too: the autotuner may choose them.
+        c.resident = true;
+        snprintf(name, sizeof name, "resident_2d%s/n%d", c.model == kModelQAA ? "_qaa" : "", c.nx);
+        c.fam_res = family_index(p, name, 8.0);
+      }
       // leapfrog stages: the row pass reads psi and f and writes the partial H v (4 B),
       // the column pass reads psi and it and writes psi
       const char* tag = c.leapfrog ? "_qaa_lf" : (c.model == kModelQAA ? "_qaa" : "");
@@ -795,23 +862,40 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
     for (auto& c : arch) if (c == ' ' || c == ':') c = '_';
     bool refill = false;
     const bool env_cap = std::getenv("QHD_GRID_CAP") != nullptr;
+    const bool autotune = (p->opts.flags & QHD_OPT_AUTOTUNE) != 0;
     for (auto& c : p->classes) {
       c.cap_row = c.cap_col = p->grid_cap;
       if (c.ndim != 2) continue;
-      if (c.model == kModelQAA || c.resident) continue;  // one fixed launch form each
-      if (!env_cap) {
-        // measured defaults (uniform batches of 256 instances per size on MI355X)
-        c.cap_row = c.nx >= 512 ? 8192 : (c.nx >= 256 ? 4096 : 1024);
-        c.cap_col = c.ny >= 512 ? 4096 : (c.ny >= 256 ? 2048 : 1024);
+      if (c.model != kModelQAA) {  // QAA passes have one fixed launch form
+        if (!env_cap) {
+          // measured defaults (uniform batches of 256 instances per size on MI355X)
+          c.cap_row = c.nx >= 512 ? 8192 : (c.nx >= 256 ? 4096 : 1024);
+          c.cap_col = c.ny >= 512 ? 4096 : (c.ny >= 256 ? 2048 : 1024);
+        }
+        const std::string key = tune_key(arch, c);
+        const bool cached = !p->tune_cache.empty() && tune_lookup(p->tune_cache, key, c);
+        if (!cached && autotune) {
+          double us_row = 0.0, us_col = 0.0;
+          qhd_status st = autotune_class(p, c, us_row, us_col);
+          if (st != QHD_OK) return bail(st);
+          refill = true;
+          if (!p->tune_cache.empty()) tune_append(p->tune_cache, key, c, us_row, us_col);
+        }
       }
-      const std::string key = tune_key(arch, c);
-      if (!p->tune_cache.empty() && tune_lookup(p->tune_cache, key, c)) continue;
-      if (!(p->opts.flags & QHD_OPT_AUTOTUNE)) continue;
-      double us_row = 0.0, us_col = 0.0;
-      qhd_status st = autotune_class(p, c, us_row, us_col);
-      if (st != QHD_OK) return bail(st);
-      refill = true;
-      if (!p->tune_cache.empty()) tune_append(p->tune_cache, key, c, us_row, us_col);
+      if (c.resident && autotune) {
+        // resident or streaming, whichever runs this class faster (or the cached choice)
+        const std::string rkey = resident_key(arch, c);
+        int dec = p->tune_cache.empty() ? -1 : resident_lookup(p->tune_cache, rkey);
+        if (dec < 0) {
+          double us_res = 0.0, us_str = 0.0;
+          qhd_status st = compare_resident(p, c, us_res, us_str);
+          if (st != QHD_OK) return bail(st);
+          refill = true;
+          dec = us_res <= us_str ? 1 : 0;
+          if (!p->tune_cache.empty()) resident_append(p->tune_cache, rkey, dec, us_res, us_str);
+        }
+        c.resident = dec == 1;
+      }
     }
     if (refill) {
       for (auto& c : p->classes) {

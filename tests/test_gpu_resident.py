@@ -213,3 +213,32 @@ def test_user_graph_capture_with_resident_and_streaming_classes():
     finally:
         eager.close()
         cap.close()
+
+
+def test_autotune_keeps_resident_only_where_faster(tmp_path):
+    """QHD_OPT_RESIDENT | QHD_OPT_AUTOTUNE: a lone 128^2 instance (one CU against the
+    whole GPU) streams, 512 instances of 64^2 stay resident; the choices are cached and
+    a second plan reads them without timing; the values are those of the streaming run."""
+    cache = str(tmp_path / "tune.txt")
+    flags = q.QHD_OPT_RESIDENT | q.QHD_OPT_AUTOTUNE
+    single = [q.InstanceSpec(shape=(128, 128), nsteps=120, dt=1e-3)]
+    many = [q.InstanceSpec(shape=(64, 64), nsteps=60, dt=1e-3) for _ in range(512)]
+
+    def resident_of(specs):
+        plan = q.Plan(specs, flags=flags, tune_cache=cache)
+        try:
+            return plan.graph_info()["classes"][0]["resident"]
+        finally:
+            plan.close()
+
+    assert resident_of(single) is False
+    assert resident_of(many) is True
+    lines = [ln for ln in open(cache) if ln.startswith("qhd-resident")]
+    note("  " + "  ".join(lines).strip())
+    assert len(lines) == 2
+    assert resident_of(single) is False and resident_of(many) is True
+    assert len([ln for ln in open(cache) if ln.startswith("qhd-resident")]) == 2
+    f = _landscapes([(128, 128)], 840)
+    _, a, _, _ = run_gpu(single, f, flags=flags)
+    _, b, _, _ = run_gpu(single, f)
+    assert np.array_equal(a[0], b[0])
