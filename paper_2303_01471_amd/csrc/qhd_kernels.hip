@@ -123,14 +123,17 @@ k_row_pass_2d(const InstDev* __restrict__ inst, int ninst,
 // 2-D column pass: a tile column (8 mesh columns) is staged through LDS with
 // 512-byte tile loads; each column is then one line of TPL lanes.
 
-template <int NY, int P>
+template <int NY, int P, bool WIDE = false>  // WIDE: the staged pass's one-line-per-wave form
 struct ColCfg {
   static constexpr int TPL = NY / P;
-  static constexpr int NT = 256;                                          // threads per block
+  static constexpr bool EY_LDS = WIDE && NY == 512 && P == 8;           // one line per wave, E_y in LDS
+  static constexpr int NT = EY_LDS ? 512 : 256;                           // threads per block
   static constexpr int ITEMS = (8 * TPL >= NT) ? 1 : NT / (8 * TPL);     // tile columns per block
   // waves per SIMD the register budget must allow: the LDS of a block (line buffers,
-  // twiddle table) lets three blocks share a CU when 8 points per lane
-  static constexpr int MIN_WAVES = P == 8 ? 3 : 1;
+  // twiddle table) lets three blocks share a CU when 8 points per lane; at 512 points a
+  // block of 8 waves takes one line each and keeps E_y in LDS (100 VGPRs instead of 168),
+  // two blocks per CU: four waves per SIMD (measured 9 % faster than three blocks of 4)
+  static constexpr int MIN_WAVES = EY_LDS ? 4 : (P == 8 ? 3 : 1);
   static constexpr int LINES = ITEMS * 8;                                 // columns per block
   static constexpr int SUBS = (LINES * TPL) / NT;                         // column rounds per item
   // line stride in LDS slots, = 2 (mod 16) so the tile scatter hits distinct banks
@@ -138,13 +141,14 @@ struct ColCfg {
 };
 
 template <int NY, int P, int MODEL = kModelQHD, bool Y4 = true>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColCfg<NY, P>::MIN_WAVES))) k_col_pass_2d(
+__global__ void __launch_bounds__((ColCfg<NY, P, true>::NT)) __attribute__((amdgpu_waves_per_eu(ColCfg<NY, P, true>::MIN_WAVES))) k_col_pass_2d(
     const InstDev* __restrict__ inst, int ninst, int nx_log2, float2* __restrict__ psi,
     const double2* __restrict__ twtab, int s, long long max_steps) {
-  using C = ColCfg<NY, P>;
+  using C = ColCfg<NY, P, true>;
   constexpr int TPL = C::TPL, ITEMS = C::ITEMS, NT = C::NT, STRIDE = C::STRIDE, SUBS = C::SUBS;
   constexpr int TILES = NY / 8;
   __shared__ float2 lds[C::LINES * STRIDE];
+  __shared__ double2 eyl[C::EY_LDS ? NY : 1];
   const int tid = threadIdx.x;
   const int line0 = tid / TPL, t = tid % TPL;  // first column of this lane group
   __shared__ double2 twl[TwLdsSize<NY, P>::value];
@@ -158,6 +162,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColCfg
   double cached = -1.0;  // E_y depends on the instance only through a_j * pi dt / L_y^2
   double2 ey[P];
   for (long long g0 = begin; g0 < end; g0 += ITEMS) {
+    if constexpr (C::EY_LDS) {
+      // the block's item is one tile column of one instance: E_y / (nx ny) for it, read
+      // after the staging barrier
+      const InstDev& I = inst[(int)(g0 >> tc_log2)];
+      double a, b;
+      sched_ab<Y4>(I, I.steps_done + s, a, b);
+      const double cy = a * (MODEL == kModelQAA ? I.dt : I.kin_turns[1]);
+      if (cy != cached) {
+        for (int k = tid; k < NY; k += NT) {
+          double arg;
+          if constexpr (MODEL == kModelQAA) {
+            arg = a * axis_turns<MODEL>(I, 1, k, NY);
+          } else {
+            const int nyf = freq(k, NY);
+            arg = cy * (double)(nyf * nyf);
+          }
+          const double2 e = phase_turns_d(arg);
+          eyl[k] = make_double2(e.x * inv_n, e.y * inv_n);
+        }
+        cached = cy;
+      }
+    }
     // stage the tile columns: each thread moves float4 = two complex values; the
     // item decode is wave-uniform
 #pragma unroll
@@ -193,7 +219,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColCfg
       double a, b;
       sched_ab<Y4>(I, I.steps_done + s, a, b);
       const double cy = a * (MODEL == kModelQAA ? I.dt : I.kin_turns[1]);
-      if (cy != cached) {
+      if (!C::EY_LDS && cy != cached) {
         // E_y / (nx ny) for this lane's slots: computed once per distinct coefficient
 #pragma unroll
         for (int q = 0; q < P; ++q) {
@@ -234,7 +260,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColCfg
         // E_x E_y and its product with psi in FP64: a factor rounded to FP32 has a
         // one-sided magnitude error where the phase is tiny (cos rounds to 1, sin does
         // not), and that error repeats every step
-        const double2 k = make_double2(fma(ex.x, ey[q].x, -ex.y * ey[q].y), fma(ex.x, ey[q].y, ex.y * ey[q].x));
+        const double2 eq = C::EY_LDS ? eyl[t + q * TPL] : ey[q];
+        const double2 k = make_double2(fma(ex.x, eq.x, -ex.y * eq.y), fma(ex.x, eq.y, ex.y * eq.x));
         kd[q] = cmul_fd(kd[q], k);
       }
       if constexpr (MODEL == kModelQAA) {
@@ -968,16 +995,16 @@ hipError_t col_pass_qhd(int nx, int ny, const InstDev* inst, int ninst, float2* 
   }
   if (v == kColStaged16) {
     if (ny == 256)
-      hipLaunchKernelGGL((k_col_pass_2d<256, 16, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<256, 16>::NT), 0, stream,
+      hipLaunchKernelGGL((k_col_pass_2d<256, 16, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<256, 16, true>::NT), 0, stream,
                          inst, ninst, ilog2(nx), psi, tw, s, max_steps);
     else
-      hipLaunchKernelGGL((k_col_pass_2d<512, 16, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<512, 16>::NT), 0, stream,
+      hipLaunchKernelGGL((k_col_pass_2d<512, 16, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<512, 16, true>::NT), 0, stream,
                          inst, ninst, ilog2(nx), psi, tw, s, max_steps);
     return hipGetLastError();
   }
   QHD_SWITCH_N(ny, {
     constexpr int P_ = pts_per_lane<N_>();
-    hipLaunchKernelGGL((k_col_pass_2d<N_, P_, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0, stream,
+    hipLaunchKernelGGL((k_col_pass_2d<N_, P_, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<N_, P_, true>::NT), 0, stream,
                        inst, ninst, ilog2(nx), psi, tw, s, max_steps);
     return hipGetLastError();
   });
@@ -990,7 +1017,7 @@ hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, fl
     const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap, kColStaged);
     QHD_SWITCH_N(ny, {
       constexpr int P_ = pts_per_lane<N_>();
-      hipLaunchKernelGGL((k_col_pass_2d<N_, P_, kModelQAA, false>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0,
+      hipLaunchKernelGGL((k_col_pass_2d<N_, P_, kModelQAA, false>), dim3(blocks), dim3(ColCfg<N_, P_, true>::NT), 0,
                          stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps);
       return hipGetLastError();
     });

@@ -242,3 +242,31 @@ def test_autotune_keeps_resident_only_where_faster(tmp_path):
     _, a, _, _ = run_gpu(single, f, flags=flags)
     _, b, _, _ = run_gpu(single, f)
     assert np.array_equal(a[0], b[0])
+
+
+def test_pass_timing_with_resident_classes():
+    """QHD_OPT_TIME_PASSES with a resident class beside a streaming one: the resident
+    launches are timed on their own streams (one sample per evolve call) and the values
+    are those of the untimed plan."""
+    import torch
+    shapes = [(128, 128), (256, 256)]
+    specs = [q.InstanceSpec(shape=sh, nsteps=90, dt=1e-3) for sh in shapes]
+    fs = _landscapes(shapes, 860)
+    _, ref, _, _ = run_gpu(specs, fs, chunks=[30], flags=q.QHD_OPT_RESIDENT)
+    plan = q.Plan(specs, flags=q.QHD_OPT_RESIDENT | q.QHD_OPT_TIME_PASSES, timing_stride=4)
+    try:
+        for i, f in enumerate(fs):
+            plan.set_potential(i, f)
+        plan.evolve(30)
+        plan.evolve()
+        _, psi, _, st = plan.observe(want_psi=True)
+        torch.cuda.synchronize()
+        kt = {t["name"]: t for t in plan.kernel_timings() if t["launches"]}
+        note("  timed families: " + ", ".join(f"{k} x{v['launches']}" for k, v in kt.items()))
+        assert st == q.QHD_OK
+        assert kt["resident_2d/n128"]["launches"] == 2 and kt["resident_2d/n128"]["total_ms"] > 0
+        assert kt["row_pass_2d/n256"]["launches"] > 0
+        for i in range(len(specs)):
+            assert np.array_equal(plan.psi_of(psi, i).cpu().numpy(), ref[i])
+    finally:
+        plan.close()
