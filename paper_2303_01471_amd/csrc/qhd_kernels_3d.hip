@@ -97,6 +97,7 @@ __global__ void __launch_bounds__((ZCfg<NZ>::NT)) k_zpass_3d(
   using C = ZCfg<NZ>;
   constexpr int P = C::P, W = C::W, STRIDE = C::STRIDE;
   __shared__ float2 lds[64 * STRIDE];
+  __shared__ double2 ezl[NZ];  // E_z(k_z) / (nx ny nz) of the current instance and step
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t = wave;
   float2* my = lds + lane * STRIDE;
@@ -110,6 +111,7 @@ __global__ void __launch_bounds__((ZCfg<NZ>::NT)) k_zpass_3d(
   const double inv_n = 1.0 / ((double)nx * (double)ny * (double)NZ);
   long long begin, end;
   block_share(total, 1, begin, end);
+  double cached = -1.0;  // the block's item is one tile of one instance: cz is block-uniform
   for (long long g = begin; g < end; ++g) {
     const int i = (int)(g >> tiles_log2);
     const int tile = (int)(g & ((1LL << tiles_log2) - 1));
@@ -123,6 +125,18 @@ __global__ void __launch_bounds__((ZCfg<NZ>::NT)) k_zpass_3d(
     // kinetic phase in turns: a (pi dt / L_x^2 n_x^2 + pi dt / L_y^2 n_y^2 + pi dt / L_z^2 n_z^2)
     const double cxy = a * fma(I.kin_turns[0], (double)(nxf * nxf), I.kin_turns[1] * (double)(nyf * nyf));
     const double cz = a * I.kin_turns[2];
+    if (cz != cached) {
+      // K = E_xy E_z, separable: E_z once per coefficient into LDS, E_xy once per lane
+      __syncthreads();  // the previous item's readers are done
+      for (int k = threadIdx.x; k < NZ; k += C::NT) {
+        const int nzf = freq(k, NZ);
+        const double2 e = phase_turns_d(cz * (double)(nzf * nzf));
+        ezl[k] = make_double2(e.x * inv_n, e.y * inv_n);
+      }
+      __syncthreads();
+      cached = cz;
+    }
+    const double2 exy = phase_turns_d(cxy);
     float2* __restrict__ base = psi + I.psi_off + ((long long)tile << 6) + lane + (long long)t * slab;
     float2 reg[P];
 #pragma unroll
@@ -131,9 +145,8 @@ __global__ void __launch_bounds__((ZCfg<NZ>::NT)) k_zpass_3d(
     line_fft_io<NZ, P, -1, (W > 1)>(reg, kd, t, tw, my);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      const int nzf = freq(t + q * W, NZ);
-      const double2 k = phase_turns_d(fma(cz, (double)(nzf * nzf), cxy));
-      kd[q] = cmul_fd(kd[q], make_double2(k.x * inv_n, k.y * inv_n));
+      const double2 ez = ezl[t + q * W];
+      kd[q] = cmul_fd(kd[q], make_double2(fma(exy.x, ez.x, -exy.y * ez.y), fma(exy.x, ez.y, exy.y * ez.x)));
     }
     line_fft_io<NZ, P, +1, (W > 1)>(kd, reg, t, tw, my);
     if (active) {
