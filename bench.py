@@ -663,6 +663,16 @@ def main():
                "sample": f"instance {i0} of the batch ({'x'.join(map(str, sp.shape))}), first {sample_steps} "
                          f"of its {sp.nsteps} steps, FP64, {tcpu:.1f}s"}
         log(f"cpu oracle: {cpu_rate / 1e6:.2f} M gp-steps/s on {cpu['cores']} threads ({tcpu:.1f}s)")
+        # the same oracle on one thread, over a shorter stretch of the same instance (run
+        # last: the OpenMP thread count it sets persists in this process)
+        st_steps = max(1, min(sample_steps, int(1.5e7 // sp.points)))
+        t = time.perf_counter()
+        oracle.evolve(oracle.Problem(shape=sp.shape, dt=sp.dt, threads=1), f0, oracle.uniform_state(sp.shape), 0,
+                      st_steps)
+        t1 = time.perf_counter() - t
+        cpu["single_thread"] = {"value": round(sp.points * st_steps / t1, 1), "unit": "grid-point-steps/s",
+                                "cores": 1, "sample": f"first {st_steps} steps of the same instance, {t1:.1f}s"}
+        log(f"cpu oracle, one thread: {sp.points * st_steps / t1 / 1e6:.2f} M gp-steps/s ({t1:.1f}s)")
         p1 = build_plan([type(sp)(sp.seed, sp.shape, sample_steps, sp.dt, sp.n_terms, sp.kmax)], q, flags=extra)
         p1.set_potential(0, f0)
         p1.evolve(-1, stream)
