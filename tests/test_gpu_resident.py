@@ -270,3 +270,29 @@ def test_pass_timing_with_resident_classes():
             assert np.array_equal(plan.psi_of(psi, i).cpu().numpy(), ref[i])
     finally:
         plan.close()
+
+
+def test_reset_then_evolve_repeats_the_run():
+    """qhd_reset on a plan with resident classes (and a streaming one): the next run from
+    step 0 equals the first bitwise."""
+    import torch
+    shapes = [(128, 128), (64, 32), (256, 256)]
+    specs = [q.InstanceSpec(shape=sh, nsteps=n, dt=1e-3) for sh, n in zip(shapes, (150, 90, 120))]
+    fs = _landscapes(shapes, 880)
+    plan = q.Plan(specs, flags=q.QHD_OPT_RESIDENT)
+    try:
+        for i, f in enumerate(fs):
+            plan.set_potential(i, f)
+        runs = []
+        for _ in range(2):
+            plan.evolve(40)
+            plan.evolve()
+            _, psi, _, st = plan.observe(want_psi=True)
+            torch.cuda.synchronize()
+            assert st == q.QHD_OK
+            runs.append([plan.psi_of(psi, i).cpu().numpy() for i in range(len(specs))])
+            plan.reset()
+        for a, b in zip(*runs):
+            assert np.array_equal(a, b)
+    finally:
+        plan.close()
