@@ -165,6 +165,7 @@ def RQP_BYTES_PER_POINT_STEP(d, np_):
 
 
 FP64_PEAK_TFLOPS = 78.6
+QAA_LEG_COUNT = 512  # the baseline-QAA leg of the default run: the QAA workload's batch
 
 
 def rqp_run(q, probs, r, dt, nsteps, steps, warmup, stream, label):
@@ -383,7 +384,7 @@ def main():
         pts = {}
         legs = [(specs, "_qaa" if qaa else "")]
         if args.workload == "batched2d" and not args.no_qaa_summary:
-            legs.append((qhd_inputs.qaa_batch(count=256), "_qaa"))
+            legs.append((qhd_inputs.qaa_batch(count=QAA_LEG_COUNT), "_qaa"))
         for leg, tag in legs:
             for s in leg:
                 n = s.shape[0]
@@ -463,7 +464,7 @@ def main():
     # ---- batched2d: a short baseline-QAA leg (its own batch) beside the main line ----
     qaa_summary = None
     if args.workload == "batched2d" and not args.no_qaa_summary:
-        qs = qhd_inputs.qaa_batch(count=256)
+        qs = qhd_inputs.qaa_batch(count=QAA_LEG_COUNT)
         if args.cap_steps > 0:
             for s_ in qs:
                 s_.nsteps = min(s_.nsteps, args.cap_steps)
