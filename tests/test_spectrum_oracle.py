@@ -61,3 +61,18 @@ def test_planted_mistake_dropped_half_is_caught(monkeypatch):
     monkeypatch.setattr(sr, "kinetic_matrix", wrong)
     w, _ = sr.lowest(f, box, 1.0, 1.0, 6)
     assert np.max(np.abs(w - _ho_levels(1.0, 1.0, (1.0, 2.0), 6))) > 1e-2
+
+
+def test_oscillator_virial_theorem():
+    # for a harmonic potential every eigenstate splits its energy evenly between the
+    # kinetic and the potential term: <a K> = <b V> = E / 2 (the six lowest levels of the
+    # anisotropic oscillator are non-degenerate, so each eigenvector is a pure eigenstate)
+    f, box = _ho()
+    a, b = 0.8, 1.25
+    w, v = sr.lowest(f, box, a, b, 6)
+    K = sr.kinetic_matrix(f.shape, box)
+    for n in range(6):
+        psi = v[:, n]
+        ek = float(np.real(np.vdot(psi, a * (K @ psi))))
+        ev = float(np.real(np.vdot(psi, b * (f.reshape(-1) * psi))))
+        assert abs(ek - 0.5 * w[n]) < 1e-8 and abs(ev - 0.5 * w[n]) < 1e-8, (n, ek, ev, w[n])
