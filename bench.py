@@ -318,8 +318,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this engine targets one GPU; instances are independent and a multi-GPU run "
-              "would only split the batch (see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py: this engine runs on one GPU; its instances are independent, so more GPUs would "
+              "only split the batch between them. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     if not args.tune_cache:
