@@ -79,11 +79,15 @@ __global__ void __launch_bounds__((YCfg<NY>::NT)) k_ypass_3d(
 
 // ------------------------------------------------------------------------------------
 // z-pass: the 64 lanes of a wavefront own the 64 (x, y) points of one 8x8 tile,
-// wavefront w is row group t = w of every z-line, slot q holds z = w + q*W.
+// wavefront w is row group t = w of every z-line, slot q holds z = w + q*W.  A line
+// spans W wavefronts, so every exchange of its transform is a block barrier: 128-point
+// lines take 16 points per lane (radices 16 and 8, one exchange per transform, eight
+// wavefronts) instead of 8 (radices 8, 8, 2, two exchanges, sixteen wavefronts), which
+// cuts the pass time by a quarter at the price of two waves per SIMD.
 
 template <int NZ>
 struct ZCfg {
-  static constexpr int P = 8;
+  static constexpr int P = NZ >= 128 ? 16 : 8;
   static constexpr int W = NZ / P;  // wavefronts per block = lanes per line
   static constexpr int NT = W * 64;
   // line stride = 1 (mod 16) float2 slots: the 64 lines of a wavefront spread over the banks

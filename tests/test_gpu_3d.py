@@ -41,6 +41,8 @@ def test_3d_shapes_against_oracle():
                        box=[(0.0, 0.5), (-1.0, 1.0), (0.0, 1.5)], radius=0.3),
         q.InstanceSpec(shape=(64, 32, 16), nsteps=80, dt=2e-3, sched=q.QHD_SCHED_CONST, sched_p=(0.8, 3.0)),
         q.InstanceSpec(shape=(16, 16, 16), nsteps=150, dt=2e-3),
+        # 128-point z-lines (16 points per lane) on a non-square tile grid, ragged length
+        q.InstanceSpec(shape=(16, 32, 128), nsteps=45, dt=2e-3),
     ]
     fs = [_f3(10 + k, s.shape, s.box) for k, s in enumerate(specs)]
     res, psis, _, st = run_gpu(specs, fs)
