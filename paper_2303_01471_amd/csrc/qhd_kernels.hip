@@ -306,7 +306,11 @@ __global__ void __launch_bounds__((ColCfg<NY, P, true>::NT)) __attribute__((amdg
 // holds the rows t + q*TPL (q = 0..P-1).  Slot q of a wavefront is then exactly
 // one 8x8 tile (64 consecutive complex values, 512 bytes): loads and stores are
 // fully coalesced and go straight to registers.  A column spans W = TPL/8
-// wavefronts; with W > 1 the FFT exchanges use workgroup barriers.
+// wavefronts; with W > 1 the FFT exchanges use workgroup barriers.  256-point columns
+// take 16 points per lane (radices 16 and 16: one exchange per transform over two
+// wavefronts, instead of two exchanges over four), with E_y in an LDS table per item
+// instead of 16 FP64 pairs per lane.  Columns of at most 128 points keep 8 points per
+// lane: the same arithmetic as the resident steps, so both paths stay bitwise equal.
 
 template <int NY, int P>
 struct ColTwCfg {
@@ -315,6 +319,7 @@ struct ColTwCfg {
   static constexpr int ITEMS = W >= 4 ? 1 : 4 / W;        // tile columns per block
   static constexpr int NT = ITEMS * W * 64;
   static constexpr int STRIDE = ((LineLds<NY>::kSlots + 13) / 16) * 16 + 2;
+  static constexpr bool EY_LDS = P >= 16;                 // E_y / (nx ny) per item in LDS
   static_assert(TPL % 8 == 0, "tile-wave column pass needs TPL multiple of 8");
 };
 
@@ -325,6 +330,7 @@ __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
   using C = ColTwCfg<NY, P>;
   constexpr int TPL = C::TPL, W = C::W, ITEMS = C::ITEMS, STRIDE = C::STRIDE;
   __shared__ float2 lds[ITEMS * 8 * STRIDE];
+  __shared__ double2 eyl[C::EY_LDS ? ITEMS * NY : 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int item = wave / W, wv = wave - item * W;  // item within the block, wave within the item
   const int c = lane & 7;
@@ -339,7 +345,10 @@ __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
   long long begin, end;
   block_share(total, ITEMS, begin, end);
   double cached = -1.0;  // E_y depends on the instance only through a_j * pi dt / L_y^2
-  double2 ey[P];
+  double2 ey[C::EY_LDS ? 1 : P];
+  double cached_items[ITEMS];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) cached_items[it] = -1.0;
   for (long long g0 = begin; g0 < end; g0 += ITEMS) {
     const long long g = g0 + item;
     const bool valid = g < end;
@@ -350,7 +359,36 @@ __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
     double a, b;
     sched_ab<Y4>(I, I.steps_done + s, a, b);
     const double cy = a * I.kin_turns[1];
-    if (cy != cached) {
+    if constexpr (C::EY_LDS) {
+      // every thread evaluates the coefficient of every item of the block, so the
+      // refresh decision (and its barriers) is block-uniform
+      double cys[ITEMS];
+      bool refresh = false;
+#pragma unroll
+      for (int it = 0; it < ITEMS; ++it) {
+        const long long gi = g0 + it < end ? g0 + it : end - 1;
+        const InstDev& Ii = inst[(int)(gi >> tc_log2)];
+        double ai, bi;
+        sched_ab<Y4>(Ii, Ii.steps_done + s, ai, bi);
+        cys[it] = ai * Ii.kin_turns[1];
+        refresh |= cys[it] != cached_items[it];
+      }
+      if (refresh) {
+        __syncthreads();  // the previous items' readers are done
+        for (int e = threadIdx.x; e < ITEMS * NY; e += C::NT) {
+          const int it = e / NY, k = e - it * NY;
+          double cyi = cys[0];
+#pragma unroll
+          for (int u = 1; u < ITEMS; ++u) cyi = it == u ? cys[u] : cyi;
+          const int nyf = freq(k, NY);
+          const double2 ph = phase_turns_d(cyi * (double)(nyf * nyf));
+          eyl[e] = make_double2(ph.x * inv_n, ph.y * inv_n);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) cached_items[it] = cys[it];
+      }
+    } else if (cy != cached) {
 #pragma unroll
       for (int q = 0; q < P; ++q) {
         const int nyf = freq(t + q * TPL, NY);
@@ -369,7 +407,8 @@ __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
     line_fft_io<NY, P, -1, (W > 1)>(reg, kd, t, tw, my);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      const double2 k = make_double2(fma(ex.x, ey[q].x, -ex.y * ey[q].y), fma(ex.x, ey[q].y, ex.y * ey[q].x));
+      const double2 e = C::EY_LDS ? eyl[item * NY + t + q * TPL] : ey[C::EY_LDS ? 0 : q];
+      const double2 k = make_double2(fma(ex.x, e.x, -ex.y * e.y), fma(ex.x, e.y, ex.y * e.x));
       kd[q] = cmul_fd(kd[q], k);
     }
     line_fft_io<NY, P, +1, (W > 1)>(kd, reg, t, tw, my);
@@ -907,7 +946,7 @@ int pass_blocks_row_2d(int nx, int ny, int ninst, int grid_cap, int points_per_l
 }
 
 template <int N>
-constexpr int col_tw_p() { return N >= 1024 ? 16 : 8; }
+constexpr int col_tw_p() { return (N >= 1024 || N == 256) ? 16 : 8; }
 
 template <int N, bool Y4>
 hipError_t launch_col_tw(int blocks, int nx, const InstDev* inst, int ninst, float2* psi,
@@ -934,7 +973,7 @@ int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant) {
   int items;
   const int v = col_variant_resolve(ny, variant);
   if (v == kColTileWave) {
-    const int P = 8;  // col_tw_p<N>() for every tile-wave size
+    const int P = ny == 256 ? 16 : 8;  // col_tw_p<N>() for every tile-wave size
     const int w = ny / P / 8;
     items = w >= 4 ? 1 : 4 / w;
   } else if (v == kColStaged16) {
