@@ -161,6 +161,29 @@ __global__ void __launch_bounds__((ColCfg<NY, P, true>::NT)) __attribute__((amdg
   block_share(total, ITEMS, begin, end);
   double cached = -1.0;  // E_y depends on the instance only through a_j * pi dt / L_y^2
   double2 ey[P];
+  // 512-point form (one item per block): the next item's tile column is loaded into
+  // registers while the current one is transformed, so its HBM latency overlaps the
+  // line transforms instead of standing between the block's barriers
+  constexpr int PF = C::EY_LDS ? (TILES * 32) / NT : 1;  // float4 per thread and item
+  float4 pf[PF];
+  bool pf_live = false;
+  double a_item = 0.0;  // a_j of the block's current item
+  auto fetch = [&](long long g) -> bool {
+    const int i = (int)(g >> tc_log2), tc = (int)(g & (tcols - 1));
+    const InstDev& I = inst[i];
+    if (!(s < step_limit(I, max_steps))) return false;
+    const float4* __restrict__ src = reinterpret_cast<const float4*>(psi + I.psi_off) + tc * 32;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int e = tid + k * NT, ty = e >> 5, w = e & 31;
+      pf[k] = src[(long long)ty * tcols * 32 + w];
+    }
+    return true;
+  };
+  if constexpr (C::EY_LDS) {
+    static_assert(ITEMS == 1 && (TILES * 32) % NT == 0, "one item per block, whole float4 rounds");
+    if (begin < end) pf_live = fetch(begin);
+  }
   for (long long g0 = begin; g0 < end; g0 += ITEMS) {
     if constexpr (C::EY_LDS) {
       // the block's item is one tile column of one instance: E_y / (nx ny) for it, read
@@ -168,6 +191,7 @@ __global__ void __launch_bounds__((ColCfg<NY, P, true>::NT)) __attribute__((amdg
       const InstDev& I = inst[(int)(g0 >> tc_log2)];
       double a, b;
       sched_ab<Y4>(I, I.steps_done + s, a, b);
+      a_item = a;
       const double cy = a * (MODEL == kModelQAA ? I.dt : I.kin_turns[1]);
       if (cy != cached) {
         for (int k = tid; k < NY; k += NT) {
@@ -184,40 +208,58 @@ __global__ void __launch_bounds__((ColCfg<NY, P, true>::NT)) __attribute__((amdg
         cached = cy;
       }
     }
-    // stage the tile columns: each thread moves float4 = two complex values; the
-    // item decode is wave-uniform
+    if constexpr (C::EY_LDS) {
+      if (pf_live) {
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      const long long g = g0 + it;
-      if (g < end) {
-        const int i = (int)(g >> tc_log2), tc = (int)(g & (tcols - 1));
-        const InstDev& I = inst[i];
-        if (s < step_limit(I, max_steps)) {
-          const float4* __restrict__ src = reinterpret_cast<const float4*>(psi + I.psi_off) + tc * 32;
-          float2* __restrict__ dst = lds + it * 8 * STRIDE;
+        for (int k = 0; k < PF; ++k) {
+          const int e = tid + k * NT, ty = e >> 5, w = e & 31;
+          const int y = ty * 8 + (w >> 2), xx = (w & 3) << 1;
+          lds[xx * STRIDE + lds_slot(y)] = make_float2(pf[k].x, pf[k].y);
+          lds[(xx + 1) * STRIDE + lds_slot(y)] = make_float2(pf[k].z, pf[k].w);
+        }
+      }
+    } else {
+      // stage the tile columns: each thread moves float4 = two complex values; the
+      // item decode is wave-uniform
 #pragma unroll
-          for (int e = tid; e < TILES * 32; e += NT) {
-            const int ty = e >> 5, w = e & 31;
-            const float4 v = src[(long long)ty * tcols * 32 + w];
-            const int y = ty * 8 + (w >> 2), xx = (w & 3) << 1;
-            dst[xx * STRIDE + lds_slot(y)] = make_float2(v.x, v.y);
-            dst[(xx + 1) * STRIDE + lds_slot(y)] = make_float2(v.z, v.w);
+      for (int it = 0; it < ITEMS; ++it) {
+        const long long g = g0 + it;
+        if (g < end) {
+          const int i = (int)(g >> tc_log2), tc = (int)(g & (tcols - 1));
+          const InstDev& I = inst[i];
+          if (s < step_limit(I, max_steps)) {
+            const float4* __restrict__ src = reinterpret_cast<const float4*>(psi + I.psi_off) + tc * 32;
+            float2* __restrict__ dst = lds + it * 8 * STRIDE;
+#pragma unroll
+            for (int e = tid; e < TILES * 32; e += NT) {
+              const int ty = e >> 5, w = e & 31;
+              const float4 v = src[(long long)ty * tcols * 32 + w];
+              const int y = ty * 8 + (w >> 2), xx = (w & 3) << 1;
+              dst[xx * STRIDE + lds_slot(y)] = make_float2(v.x, v.y);
+              dst[(xx + 1) * STRIDE + lds_slot(y)] = make_float2(v.z, v.w);
+            }
           }
         }
       }
     }
     __syncthreads();
+    if constexpr (C::EY_LDS) pf_live = g0 + 1 < end && fetch(g0 + 1);
 #pragma unroll
     for (int sub = 0; sub < SUBS; ++sub) {
       const int line = line0 + sub * (NT / TPL);
       float2* my = lds + line * STRIDE;
-      const long long g = g0 + line / 8;
+      // one item per block: a block-uniform index keeps the instance reads on the scalar
+      // unit, whose waits do not wait for the prefetched tile column
+      const long long g = C::EY_LDS ? g0 : g0 + line / 8;
       const long long gc = g < end ? g : end - 1;
       const int i = (int)(gc >> tc_log2), tc = (int)(gc & (tcols - 1));
       const InstDev& I = inst[i];
       const int x = tc * 8 + (line & 7);
-      double a, b;
-      sched_ab<Y4>(I, I.steps_done + s, a, b);
+      double a, b = 0.0;
+      // a_j of the item, evaluated before the prefetch: a schedule-table read here would
+      // be a vector load whose wait also waits for the prefetched loads
+      if constexpr (C::EY_LDS) a = a_item;
+      else sched_ab<Y4>(I, I.steps_done + s, a, b);
       const double cy = a * (MODEL == kModelQAA ? I.dt : I.kin_turns[1]);
       if (!C::EY_LDS && cy != cached) {
         // E_y / (nx ny) for this lane's slots: computed once per distinct coefficient
