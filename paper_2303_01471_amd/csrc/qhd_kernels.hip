@@ -83,7 +83,12 @@ k_row_pass_2d(const InstDev* __restrict__ inst, int ninst,
     const long long L = l0 + ll;
     const bool valid = L < end;
     const long long Lc = valid ? L : end - 1;
-    const int i = (int)(Lc >> ny_log2), y = (int)(Lc & ((1 << ny_log2) - 1));
+    int i = (int)(Lc >> ny_log2);
+    const int y = (int)(Lc & ((1 << ny_log2) - 1));
+    // a wavefront's rows (64 P / NX of them, aligned) lie in one instance when they are
+    // at most 8, the smallest mesh size: the index is then wave-uniform and the instance
+    // record is read with scalar loads instead of a chain of waited vector loads
+    if constexpr (64 * P <= 8 * NX) i = __builtin_amdgcn_readfirstlane(i);
     const InstDev& I = inst[i];
     const bool active = valid && s < step_limit(I, max_steps);
     const long long j = I.steps_done + s;
@@ -374,7 +379,9 @@ __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
   __shared__ float2 lds[ITEMS * 8 * STRIDE];
   __shared__ double2 eyl[C::EY_LDS ? ITEMS * NY : 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int item = wave / W, wv = wave - item * W;  // item within the block, wave within the item
+  // item within the block and wave within the item; wave-uniform, so the instance
+  // record is read with scalar loads
+  const int item = __builtin_amdgcn_readfirstlane(wave / W), wv = wave - item * W;
   const int c = lane & 7;
   const int t = (lane >> 3) + 8 * wv;
   float2* my = lds + (item * 8 + c) * STRIDE;

@@ -41,7 +41,8 @@ __global__ void __launch_bounds__((YCfg<NY>::NT)) k_ypass_3d(
   constexpr int P = C::P, TPL = C::TPL, W = C::W, ITEMS = C::ITEMS, STRIDE = C::STRIDE;
   __shared__ float2 lds[ITEMS * 8 * STRIDE];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int item = wave / W, wv = wave - item * W;
+  // wave-uniform: the instance record is read with scalar loads
+  const int item = __builtin_amdgcn_readfirstlane(wave / W), wv = wave - item * W;
   const int c = lane & 7;
   const int t = (lane >> 3) + 8 * wv;
   float2* my = lds + (item * 8 + c) * STRIDE;
