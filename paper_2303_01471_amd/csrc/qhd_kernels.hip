@@ -254,8 +254,11 @@ __global__ void __launch_bounds__((ColCfg<NY, P, true>::NT)) __attribute__((amdg
       const int line = line0 + sub * (NT / TPL);
       float2* my = lds + line * STRIDE;
       // one item per block: a block-uniform index keeps the instance reads on the scalar
-      // unit, whose waits do not wait for the prefetched tile column
-      const long long g = C::EY_LDS ? g0 : g0 + line / 8;
+      // unit, whose waits do not wait for the prefetched tile column.  Otherwise, with at
+      // least 8 lanes per line a wavefront's lines (aligned) lie in one 8-line item: the
+      // item index is wave-uniform and goes through readfirstlane for the same reason.
+      const int item_of_line = TPL >= 8 ? __builtin_amdgcn_readfirstlane(line / 8) : line / 8;
+      const long long g = C::EY_LDS ? g0 : g0 + item_of_line;
       const long long gc = g < end ? g : end - 1;
       const int i = (int)(gc >> tc_log2), tc = (int)(gc & (tcols - 1));
       const InstDev& I = inst[i];
@@ -492,7 +495,9 @@ __global__ void __launch_bounds__(256) k_lf_row_2d(const InstDev* __restrict__ i
     const long long L = l0 + ll;
     const bool valid = L < end;
     const long long Lc = valid ? L : end - 1;
-    const int i = (int)(Lc >> ny_log2), y = (int)(Lc & ((1 << ny_log2) - 1));
+    int i = (int)(Lc >> ny_log2);
+    const int y = (int)(Lc & ((1 << ny_log2) - 1));
+    if constexpr (64 * P <= 8 * NX) i = __builtin_amdgcn_readfirstlane(i);  // as in the row pass
     const InstDev& I = inst[i];
     const bool active = valid && s < step_limit(I, max_steps);
     double a, b, c;
@@ -578,7 +583,8 @@ __global__ void __launch_bounds__(256) k_lf_col_2d(const InstDev* __restrict__ i
       const int line = line0 + sub * (NT / TPL);
       float2* my = lds + line * STRIDE;
       const float* myu = ulds + line * STRIDE;
-      const long long g = g0 + line / 8;
+      // wave-uniform with at least 8 lanes per line, as in the staged column pass
+      const long long g = g0 + (TPL >= 8 ? __builtin_amdgcn_readfirstlane(line / 8) : line / 8);
       const long long gc = g < end ? g : end - 1;
       const InstDev& I = inst[(int)(gc >> tc_log2)];
       double a, b, c;
