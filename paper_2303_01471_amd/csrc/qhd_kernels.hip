@@ -136,8 +136,9 @@ struct ColCfg {
   static constexpr int ITEMS = (8 * TPL >= NT) ? 1 : NT / (8 * TPL);     // tile columns per block
   // waves per SIMD the register budget must allow: the LDS of a block (line buffers,
   // twiddle table) lets three blocks share a CU when 8 points per lane; at 512 points a
-  // block of 8 waves takes one line each and keeps E_y in LDS (100 VGPRs instead of 168),
-  // two blocks per CU: four waves per SIMD (measured 9 % faster than three blocks of 4)
+  // block of 8 waves takes one line each and keeps E_y in LDS (100 VGPRs instead of 168;
+  // 128 with the next tile column held in registers), two blocks per CU: four waves per
+  // SIMD (measured 9 % faster than three blocks of 4)
   static constexpr int MIN_WAVES = EY_LDS ? 4 : (P == 8 ? 3 : 1);
   static constexpr int LINES = ITEMS * 8;                                 // columns per block
   static constexpr int SUBS = (LINES * TPL) / NT;                         // column rounds per item
