@@ -2,6 +2,7 @@
 batch through the FP64 oracle."""
 from __future__ import annotations
 
+import math
 import sys
 from typing import List, Optional, Sequence
 
@@ -12,6 +13,32 @@ from paper_2303_01471_amd import qhd as q
 
 PSI_TOL = 1e-4      # max |dpsi| against the FP64 oracle (FP32 state)
 NORM_TOL = 1e-5     # |sum |psi|^2 - 1| per 10k steps
+
+
+def stages_of(spec) -> int:
+    """Symmetric steps per step of the spec's scheme: the fourth-order composition runs
+    three, every other scheme one."""
+    return 3 if getattr(spec, "scheme", 0) == q.QHD_SCHEME_YOSHIDA4 else 1
+
+
+def spec_allowance(spec, nsteps: Optional[int] = None) -> float:
+    """drift_allowance over the spec's symmetric steps."""
+    n = spec.nsteps if nsteps is None else nsteps
+    return drift_allowance(n * stages_of(spec))
+
+
+def drift_allowance(nsteps: int) -> float:
+    """|norm - 1| a run of nsteps steps may show under the bar of 1e-5 per 10^4 steps.
+
+    From 10^4 steps on the bar is a rate: 1e-5 * nsteps / 1e4.  A shorter run is held
+    to 1e-5 * sqrt(nsteps / 1e4): the FP32 rounding of the state is unbiased and its
+    norm error walks like sqrt(steps), so a walk that meets the bar at 10^4 steps stays
+    under this curve, while a systematic drift at the bar's rate r per step exceeds it
+    once r * nsteps > 1e-5 sqrt(nsteps / 1e4), i.e. a short run catches any bias more
+    than sqrt(1e4 / nsteps) times the bar's rate (the full-length tests hold the rate
+    itself)."""
+    x = max(int(nsteps), 1) / 1e4
+    return NORM_TOL * max(x, math.sqrt(x))
 
 
 def note(msg: str):
