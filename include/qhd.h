@@ -265,6 +265,39 @@ qhd_status qhd_reset(qhd_plan plan, void *stream);
 qhd_status qhd_observe(qhd_plan plan, void *stream, qhd_observables *host_out, float *rho_dev,
                        float *psi_dev);
 
+/* One instance's readouts as qhd_readouts_static writes them (device memory). */
+typedef struct {
+  double norm;          /* sum |psi|^2                                                   */
+  double e_f;           /* sum f |psi|^2 / norm                                          */
+  double success_mass;  /* sum over |x - x*| < r of |psi|^2 / norm (unwrapped distance)  */
+  double f_min;         /* f(x*)                                                         */
+  int64_t argmin_index; /* flat index of x*, lowest-index minimiser of the finite f values;
+                           -1 (and success_mass 0) if f has no finite value              */
+} qhd_readout;
+
+/* Mesh lines (count * n[1] * n[2]) one qhd_readouts_static call may cover. */
+#define QHD_STATIC_MAX_LINES 65536
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the readouts of qhd_observe for
+ * states the caller holds, without a plan and without any allocation.
+ *   psi_dev  count states, interleaved complex FP32, row-major (x fastest), instance
+ *            after instance, each taken as it is (no pending half step is closed);
+ *   f_dev    count potentials, FP64, same layout;
+ *   n, lo, hi  host arrays of ndim entries (axis 0 = x): the mesh and periodic box of
+ *            every instance (App. E.1), powers of two 8 <= n <= 1024;
+ *   success_radius  r of |x - x*| < r;
+ *   out_dev  count qhd_readout entries in device memory, written on `stream`.
+ * Asynchronous on `stream` (four kernel launches, no host synchronisation, capturable).
+ * The per-line partial results live in a static device array of the library (about
+ * 3.5 MB on every GPU it runs on, held until the process ends), which bounds a call to
+ * count * n[1] * n[2] <= QHD_STATIC_MAX_LINES mesh lines (QHD_EINVAL beyond).  Calls
+ * whose work overlaps on one GPU share that array and race: order them on one stream.
+ * Non-finite f values are skipped by the x* search and make the sums non-finite. */
+qhd_status qhd_readouts_static(int32_t ndim, const int32_t *n, const double *lo, const double *hi,
+                               double success_radius, int32_t count, const float *psi_dev,
+                               const double *f_dev, qhd_readout *out_dev, void *stream);
+
 /* Total mesh points of the plan (sum over instances), for sizing rho/psi buffers. */
 qhd_status qhd_plan_points(qhd_plan plan, int64_t *total_points);
 

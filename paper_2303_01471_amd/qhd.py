@@ -147,6 +147,18 @@ class qhd_class_info(ctypes.Structure):
     ]
 
 
+class qhd_readout(ctypes.Structure):
+    _fields_ = [
+        ("norm", ctypes.c_double),
+        ("e_f", ctypes.c_double),
+        ("success_mass", ctypes.c_double),
+        ("f_min", ctypes.c_double),
+        ("argmin_index", ctypes.c_int64),
+    ]
+
+
+QHD_STATIC_MAX_LINES = 65536
+
 _lib = None
 
 # every entry point declared in include/qhd.h, include/qhd_sno.h and include/qhd_rqp.h,
@@ -161,6 +173,10 @@ _SIGNATURES = {
     "qhd_observe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(qhd_observables),
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "qhd_reset": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "qhd_readouts_static": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                           ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
     "qhd_plan_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "qhd_kernel_timings": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(qhd_kernel_timing),
                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -261,6 +277,19 @@ def qhd_observe(plan: int, stream: int, out, rho_ptr: int, psi_ptr: int) -> int:
     if st not in (QHD_OK, QHD_ENUMERIC):
         _check(st)
     return st
+
+
+def qhd_readouts_static(shape: Sequence[int], count: int, psi_ptr: int, f_ptr: int, out_ptr: int,
+                        box=None, radius: float = 0.1, stream: int = 0):
+    """qhd_readouts_static on caller-owned device buffers; ``shape`` and ``box`` in array
+    order ([y, x] or [z, y, x]); out_ptr receives ``count`` qhd_readout entries (device)."""
+    nd = len(shape)
+    box = box if box is not None else [(0.0, 1.0)] * nd
+    n = (ctypes.c_int32 * 3)(*[int(shape[nd - 1 - a]) if a < nd else 1 for a in range(3)])
+    lo = (ctypes.c_double * 3)(*[float(box[nd - 1 - a][0]) if a < nd else 0.0 for a in range(3)])
+    hi = (ctypes.c_double * 3)(*[float(box[nd - 1 - a][1]) if a < nd else 1.0 for a in range(3)])
+    _check(load_library().qhd_readouts_static(nd, n, lo, hi, float(radius), int(count), psi_ptr, f_ptr, out_ptr,
+                                              stream))
 
 
 def qhd_plan_points(plan: int) -> int:
