@@ -43,9 +43,9 @@ METRIC = "grid-point-steps/s (batched vs plain, 1 GPU) at max|Δψ|≤1e-4 vs FP
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per grid-point-step of each workload's pass schedule (algorithmic): 2-D, a row
 # pass (psi read + write, f read: 24 B) and a column pass (psi read + write: 16 B); 3-D, an
-# x-pass (24 B) and three single-axis passes y, z, y (16 B each); QAA, the same two passes
-# as 2-D QHD
-WORKLOAD_BYTES_PER_GP_STEP = {"batched2d": 40.0, "3d": 72.0, "qaa": 40.0}
+# x-pass (24 B) and a (y, z)-plane pass (16 B), or with the matrix-core transforms an
+# x-pass and three single-axis passes y, z, y (72 B); QAA, the same two passes as 2-D QHD
+WORKLOAD_BYTES_PER_GP_STEP = {"batched2d": 40.0, "3d": 40.0, "3d_mfma": 72.0, "qaa": 40.0}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -110,6 +110,14 @@ def roofline_of(kt):
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "algorithmic_bytes_per_point": dom["bytes_per_point"],
             "mean_launch_us": round(dom["total_ms"] * 1e3 / dom["launches"], 2)}
+
+
+def _by_class(specs, values):
+    """values grouped by instance shape"""
+    out = {}
+    for s_, v in zip(specs, values):
+        out.setdefault(tuple(s_.shape), []).append(v)
+    return out
 
 
 def upload(plan, specs, label):
@@ -395,7 +403,7 @@ def main():
         for leg, tag in legs:
             for s in leg:
                 n = s.shape[0]
-                fams = ((f"xpass_3d/n{n}", f"ypass_3d/n{n}", f"zpass_3d/n{n}") if len(s.shape) == 3
+                fams = ((f"xpass_3d/n{n}", f"plane_3d/n{n}x{n}") if len(s.shape) == 3
                         else (f"row_pass_2d{tag}/n{n}", f"col_pass_2d{tag}/n{n}"))
                 for fam in fams:
                     pts[fam] = pts.get(fam, 0) + s.points
@@ -721,6 +729,9 @@ def main():
                 "worst_drift_per_1e4_steps": drift_rates[w],
                 "worst_drift_instance": {"index": w, "shape": list(specs[w].shape), "steps": specs[w].nsteps,
                                          "abs_norm_minus_1": abs(res[w]["norm"] - 1.0)},
+                "drift_per_1e4_steps_by_class": {
+                    "x".join(map(str, sh)): {"max": float(max(v)), "median": float(np.median(v)), "members": len(v)}
+                    for sh, v in sorted(_by_class(specs, drift_rates).items())},
                 "status": ("pass" if ok_psi and ok_drift else "fail") if parity else
                           ("fail" if not ok_drift else "unchecked")}
         log(f"gate: {gate['status']} (worst drift {drift_rates[w]:.2e} per 1e4 steps on instance {w}, "
@@ -771,7 +782,7 @@ def main():
 
     # whole-batch figure beside the dominant kernel's: the design's algorithmic bytes per
     # grid-point-step times the measured rate
-    bpgs = WORKLOAD_BYTES_PER_GP_STEP["qaa" if qaa else args.workload]
+    bpgs = WORKLOAD_BYTES_PER_GP_STEP["qaa" if qaa else ("3d_mfma" if args.mfma_dft else args.workload)]
     batch_roofline = {"bound": "hbm", "algorithmic_bytes_per_grid_point_step": bpgs,
                       "achieved": round(value * bpgs / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": round(value * bpgs / 1e9 / HBM_PEAK_GBS, 4)}

@@ -116,8 +116,8 @@ typedef struct {
   uint32_t flags;          /* QHD_OPT_* bits                                          */
   double norm_tolerance;   /* qhd_observe returns QHD_ENUMERIC if |norm-1| exceeds
                               this; <= 0 selects 1e-3                                  */
-  int32_t timing_stride;   /* with QHD_OPT_TIME_PASSES: time one sub-step in this many
-                              (<= 0 selects 16)                                        */
+  int32_t timing_stride;   /* with QHD_OPT_TIME_PASSES: time every pass of one evolve
+                              chunk in this many (<= 0 selects 16)                     */
   const char *tune_cache;  /* path of a text tuning cache, or NULL.  Entries found for
                               a shape class are used; with QHD_OPT_AUTOTUNE, classes
                               without an entry are tuned and appended.  A missing or
@@ -132,10 +132,13 @@ typedef struct {
 #define QHD_OPT_NO_GRAPH 0x4u    /* never replay captured step chunks (see qhd_evolve)  */
 #define QHD_OPT_MFMA_DFT 0x8u    /* 3-D instances with n = 128 on every axis: the line
                                     transforms run as dense 128 x 128 DFT products on
-                                    the matrix cores with split FP16 hi/lo operands and
-                                    FP32 accumulation (relative error ~2^-22 per
-                                    transform, against ~2^-24 for the FP32 FFT); other
-                                    instances are unaffected                            */
+                                    the matrix cores (FP16 operands, FP32 accumulation):
+                                    the data in two scaled FP16 terms, the DFT matrix in
+                                    three (to ~2^-36, so that no error of its own repeats
+                                    on every transform), relative error ~2^-23 per
+                                    transform; four streaming passes per step (72 bytes
+                                    per grid point) in the slab layout; other instances
+                                    are unaffected                                      */
 #define QHD_OPT_RESIDENT 0x10u   /* 2-D instances with n_x, n_y in {32, 64, 128} (QHD
                                     with any scheme, or QAA integrated by the split step):
                                     all the steps of an evolve call run in
@@ -217,12 +220,18 @@ qhd_status qhd_set_steps_done(qhd_plan plan, int32_t i, int64_t j);
  * to the end).  Asynchronous on `stream`; allocates nothing.  Between evolve
  * calls the state may carry a pending half step; the result does not depend on
  * how the steps are split into calls.
- * When every instance of the plan has the same number of steps left, whole
- * chunks of steps are replayed from a HIP graph captured at plan creation (one
- * launch per chunk instead of one per pass); the arithmetic is the same, so the
- * results are bitwise identical to direct launches.  Not with
- * QHD_OPT_TIME_PASSES or QHD_OPT_NO_GRAPH, and not while `stream` is itself being
- * captured (the passes are then launched directly into the caller's capture). */
+ * The steps run in chunks of at most K steps (K = 64 / the most stages per step of
+ * any instance; qhd_plan_info reports it).  Inside a chunk every shape class runs
+ * on a stream of its own, forked from `stream` and joined back before the chunk's
+ * step commit, so classes overlap on the GPU; the members a pass visits are
+ * counted on the device at the start of the chunk.  A full chunk of every class is
+ * captured as a HIP graph at plan creation and replayed for every chunk in which
+ * each class still has a member with K steps to go, uneven batches included; the
+ * rest runs as direct launches.  The arithmetic is the same, so the results are
+ * bitwise identical to direct launches.  Not with QHD_OPT_NO_GRAPH, and not while
+ * `stream` is itself being captured (the passes are then launched directly into
+ * the caller's capture).  With QHD_OPT_TIME_PASSES one chunk in timing_stride is
+ * launched directly with its classes serialised and every pass timed. */
 qhd_status qhd_evolve(qhd_plan plan, int64_t max_steps, void *stream);
 
 /* Lowest eigenpairs of the discrete Hamiltonian of 2-D instance i at time t,

@@ -143,13 +143,19 @@ struct ShapeClass {
   int cap_row = 2048, cap_col = 2048;
   bool tuned = false;
   bool mfma = false;  // 3-D 128^3 with QHD_OPT_MFMA_DFT
+  bool plane = false; // 3-D in the plane layout (x slowest, (y, z) planes in 8x8 tiles)
   int model = kModelQHD;
   bool leapfrog = false;           // QAA members integrated by leapfrog stages
   bool y4 = false;                 // some member runs the fourth-order scheme
   float* scratch = nullptr;        // leapfrog: partial H v between the row and column passes
-  bool resident = false;           // QHD_OPT_RESIDENT: all steps of a call in one launch, psi in LDS
+  bool resident = false;           // QHD_OPT_RESIDENT: all steps of a chunk in one launch, psi in LDS
   int fam_res = -1;
-  int res_slot = -1;               // its stream and join event in the plan
+  int sps = 1;                     // stages per step of the class (the most of its members)
+  // device counts: [0, kMaxSub) members visited per sub-step of the current chunk (written
+  // by the chunk-plan kernel), [kMaxSub] every member (launches outside evolve)
+  int* nact = nullptr;
+  hipStream_t stream = nullptr;    // the class's own stream inside a chunk (default priority)
+  hipEvent_t join = nullptr;
 };
 
 struct qhd_plan_s {
@@ -174,20 +180,18 @@ struct qhd_plan_s {
   int grid_cap = 2048;
   std::string tune_cache;
   void* dft_tables = nullptr;  // FP16 split DFT matrices for the matrix-core 3-D passes
-  // a chunk of graph_k steps of every class, captured at plan creation (see qhd_evolve)
+  // evolve runs in chunks of at most chunk_k steps; a full chunk of every class (chunk
+  // plan, passes, commit) is captured once as a graph and replayed (see qhd_evolve)
+  int chunk_k = 64;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  int graph_k = 0;    // stages per replay
-  int graph_sps = 1;  // stages per step of every instance of a graph plan
   // timing
   std::vector<Family> families;
   std::vector<Pending> pending;
   std::vector<hipEvent_t> free_events;
-  // resident classes run on streams of their own, forked from the caller's stream and
-  // joined back before the step commit (default priority)
-  std::vector<hipStream_t> res_streams;
-  std::vector<hipEvent_t> res_join;
-  hipEvent_t res_fork = nullptr;
+  // inside a chunk the classes run concurrently, each on its own stream, forked from
+  // the caller's stream and joined back before the step commit
+  hipEvent_t fork = nullptr;
 };
 
 namespace {
@@ -197,11 +201,13 @@ void free_plan(qhd_plan p) {
   (void)hipSetDevice(p->device);
   if (p->internal) (void)hipStreamSynchronize(p->internal);
   if (p->last_stream_valid) (void)hipStreamSynchronize(p->last_stream);
-  for (auto st : p->res_streams) (void)hipStreamSynchronize(st);
-  for (auto ev : p->res_join) (void)hipEventDestroy(ev);
-  if (p->res_fork) (void)hipEventDestroy(p->res_fork);
-  for (auto st : p->res_streams) (void)hipStreamDestroy(st);
+  for (auto& c : p->classes)
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+  if (p->fork) (void)hipEventDestroy(p->fork);
   for (auto& c : p->classes) {
+    if (c.join) (void)hipEventDestroy(c.join);
+    if (c.stream) (void)hipStreamDestroy(c.stream);
+    (void)hipFree(c.nact);
     (void)hipFree(c.dev);
     (void)hipFree(c.psi);
     (void)hipFree(c.f);
@@ -262,123 +268,139 @@ qhd_status push_inst(qhd_plan p, int i) {
   return QHD_OK;
 }
 
-// Launch sub-steps s = 0..S-1 of every class (lim: steps each member takes in this
-// call; kmax: the step cap the kernels apply) and the commit that advances the
-// device step counters by min(kmax, remaining).
-qhd_status enqueue_steps(qhd_plan p, long long S, const std::vector<std::vector<long long>>& lim,
-                         long long max_steps, hipStream_t stream, bool timing) {
-  const int stride = p->opts.timing_stride;
-  auto timed_on = [&](hipStream_t st, int fam, double points, bool sample, auto&& fn) -> hipError_t {
+constexpr int kMaxSub = 64;  // sub-steps of one class in one chunk (chunk_k * stages <= 64)
+
+// stages member I takes in a chunk capped at ks steps (host mirror of step_limit)
+long long host_limit(const InstDev& I, long long ks) {
+  const long long rem = I.nsteps - I.steps_done;
+  const long long cap = ks * I.stages;
+  return cap > rem ? rem : cap;
+}
+
+// members visited in sub-step s of such a chunk (host mirror of the chunk-plan kernel)
+int host_nact(const ShapeClass& c, long long ks, long long s) {
+  for (int k = (int)c.members.size() - 1; k >= 0; --k)
+    if (s < host_limit(c.host[k], ks)) return k + 1;
+  return 0;
+}
+
+// Launch one chunk of at most ks steps of every class: per class the chunk plan (the
+// members each sub-step visits, from the device step counters), then its sub-steps;
+// then the commit that advances every member by min(ks, remaining) steps.  full: every
+// class issues ks * sps sub-steps (the captured form, valid whatever the counters say);
+// otherwise each class issues the sub-steps its members need (from the host mirror).
+// concurrent: each class on its own stream, forked from and joined back to `stream`.
+// timing: every pass launch is bracketed by HIP events (serialised on `stream`).
+qhd_status enqueue_chunk(qhd_plan p, long long ks, hipStream_t stream, bool timing, bool concurrent, bool full) {
+  auto timed_on = [&](hipStream_t st, int fam, double points, auto&& fn) -> hipError_t {
     hipEvent_t a = nullptr, b = nullptr;
-    if (sample) {
+    if (timing) {
       a = take_event(p);
       b = take_event(p);
       if (a && b) (void)hipEventRecord(a, st);
     }
     hipError_t r = fn();
-    if (sample && a && b) {
+    if (timing && a && b) {
       (void)hipEventRecord(b, st);
       p->pending.push_back({a, b, fam, points});
     }
     return r;
   };
-  auto timed_launch = [&](int fam, double points, bool sample, auto&& fn) -> hipError_t {
-    return timed_on(stream, fam, points, sample, fn);
-  };
-  // resident classes: every sub-step of the call in one launch each, on the class's own
-  // stream, so that CUs left idle by one class (its last wave of workgroups) serve the
-  // others; timed as a whole (points = the call's grid-point stages)
+  concurrent = concurrent && !timing && p->classes.size() > 1;
+  if (concurrent) HIP_TRY(hipEventRecord(p->fork, stream));
   std::vector<int> joined;
   for (size_t ci = 0; ci < p->classes.size(); ++ci) {
     ShapeClass& c = p->classes[ci];
-    if (!c.resident) continue;
-    int nact = 0;
-    double gps = 0.0;
-    for (size_t k = 0; k < c.members.size(); ++k) {
-      if (lim[ci][k] > 0) nact = (int)k + 1;
-      gps += (double)lim[ci][k] * (double)c.points;
+    const int m = (int)c.members.size();
+    long long S = 0;
+    if (full) {
+      S = ks * c.sps;
+    } else {
+      for (int k = 0; k < m; ++k) S = std::max(S, host_limit(c.host[k], ks));
     }
-    if (nact == 0) continue;
-    if (joined.empty()) HIP_TRY(hipEventRecord(p->res_fork, stream));
-    hipStream_t rs = p->res_streams[c.res_slot];
-    HIP_TRY(hipStreamWaitEvent(rs, p->res_fork, 0));
-    HIP_TRY(timed_on(rs, c.fam_res, gps, timing, [&] {
-      return launch_resident_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, c.tw_y, max_steps, c.model, c.y4, rs);
-    }));
-    HIP_TRY(hipEventRecord(p->res_join[c.res_slot], rs));
-    joined.push_back(c.res_slot);
-  }
-  for (long long s = 0; s < S; ++s) {
-    const bool sample = timing && (s % stride == 0);
-    for (size_t ci = 0; ci < p->classes.size(); ++ci) {
-      ShapeClass& c = p->classes[ci];
-      int nact = 0;
-      for (size_t k = 0; k < c.members.size(); ++k)
-        if (lim[ci][k] > s) nact = (int)k + 1;
-      if (nact == 0 || c.resident) continue;
-      const double pts = (double)nact * (double)c.points;
-      if (c.ndim == 3 && c.mfma) {
-        HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
-          return launch_mfma_pass_3d(0, 0, c.dev, nact, p->dft_tables, c.psi, c.f, (int)s, max_steps,
-                                     p->grid_cap, stream);
-        }));
-        HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
-          return launch_mfma_pass_3d(1, -1, c.dev, nact, p->dft_tables, c.psi, c.f, (int)s, max_steps,
-                                     p->grid_cap, stream);
-        }));
-        HIP_TRY(timed_launch(c.fam_z, pts, sample, [&] {
-          return launch_mfma_pass_3d(2, 0, c.dev, nact, p->dft_tables, c.psi, c.f, (int)s, max_steps,
-                                     p->grid_cap, stream);
-        }));
-        HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
-          return launch_mfma_pass_3d(1, +1, c.dev, nact, p->dft_tables, c.psi, c.f, (int)s, max_steps,
-                                     p->grid_cap, stream);
-        }));
-      } else if (c.ndim == 3) {
-        HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
-          return launch_row_pass_2d(c.nx, c.ny * c.nz, c.dev, nact, c.psi, c.f, c.tw_x, (int)s,
-                                    max_steps, p->grid_cap, 8, stream);
-        }));
-        HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
-          return launch_ypass_3d(c.nx, c.ny, c.nz, -1, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
-                                 p->grid_cap, stream);
-        }));
-        HIP_TRY(timed_launch(c.fam_z, pts, sample, [&] {
-          return launch_zpass_3d(c.nx, c.ny, c.nz, c.dev, nact, c.psi, c.tw_z, (int)s, max_steps,
-                                 p->grid_cap, stream);
-        }));
-        HIP_TRY(timed_launch(c.fam_y, pts, sample, [&] {
-          return launch_ypass_3d(c.nx, c.ny, c.nz, +1, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
-                                 p->grid_cap, stream);
-        }));
-      } else if (c.ndim == 2 && c.leapfrog) {
-        HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
-          return launch_lf_row_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.scratch, (int)s, max_steps, c.cap_row,
-                                  stream);
-        }));
-        HIP_TRY(timed_launch(c.fam_col, pts, sample, [&] {
-          return launch_lf_col_2d(c.nx, c.ny, c.dev, nact, c.psi, c.scratch, (int)s, max_steps, c.cap_col, stream);
-        }));
-      } else if (c.ndim == 2) {
-        HIP_TRY(timed_launch(c.fam_row, pts, sample, [&] {
-          return launch_row_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.f, c.tw_x, (int)s, max_steps,
-                                    c.cap_row, c.row_points, stream, c.model, c.y4);
-        }));
-        HIP_TRY(timed_launch(c.fam_col, pts, sample, [&] {
-          return launch_col_pass_2d(c.nx, c.ny, c.dev, nact, c.psi, c.tw_y, (int)s, max_steps,
-                                    c.cap_col, c.col_variant, stream, c.model, c.y4);
-        }));
-      } else {
-        HIP_TRY(timed_launch(c.fam_line, pts, sample, [&] {
-          return launch_line_pass_1d(c.nx, c.dev, nact, c.psi, c.f, c.tw_x, (int)s, max_steps,
-                                     p->grid_cap, stream);
-        }));
+    if (S <= 0) continue;
+    if (S > kMaxSub) return fail(QHD_EINVAL, "internal: %lld sub-steps in one chunk", S);
+    hipStream_t st = concurrent ? c.stream : stream;
+    if (concurrent) HIP_TRY(hipStreamWaitEvent(st, p->fork, 0));
+    HIP_TRY(launch_chunk_plan(c.dev, m, ks, (int)S, c.nact, st));
+    if (c.resident) {
+      // every sub-step of the chunk in one launch, psi in LDS (timed as a whole: points =
+      // the chunk's grid-point stages)
+      double gps = 0.0;
+      if (timing)
+        for (int k = 0; k < m; ++k) gps += (double)host_limit(c.host[k], ks) * (double)c.points;
+      HIP_TRY(timed_on(st, c.fam_res, gps, [&] {
+        return launch_resident_2d(c.nx, c.ny, c.dev, m, c.nact, c.psi, c.f, c.tw_x, c.tw_y, ks, c.model, c.y4, st);
+      }));
+    } else {
+      for (long long sub = 0; sub < S; ++sub) {
+        const int s = (int)sub;
+        const int* na = c.nact + s;
+        const double pts = timing ? (double)host_nact(c, ks, s) * (double)c.points : 0.0;
+        if (c.ndim == 3 && c.mfma) {
+          HIP_TRY(timed_on(st, c.fam_row, pts, [&] {
+            return launch_mfma_pass_3d(0, 0, c.dev, m, na, p->dft_tables, c.psi, c.f, s, ks, p->grid_cap, st);
+          }));
+          HIP_TRY(timed_on(st, c.fam_y, pts, [&] {
+            return launch_mfma_pass_3d(1, -1, c.dev, m, na, p->dft_tables, c.psi, c.f, s, ks, p->grid_cap, st);
+          }));
+          HIP_TRY(timed_on(st, c.fam_z, pts, [&] {
+            return launch_mfma_pass_3d(2, 0, c.dev, m, na, p->dft_tables, c.psi, c.f, s, ks, p->grid_cap, st);
+          }));
+          HIP_TRY(timed_on(st, c.fam_y, pts, [&] {
+            return launch_mfma_pass_3d(1, +1, c.dev, m, na, p->dft_tables, c.psi, c.f, s, ks, p->grid_cap, st);
+          }));
+        } else if (c.ndim == 3) {
+          HIP_TRY(timed_on(st, c.fam_row, pts, [&] {
+            return launch_xpass_3d(c.nx, c.ny, c.nz, c.dev, m, na, c.psi, c.f, c.tw_x, s, ks, p->grid_cap, c.y4, st);
+          }));
+          HIP_TRY(timed_on(st, c.fam_y, pts, [&] {
+            return launch_plane_3d(c.nx, c.ny, c.nz, c.dev, m, na, c.psi, c.tw_y, c.tw_z, s, ks, p->grid_cap, c.y4,
+                                   st);
+          }));
+        } else if (c.ndim == 2 && c.leapfrog) {
+          HIP_TRY(timed_on(st, c.fam_row, pts, [&] {
+            return launch_lf_row_2d(c.nx, c.ny, c.dev, m, na, c.psi, c.f, c.scratch, s, ks, c.cap_row, st);
+          }));
+          HIP_TRY(timed_on(st, c.fam_col, pts, [&] {
+            return launch_lf_col_2d(c.nx, c.ny, c.dev, m, na, c.psi, c.scratch, s, ks, c.cap_col, st);
+          }));
+        } else if (c.ndim == 2) {
+          HIP_TRY(timed_on(st, c.fam_row, pts, [&] {
+            return launch_row_pass_2d(c.nx, c.ny, c.dev, m, na, c.psi, c.f, c.tw_x, s, ks, c.cap_row, c.row_points,
+                                      st, c.model, c.y4);
+          }));
+          HIP_TRY(timed_on(st, c.fam_col, pts, [&] {
+            return launch_col_pass_2d(c.nx, c.ny, c.dev, m, na, c.psi, c.tw_y, s, ks, c.cap_col, c.col_variant, st,
+                                      c.model, c.y4);
+          }));
+        } else {
+          HIP_TRY(timed_on(st, c.fam_line, pts, [&] {
+            return launch_line_pass_1d(c.nx, c.dev, m, na, c.psi, c.f, c.tw_x, s, ks, p->grid_cap, st);
+          }));
+        }
       }
     }
+    if (concurrent) {
+      HIP_TRY(hipEventRecord(c.join, st));
+      joined.push_back((int)ci);
+    }
   }
-  for (int k : joined) HIP_TRY(hipStreamWaitEvent(stream, p->res_join[k], 0));
-  for (auto& c : p->classes) HIP_TRY(launch_commit(c.dev, (int)c.members.size(), max_steps, stream));
+  for (int ci : joined) HIP_TRY(hipStreamWaitEvent(stream, p->classes[ci].join, 0));
+  for (auto& c : p->classes) HIP_TRY(launch_commit(c.dev, (int)c.members.size(), ks, stream));
   return QHD_OK;
+}
+
+// advance the host mirror as a chunk of ks steps does on the device
+void mirror_chunk(qhd_plan p, long long ks) {
+  for (auto& c : p->classes)
+    for (auto& I : c.host) {
+      const long long l = host_limit(I, ks);
+      if (l > 0) {
+        I.steps_done += l;
+        I.mode = kModePending;
+      }
+    }
 }
 
 // ---- launch tuning ----------------------------------------------------------------
@@ -460,7 +482,8 @@ qhd_status autotune_class(qhd_plan p, ShapeClass& c, double& us_row, double& us_
   for (int rp : row_pts)
     for (int cap : caps) {
       const double t = time_launches(p->internal, a, b, reps, [&] {
-        return launch_row_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.f, c.tw_x, 0, 1, cap, rp, p->internal, c.model,
+        return launch_row_pass_2d(c.nx, c.ny, c.dev, m, c.nact + kMaxSub, c.psi, c.f, c.tw_x, 0, 1, cap, rp,
+                                  p->internal, c.model,
                                   c.y4);
       });
       if (t < 0) ok = false;
@@ -472,7 +495,8 @@ qhd_status autotune_class(qhd_plan p, ShapeClass& c, double& us_row, double& us_
   for (int v : variants)
     for (int cap : caps) {
       const double t = time_launches(p->internal, a, b, reps, [&] {
-        return launch_col_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.tw_y, 0, 1, cap, v, p->internal, c.model, c.y4);
+        return launch_col_pass_2d(c.nx, c.ny, c.dev, m, c.nact + kMaxSub, c.psi, c.tw_y, 0, 1, cap, v, p->internal,
+                                  c.model, c.y4);
       });
       if (t < 0) ok = false;
       else if (t < us_col) us_col = t, best_col = cap, best_var = v;
@@ -533,15 +557,17 @@ qhd_status compare_resident(qhd_plan p, ShapeClass& c, double& us_res, double& u
     return fail(QHD_EDEVICE, "hipEventCreate failed");
   }
   us_res = time_launches(p->internal, a, b, 2, [&] {
-    return launch_resident_2d(c.nx, c.ny, c.dev, m, c.psi, c.f, c.tw_x, c.tw_y, k, c.model, c.y4, p->internal);
+    return launch_resident_2d(c.nx, c.ny, c.dev, m, c.nact + kMaxSub, c.psi, c.f, c.tw_x, c.tw_y, k, c.model, c.y4,
+                              p->internal);
   });
   us_str = time_launches(p->internal, a, b, 2, [&] {
     hipError_t r = hipSuccess;
     for (int s = 0; s < k && r == hipSuccess; ++s) {
-      r = launch_row_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.f, c.tw_x, s, k, c.cap_row, c.row_points, p->internal,
+      r = launch_row_pass_2d(c.nx, c.ny, c.dev, m, c.nact + kMaxSub, c.psi, c.f, c.tw_x, s, k, c.cap_row, c.row_points,
+                             p->internal,
                              c.model, c.y4);
       if (r == hipSuccess)
-        r = launch_col_pass_2d(c.nx, c.ny, c.dev, m, c.psi, c.tw_y, s, k, c.cap_col, c.col_variant, p->internal,
+        r = launch_col_pass_2d(c.nx, c.ny, c.dev, m, c.nact + kMaxSub, c.psi, c.tw_y, s, k, c.cap_col, c.col_variant, p->internal,
                                c.model, c.y4);
     }
     return r;
@@ -553,13 +579,12 @@ qhd_status compare_resident(qhd_plan p, ShapeClass& c, double& us_res, double& u
   return QHD_OK;
 }
 
-// Capture k steps (k * sps stages) of every class (all members active) plus the commit;
-// every instance takes sps stages per step.
-qhd_status build_step_graph(qhd_plan p, int k, int sps) {
-  std::vector<std::vector<long long>> lim(p->classes.size());
-  for (size_t ci = 0; ci < p->classes.size(); ++ci) lim[ci].assign(p->classes[ci].members.size(), (long long)k * sps);
+// Capture one full chunk of chunk_k steps of every class (classes concurrent) on the
+// plan's internal stream; replayed by qhd_evolve for every chunk in which every class
+// still has a member with at least chunk_k steps to go.
+qhd_status build_chunk_graph(qhd_plan p) {
   HIP_TRY(hipStreamBeginCapture(p->internal, hipStreamCaptureModeThreadLocal));
-  qhd_status st = enqueue_steps(p, (long long)k * sps, lim, k, p->internal, false);
+  qhd_status st = enqueue_chunk(p, p->chunk_k, p->internal, false, true, true);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(p->internal, &g);
   if (st != QHD_OK) {
@@ -573,8 +598,6 @@ qhd_status build_step_graph(qhd_plan p, int k, int sps) {
     return fail(QHD_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
   }
   p->graph = g;
-  p->graph_k = k * sps;
-  p->graph_sps = sps;
   return QHD_OK;
 }
 
@@ -678,6 +701,7 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
     }
     p->classes[c].members.push_back(i);
     p->classes[c].y4 = p->classes[c].y4 || d.scheme == QHD_SCHEME_YOSHIDA4;
+    p->classes[c].sps = std::max(p->classes[c].sps, stages_per_step(d));
     p->cls_of[i] = c;
   }
   // twiddle tables W_N^j = exp(-2 pi i j / N) for every line length in use
@@ -784,6 +808,11 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
     if (e == hipSuccess) e = hipMalloc(&c.f, sizeof(double) * pts);
     if (e == hipSuccess) e = hipMalloc(&c.partials, sizeof(double) * 3 * (size_t)m * c.lines);
     if (e == hipSuccess) e = hipMalloc(&c.results, sizeof(double) * 3 * (size_t)m);
+    if (e == hipSuccess) e = hipMalloc(&c.nact, sizeof(int) * (kMaxSub + 1));
+    if (e == hipSuccess) {
+      std::vector<int> counts(kMaxSub + 1, m);
+      e = hipMemcpy(c.nact, counts.data(), sizeof(int) * counts.size(), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMemcpy(c.dev, c.host.data(), sizeof(InstDev) * m, hipMemcpyHostToDevice);
     if (e == hipSuccess) {
       // uniform initial state N^{-1/2} (App. C.2.1 experiment); USER states are
@@ -802,12 +831,12 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       c.fam_y = family_index(p, "ypass_3d_mfma/n128", 16.0);
       c.fam_z = family_index(p, "zpass_3d_mfma/n128", 16.0);
     } else if (c.ndim == 3) {
+      // plane layout: an x-pass (psi read + write, f read) and a (y, z)-plane pass
+      c.plane = true;
       snprintf(name, sizeof name, "xpass_3d/n%d", c.nx);
       c.fam_row = family_index(p, name, 24.0);
-      snprintf(name, sizeof name, "ypass_3d/n%d", c.ny);
+      snprintf(name, sizeof name, "plane_3d/n%dx%d", c.ny, c.nz);
       c.fam_y = family_index(p, name, 16.0);
-      snprintf(name, sizeof name, "zpass_3d/n%d", c.nz);
-      c.fam_z = family_index(p, name, 16.0);
     } else if (c.ndim == 2) {
       if ((p->opts.flags & QHD_OPT_RESIDENT) && !c.leapfrog && resident_supported(c.nx, c.ny)) {
         // psi stays in LDS; per grid-point step only f (8 B, FP64) is read, from the caches.
@@ -830,21 +859,27 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
   }
   for (int i = 0; i < batch; ++i) p->state_ready[i] = inst[i].init_kind == QHD_INIT_UNIFORM;
   if (std::any_of(p->classes.begin(), p->classes.end(), [](const ShapeClass& c) { return c.mfma; })) {
-    // W_jk = e^{-+2 pi i jk / 128} as FP16 hi/lo pairs of the real and imaginary parts
+    // the 128 distinct entries w(m) = e^{-+2 pi i m / 128} of W_jk = w(jk mod 128), each
+    // part written as w0 + 2^-12 w1 + 2^-24 w2 with FP16 terms: [sign][m][re w0, re w1,
+    // re w2, im w0, im w1, im w2, 0, 0]
     const int n = 128;
-    std::vector<_Float16> tab((size_t)2 * 4 * n * n);
+    std::vector<_Float16> tab((size_t)2 * n * 8, (_Float16)0.0f);
+    auto split3 = [](long double v, _Float16* out) {
+      const _Float16 a = (_Float16)(float)v;
+      const long double r1 = (v - (long double)(float)a) * 4096.0L;
+      const _Float16 b = (_Float16)(float)r1;
+      const long double r2 = (r1 - (long double)(float)b) * 4096.0L;
+      out[0] = a;
+      out[1] = b;
+      out[2] = (_Float16)(float)r2;
+    };
     for (int sg = 0; sg < 2; ++sg)
-      for (int jj = 0; jj < n; ++jj)
-        for (int kk = 0; kk < n; ++kk) {
-          const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)((jj * kk) % n) / n;
-          const double re = (double)cosl(ang), im = (sg == 0 ? -1.0 : 1.0) * (double)sinl(ang);
-          const _Float16 rh = (_Float16)re, ih = (_Float16)im;
-          const size_t o = (size_t)jj * n + kk;
-          tab[((size_t)sg * 4 + 0) * n * n + o] = rh;
-          tab[((size_t)sg * 4 + 1) * n * n + o] = (_Float16)(re - (double)rh);
-          tab[((size_t)sg * 4 + 2) * n * n + o] = ih;
-          tab[((size_t)sg * 4 + 3) * n * n + o] = (_Float16)(im - (double)ih);
-        }
+      for (int m = 0; m < n; ++m) {
+        const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / n;
+        _Float16* e = &tab[((size_t)sg * n + m) * 8];
+        split3(cosl(ang), e);
+        split3((sg == 0 ? -1.0L : 1.0L) * sinl(ang), e + 3);
+      }
     e = hipMalloc(&p->dft_tables, tab.size() * sizeof(_Float16));
     if (e == hipSuccess) e = hipMemcpy(p->dft_tables, tab.data(), tab.size() * sizeof(_Float16), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -908,43 +943,36 @@ qhd_status qhd_plan_create(const qhd_instance* inst, int32_t batch, const qhd_pl
       }
     }
   }
-  // a stream and a join event per resident class, one fork event
-  for (auto& c : p->classes) {
-    if (!c.resident) continue;
-    hipStream_t rs = nullptr;
-    hipEvent_t ev = nullptr;
-    e = hipStreamCreateWithFlags(&rs, hipStreamNonBlocking);
-    if (e == hipSuccess) {
-      p->res_streams.push_back(rs);
-      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  // a stream and a join event per class, one fork event: the classes of a chunk run
+  // concurrently (default stream priority)
+  if (p->classes.size() > 1) {
+    e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    for (auto& c : p->classes) {
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&c.join, hipEventDisableTiming);
     }
-    if (e == hipSuccess) {
-      p->res_join.push_back(ev);
-      c.res_slot = (int)p->res_join.size() - 1;
-    }
-    if (e == hipSuccess && !p->res_fork) e = hipEventCreateWithFlags(&p->res_fork, hipEventDisableTiming);
     if (e != hipSuccess) {
-      fail(QHD_EDEVICE, "resident stream: %s", hipGetErrorString(e));
+      fail(QHD_EDEVICE, "class streams: %s", hipGetErrorString(e));
       return bail(QHD_EDEVICE);
     }
   }
-  // step-chunk graph for plans whose instances all take the same number of steps of
-  // the same number of stages
+  // chunk length: 64 sub-steps of the class with the most stages per step; one full chunk
+  // of every class captured as a graph
   {
-    const long long n0 = inst[0].nsteps;
-    const int sps = stages_per_step(inst[0]);
-    bool same = true;
-    for (int i = 1; i < batch; ++i) same = same && inst[i].nsteps == n0 && stages_per_step(inst[i]) == sps;
-    const int k = (int)std::min<long long>(64 / sps, n0);
-    if (same && k >= 8 && !(p->opts.flags & (QHD_OPT_NO_GRAPH | QHD_OPT_TIME_PASSES))) {
-      qhd_status st = build_step_graph(p, k, sps);
+    int sps = 1;
+    for (auto& c : p->classes) sps = std::max(sps, c.sps);
+    p->chunk_k = std::max(1, kMaxSub / sps);
+    long long most = 0;
+    for (int i = 0; i < batch; ++i) most = std::max(most, (long long)inst[i].nsteps);
+    if (most >= p->chunk_k && !(p->opts.flags & QHD_OPT_NO_GRAPH)) {
+      qhd_status st = build_chunk_graph(p);
       if (st != QHD_OK) return bail(st);
     }
   }
   e = hipMalloc(&p->staging_f, sizeof(double) * max_pts);
   if (e == hipSuccess) e = hipMalloc(&p->staging_psi, sizeof(float2) * max_pts);
-  if (e == hipSuccess) e = hipMalloc(&p->amin_val, sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&p->amin_idx, 2 * sizeof(long long));
+  if (e == hipSuccess) e = hipMalloc(&p->amin_val, sizeof(double) * (1 + kArgminBlocks));
+  if (e == hipSuccess) e = hipMalloc(&p->amin_idx, sizeof(long long) * (2 + 2 * kArgminBlocks));
   if (e == hipSuccess) e = hipHostMalloc((void**)&p->host_results, sizeof(double) * 3 * max_members);
   if (e == hipSuccess) e = hipStreamSynchronize(p->internal);
   if (e != hipSuccess) {
@@ -980,8 +1008,13 @@ qhd_status qhd_set_potential(qhd_plan p, int32_t i, const double* f, int32_t on_
   const int pos = p->pos_of[i];
   HIP_TRY(hipMemcpyAsync(p->staging_f, f, sizeof(double) * c.points,
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->internal));
-  HIP_TRY(launch_argmin(p->staging_f, c.points, p->amin_val, p->amin_idx, p->internal));
-  HIP_TRY(launch_import_f(c.ndim >= 2 ? 2 : 1, c.nx, c.ny * c.nz, p->staging_f, c.f + c.host[pos].psi_off, p->internal));
+  HIP_TRY(launch_argmin(p->staging_f, c.points, p->amin_val, p->amin_idx, p->amin_val + 1, p->amin_idx + 2,
+                        p->amin_idx + 2 + kArgminBlocks, p->internal));
+  if (c.plane)
+    HIP_TRY(launch_import_f_plane(c.nx, c.ny, c.nz, p->staging_f, c.f + c.host[pos].psi_off, p->internal));
+  else
+    HIP_TRY(launch_import_f(c.ndim >= 2 ? 2 : 1, c.nx, c.ny * c.nz, p->staging_f, c.f + c.host[pos].psi_off,
+                            p->internal));
   double v = 0.0;
   long long idx[2] = {0, 0};
   HIP_TRY(hipMemcpyAsync(&v, p->amin_val, sizeof v, hipMemcpyDeviceToHost, p->internal));
@@ -1006,7 +1039,11 @@ qhd_status qhd_set_state(qhd_plan p, int32_t i, const float* psi, int32_t on_dev
   const int pos = p->pos_of[i];
   HIP_TRY(hipMemcpyAsync(p->staging_psi, psi, sizeof(float2) * c.points,
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->internal));
-  HIP_TRY(launch_import_psi(c.ndim >= 2 ? 2 : 1, c.nx, c.ny * c.nz, p->staging_psi, c.psi + c.host[pos].psi_off, p->internal));
+  if (c.plane)
+    HIP_TRY(launch_import_psi_plane(c.nx, c.ny, c.nz, p->staging_psi, c.psi + c.host[pos].psi_off, p->internal));
+  else
+    HIP_TRY(launch_import_psi(c.ndim >= 2 ? 2 : 1, c.nx, c.ny * c.nz, p->staging_psi, c.psi + c.host[pos].psi_off,
+                              p->internal));
   c.host[pos].mode = kModeClean;
   p->state_ready[i] = 1;
   return push_inst(p, i);
@@ -1039,51 +1076,44 @@ qhd_status qhd_evolve(qhd_plan p, int64_t max_steps, void* stream_v) {
   }
   hipStream_t stream = (hipStream_t)stream_v;
   HIP_TRY(hipSetDevice(p->device));
-  // host-side step limits (mirror of the device's)
-  long long S = 0;
-  std::vector<std::vector<long long>> lim(p->classes.size());
-  for (size_t ci = 0; ci < p->classes.size(); ++ci) {
-    ShapeClass& c = p->classes[ci];
-    lim[ci].resize(c.members.size());
-    for (size_t k = 0; k < c.members.size(); ++k) {
-      // in stages, like the kernels' step_limit
-      const long long rem = c.host[k].nsteps - c.host[k].steps_done;
-      const long long cap = max_steps * c.host[k].stages;
-      const long long l = (max_steps < 0 || cap > rem) ? rem : cap;
-      lim[ci][k] = l;
-      S = std::max(S, l);
+  // steps every class still has to take in this call (host mirror of the device counters)
+  long long S = 0, rmin = -1;
+  for (auto& c : p->classes) {
+    long long rc = 0;
+    for (auto& I : c.host) {
+      long long r = (I.nsteps - I.steps_done) / I.stages;
+      if (max_steps >= 0 && r > max_steps) r = max_steps;
+      rc = std::max(rc, r);
     }
+    S = std::max(S, rc);
+    rmin = rmin < 0 ? rc : std::min(rmin, rc);
   }
   const bool timing = (p->opts.flags & QHD_OPT_TIME_PASSES) != 0;
-  // whole chunks from the captured graph when every instance has the same number of
-  // steps left (the graph's kernels run every member for exactly graph_k steps)
-  bool uniform = true;
-  for (size_t ci = 0; ci < p->classes.size(); ++ci)
-    for (long long l : lim[ci]) uniform = uniform && (l == S);
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(stream, &cap));
+  const long long K = p->chunk_k;
+  // full chunks, in which every class has a member to advance by all K steps: replays of
+  // the captured chunk (with pass timing, one in timing_stride of them is launched directly
+  // with every pass timed instead); then the rest in direct chunks of at most K steps,
+  // each issuing only the sub-steps its members need
+  const bool replay = p->graph_exec && cap == hipStreamCaptureStatusNone && !(p->opts.flags & QHD_OPT_NO_GRAPH);
+  const long long full = replay ? rmin / K : 0;
   long long done = 0;
-  if (p->graph_exec && !timing && uniform && cap == hipStreamCaptureStatusNone &&
-      !(p->opts.flags & QHD_OPT_NO_GRAPH)) {
-    for (; done + p->graph_k <= S; done += p->graph_k) HIP_TRY(hipGraphLaunch(p->graph_exec, stream));
-  }
-  if (done < S) {
-    std::vector<std::vector<long long>> rest(lim);
-    for (auto& v : rest)
-      for (auto& l : v) l -= done;
-    // after whole graph chunks every instance has (S - done) / graph_sps steps left
-    qhd_status st = enqueue_steps(p, S - done, rest, done > 0 ? (S - done) / p->graph_sps : max_steps, stream,
-                                  timing);
-    if (st != QHD_OK) return st;
-  }
-  for (size_t ci = 0; ci < p->classes.size(); ++ci) {
-    ShapeClass& c = p->classes[ci];
-    for (size_t k = 0; k < c.members.size(); ++k) {
-      if (lim[ci][k] > 0) {
-        c.host[k].steps_done += lim[ci][k];
-        c.host[k].mode = kModePending;
-      }
+  for (long long ch = 0; ch < full; ++ch, done += K) {
+    if (timing && ch % p->opts.timing_stride == 0) {
+      qhd_status st = enqueue_chunk(p, K, stream, true, false, true);
+      if (st != QHD_OK) return st;
+    } else {
+      HIP_TRY(hipGraphLaunch(p->graph_exec, stream));
     }
+    mirror_chunk(p, K);
+  }
+  for (long long ch = 0; done < S; ++ch) {
+    const long long ks = std::min(K, S - done);
+    qhd_status st = enqueue_chunk(p, ks, stream, timing && ch % p->opts.timing_stride == 0, true, false);
+    if (st != QHD_OK) return st;
+    mirror_chunk(p, ks);
+    done += ks;
   }
   p->last_stream = stream;
   p->last_stream_valid = true;
@@ -1095,7 +1125,7 @@ qhd_status qhd_plan_info(qhd_plan p, qhd_class_info* out, int32_t cap, int32_t* 
   g_err.clear();
   if (!p || !n_classes || !graph_steps || (cap > 0 && !out)) return fail(QHD_EINVAL, "NULL argument");
   *n_classes = (int32_t)p->classes.size();
-  *graph_steps = p->graph_exec ? p->graph_k / p->graph_sps : 0;
+  *graph_steps = p->graph_exec ? p->chunk_k : 0;
   for (int k = 0; k < cap && k < (int)p->classes.size(); ++k) {
     const ShapeClass& c = p->classes[k];
     qhd_class_info& o = out[k];
@@ -1148,7 +1178,10 @@ qhd_status qhd_observe(qhd_plan p, void* stream_v, qhd_observables* out, float* 
   qhd_status status = QHD_OK;
   for (auto& c : p->classes) {
     const int m = (int)c.members.size();
-    if (c.ndim >= 2)
+    if (c.plane)
+      HIP_TRY(launch_observe_plane(c.nx, c.ny, c.nz, c.dev, m, c.psi, c.f, c.tw_x, reinterpret_cast<float2*>(psi_dev),
+                                   rho_dev, c.partials, stream));
+    else if (c.ndim >= 2)
       HIP_TRY(launch_observe_2d(c.nx, c.ny * c.nz, c.ny, c.dev, m, c.psi, c.f, c.tw_x,
                                 reinterpret_cast<float2*>(psi_dev), rho_dev, c.partials, stream, c.model));
     else

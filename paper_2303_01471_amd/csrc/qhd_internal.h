@@ -55,7 +55,11 @@ struct TimingSink {
 
 // Launchers (qhd_kernels.hip).  All are asynchronous on `stream` and return
 // hipSuccess or the launch error.  `nx`, `ny` are the class's mesh sizes.
-hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
+// Pass launchers take two member counts: `ninst` sizes the grid (the class's members),
+// `nact` is the device address of the number of members the kernel visits in this
+// sub-step (a prefix of the class, written by launch_chunk_plan or set once at plan
+// creation), so that a captured launch stays valid while members finish.
+hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, const int* nact, float2* psi,
                               const double* f, const double2* tw_nx, int s, long long max_steps,
                               int grid_cap, int points_per_lane, hipStream_t stream, int model = kModelQHD,
                               bool y4 = true);
@@ -68,34 +72,52 @@ int col_variant_resolve(int ny, int variant);
 int row_points_resolve(int nx, int points_per_lane);
 // leapfrog stages of the QAA model: the row pass writes the partial H v into scratch
 // (float per point, psi's layout), the column pass completes H v and updates psi
-hipError_t launch_lf_row_2d(int nx, int ny, const InstDev* inst, int ninst, const float2* psi, const double* f,
+hipError_t launch_lf_row_2d(int nx, int ny, const InstDev* inst, int ninst, const int* nact, const float2* psi,
+                            const double* f,
                             float* scratch, int s, long long max_steps, int grid_cap, hipStream_t stream);
-hipError_t launch_lf_col_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi, const float* scratch, int s,
+hipError_t launch_lf_col_2d(int nx, int ny, const InstDev* inst, int ninst, const int* nact, float2* psi,
+                            const float* scratch, int s,
                             long long max_steps, int grid_cap, hipStream_t stream);
-hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
+hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, const int* nact, float2* psi,
                               const double2* tw_ny, int s, long long max_steps, int grid_cap,
                               int variant, hipStream_t stream, int model = kModelQHD, bool y4 = true);
-hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* psi, const double* f,
+hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, const int* nact, float2* psi, const double* f,
                                const double2* tw, int s, long long max_steps, int grid_cap,
                                hipStream_t stream);
 hipError_t launch_commit(InstDev* inst, int ninst, long long max_steps, hipStream_t stream);
+// Active-member counts of the sub-steps s = 0..S-1 of an evolve chunk capped at
+// max_steps steps: nact[s] = 1 + the last member k with step_limit(inst[k]) > s (0 if
+// none).  Members are sorted by step count, so the prefix is tight for batches evolved
+// together; a finished member inside it is computed and its result discarded.
+hipError_t launch_chunk_plan(const InstDev* inst, int ninst, long long max_steps, int S, int* nact,
+                             hipStream_t stream);
 
 // Resident 2-D steps (qhd_kernels_resident.hip): one workgroup per instance holds psi in
 // LDS for every step of the call (max_steps as for the passes), reading and writing the
 // tiled HBM state once.  nx, ny in {32, 64, 128}.
 bool resident_supported(int nx, int ny);
-hipError_t launch_resident_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi, const double* f,
+hipError_t launch_resident_2d(int nx, int ny, const InstDev* inst, int ninst, const int* nact, float2* psi,
+                              const double* f,
                               const double2* tw_nx, const double2* tw_ny, long long max_steps, int model,
                               bool y4, hipStream_t stream);
 
-// 3-D (qhd_kernels_3d.hip): y-lines (dir -1 forward, +1 inverse) and the z-pass
-// with the kinetic factor.  The x-pass is launch_row_pass_2d with rows = ny*nz.
-hipError_t launch_ypass_3d(int nx, int ny, int nz, int dir, const InstDev* inst, int ninst,
-                           float2* psi, const double2* tw_y, int s, long long max_steps,
-                           int grid_cap, hipStream_t stream);
-hipError_t launch_zpass_3d(int nx, int ny, int nz, const InstDev* inst, int ninst, float2* psi,
-                           const double2* tw_z, int s, long long max_steps, int grid_cap,
+// 3-D (qhd_kernels_3d.hip), plane layout: x slowest, every (y, z) plane contiguous in 8x8
+// tiles of (y, z).  The x-pass does F_x . V . F_x^{-1} (lines along x, f read), the plane
+// pass F_y^{-1} F_z^{-1} K F_z F_y on one (y, z) plane per k_x held in LDS.
+hipError_t launch_xpass_3d(int nx, int ny, int nz, const InstDev* inst, int ninst, const int* nact, float2* psi,
+                           const double* f, const double2* tw_x, int s, long long max_steps, int grid_cap, bool y4,
                            hipStream_t stream);
+hipError_t launch_plane_3d(int nx, int ny, int nz, const InstDev* inst, int ninst, const int* nact, float2* psi,
+                           const double2* tw_y, const double2* tw_z, int s, long long max_steps, int grid_cap,
+                           bool y4, hipStream_t stream);
+// readouts of plane-layout instances: partials as launch_observe_2d (one triple per x-line,
+// line (y, z) of instance i at i * ny * nz + z * ny + y)
+hipError_t launch_observe_plane(int nx, int ny, int nz, const InstDev* inst, int ninst, const float2* psi,
+                                const double* f, const double2* tw_x, float2* out_psi, float* out_rho,
+                                double* partials, hipStream_t stream);
+// user row-major (x fastest) -> plane layout
+hipError_t launch_import_f_plane(int nx, int ny, int nz, const double* user, double* dst, hipStream_t stream);
+hipError_t launch_import_psi_plane(int nx, int ny, int nz, const float2* user, float2* dst, hipStream_t stream);
 
 // Observe: closes the pending half step, writes the user-layout psi / rho
 // (optional, plan-wide concatenated buffers) and per-line FP64 partial sums
@@ -121,16 +143,19 @@ hipError_t launch_import_psi(int ndim, int nx, int ny, const float2* user, float
 hipError_t launch_fill_psi(float2* dst, long long count, float value, hipStream_t stream);
 // steps_done = 0, mode = clean for every instance of a class
 hipError_t launch_reset_inst(InstDev* inst, int ninst, hipStream_t stream);
-// Lowest-index minimiser of f (user row-major layout): out_val, out_idx.
-hipError_t launch_argmin(const double* f, long long count, double* out_val, long long* out_idx,
-                         hipStream_t stream);
+// Lowest-index minimiser of f (user row-major layout) and the count of non-finite values:
+// out_val[0], out_idx[0], out_idx[1].  Two launches: per-block partials into
+// part_val / part_idx / part_bad (kArgminBlocks entries each), then their reduction.
+constexpr int kArgminBlocks = 512;
+hipError_t launch_argmin(const double* f, long long count, double* out_val, long long* out_idx, double* part_val,
+                         long long* part_idx, long long* part_bad, hipStream_t stream);
 
 // Size the launch of the pass kernels (blocks actually used for a class).
 // 3-D pass with the line transforms as split-FP16 DFT products on the matrix cores
 // (128^3 only): axis 0 = x-pass (F_x V F_x^{-1}), 1 = y-pass (dir -1 forward, +1
 // inverse), 2 = z-pass (F_z^{-1} K F_z).  tables: FP16 [sign][re hi, re lo, im hi,
 // im lo][128][128], sign 0 = e^{-2 pi i jk/128}, 1 = e^{+2 pi i jk/128}.
-hipError_t launch_mfma_pass_3d(int axis, int dir, const InstDev* inst, int ninst, const void* tables,
+hipError_t launch_mfma_pass_3d(int axis, int dir, const InstDev* inst, int ninst, const int* nact, const void* tables,
                                float2* psi, const double* f, int s, long long max_steps, int grid_cap,
                                hipStream_t stream);
 

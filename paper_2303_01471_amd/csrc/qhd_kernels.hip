@@ -62,11 +62,12 @@ namespace qhd {
 // register budget is held to that.)
 template <int NX, int P, int MODEL = kModelQHD, bool Y4 = true>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((P == 16 && NX == 512) ? 3 : 1)))
-k_row_pass_2d(const InstDev* __restrict__ inst, int ninst,
+k_row_pass_2d(const InstDev* __restrict__ inst, const int* __restrict__ nact_p,
                                                      int ny_log2, float2* __restrict__ psi,
                                                      const double* __restrict__ f,
                                                      const double2* __restrict__ twtab, int s,
                                                      long long max_steps) {
+  const int ninst = *nact_p;  // members active in this sub-step (device, set per chunk)
   constexpr int TPL = NX / P;
   constexpr int LPW = 256 / TPL;
   constexpr int SLOTS = LineLds<NX>::kSlots;
@@ -148,8 +149,9 @@ struct ColCfg {
 
 template <int NY, int P, int MODEL = kModelQHD, bool Y4 = true>
 __global__ void __launch_bounds__((ColCfg<NY, P, true>::NT)) __attribute__((amdgpu_waves_per_eu(ColCfg<NY, P, true>::MIN_WAVES))) k_col_pass_2d(
-    const InstDev* __restrict__ inst, int ninst, int nx_log2, float2* __restrict__ psi,
+    const InstDev* __restrict__ inst, const int* __restrict__ nact_p, int nx_log2, float2* __restrict__ psi,
     const double2* __restrict__ twtab, int s, long long max_steps) {
+  const int ninst = *nact_p;  // members active in this sub-step (device, set per chunk)
   using C = ColCfg<NY, P, true>;
   constexpr int TPL = C::TPL, ITEMS = C::ITEMS, NT = C::NT, STRIDE = C::STRIDE, SUBS = C::SUBS;
   constexpr int TILES = NY / 8;
@@ -360,8 +362,13 @@ __global__ void __launch_bounds__((ColCfg<NY, P, true>::NT)) __attribute__((amdg
 // wavefronts; with W > 1 the FFT exchanges use workgroup barriers.  256-point columns
 // take 16 points per lane (radices 16 and 16: one exchange per transform over two
 // wavefronts, instead of two exchanges over four), with E_y in an LDS table per item
-// instead of 16 FP64 pairs per lane.  Columns of at most 128 points keep 8 points per
-// lane: the same arithmetic as the resident steps, so both paths stay bitwise equal.
+// instead of 16 FP64 pairs per lane.  128-point columns take 16 points per lane too
+// (radices 16 and 8, one wavefront per column): with 8 (radices 8, 8, 2) the FP32
+// exchange before the FP64 last stage rounds values that each carry half of a
+// concentrated column's mass, with 16 a sixteenth before it and an eighth after the
+// FP64 first inverse stage, which roughly halves the norm's rounding walk while the
+// state is near uniform (and no block barrier is needed).  Columns of 64 points or fewer
+// keep 8 points per lane, the arithmetic of the resident steps.
 
 template <int NY, int P>
 struct ColTwCfg {
@@ -376,8 +383,9 @@ struct ColTwCfg {
 
 template <int NY, int P, bool Y4 = true>
 __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
-    const InstDev* __restrict__ inst, int ninst, int nx_log2, float2* __restrict__ psi,
+    const InstDev* __restrict__ inst, const int* __restrict__ nact_p, int nx_log2, float2* __restrict__ psi,
     const double2* __restrict__ twtab, int s, long long max_steps) {
+  const int ninst = *nact_p;  // members active in this sub-step (device, set per chunk)
   using C = ColTwCfg<NY, P>;
   constexpr int TPL = C::TPL, W = C::W, ITEMS = C::ITEMS, STRIDE = C::STRIDE;
   __shared__ float2 lds[ITEMS * 8 * STRIDE];
@@ -482,9 +490,10 @@ __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
 // a W_y^{-1} d_y W_y v and updates the target.  Lines in FP64.
 
 template <int NX, int P>
-__global__ void __launch_bounds__(256) k_lf_row_2d(const InstDev* __restrict__ inst, int ninst, int ny_log2,
+__global__ void __launch_bounds__(256) k_lf_row_2d(const InstDev* __restrict__ inst, const int* __restrict__ nact_p, int ny_log2,
                                                    const float2* __restrict__ psi, const double* __restrict__ f,
                                                    float* __restrict__ scratch, int s, long long max_steps) {
+  const int ninst = *nact_p;  // members active in this sub-step (device, set per chunk)
   constexpr int TPL = NX / P;
   constexpr int LPW = 256 / TPL;
   constexpr int BITS = ilog2_c(NX);
@@ -530,9 +539,10 @@ __global__ void __launch_bounds__(256) k_lf_row_2d(const InstDev* __restrict__ i
 }
 
 template <int NY, int P>
-__global__ void __launch_bounds__(256) k_lf_col_2d(const InstDev* __restrict__ inst, int ninst, int nx_log2,
+__global__ void __launch_bounds__(256) k_lf_col_2d(const InstDev* __restrict__ inst, const int* __restrict__ nact_p, int nx_log2,
                                                    float2* __restrict__ psi, const float* __restrict__ scratch, int s,
                                                    long long max_steps) {
+  const int ninst = *nact_p;  // members active in this sub-step (device, set per chunk)
   using C = ColCfg<NY, P>;
   constexpr int TPL = C::TPL, ITEMS = C::ITEMS, NT = C::NT, STRIDE = C::STRIDE, SUBS = C::SUBS;
   constexpr int TILES = NY / 8;
@@ -642,11 +652,12 @@ __global__ void __launch_bounds__(256) k_lf_col_2d(const InstDev* __restrict__ i
 // with the trailing half step of the last step pending.
 
 template <int N, int P>
-__global__ void __launch_bounds__(256) k_line_pass_1d(const InstDev* __restrict__ inst, int ninst,
+__global__ void __launch_bounds__(256) k_line_pass_1d(const InstDev* __restrict__ inst, const int* __restrict__ nact_p,
                                                       float2* __restrict__ psi,
                                                       const double* __restrict__ f,
                                                       const double2* __restrict__ twtab, int s,
                                                       long long max_steps) {
+  const int ninst = *nact_p;  // members active in this sub-step (device, set per chunk)
   constexpr int TPL = N / P;
   constexpr int LPW = (256 / TPL) > 0 ? 256 / TPL : 1;
   constexpr int SLOTS = LineLds<N>::kSlots;
@@ -688,6 +699,20 @@ __global__ void __launch_bounds__(256) k_line_pass_1d(const InstDev* __restrict_
 #pragma unroll
       for (int q = 0; q < P; ++q) psi[base + t + q * TPL] = reg[q];
     }
+  }
+}
+
+__global__ void k_chunk_plan(const InstDev* __restrict__ inst, int ninst, long long max_steps, int S,
+                             int* __restrict__ nact) {
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
+    int n = 0;
+    for (int k = ninst - 1; k >= 0; --k) {
+      if (s < step_limit(inst[k], max_steps)) {
+        n = k + 1;
+        break;
+      }
+    }
+    nact[s] = n;
   }
 }
 
@@ -858,22 +883,47 @@ __global__ void __launch_bounds__(256) k_observe_1d(const InstDev* __restrict__ 
   }
 }
 
-// Neumaier-compensated, fixed-order sum of each instance's line partials.
-__global__ void k_finalize(const double* __restrict__ partials, int lines, int ninst,
-                           double* __restrict__ results) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ninst) return;
+// Fixed-order compensated sum of each instance's line partials, one block per instance:
+// every thread sums a contiguous run of lines (Neumaier), then the 256 runs are combined
+// pairwise in a fixed tree (sums and compensations separately), so the result does not
+// depend on timing.
+__device__ __forceinline__ void neumaier_add(double& s, double& comp, double v) {
+  const double t = s + v;
+  comp += (fabs(s) >= fabs(v)) ? ((s - t) + v) : ((v - t) + s);
+  s = t;
+}
+
+__global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ partials, int lines, int ninst,
+                                                  double* __restrict__ results) {
+  __shared__ double ss[3][256], sc[3][256];
+  const int i = blockIdx.x;
+  const int per = (lines + 255) / 256;
+  const int l0 = threadIdx.x * per, l1 = l0 + per < lines ? l0 + per : lines;
+  double s[3] = {0.0, 0.0, 0.0}, comp[3] = {0.0, 0.0, 0.0};
+  for (int l = l0; l < l1; ++l) {
+    const double* pl = partials + 3 * ((long long)i * lines + l);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) neumaier_add(s[c], comp[c], pl[c]);
+  }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double s = 0.0, comp = 0.0;
-    for (int l = 0; l < lines; ++l) {
-      const double v = partials[3 * ((long long)i * lines + l) + c];
-      const double tt = s + v;
-      comp += (fabs(s) >= fabs(v)) ? ((s - tt) + v) : ((v - tt) + s);
-      s = tt;
-    }
-    results[3 * i + c] = s + comp;
+    ss[c][threadIdx.x] = s[c];
+    sc[c][threadIdx.x] = comp[c];
   }
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double a = ss[c][threadIdx.x], ca = sc[c][threadIdx.x] + sc[c][threadIdx.x + o];
+        neumaier_add(a, ca, ss[c][threadIdx.x + o]);
+        ss[c][threadIdx.x] = a;
+        sc[c][threadIdx.x] = ca;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) results[3 * i + threadIdx.x] = ss[threadIdx.x][0] + sc[threadIdx.x][0];
 }
 
 // ------------------------------------------------------------------------------------
@@ -910,43 +960,71 @@ __global__ void k_fill(float2* __restrict__ dst, long long n, float v) {
   if (p < n) dst[p] = make_float2(v, 0.0f);
 }
 
-// lowest-index minimiser; also counts non-finite entries (reported in out_idx[1])
-__global__ void __launch_bounds__(1024) k_argmin(const double* __restrict__ f, long long n,
-                                                 double* __restrict__ out_val,
-                                                 long long* __restrict__ out_idx) {
-  __shared__ double sv[1024];
-  __shared__ long long si[1024];
-  __shared__ int sbad[1024];
+// lowest-index minimiser; also counts non-finite entries.  Stage 1: every block reduces a
+// contiguous share of f to (value, index, non-finite count); stage 2: one block reduces
+// the blocks' partials.  Ties go to the lower index in both stages, so the result is the
+// lowest-index minimiser whatever the block count.
+__device__ __forceinline__ void argmin_merge(double& v, long long& i, double v2, long long i2) {
+  if (v2 < v || (v2 == v && i2 < i)) {
+    v = v2;
+    i = i2;
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void argmin_block(double bv, long long bi, long long bad, double* sv, long long* si,
+                                             long long* sbad) {
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      double v = sv[threadIdx.x];
+      long long id = si[threadIdx.x];
+      argmin_merge(v, id, sv[threadIdx.x + o], si[threadIdx.x + o]);
+      sv[threadIdx.x] = v;
+      si[threadIdx.x] = id;
+      sbad[threadIdx.x] += sbad[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_argmin_partial(const double* __restrict__ f, long long n,
+                                                        double* __restrict__ part_val,
+                                                        long long* __restrict__ part_idx,
+                                                        long long* __restrict__ part_bad) {
+  __shared__ double sv[256];
+  __shared__ long long si[256], sbad[256];
+  const long long per = (n + gridDim.x - 1) / gridDim.x;
+  const long long b0 = (long long)blockIdx.x * per, b1 = b0 + per < n ? b0 + per : n;
   double bv = INFINITY;
-  long long bi = LLONG_MAX;
-  int bad = 0;
-  for (long long p = threadIdx.x; p < n; p += blockDim.x) {
+  long long bi = LLONG_MAX, bad = 0;
+  for (long long p = b0 + threadIdx.x; p < b1; p += 256) {
     const double v = f[p];
     if (!isfinite(v)) {
       ++bad;
       continue;
     }
-    if (v < bv || (v == bv && p < bi)) {
-      bv = v;
-      bi = p;
-    }
+    argmin_merge(bv, bi, v, p);
   }
-  sv[threadIdx.x] = bv;
-  si[threadIdx.x] = bi;
-  sbad[threadIdx.x] = bad;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      const double v = sv[threadIdx.x + o];
-      const long long id = si[threadIdx.x + o];
-      if (v < sv[threadIdx.x] || (v == sv[threadIdx.x] && id < si[threadIdx.x])) {
-        sv[threadIdx.x] = v;
-        si[threadIdx.x] = id;
-      }
-      sbad[threadIdx.x] += sbad[threadIdx.x + o];
-    }
-    __syncthreads();
+  argmin_block<256>(bv, bi, bad, sv, si, sbad);
+  if (threadIdx.x == 0) {
+    part_val[blockIdx.x] = sv[0];
+    part_idx[blockIdx.x] = si[0];
+    part_bad[blockIdx.x] = sbad[0];
   }
+}
+
+__global__ void __launch_bounds__(kArgminBlocks) k_argmin_final(const double* __restrict__ part_val,
+                                                                const long long* __restrict__ part_idx,
+                                                                const long long* __restrict__ part_bad,
+                                                                double* __restrict__ out_val,
+                                                                long long* __restrict__ out_idx) {
+  __shared__ double sv[kArgminBlocks];
+  __shared__ long long si[kArgminBlocks], sbad[kArgminBlocks];
+  argmin_block<kArgminBlocks>(part_val[threadIdx.x], part_idx[threadIdx.x], part_bad[threadIdx.x], sv, si, sbad);
   if (threadIdx.x == 0) {
     out_val[0] = sv[0];
     out_idx[0] = si[0];
@@ -1002,15 +1080,15 @@ int pass_blocks_row_2d(int nx, int ny, int ninst, int grid_cap, int points_per_l
 }
 
 template <int N>
-constexpr int col_tw_p() { return (N >= 1024 || N == 256) ? 16 : 8; }
+constexpr int col_tw_p() { return (N >= 1024 || N == 256 || N == 128) ? 16 : 8; }
 
 template <int N, bool Y4>
-hipError_t launch_col_tw(int blocks, int nx, const InstDev* inst, int ninst, float2* psi,
+hipError_t launch_col_tw(int blocks, int nx, const InstDev* inst, int ninst, const int* nact, float2* psi,
                          const double2* tw, int s, long long max_steps, hipStream_t stream) {
   if constexpr (N >= 64 && N <= 512) {
     constexpr int P_ = col_tw_p<N>();
     hipLaunchKernelGGL((k_col_pass_tw<N, P_, Y4>), dim3(blocks), dim3(ColTwCfg<N, P_>::NT), 0, stream,
-                       inst, ninst, ilog2(nx), psi, tw, s, max_steps);
+                       inst, nact, ilog2(nx), psi, tw, s, max_steps);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -1029,7 +1107,7 @@ int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant) {
   int items;
   const int v = col_variant_resolve(ny, variant);
   if (v == kColTileWave) {
-    const int P = ny == 256 ? 16 : 8;  // col_tw_p<N>() for every tile-wave size
+    const int P = (ny == 256 || ny == 128) ? 16 : 8;  // col_tw_p<N>() for every tile-wave size
     const int w = ny / P / 8;
     items = w >= 4 ? 1 : 4 / w;
   } else if (v == kColStaged16) {
@@ -1043,69 +1121,69 @@ int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant) {
 }
 
 template <bool Y4>
-hipError_t row_pass_qhd(int nx, int ny, const InstDev* inst, int ninst, float2* psi, const double* f,
+hipError_t row_pass_qhd(int nx, int ny, const InstDev* inst, int ninst, const int* nact, float2* psi, const double* f,
                         const double2* tw, int s, long long max_steps, int grid_cap, int points_per_lane,
                         hipStream_t stream) {
   const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap, points_per_lane);
   if (row_points_resolve(nx, points_per_lane) == 16 && nx < 1024) {
     if (nx == 256)
-      hipLaunchKernelGGL((k_row_pass_2d<256, 16, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+      hipLaunchKernelGGL((k_row_pass_2d<256, 16, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, nact,
                          ilog2(ny), psi, f, tw, s, max_steps);
     else
-      hipLaunchKernelGGL((k_row_pass_2d<512, 16, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+      hipLaunchKernelGGL((k_row_pass_2d<512, 16, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, nact,
                          ilog2(ny), psi, f, tw, s, max_steps);
     return hipGetLastError();
   }
   QHD_SWITCH_N(nx, {
     constexpr int P_ = pts_per_lane<N_>();
-    hipLaunchKernelGGL((k_row_pass_2d<N_, P_, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+    hipLaunchKernelGGL((k_row_pass_2d<N_, P_, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, nact,
                        ilog2(ny), psi, f, tw, s, max_steps);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
+hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, const int* nact, float2* psi,
                               const double* f, const double2* tw, int s, long long max_steps,
                               int grid_cap, int points_per_lane, hipStream_t stream, int model, bool y4) {
   if (model == kModelQAA) {  // the QAA model runs the symmetric scheme or leapfrog
     const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap, 8);
     QHD_SWITCH_N(nx, {
       constexpr int P_ = pts_per_lane<N_>();
-      hipLaunchKernelGGL((k_row_pass_2d<N_, P_, kModelQAA, false>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+      hipLaunchKernelGGL((k_row_pass_2d<N_, P_, kModelQAA, false>), dim3(blocks), dim3(256), 0, stream, inst, nact,
                          ilog2(ny), psi, f, tw, s, max_steps);
       return hipGetLastError();
     });
   }
-  return y4 ? row_pass_qhd<true>(nx, ny, inst, ninst, psi, f, tw, s, max_steps, grid_cap, points_per_lane, stream)
-            : row_pass_qhd<false>(nx, ny, inst, ninst, psi, f, tw, s, max_steps, grid_cap, points_per_lane, stream);
+  return y4 ? row_pass_qhd<true>(nx, ny, inst, ninst, nact, psi, f, tw, s, max_steps, grid_cap, points_per_lane, stream)
+            : row_pass_qhd<false>(nx, ny, inst, ninst, nact, psi, f, tw, s, max_steps, grid_cap, points_per_lane, stream);
 }
 
 template <bool Y4>
-hipError_t col_pass_qhd(int nx, int ny, const InstDev* inst, int ninst, float2* psi, const double2* tw, int s,
+hipError_t col_pass_qhd(int nx, int ny, const InstDev* inst, int ninst, const int* nact, float2* psi, const double2* tw, int s,
                         long long max_steps, int grid_cap, int variant, hipStream_t stream) {
   const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap, variant);
   const int v = col_variant_resolve(ny, variant);
   if (v == kColTileWave) {
-    QHD_SWITCH_N(ny, { return (launch_col_tw<N_, Y4>)(blocks, nx, inst, ninst, psi, tw, s, max_steps, stream); });
+    QHD_SWITCH_N(ny, { return (launch_col_tw<N_, Y4>)(blocks, nx, inst, ninst, nact, psi, tw, s, max_steps, stream); });
   }
   if (v == kColStaged16) {
     if (ny == 256)
       hipLaunchKernelGGL((k_col_pass_2d<256, 16, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<256, 16, true>::NT), 0, stream,
-                         inst, ninst, ilog2(nx), psi, tw, s, max_steps);
+                         inst, nact, ilog2(nx), psi, tw, s, max_steps);
     else
       hipLaunchKernelGGL((k_col_pass_2d<512, 16, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<512, 16, true>::NT), 0, stream,
-                         inst, ninst, ilog2(nx), psi, tw, s, max_steps);
+                         inst, nact, ilog2(nx), psi, tw, s, max_steps);
     return hipGetLastError();
   }
   QHD_SWITCH_N(ny, {
     constexpr int P_ = pts_per_lane<N_>();
     hipLaunchKernelGGL((k_col_pass_2d<N_, P_, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<N_, P_, true>::NT), 0, stream,
-                       inst, ninst, ilog2(nx), psi, tw, s, max_steps);
+                       inst, nact, ilog2(nx), psi, tw, s, max_steps);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi,
+hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, const int* nact, float2* psi,
                               const double2* tw, int s, long long max_steps, int grid_cap,
                               int variant, hipStream_t stream, int model, bool y4) {
   if (model == kModelQAA) {  // staged form only: the Walsh-Hadamard lines use in-wave shuffles
@@ -1113,37 +1191,37 @@ hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, fl
     QHD_SWITCH_N(ny, {
       constexpr int P_ = pts_per_lane<N_>();
       hipLaunchKernelGGL((k_col_pass_2d<N_, P_, kModelQAA, false>), dim3(blocks), dim3(ColCfg<N_, P_, true>::NT), 0,
-                         stream, inst, ninst, ilog2(nx), psi, tw, s, max_steps);
+                         stream, inst, nact, ilog2(nx), psi, tw, s, max_steps);
       return hipGetLastError();
     });
   }
-  return y4 ? col_pass_qhd<true>(nx, ny, inst, ninst, psi, tw, s, max_steps, grid_cap, variant, stream)
-            : col_pass_qhd<false>(nx, ny, inst, ninst, psi, tw, s, max_steps, grid_cap, variant, stream);
+  return y4 ? col_pass_qhd<true>(nx, ny, inst, ninst, nact, psi, tw, s, max_steps, grid_cap, variant, stream)
+            : col_pass_qhd<false>(nx, ny, inst, ninst, nact, psi, tw, s, max_steps, grid_cap, variant, stream);
 }
 
-hipError_t launch_lf_row_2d(int nx, int ny, const InstDev* inst, int ninst, const float2* psi, const double* f,
+hipError_t launch_lf_row_2d(int nx, int ny, const InstDev* inst, int ninst, const int* nact, const float2* psi, const double* f,
                             float* scratch, int s, long long max_steps, int grid_cap, hipStream_t stream) {
   const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap, 8);
   QHD_SWITCH_N(nx, {
     constexpr int P_ = pts_per_lane<N_>();
-    hipLaunchKernelGGL((k_lf_row_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst, ilog2(ny), psi, f,
+    hipLaunchKernelGGL((k_lf_row_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, nact, ilog2(ny), psi, f,
                        scratch, s, max_steps);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_lf_col_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi, const float* scratch, int s,
+hipError_t launch_lf_col_2d(int nx, int ny, const InstDev* inst, int ninst, const int* nact, float2* psi, const float* scratch, int s,
                             long long max_steps, int grid_cap, hipStream_t stream) {
   const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap, kColStaged);
   QHD_SWITCH_N(ny, {
     constexpr int P_ = pts_per_lane<N_>();
-    hipLaunchKernelGGL((k_lf_col_2d<N_, P_>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0, stream, inst, ninst,
+    hipLaunchKernelGGL((k_lf_col_2d<N_, P_>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0, stream, inst, nact,
                        ilog2(nx), psi, scratch, s, max_steps);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* psi, const double* f,
+hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, const int* nact, float2* psi, const double* f,
                                const double2* tw, int s, long long max_steps, int grid_cap,
                                hipStream_t stream) {
   QHD_SWITCH_N(n, {
@@ -1151,7 +1229,7 @@ hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* ps
     constexpr int TPL_ = N_ / P_;
     constexpr int LPW_ = (256 / TPL_) > 0 ? 256 / TPL_ : 1;
     const int blocks = blocks_for(ninst, LPW_, grid_cap);
-    hipLaunchKernelGGL((k_line_pass_1d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+    hipLaunchKernelGGL((k_line_pass_1d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, nact,
                        psi, f, tw, s, max_steps);
     return hipGetLastError();
   });
@@ -1160,6 +1238,13 @@ hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, float2* ps
 hipError_t launch_commit(InstDev* inst, int ninst, long long max_steps, hipStream_t stream) {
   hipLaunchKernelGGL(k_commit, dim3((ninst + 255) / 256), dim3(256), 0, stream, inst, ninst,
                      max_steps);
+  return hipGetLastError();
+}
+
+hipError_t launch_chunk_plan(const InstDev* inst, int ninst, long long max_steps, int S, int* nact,
+                             hipStream_t stream) {
+  if (S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_chunk_plan, dim3((S + 255) / 256), dim3(256), 0, stream, inst, ninst, max_steps, S, nact);
   return hipGetLastError();
 }
 
@@ -1202,8 +1287,7 @@ hipError_t launch_observe_1d(int n, const InstDev* inst, int ninst, const float2
 
 hipError_t launch_finalize(const double* partials, int lines_per_inst, int ninst, double* results,
                            hipStream_t stream) {
-  hipLaunchKernelGGL(k_finalize, dim3((ninst + 63) / 64), dim3(64), 0, stream, partials,
-                     lines_per_inst, ninst, results);
+  hipLaunchKernelGGL(k_finalize, dim3(ninst), dim3(256), 0, stream, partials, lines_per_inst, ninst, results);
   return hipGetLastError();
 }
 
@@ -1235,9 +1319,12 @@ hipError_t launch_fill_psi(float2* dst, long long count, float value, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_argmin(const double* f, long long count, double* out_val, long long* out_idx,
-                         hipStream_t stream) {
-  hipLaunchKernelGGL(k_argmin, dim3(1), dim3(1024), 0, stream, f, count, out_val, out_idx);
+hipError_t launch_argmin(const double* f, long long count, double* out_val, long long* out_idx, double* part_val,
+                         long long* part_idx, long long* part_bad, hipStream_t stream) {
+  hipLaunchKernelGGL(k_argmin_partial, dim3(kArgminBlocks), dim3(256), 0, stream, f, count, part_val, part_idx,
+                     part_bad);
+  hipLaunchKernelGGL(k_argmin_final, dim3(1), dim3(kArgminBlocks), 0, stream, part_val, part_idx, part_bad, out_val,
+                     out_idx);
   return hipGetLastError();
 }
 

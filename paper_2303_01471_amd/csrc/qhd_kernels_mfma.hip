@@ -6,17 +6,21 @@
 //
 // A work item is a group of 32 lines of one axis.  The group is staged in LDS as
 // split FP16 operands: each line is scaled by a power of two 2^e (its largest
-// component then lies in [1/2, 1)) and every component v is stored as
-// hi = fp16(v 2^-e), lo = fp16(v 2^-e - hi).  The 128 x 128 DFT matrix W
-// (W_jk = e^{-+2 pi i jk / 128}) is stored the same way (hi/lo of its real and
-// imaginary parts, row-major, L2-resident).  Each real product W X takes the three
-// terms hi.hi + hi.lo + lo.hi on v_mfma_f32_32x32x16_f16 with FP32 accumulation:
-// relative error ~2^-22 per product instead of FP32's 2^-24.
+// component then lies in [1/2, 1)) and every component v is stored as two terms,
+// x0 = fp16(v 2^-e) and x1 = fp16((v 2^-e - x0) 2^12) (the second term scaled up so that
+// it stays in FP16's normal range).  The DFT matrix W_jk = e^{-+2 pi i jk / 128} has only
+// 128 distinct entries, w(m) with m = jk mod 128; each is written as three terms
+// w = w0 + 2^-12 w1 + 2^-24 w2 (each FP16, normal range), a table of 4 KB that every
+// workgroup keeps in LDS and from which a lane gathers its MFMA operand entries.  The
+// products run on v_mfma_f32_32x32x16_f16 with FP32 accumulation in three accumulators
+// by scale:
+//     a0 = w0 x0,   a1 = w0 x1 + w1 x0,   a2 = w2 x0,    W X = a0 + 2^-12 a1 + 2^-24 a2.
+// The terms left out (w1 x1, w2 x1 and beyond) are at most ~2^-24 of the result and
+// carry the rounding residual x1 of the data, whose sign varies from point to point;
+// every term that carries W's own residual is kept, since that one repeats identically
+// on every transform: with W represented to 2^-22 only (two terms), its error drained the
+// norm systematically, ~2e-8 per step on 128^3.
 //
-// MFMA operand layouts (gfx950, 32x32x16): A lane l holds row l%32, k = 8(l/32)+i;
-// B lane l holds column l%32, the same k; accumulator register r of lane l is row
-// 8(r/4) + 4(l/32) + r%4, column l%32.  A wavefront computes 32 output rows for all
-// 32 lines of the group; four wavefronts cover the 128 rows.
 #include "line_fft.h"
 #include "pass_common.h"
 #include "qhd_internal.h"
@@ -34,6 +38,7 @@ constexpr int kGroups = kN * kN / kLines;  // work items per instance and axis
 constexpr int kPitch = kN + 8;             // FP16 row pitch in LDS (272 bytes)
 constexpr int kYPitch = kN + 1;            // float2 row pitch of the output staging
 constexpr long long kSlab = (long long)kN * kN;
+constexpr float kLoScale = 4096.0f;        // 2^12: scale of the second operand term
 
 // element offset (instance-relative) of point k of line n in group g
 template <int AXIS>
@@ -71,13 +76,14 @@ __device__ __forceinline__ int scale_exp(unsigned bits) {
   return e;
 }
 
+// operand planes in LDS: [re x0, re x1, im x0, im x1][line][k]
 __device__ __forceinline__ void split_store(_Float16* xs, int n, int k, float2 v, int e) {
   const float vr = ldexpf(v.x, -e), vi = ldexpf(v.y, -e);
   const _Float16 rh = (_Float16)vr, ih = (_Float16)vi;
   xs[(0 * kLines + n) * kPitch + k] = rh;
-  xs[(1 * kLines + n) * kPitch + k] = (_Float16)(vr - (float)rh);
+  xs[(1 * kLines + n) * kPitch + k] = (_Float16)((vr - (float)rh) * kLoScale);
   xs[(2 * kLines + n) * kPitch + k] = ih;
-  xs[(3 * kLines + n) * kPitch + k] = (_Float16)(vi - (float)ih);
+  xs[(3 * kLines + n) * kPitch + k] = (_Float16)((vi - (float)ih) * kLoScale);
 }
 
 __device__ __forceinline__ half8 neg8(half8 v) {
@@ -90,40 +96,65 @@ __device__ __forceinline__ half8 neg8(half8 v) {
   return __builtin_bit_cast(half8, u);
 }
 
-// acc (real, imaginary) = W X for this wavefront's 32 rows; w = 4 planes (re hi,
-// re lo, im hi, im lo) of the 128 x 128 matrix
-__device__ __forceinline__ void dft_gemm(const _Float16* __restrict__ w, const _Float16* xs, int wave,
-                                         int lane, f32x16& ar, f32x16& ai) {
+// W table entry m of one sign: (re w0, re w1, re w2, im w0, im w1, im w2, 0, 0)
+struct WEntry {
+  _Float16 v[8];
+};
+
+// (real, imaginary) of W X for this wavefront's 32 rows as the three scaled
+// accumulators; wt = the 128-entry table of W's sign (LDS)
+__device__ __forceinline__ void dft_gemm(const WEntry* wt, const _Float16* xs, int wave, int lane, f32x16 (&ar)[3],
+                                         f32x16 (&ai)[3]) {
   const int row = 32 * wave + (lane & 31), h = lane >> 5, n = lane & 31;
-  const _Float16* __restrict__ wrow = w + row * kN + 8 * h;
   const _Float16* xrow = xs + n * kPitch + 8 * h;
-  ar = f32x16{};
-  ai = f32x16{};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    ar[c] = f32x16{};
+    ai[c] = f32x16{};
+  }
 #pragma unroll 2
   for (int kk = 0; kk < kN / 16; ++kk) {
-    const half8 wrh = *reinterpret_cast<const half8*>(wrow + 0 * kN * kN + 16 * kk);
-    const half8 wrl = *reinterpret_cast<const half8*>(wrow + 1 * kN * kN + 16 * kk);
-    const half8 wih = *reinterpret_cast<const half8*>(wrow + 2 * kN * kN + 16 * kk);
-    const half8 wil = *reinterpret_cast<const half8*>(wrow + 3 * kN * kN + 16 * kk);
-    const half8 xrh = *reinterpret_cast<const half8*>(xrow + 0 * kLines * kPitch + 16 * kk);
-    const half8 xrl = *reinterpret_cast<const half8*>(xrow + 1 * kLines * kPitch + 16 * kk);
-    const half8 xih = *reinterpret_cast<const half8*>(xrow + 2 * kLines * kPitch + 16 * kk);
-    const half8 xil = *reinterpret_cast<const half8*>(xrow + 3 * kLines * kPitch + 16 * kk);
-    const half8 nxih = neg8(xih), nxil = neg8(xil);
-    // Re: Wr Xr - Wi Xi ; Im: Wr Xi + Wi Xr ; each as hi.hi + hi.lo + lo.hi
-    ar = __builtin_amdgcn_mfma_f32_32x32x16_f16(wrh, xrh, ar, 0, 0, 0);
-    ar = __builtin_amdgcn_mfma_f32_32x32x16_f16(wrh, xrl, ar, 0, 0, 0);
-    ar = __builtin_amdgcn_mfma_f32_32x32x16_f16(wrl, xrh, ar, 0, 0, 0);
-    ar = __builtin_amdgcn_mfma_f32_32x32x16_f16(wih, nxih, ar, 0, 0, 0);
-    ar = __builtin_amdgcn_mfma_f32_32x32x16_f16(wih, nxil, ar, 0, 0, 0);
-    ar = __builtin_amdgcn_mfma_f32_32x32x16_f16(wil, nxih, ar, 0, 0, 0);
-    ai = __builtin_amdgcn_mfma_f32_32x32x16_f16(wrh, xih, ai, 0, 0, 0);
-    ai = __builtin_amdgcn_mfma_f32_32x32x16_f16(wrh, xil, ai, 0, 0, 0);
-    ai = __builtin_amdgcn_mfma_f32_32x32x16_f16(wrl, xih, ai, 0, 0, 0);
-    ai = __builtin_amdgcn_mfma_f32_32x32x16_f16(wih, xrh, ai, 0, 0, 0);
-    ai = __builtin_amdgcn_mfma_f32_32x32x16_f16(wih, xrl, ai, 0, 0, 0);
-    ai = __builtin_amdgcn_mfma_f32_32x32x16_f16(wil, xrh, ai, 0, 0, 0);
+    // this lane's A operand: row `row`, k = 16 kk + 8 h + i, entries w((row k) mod 128)
+    half8 w0r, w1r, w2r, w0i, w1i, w2i;
+    const int kb = 16 * kk + 8 * h;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const WEntry e = wt[(row * (kb + i)) & (kN - 1)];
+      w0r[i] = e.v[0];
+      w1r[i] = e.v[1];
+      w2r[i] = e.v[2];
+      w0i[i] = e.v[3];
+      w1i[i] = e.v[4];
+      w2i[i] = e.v[5];
+    }
+    const half8 xr0 = *reinterpret_cast<const half8*>(xrow + 0 * kLines * kPitch + 16 * kk);
+    const half8 xr1 = *reinterpret_cast<const half8*>(xrow + 1 * kLines * kPitch + 16 * kk);
+    const half8 xi0 = *reinterpret_cast<const half8*>(xrow + 2 * kLines * kPitch + 16 * kk);
+    const half8 xi1 = *reinterpret_cast<const half8*>(xrow + 3 * kLines * kPitch + 16 * kk);
+    const half8 nxi0 = neg8(xi0), nxi1 = neg8(xi1);
+    // Re: Wr Xr - Wi Xi ; Im: Wr Xi + Wi Xr
+    ar[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w0r, xr0, ar[0], 0, 0, 0);
+    ar[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w0i, nxi0, ar[0], 0, 0, 0);
+    ar[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w0r, xr1, ar[1], 0, 0, 0);
+    ar[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w0i, nxi1, ar[1], 0, 0, 0);
+    ar[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w1r, xr0, ar[1], 0, 0, 0);
+    ar[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w1i, nxi0, ar[1], 0, 0, 0);
+    ar[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w2r, xr0, ar[2], 0, 0, 0);
+    ar[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w2i, nxi0, ar[2], 0, 0, 0);
+    ai[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w0r, xi0, ai[0], 0, 0, 0);
+    ai[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w0i, xr0, ai[0], 0, 0, 0);
+    ai[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w0r, xi1, ai[1], 0, 0, 0);
+    ai[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w0i, xr1, ai[1], 0, 0, 0);
+    ai[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w1r, xi0, ai[1], 0, 0, 0);
+    ai[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w1i, xr0, ai[1], 0, 0, 0);
+    ai[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w2r, xi0, ai[2], 0, 0, 0);
+    ai[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w2i, xr0, ai[2], 0, 0, 0);
   }
+}
+
+// register r of the combined product a0 + 2^-12 a1 + 2^-24 a2 (FP32)
+__device__ __forceinline__ float combine(const f32x16 (&a)[3], int r) {
+  return fmaf(a[2][r], 0x1p-24f, fmaf(a[1][r], 0x1p-12f, a[0][r]));
 }
 
 // output row of accumulator register r
@@ -133,18 +164,22 @@ __device__ __forceinline__ int acc_row(int wave, int lane, int r) {
 
 // MODE 0: Y = W_dir X (y-pass).  MODE 1: x-pass F_x V F_x^{-1} (the first product
 // is skipped on the entry step, where the state is in position space).  MODE 2:
-// z-pass F_z^{-1} K F_z.  tables: [sign][plane][128][128] FP16, sign 0 = e^{-i..}.
+// z-pass F_z^{-1} K F_z.  tables: [sign][128] W entries, sign 0 = e^{-i..}.
 template <int AXIS, int MODE>
-__global__ void __launch_bounds__(256) k_mfma_pass_3d(const InstDev* __restrict__ inst, int ninst,
-                                                      const _Float16* __restrict__ tables,
+__global__ void __launch_bounds__(256) k_mfma_pass_3d(const InstDev* __restrict__ inst, const int* __restrict__ nact_p,
+                                                      const WEntry* __restrict__ tables,
                                                       float2* __restrict__ psi, const double* __restrict__ f,
                                                       int dir, int s, long long max_steps) {
+  const int ninst = *nact_p;  // members active in this sub-step (device, set per chunk)
   __shared__ __attribute__((aligned(16))) _Float16 xs[4 * kLines * kPitch];
   __shared__ unsigned smax[2][kLines];
   float2* ys = reinterpret_cast<float2*>(xs);  // output staging, aliases the operands
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const _Float16* __restrict__ wfwd = tables;
-  const _Float16* __restrict__ winv = tables + 4 * kN * kN;
+  __shared__ WEntry wl[2 * kN];  // both signs of the W table
+  for (int e = threadIdx.x; e < 2 * kN; e += blockDim.x) wl[e] = tables[e];
+  __syncthreads();
+  const WEntry* wfwd = wl;
+  const WEntry* winv = wl + kN;
   const long long total = (long long)ninst * kGroups;
   long long begin, end;
   block_share(total, 1, begin, end);
@@ -184,7 +219,8 @@ __global__ void __launch_bounds__(256) k_mfma_pass_3d(const InstDev* __restrict_
       for (int q = 0; q < 16; ++q) split_store(xs, n_ld, k0 + q, v[q], e);
     }
     __syncthreads();
-    f32x16 ar, ai;
+    f32x16 ar[3], ai[3];
+    float pr[16], pi[16];
     int e_acc = scale_exp(smax[0][n_acc]);
     if (MODE == 2 || (MODE == 1 && !entry)) {
       // ---- first product, phase, re-split
@@ -194,10 +230,10 @@ __global__ void __launch_bounds__(256) k_mfma_pass_3d(const InstDev* __restrict_
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int k = acc_row(wave, lane, r);
-          const float2 y = make_float2(ldexpf(ar[r], e_acc), ldexpf(ai[r], e_acc));
+          const float2 y = make_float2(ldexpf(combine(ar, r), e_acc), ldexpf(combine(ai, r), e_acc));
           const float2 z = cmul_fd(y, phase_turns_d(cpot * fl[line_off<AXIS>(g, n_acc, k)]));
-          ar[r] = z.x;
-          ai[r] = z.y;
+          pr[r] = z.x;
+          pi[r] = z.y;
           mm = fmaxf(mm, fmaxf(fabsf(z.x), fabsf(z.y)));
         }
       } else {
@@ -212,10 +248,10 @@ __global__ void __launch_bounds__(256) k_mfma_pass_3d(const InstDev* __restrict_
         for (int r = 0; r < 16; ++r) {
           const int nzf = freq(acc_row(wave, lane, r), kN);
           const double2 kf = phase_turns_d(fma(cz, (double)(nzf * nzf), cxy));
-          const float2 y2 = make_float2(ldexpf(ar[r], e_acc), ldexpf(ai[r], e_acc));
+          const float2 y2 = make_float2(ldexpf(combine(ar, r), e_acc), ldexpf(combine(ai, r), e_acc));
           const float2 z = cmul_fd(y2, make_double2(kf.x * inv_n, kf.y * inv_n));
-          ar[r] = z.x;
-          ai[r] = z.y;
+          pr[r] = z.x;
+          pi[r] = z.y;
           mm = fmaxf(mm, fmaxf(fabsf(z.x), fabsf(z.y)));
         }
       }
@@ -224,16 +260,17 @@ __global__ void __launch_bounds__(256) k_mfma_pass_3d(const InstDev* __restrict_
       e_acc = scale_exp(smax[1][n_acc]);
 #pragma unroll
       for (int r = 0; r < 16; ++r)
-        split_store(xs, n_acc, acc_row(wave, lane, r), make_float2(ar[r], ai[r]), e_acc);
+        split_store(xs, n_acc, acc_row(wave, lane, r), make_float2(pr[r], pi[r]), e_acc);
       __syncthreads();
     }
     // ---- final product
-    const _Float16* __restrict__ wlast = MODE == 0 ? (dir < 0 ? wfwd : winv) : (MODE == 1 ? wfwd : winv);
+    const WEntry* wlast = MODE == 0 ? (dir < 0 ? wfwd : winv) : (MODE == 1 ? wfwd : winv);
     dft_gemm(wlast, xs, wave, lane, ar, ai);
     __syncthreads();  // operands no longer needed: stage the output in the same LDS
 #pragma unroll
     for (int r = 0; r < 16; ++r)
-      ys[n_acc * kYPitch + acc_row(wave, lane, r)] = make_float2(ldexpf(ar[r], e_acc), ldexpf(ai[r], e_acc));
+      ys[n_acc * kYPitch + acc_row(wave, lane, r)] =
+          make_float2(ldexpf(combine(ar, r), e_acc), ldexpf(combine(ai, r), e_acc));
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 16; ++q) pl[line_off<AXIS>(g, n_ld, k0 + q)] = ys[n_ld * kYPitch + k0 + q];
@@ -243,19 +280,19 @@ __global__ void __launch_bounds__(256) k_mfma_pass_3d(const InstDev* __restrict_
 
 }  // namespace
 
-hipError_t launch_mfma_pass_3d(int axis, int dir, const InstDev* inst, int ninst, const void* tables,
+hipError_t launch_mfma_pass_3d(int axis, int dir, const InstDev* inst, int ninst, const int* nact, const void* tables,
                                float2* psi, const double* f, int s, long long max_steps, int grid_cap,
                                hipStream_t stream) {
   long long items = (long long)ninst * kGroups;
   if (grid_cap > 0 && items > grid_cap) items = grid_cap;
   const dim3 grid((unsigned)items), block(256);
-  const _Float16* t = static_cast<const _Float16*>(tables);
+  const WEntry* t = static_cast<const WEntry*>(tables);
   if (axis == 0)
-    hipLaunchKernelGGL((k_mfma_pass_3d<0, 1>), grid, block, 0, stream, inst, ninst, t, psi, f, dir, s, max_steps);
+    hipLaunchKernelGGL((k_mfma_pass_3d<0, 1>), grid, block, 0, stream, inst, nact, t, psi, f, dir, s, max_steps);
   else if (axis == 1)
-    hipLaunchKernelGGL((k_mfma_pass_3d<1, 0>), grid, block, 0, stream, inst, ninst, t, psi, f, dir, s, max_steps);
+    hipLaunchKernelGGL((k_mfma_pass_3d<1, 0>), grid, block, 0, stream, inst, nact, t, psi, f, dir, s, max_steps);
   else if (axis == 2)
-    hipLaunchKernelGGL((k_mfma_pass_3d<2, 2>), grid, block, 0, stream, inst, ninst, t, psi, f, dir, s, max_steps);
+    hipLaunchKernelGGL((k_mfma_pass_3d<2, 2>), grid, block, 0, stream, inst, nact, t, psi, f, dir, s, max_steps);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -40,12 +40,13 @@ struct ResCfg {
 };
 
 template <int NX, int NY, int MODEL, bool Y4>
-__global__ void __launch_bounds__((ResCfg<NX, NY, MODEL>::NT)) k_resident_2d(const InstDev* __restrict__ inst, int ninst,
+__global__ void __launch_bounds__((ResCfg<NX, NY, MODEL>::NT)) k_resident_2d(const InstDev* __restrict__ inst, const int* __restrict__ nact_p,
                                                                      float2* __restrict__ psi,
                                                                      const double* __restrict__ f,
                                                                      const double2* __restrict__ twx,
                                                                      const double2* __restrict__ twy,
                                                                      long long max_steps) {
+  const int ninst = *nact_p;  // members active in this sub-step (device, set per chunk)
   using C = ResCfg<NX, NY, MODEL>;
   constexpr int P = C::P, TX = C::TX, TY = C::TY, NT = C::NT, RS = C::RS;
   __shared__ float2 st[NY * RS];
@@ -179,7 +180,8 @@ bool resident_supported(int nx, int ny) {
   return ok(nx) && ok(ny);
 }
 
-hipError_t launch_resident_2d(int nx, int ny, const InstDev* inst, int ninst, float2* psi, const double* f,
+hipError_t launch_resident_2d(int nx, int ny, const InstDev* inst, int ninst, const int* nact, float2* psi,
+                              const double* f,
                               const double2* tw_nx, const double2* tw_ny, long long max_steps, int model,
                               bool y4, hipStream_t stream) {
   if (ninst <= 0) return hipSuccess;
@@ -189,13 +191,13 @@ hipError_t launch_resident_2d(int nx, int ny, const InstDev* inst, int ninst, fl
     constexpr int NT_ = ResCfg<NX_, NY_>::NT, NTQ_ = ResCfg<NX_, NY_, kModelQAA>::NT;                         \
     if (model == kModelQAA)                                                                                   \
       hipLaunchKernelGGL((k_resident_2d<NX_, NY_, kModelQAA, false>), dim3(ninst), dim3(NTQ_), 0, stream,     \
-                         inst, ninst, psi, f, tw_nx, tw_ny, max_steps);                                       \
+                         inst, nact, psi, f, tw_nx, tw_ny, max_steps);                                       \
     else if (y4)                                                                                              \
       hipLaunchKernelGGL((k_resident_2d<NX_, NY_, kModelQHD, true>), dim3(ninst), dim3(NT_), 0, stream,       \
-                         inst, ninst, psi, f, tw_nx, tw_ny, max_steps);                                       \
+                         inst, nact, psi, f, tw_nx, tw_ny, max_steps);                                       \
     else                                                                                                      \
       hipLaunchKernelGGL((k_resident_2d<NX_, NY_, kModelQHD, false>), dim3(ninst), dim3(NT_), 0, stream,      \
-                         inst, ninst, psi, f, tw_nx, tw_ny, max_steps);                                       \
+                         inst, nact, psi, f, tw_nx, tw_ny, max_steps);                                       \
     return hipGetLastError();                                                                                 \
   }
   QHD_RES_LAUNCH(32, 32)

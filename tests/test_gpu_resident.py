@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import qhd_inputs
-from gpu_helpers import NORM_TOL, PSI_TOL, compare, note, run_gpu, run_oracle
+from gpu_helpers import PSI_TOL, compare, spec_allowance, note, run_gpu, run_oracle
 from paper_2303_01471_amd import qhd as q
 
 pytestmark = pytest.mark.gpu
@@ -44,7 +44,7 @@ def _oracle_check(specs, fs, res, psis, label):
         ref, ro = run_oracle(spec, f)
         err, nd, d_ef, d_p = compare(spec, f, res[i], psis[i], ref, ro, f"{label}[{i}]")
         assert err <= PSI_TOL
-        assert abs(res[i]["norm"] - ro.norm) <= NORM_TOL * max(1.0, spec.nsteps / 1e4)
+        assert abs(res[i]["norm"] - ro.norm) <= spec_allowance(spec)
         assert d_ef <= 1e-3 and d_p <= 1e-4
         assert res[i]["argmin_index"] == ro.argmin and res[i]["f_min"] == ro.f_min
         assert res[i]["steps_done"] == spec.nsteps
@@ -62,8 +62,20 @@ def test_every_shape_matches_streaming_and_oracle():
     for i in range(len(specs)):
         d = float(np.max(np.abs(psi_r[i] - psi_s[i])))
         note(f"  {SHAPES[i]}: resident vs streaming max|dpsi| = {d:.3e}")
-        assert np.array_equal(psi_r[i], psi_s[i])
+        # the same arithmetic where both take 8 points per lane on the columns; the
+        # streaming 128-point columns take 16 (another FFT factorisation, same rounding order
+        # of magnitude)
+        if SHAPES[i][0] <= 64:
+            assert np.array_equal(psi_r[i], psi_s[i])
+        else:
+            assert d <= 1e-6
     _oracle_check(specs, fs, res_r, psi_r, "resident")
+    # the streaming side against the oracle too (its norm drift is bounded by the
+    # streaming tests, at full length among them)
+    for i, (spec, f) in enumerate(zip(specs, fs)):
+        ref, ro = run_oracle(spec, f)
+        err, *_ = compare(spec, f, res_s[i], psi_s[i], ref, ro, f"streaming[{i}]")
+        assert err <= PSI_TOL and res_s[i]["argmin_index"] == ro.argmin
 
 
 def test_schemes_and_schedules_against_oracle():
@@ -238,10 +250,20 @@ def test_autotune_keeps_resident_only_where_faster(tmp_path):
     assert len(lines) == 2
     assert resident_of(single) is False and resident_of(many) is True
     assert len([ln for ln in open(cache) if ln.startswith("qhd-resident")]) == 2
+    # the streaming run of the same launch choice (read from the cache) gives the same values
     f = _landscapes([(128, 128)], 840)
-    _, a, _, _ = run_gpu(single, f, flags=flags)
-    _, b, _, _ = run_gpu(single, f)
-    assert np.array_equal(a[0], b[0])
+    outs = []
+    for fl in (flags, q.QHD_OPT_AUTOTUNE):
+        plan = q.Plan(single, flags=fl, tune_cache=cache)
+        try:
+            plan.set_potential(0, f[0])
+            plan.evolve()
+            _, psi, _, st = plan.observe(want_psi=True)
+            assert st == q.QHD_OK and not plan.graph_info()["classes"][0]["resident"]
+            outs.append(psi.cpu().numpy())
+        finally:
+            plan.close()
+    assert np.array_equal(outs[0], outs[1])
 
 
 def test_pass_timing_with_resident_classes():

@@ -66,11 +66,34 @@ def test_graph_replay_is_bitwise_identical_to_direct_launches():
     assert err <= PSI_TOL
 
 
-def test_no_graph_for_uneven_plans():
-    specs = [q.InstanceSpec(shape=(64, 64), nsteps=100, dt=1e-3), q.InstanceSpec(shape=(64, 64), nsteps=90, dt=1e-3)]
-    fs = [qhd_inputs.landscape_grid(5, (64, 64))] * 2
-    _, _, _, info = _run(specs, fs)
-    assert info["graph_steps"] == 0
+def test_uneven_multiclass_graph_replay_is_bitwise_identical_to_direct_launches():
+    """Uneven sizes and step counts in one plan (four shape classes on their own streams,
+    members finishing at different steps, so the visited prefix of each class shrinks
+    during the run): replays of the captured chunk, with direct chunks for the rest, give
+    bitwise the states of direct launches, at every readout of a sequence of uneven calls."""
+    note("case: uneven batch, graph replay vs direct launches")
+    specs = [q.InstanceSpec(shape=(128, 128), nsteps=300, dt=1e-3),
+             q.InstanceSpec(shape=(128, 128), nsteps=150, dt=1e-3),
+             q.InstanceSpec(shape=(64, 64), nsteps=200, dt=1e-3),
+             q.InstanceSpec(shape=(64, 64), nsteps=90, dt=1e-3),
+             q.InstanceSpec(shape=(256, 256), nsteps=250, dt=1e-3),
+             q.InstanceSpec(shape=(64, 32), nsteps=70, dt=1e-3),
+             q.InstanceSpec(shape=(128, 128), nsteps=299, dt=1e-3)]
+    fs = [qhd_inputs.landscape_grid(40 + k, sp.shape) for k, sp in enumerate(specs)]
+    chunks = (100, 7, 64, 65)
+    r_g, psi_g, seen_g, info_g = _run(specs, fs, chunks=chunks)
+    r_d, psi_d, seen_d, info_d = _run(specs, fs, flags=q.QHD_OPT_NO_GRAPH, chunks=chunks)
+    assert info_g["graph_steps"] == 64 and info_d["graph_steps"] == 0
+    for a, b in zip(seen_g, seen_d):
+        assert np.array_equal(a, b)
+    for a, b in zip(psi_g, psi_d):
+        assert np.array_equal(a, b)
+    for a, b in zip(r_g, r_d):
+        assert a == b
+    for i in (0, 3, 4):
+        ref, ro = run_oracle(specs[i], fs[i])
+        err, *_ = compare(specs[i], fs[i], r_g[i], psi_g[i], ref, ro, f"uneven[{i}]")
+        assert err <= PSI_TOL and r_g[i]["steps_done"] == specs[i].nsteps
 
 
 @pytest.mark.parametrize("n,variant,cap_row,cap_col,row_pts", [(512, 2, 1024, 512, 8), (256, 1, 4096, 8192, 16),
