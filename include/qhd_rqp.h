@@ -85,10 +85,13 @@ qhd_status qhd_rqp_set_objective(qhd_rqp h, int32_t i, const double *Q, const do
 qhd_status qhd_rqp_evolve(qhd_rqp h, int64_t max_steps, void *stream);
 
 /* Readouts of every instance into host `out` (batch entries); optional device outputs:
- * marginals_dev (FP32, [batch][d][r+1], axis k = 1..d) and prob_dev (FP32,
- * [batch][(r+1)^d], |phi|^2).  Synchronises `stream`.  QHD_ENUMERIC on a non-finite
- * readout. */
-qhd_status qhd_rqp_observe(qhd_rqp h, void *stream, qhd_rqp_obs *out, float *marginals_dev, float *prob_dev);
+ * marginals_dev (FP32, [batch][d][r+1], axis k = 1..d), prob_dev (FP32,
+ * [batch][(r+1)^d], |phi|^2) and psi_dev (interleaved complex FP32, [batch][(r+1)^d],
+ * j_1 fastest: the state phi at the current step, the trailing potential half step of
+ * the last step applied to this copy; the handle's own state keeps it owed).
+ * Synchronises `stream`.  QHD_ENUMERIC on a non-finite readout. */
+qhd_status qhd_rqp_observe(qhd_rqp h, void *stream, qhd_rqp_obs *out, float *marginals_dev, float *prob_dev,
+                           float *psi_dev);
 
 /* Back to phi_0 at step 0 (objectives kept). */
 qhd_status qhd_rqp_reset(qhd_rqp h, void *stream);

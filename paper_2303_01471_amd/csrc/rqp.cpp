@@ -323,13 +323,22 @@ qhd_status qhd_rqp_evolve(qhd_rqp h, int64_t max_steps, void* stream_v) {
   return QHD_OK;
 }
 
-qhd_status qhd_rqp_observe(qhd_rqp h, void* stream_v, qhd_rqp_obs* out, float* marginals_dev, float* prob_dev) {
+qhd_status qhd_rqp_observe(qhd_rqp h, void* stream_v, qhd_rqp_obs* out, float* marginals_dev, float* prob_dev,
+                           float* psi_dev) {
   set_error_message("");
   if (!h || !out) return rfail(QHD_EINVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream_v;
   RQP_TRY(hipSetDevice(h->device));
-  // the owed potential half step is a phase: |phi|^2, and every readout, is unchanged
-  RQP_TRY(rqp_observe(h->psi, h->f, h->N, h->batch, h->fmin, h->desc.min_tol, h->sums, prob_dev, st));
+  // the owed potential half step is a phase: |phi|^2, and every readout, is unchanged; the
+  // state output gets it (exp(-i (dt/2) b_{j-1} f) of the last step j-1, in turns)
+  double close_turns = 0.0;
+  if (psi_dev && h->pending && h->steps_done > 0) {
+    double a, b;
+    schedule(h, h->steps_done - 1, a, b);
+    close_turns = 0.5 * h->desc.dt * b * 0.15915494309189533577;
+  }
+  RQP_TRY(rqp_observe(h->psi, h->f, h->N, h->batch, h->fmin, h->desc.min_tol, h->sums, prob_dev,
+                      reinterpret_cast<float2*>(psi_dev), close_turns, st));
   if (marginals_dev) RQP_TRY(rqp_marginals(h->NP, h->psi, h->N, h->desc.dim, h->batch, marginals_dev, st));
   RQP_TRY(hipMemcpyAsync(h->host_sums, h->sums, sizeof(double) * 3 * h->batch, hipMemcpyDeviceToHost, st));
   RQP_TRY(hipStreamSynchronize(st));

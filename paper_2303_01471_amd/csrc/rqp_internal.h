@@ -25,7 +25,9 @@ hipError_t rqp_marginals(int NP, const float2* psi, long long N, int d, int batc
 hipError_t rqp_objective(double* f, const double* Qb, int d, int NP, long long N, int batch, hipStream_t st);
 hipError_t rqp_argmin(const double* f, long long N, int batch, double* fmin, long long* amin, hipStream_t st);
 hipError_t rqp_init(float2* psi, const double* amp, int d, int NP, long long N, int batch, hipStream_t st);
+// Sums per instance (rho, f rho, rho over the minimisers), optional rho output and, with
+// psi_out, the state times exp(-2 pi i close_turns f) (the owed potential half step)
 hipError_t rqp_observe(const float2* psi, const double* f, long long N, int batch, const double* fmin, double tol,
-                       double* out, float* prob, hipStream_t st);
+                       double* out, float* prob, float2* psi_out, double close_turns, hipStream_t st);
 
 }  // namespace qhd

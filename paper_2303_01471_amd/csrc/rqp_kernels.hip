@@ -246,7 +246,8 @@ __global__ void k_rqp_init(float2* __restrict__ psi, const double* __restrict__ 
 // order: per-thread strided partial sums, then a tree), optional rho output
 __global__ void __launch_bounds__(kThreads) k_rqp_observe(const float2* __restrict__ psi, const double* __restrict__ f,
                                                          long long N, const double* __restrict__ fmin, double tol,
-                                                         double* __restrict__ out, float* __restrict__ prob) {
+                                                         double* __restrict__ out, float* __restrict__ prob,
+                                                         float2* __restrict__ psi_out, double close_turns) {
   __shared__ double s0[kThreads], s1[kThreads], s2[kThreads];
   const long long off = (long long)blockIdx.x * N;
   const double thr = fmin[blockIdx.x] + tol;
@@ -259,6 +260,7 @@ __global__ void __launch_bounds__(kThreads) k_rqp_observe(const float2* __restri
     b = fma(fv, rho, b);
     if (fv <= thr) c += rho;
     if (prob) prob[off + p] = (float)rho;
+    if (psi_out) psi_out[off + p] = close_turns != 0.0 ? cmul_fd(v, phase_turns_d(close_turns * fv)) : v;
   }
   s0[threadIdx.x] = a;
   s1[threadIdx.x] = b;
@@ -423,8 +425,9 @@ hipError_t rqp_init(float2* psi, const double* amp, int d, int NP, long long N, 
 }
 
 hipError_t rqp_observe(const float2* psi, const double* f, long long N, int batch, const double* fmin, double tol,
-                       double* out, float* prob, hipStream_t st) {
-  hipLaunchKernelGGL(k_rqp_observe, dim3((unsigned)batch), dim3(kThreads), 0, st, psi, f, N, fmin, tol, out, prob);
+                       double* out, float* prob, float2* psi_out, double close_turns, hipStream_t st) {
+  hipLaunchKernelGGL(k_rqp_observe, dim3((unsigned)batch), dim3(kThreads), 0, st, psi, f, N, fmin, tol, out, prob,
+                     psi_out, close_turns);
   return hipGetLastError();
 }
 

@@ -202,7 +202,7 @@ _SIGNATURES = {
     "qhd_rqp_set_objective": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "qhd_rqp_evolve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "qhd_rqp_observe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(qhd_rqp_obs),
-                                       ctypes.c_void_p, ctypes.c_void_p]),
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "qhd_rqp_reset": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "qhd_rqp_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "qhd_rqp_destroy": (ctypes.c_int, [ctypes.c_void_p]),
@@ -383,8 +383,8 @@ def qhd_rqp_evolve(h: int, max_steps: int, stream: int):
     _check(load_library().qhd_rqp_evolve(h, max_steps, stream))
 
 
-def qhd_rqp_observe(h: int, stream: int, out, marginals_ptr: int, prob_ptr: int) -> int:
-    st = load_library().qhd_rqp_observe(h, stream, out, marginals_ptr or None, prob_ptr or None)
+def qhd_rqp_observe(h: int, stream: int, out, marginals_ptr: int, prob_ptr: int, psi_ptr: int = 0) -> int:
+    st = load_library().qhd_rqp_observe(h, stream, out, marginals_ptr or None, prob_ptr or None, psi_ptr or None)
     if st not in (QHD_OK, QHD_ENUMERIC):
         _check(st)
     return st

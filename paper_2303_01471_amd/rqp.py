@@ -44,19 +44,24 @@ class RelaxedQP:
     def reset(self, stream=None):
         q.qhd_rqp_reset(self.handle, q._stream_handle(stream))
 
-    def observe(self, stream=None, want_marginals: bool = False, want_prob: bool = False):
+    def observe(self, stream=None, want_marginals: bool = False, want_prob: bool = False, want_psi: bool = False):
         """Returns (list of dicts, marginals [batch, d, r+1] or None, prob [batch, (r+1)^d]
-        or None, status); the tensors are FP32 on the GPU."""
+        or None, status), and with want_psi the state [batch, (r+1)^d] (complex64, the owed
+        potential half step applied) as a fifth element; the tensors are on the GPU."""
         import torch
         out = (q.qhd_rqp_obs * self.batch)()
         marg = (torch.empty((self.batch, self.dim, self.r + 1), dtype=torch.float32, device="cuda")
                 if want_marginals else None)
         prob = torch.empty((self.batch, self.points), dtype=torch.float32, device="cuda") if want_prob else None
+        psi = torch.empty((self.batch, self.points), dtype=torch.complex64, device="cuda") if want_psi else None
         st = q.qhd_rqp_observe(self.handle, q._stream_handle(stream), out,
                                marg.data_ptr() if marg is not None else 0,
-                               prob.data_ptr() if prob is not None else 0)
+                               prob.data_ptr() if prob is not None else 0,
+                               psi.data_ptr() if psi is not None else 0)
         res = [dict(norm=o.norm, e_f=o.e_f, p_min=o.p_min, f_min=o.f_min, argmin_index=o.argmin_index,
                     steps_done=o.steps_done, t=o.t) for o in out]
+        if want_psi:
+            return res, marg, prob, st, psi
         return res, marg, prob, st
 
     def close(self):

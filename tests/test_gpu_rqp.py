@@ -13,6 +13,7 @@ from paper_2303_01471_amd import qhd as q
 pytestmark = pytest.mark.gpu
 
 RHO_TOL = 1e-5   # |phi|^2 per lattice point (psi bar 1e-4 on amplitudes of O(0.1))
+PSI_TOL = 1e-4   # phi per lattice point, element by element (the state bar of the QHD path)
 OBS_TOL = 1e-5
 
 
@@ -46,16 +47,16 @@ def _run(dim, r, probs, dt, nsteps, sched=q.QHD_SCHED_NESTEROV, p=(1e-3, 0.0), t
         for c in chunks or []:
             h.evolve(c)
         h.evolve()
-        res, marg, prob, st = h.observe(want_marginals=True, want_prob=True)
+        res, marg, prob, st, psi = h.observe(want_marginals=True, want_prob=True, want_psi=True)
         torch.cuda.synchronize()
-        return res, marg.cpu().numpy(), prob.cpu().numpy(), st
+        return res, marg.cpu().numpy(), prob.cpu().numpy(), st, psi.cpu().numpy()
     finally:
         h.close()
 
 
 def _check(dim, r, probs, dt, nsteps, label, **kw):
     from oracle import rqp_reference as rq
-    res, marg, prob, st = _run(dim, r, probs, dt, nsteps, **kw)
+    res, marg, prob, st, psis = _run(dim, r, probs, dt, nsteps, **kw)
     assert st == q.QHD_OK
     ab = _ab(kw.get("sched", q.QHD_SCHED_NESTEROV), kw.get("p", (1e-3, 0.0)), kw.get("table"), dt)
     worst = 0.0
@@ -64,10 +65,12 @@ def _check(dim, r, probs, dt, nsteps, label, **kw):
         psi = rq.evolve(f, rq.initial_state(dim, r), r, dt, nsteps, ab)
         ro = rq.readout(f, psi)
         drho = float(np.max(np.abs(prob[i] - (np.abs(psi) ** 2).reshape(-1))))
+        dpsi = float(np.max(np.abs(psis[i].astype(np.complex128) - psi.reshape(-1))))
         worst = max(worst, drho)
-        note(f"  {label}[{i}] d={dim} r={r} steps={nsteps}: max|drho|={drho:.2e} |norm-1|={abs(res[i]['norm'] - 1):.2e} "
+        note(f"  {label}[{i}] d={dim} r={r} steps={nsteps}: max|dpsi|={dpsi:.2e} max|drho|={drho:.2e} "
+             f"|norm-1|={abs(res[i]['norm'] - 1):.2e} "
              f"|dE[f]|={abs(res[i]['e_f'] - ro['e_f']):.2e} p_min {res[i]['p_min']:.4f} (ref {ro['p_min']:.4f})")
-        assert drho <= RHO_TOL
+        assert drho <= RHO_TOL and dpsi <= PSI_TOL
         assert abs(res[i]["norm"] - ro["norm"]) <= OBS_TOL and abs(res[i]["e_f"] - ro["e_f"]) <= OBS_TOL
         assert abs(res[i]["p_min"] - ro["p_min"]) <= OBS_TOL and abs(res[i]["f_min"] - ro["f_min"]) <= 1e-12
         assert np.unravel_index(res[i]["argmin_index"], f.shape) == np.unravel_index(np.argmin(f), f.shape)
@@ -79,6 +82,14 @@ def _check(dim, r, probs, dt, nsteps, label, **kw):
 def test_paper_setting_5d_r8_against_reference():
     note("case: relaxed QHD, QP-5d recipe, r = 8 (9^5 lattice), 3 instances, 100 steps")
     _check(5, 8, qhd_inputs.qp_instances(3, 5), 1e-2, 100, "qp5d")
+
+
+def test_bench_setting_full_length_amplitudes():
+    """The relaxed-QP leg of the benchmark at its length: 5-D, r = 8, dt = 1e-2, 1000 steps
+    (T = 10), the state compared element by element with the FP64 reference (Algorithm 2's
+    relaxed QHD, App. F)."""
+    note("case: relaxed QHD, QP-5d recipe, r = 8, 1 instance, 1000 steps")
+    _check(5, 8, qhd_inputs.qp_instances(1, 5), 1e-2, 1000, "qp5d-full")
 
 
 def test_lattice_shapes_at_the_staged_and_direct_limits():
@@ -101,8 +112,9 @@ def test_every_schedule_kind():
 def test_chunked_equals_one_shot_and_reset():
     from paper_2303_01471_amd.rqp import RelaxedQP
     probs = qhd_inputs.qp_instances(3, 4, 12)
-    _, _, p1, _ = _run(4, 8, probs, 1e-2, 70)
-    _, _, p2, _ = _run(4, 8, probs, 1e-2, 70, chunks=[1, 13, 30])
+    _, _, p1, _, s1 = _run(4, 8, probs, 1e-2, 70)
+    _, _, p2, _, s2 = _run(4, 8, probs, 1e-2, 70, chunks=[1, 13, 30])
+    assert np.array_equal(s1, s2)
     assert np.array_equal(p1, p2)
     h = RelaxedQP(4, 8, 3, 1e-2, 70)
     try:
@@ -120,13 +132,13 @@ def test_chunked_equals_one_shot_and_reset():
 def test_kinetic_ground_state_is_stationary():
     # b = 0: the discrete Gaussian is an eigenvector of A'_d, so |phi|^2 does not move
     from oracle import rqp_reference as rq
-    _, _, prob, _ = _run(5, 8, qhd_inputs.qp_instances(1, 5, 13), 1e-2, 200, sched=q.QHD_SCHED_CONST, p=(2.0, 0.0))
+    _, _, prob, _, _ = _run(5, 8, qhd_inputs.qp_instances(1, 5, 13), 1e-2, 200, sched=q.QHD_SCHED_CONST, p=(2.0, 0.0))
     want = (np.abs(rq.initial_state(5, 8)) ** 2).reshape(-1)
     assert np.max(np.abs(prob[0] - want)) < 1e-6
 
 
 def test_norm_drift_over_two_thousand_steps():
-    res, _, _, _ = _run(5, 8, qhd_inputs.qp_instances(8, 5, 14), 5e-3, 2000)
+    res, _, _, _, _ = _run(5, 8, qhd_inputs.qp_instances(8, 5, 14), 5e-3, 2000)
     drift = max(abs(r["norm"] - 1.0) for r in res)
     note(f"  relaxed QHD 9^5, 2000 steps: max |norm - 1| = {drift:.2e}")
     assert drift <= 1e-5
@@ -142,8 +154,8 @@ def test_fused_leading_axes_equal_one_pass_per_axis(monkeypatch):
              (2, 9, qhd_inputs.qp_instances(3, 2, 18), 1e-2, 50)]
     for dim, r, probs, dt, n in cases:
         monkeypatch.delenv("QHD_RQP_UNFUSED", raising=False)
-        _, _, fused, _ = _run(dim, r, probs, dt, n, chunks=[7])
+        _, _, fused, _, fpsi = _run(dim, r, probs, dt, n, chunks=[7])
         monkeypatch.setenv("QHD_RQP_UNFUSED", "1")
-        _, _, sep, _ = _run(dim, r, probs, dt, n, chunks=[7])
+        _, _, sep, _, spsi = _run(dim, r, probs, dt, n, chunks=[7])
         note(f"  d={dim} r={r}: fused vs per-axis max|drho| = {float(np.max(np.abs(fused - sep))):.2e}")
-        assert np.array_equal(fused, sep)
+        assert np.array_equal(fused, sep) and np.array_equal(fpsi, spsi)

@@ -105,3 +105,30 @@ def test_trajectory_snapshots_match_oracle_and_weights_are_a_distribution():
         assert abs(rec["e_f"] - ro.e_f) < 1e-4 and abs(rec["success_mass"] - ro.success) < 1e-4
         assert np.all(rec["weights"] >= 0) and np.sum(rec["weights"]) <= 1 + 1e-5
         assert np.all(np.diff(rec["energies"]) >= -1e-9)
+
+
+def test_trajectory_energy_ratio_at_the_semiclassical_limit_of_the_levy_model():
+    """App. D: with f the Levy function's quadratic model at its minimiser (w1 = 1.4979,
+    w2 = 0.3536), the lowest levels of H are the oscillator's and the energy ratio that
+    trajectory.run reports through qhd_spectrum is (w1 + 3 w2) / (w1 + w2) = 1.3819; the
+    dense FP64 reference on a coarser mesh of the same box gives the same."""
+    from paper_2303_01471_amd import trajectory
+    w1 = math.sqrt((math.pi ** 2 + 1.0 + 10.0 * math.sin(1.0) ** 2) / 8.0)
+    w2 = math.sqrt(1.0 / 8.0)
+    ratio = (w1 + 3.0 * w2) / (w1 + w2)
+    n, L = 128, 20.0
+    x = -L / 2 + np.arange(n) * (L / n)
+    f = 0.5 * (w1 ** 2 * x[None, :] ** 2 + w2 ** 2 * x[:, None] ** 2)
+    spec = q.InstanceSpec(shape=(n, n), nsteps=20, dt=1e-3, box=((-L / 2, L / 2), (-L / 2, L / 2)),
+                          sched=q.QHD_SCHED_CONST, sched_p=(1.0, 1.0))
+    snaps = trajectory.run(spec, f, times=(0.01, 0.02), nev=3, krylov=300)
+    xc = -L / 2 + np.arange(40) * (L / 40)
+    fc = 0.5 * (w1 ** 2 * xc[None, :] ** 2 + w2 ** 2 * xc[:, None] ** 2)
+    wd, _ = sr.lowest(fc, [(-L / 2, L / 2)] * 2, 1.0, 1.0, 2)
+    for rec in snaps:
+        note(f"  t={rec['t']:.3f}: levels {rec['energies']}, E1/E0 {rec['ratio_e1_e0']:.6f} "
+             f"(closed form {ratio:.6f}, dense {wd[1] / wd[0]:.6f})")
+        assert round(ratio, 4) == 1.3819
+        assert abs(rec["ratio_e1_e0"] - ratio) < 2e-3
+        assert abs(rec["energies"][0] - 0.5 * (w1 + w2)) < 2e-3
+    assert abs(wd[1] / wd[0] - ratio) < 1e-6
