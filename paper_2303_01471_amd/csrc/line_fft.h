@@ -263,20 +263,30 @@ struct Twiddles {
   __device__ __forceinline__ double2 get(int j) const { return w[STAGE - 1][j]; }
 };
 
-// The same twiddles read from LDS, laid out in lane order: for every stage s >= 1,
-// butterfly m and r = 1..R-1 there is a row of TPL entries, entry t holding lane
-// t's twiddle.  A lane keeps only its base address; each read is one ds_read_b128
-// with an immediate offset, and consecutive lanes read consecutive entries (no
-// bank conflicts).  Same values as Twiddles, so results are bitwise identical.
-template <int N, int P>
+// The same twiddles read from LDS, laid out in lane order: for every stage s >= 1 and
+// butterfly m there are rows of TPL entries, entry t holding lane t's twiddle.  A lane
+// keeps only its base address; each read is one ds_read_b128 with an immediate offset,
+// and consecutive lanes read consecutive entries (no bank conflicts).
+//   POW = false: one row per power r = 1..R-1, the values of Twiddles (bitwise equal
+//                results);
+//   POW = true:  one row of first powers w^1 = W_{Ns R}^{(v mod Ns)}; the powers r >= 2
+//                are formed by FP64 products (w^r = w^{r-1} w^1, relative error below
+//                1e-14 for r <= 15, far below the FP32 rounding of the product with the
+//                data).  Fewer LDS reads for more FP64 arithmetic and registers: measured
+//                faster for 128-, 512- (8 points per lane) and 1024-point lines, slower
+//                for 256-point lines and where the register budget is tight (512 points
+//                with 16 per lane spill the chain of powers).
+template <int N, int P, bool POW>
 struct TwiddlesLds {
   using SP = StagePlan<N, P>;
   static constexpr int kStages = SP::count();
   static constexpr int kTPL = N / P;
-  // rows before stage s (s >= 1)
+  static constexpr bool kPow = POW;
+  // rows of stage s: NB first powers, or NB (R - 1) powers
+  static constexpr int rows_of(int st) { return (P / SP::radix(st)) * (POW ? 1 : SP::radix(st) - 1); }
   static constexpr int rows_before(int st) {
     int c = 0;
-    for (int q = 1; q < st; ++q) c += (P / SP::radix(q)) * (SP::radix(q) - 1);
+    for (int q = 1; q < st; ++q) c += rows_of(q);
     return c;
   }
   static constexpr int kRows = rows_before(kStages);
@@ -284,14 +294,16 @@ struct TwiddlesLds {
   const double2* tab;  // this lane's column of the table
 
   // rows of stage ST: row (m, r) holds lane tt's W^{k r STEP}, k = (tt + m TPL) mod NS
+  // (r = 1 only when POW)
   template <int ST>
   __device__ __forceinline__ static void fill_stage(const double2* __restrict__ g, double2* lds_tab) {
     if constexpr (ST < kStages) {
-      constexpr int NS = SP::ns(ST), R = SP::radix(ST), NB = P / R, STEP = N / (NS * R);
-      constexpr int ROWS = NB * (R - 1), BASE = rows_before(ST);
-      for (int e = threadIdx.x; e < ROWS * kTPL; e += blockDim.x) {
+      constexpr int NS = SP::ns(ST), R = SP::radix(ST), STEP = N / (NS * R);
+      constexpr int RPM = POW ? 1 : R - 1;  // rows per butterfly
+      constexpr int BASE = rows_before(ST);
+      for (int e = threadIdx.x; e < rows_of(ST) * kTPL; e += blockDim.x) {
         const int j = e / kTPL, tt = e % kTPL;  // powers of two: shifts and masks
-        const int m = j / (R - 1), r = j - m * (R - 1) + 1;
+        const int m = j / RPM, r = j - m * RPM + 1;
         const int k = (tt + m * kTPL) % NS;
         lds_tab[BASE * kTPL + e] = g[(k * r * STEP) & (N - 1)];
       }
@@ -307,9 +319,33 @@ struct TwiddlesLds {
     tab = lds_tab + t;
   }
 
+  // row j of stage STAGE: power (j mod RPM) + 1 of butterfly j / RPM
   template <int STAGE>
   __device__ __forceinline__ double2 get(int j) const { return tab[(rows_before(STAGE) + j) * kTPL]; }
 };
+
+// w * v with both in FP64 (twiddle powers)
+__device__ __forceinline__ double2 cmul_dd(double2 w, double2 v) {
+  return make_double2(fma(w.x, v.x, -w.y * v.y), fma(w.x, v.y, w.y * v.x));
+}
+
+// Twiddles w^r = W^{k r STEP}, r = 1..R-1, of one butterfly group from its first power
+// (TwiddlesLds with POW): applied to u[1..R-1] while the next power is formed.
+template <typename TW>
+struct TwPowers : std::false_type {};
+template <int N, int P>
+struct TwPowers<TwiddlesLds<N, P, true>> : std::true_type {};
+
+template <int S, int STAGE, int R, typename W, typename TW>
+__device__ __forceinline__ void apply_twiddle_powers(W (&u)[R], const TW& tw, int m) {
+  const double2 w1 = tw.template get<STAGE>(m);
+  double2 wr = w1;
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    u[r] = S < 0 ? cmul_fd(u[r], wr) : cmul_fd_conj(u[r], wr);
+    if (r + 1 < R) wr = cmul_dd(wr, w1);
+  }
+}
 
 // One Stockham stage on the lane's registers.  If LAST, results stay in the
 // lane's own layout; otherwise they are scattered to LDS for the next stage.
@@ -335,10 +371,14 @@ __device__ __forceinline__ void fft_stage(float2 (&reg)[P], int t, const TW& tw,
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = reg[m + r * NB];
     if constexpr (STAGE > 0) {
+      if constexpr (TwPowers<TW>::value) {
+        apply_twiddle_powers<S, STAGE>(u, tw, m);
+      } else {
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const double2 w = tw.template get<STAGE>(m * (R - 1) + (r - 1));
-        u[r] = S < 0 ? cmul_fd(u[r], w) : cmul_fd_conj(u[r], w);
+        for (int r = 1; r < R; ++r) {
+          const double2 w = tw.template get<STAGE>(m * (R - 1) + (r - 1));
+          u[r] = S < 0 ? cmul_fd(u[r], w) : cmul_fd_conj(u[r], w);
+        }
       }
     }
     dft<R, S>(u);
@@ -406,10 +446,14 @@ __device__ __forceinline__ void fft_stage_io(const A (&src)[P], B (&dst)[P], int
 #pragma unroll
     for (int r = 0; r < R; ++r) assign(u[r], src[m + r * NB]);
     if constexpr (STAGE > 0) {
+      if constexpr (TwPowers<TW>::value) {
+        apply_twiddle_powers<S, STAGE>(u, tw, m);
+      } else {
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const double2 w = tw.template get<STAGE>(m * (R - 1) + (r - 1));
-        u[r] = S < 0 ? cmul_fd(u[r], w) : cmul_fd_conj(u[r], w);
+        for (int r = 1; r < R; ++r) {
+          const double2 w = tw.template get<STAGE>(m * (R - 1) + (r - 1));
+          u[r] = S < 0 ? cmul_fd(u[r], w) : cmul_fd_conj(u[r], w);
+        }
       }
     }
     dft<R, S>(u);
@@ -461,11 +505,16 @@ __device__ __forceinline__ void line_fft_io(TIN (&in)[P], TOUT (&out)[P], int t,
 // Twiddle storage per line length: an LDS table for the long lines (register
 // pressure), per-lane registers for the short ones.
 template <int N, int P>
-using TwiddlesFor = typename std::conditional<(N >= 128), TwiddlesLds<N, P>, Twiddles<N, P>>::type;
+struct TwPow {
+  static constexpr bool value = N != 256 && !(N == 512 && P == 16);
+};
+template <int N, int P>
+using TwiddlesFor =
+    typename std::conditional<(N >= 128), TwiddlesLds<N, P, TwPow<N, P>::value>, Twiddles<N, P>>::type;
 
 template <int N, int P>
 struct TwLdsSize {
-  static constexpr int value = N >= 128 ? TwiddlesLds<N, P>::kEntries : 1;
+  static constexpr int value = N >= 128 ? TwiddlesLds<N, P, TwPow<N, P>::value>::kEntries : 1;
 };
 
 // load either kind (the LDS kind needs its table slot and a block-uniform call site)
@@ -473,8 +522,8 @@ template <int N, int P>
 __device__ __forceinline__ void load_twiddles(Twiddles<N, P>& tw, const double2* __restrict__ g, double2*, int t) {
   tw.load(g, t);
 }
-template <int N, int P>
-__device__ __forceinline__ void load_twiddles(TwiddlesLds<N, P>& tw, const double2* __restrict__ g, double2* l,
+template <int N, int P, bool POW>
+__device__ __forceinline__ void load_twiddles(TwiddlesLds<N, P, POW>& tw, const double2* __restrict__ g, double2* l,
                                               int t) {
   tw.load(g, l, t);
 }
