@@ -55,10 +55,14 @@ __global__ void __launch_bounds__((XCfg<NX>::NT)) k_xpass_3d(const InstDev* __re
   using C = XCfg<NX>;
   constexpr int P = C::P, W = C::W, STRIDE = C::STRIDE;
   __shared__ float2 lds[64 * STRIDE];
+  __shared__ double2 twl[TwLdsSize<NX, P>::value];
   const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
   float2* my = lds + lane * STRIDE;
-  Twiddles<NX, P> tw;
-  tw.load(twtab, t);
+  // twiddles from an LDS table (a wavefront's lanes share t, so each read is a
+  // broadcast): with the register cache (16 FP64 pairs per lane at 128 points) the pass
+  // took 1.48x as long on 16 x 128^3
+  TwiddlesFor<NX, P> tw;
+  load_twiddles(tw, twtab, twl, t);
   const int tiles_log2 = ny_log2 + nz_log2 - 6;  // 8 x 8 tiles per plane
   const long long plane = 1LL << (ny_log2 + nz_log2);
   const long long total = (long long)ninst << tiles_log2;
@@ -223,6 +227,148 @@ __global__ void __launch_bounds__((PlaneCfg<NY, NZ>::NT)) k_plane_3d(const InstD
 }
 
 // ------------------------------------------------------------------------------------
+// plane pass, direct form (64- and 128-point y-lines): a row line of NY points takes 8
+// lanes (NY / 8 points each, lane t holding y = t + 8 q), so a wavefront's 8 row lines
+// are the 8 z-rows of one tile row and every slot of theirs is one whole 8 x 8 tile of
+// the HBM plane: the first row phase loads from HBM straight into registers and the
+// second stores from registers, and only the column phase reads the plane from LDS.
+// The row lines exchange inside their own rows of the plane buffer (wavefront-local,
+// no block barrier), then write their results there for the column phase.  Lines of
+// 128 points take 16 points per lane (radices 16 and 8: one exchange per transform).
+//
+// LDS placement (the LDS serves an 8-byte access 16 lanes per clock over 32 four-byte
+// banks, so each group of 16 lanes should touch 16 distinct bank pairs): point (y, z) at
+// z RS + y with RS = 2 (mod 16).  The 16 lanes of a group hold two row lines z and
+// z + 4 (4 RS = 8 mod 16), whose accesses are 8 consecutive bank pairs each (row
+// exchange slot i + i/16), or two column lines y and y + 1, whose accesses are 8
+// distinct even bank pairs each (column exchange slot: z = i with its low four bits
+// rotated by i/16, so the radix-16 scatter does not put a line's 8 lanes on one bank).
+struct PlaneRowIx {
+  __device__ static constexpr int at(int i) { return i + (i >> 4); }
+};
+template <int RS>
+struct PlaneColIx {
+  __device__ static constexpr int at(int i) { return ((i & ~15) | ((i + (i >> 4)) & 15)) * RS; }
+};
+
+template <int NY, int NZ>
+struct PlaneDCfg {
+  static constexpr int TY = 8, PY = NY / 8;       // lanes per row line, points per lane
+  static constexpr int PZ = NZ >= 128 ? 16 : 8;   // points per lane of a column line
+  static constexpr int TZ = NZ / PZ;
+  // row lines per 8 lanes (two, in blocks of 512 threads without spills, measured 4 %
+  // slower at 128 x 128 than one in blocks of 1024)
+  static constexpr int ROW_ITS = 1;
+  static constexpr int NT = NZ * TY / ROW_ITS;
+  static constexpr int RS = ((NY + NY / 16 + 13) / 16) * 16 + 2;  // row stride, = 2 (mod 16)
+  static constexpr int COLS_PER_IT = NT / TZ;
+  static constexpr bool SHARE_TW = NY == NZ && PY == PZ;
+};
+
+template <int NY, int NZ, bool Y4>
+__global__ void __launch_bounds__((PlaneDCfg<NY, NZ>::NT)) k_plane_direct_3d(const InstDev* __restrict__ inst,
+                                                                             const int* __restrict__ nact_p, int nx,
+                                                                             float2* __restrict__ psi,
+                                                                             const double2* __restrict__ twy,
+                                                                             const double2* __restrict__ twz, int s,
+                                                                             long long max_steps) {
+  const int ninst = *nact_p;  // members active in this sub-step (device, set per chunk)
+  using C = PlaneDCfg<NY, NZ>;
+  constexpr int TY = C::TY, PY = C::PY, PZ = C::PZ, TZ = C::TZ, NT = C::NT, RS = C::RS;
+  constexpr int PLANE = NY * NZ;
+  static_assert(NY == 64 || NY == 128, "direct plane pass: 64- or 128-point y-lines");
+  __shared__ float2 st[NZ * RS];
+  __shared__ double2 twly[TwLdsSize<NY, PY>::value];
+  __shared__ double2 twlz[C::SHARE_TW ? 1 : TwLdsSize<NZ, PZ>::value];
+  __shared__ double2 ezl[NZ];  // E_z(k_z) / (nx ny nz) of the plane's instance and step
+  const int tid = threadIdx.x;
+  // row phase: line li of a wavefront's 8 takes z-row 8 w + 4 (li & 1) + li / 2, so the
+  // two lines of each group of 16 lanes are 4 rows apart; lane rt of the line
+  const int li = (tid >> 3) & 7;
+  const int rz0 = ((tid >> 6) << 3) + ((li & 1) << 2) + (li >> 1), rt = tid % TY;
+  constexpr int ROW_ITS = C::ROW_ITS, RSTEP = NT / TY;  // row lines of a lane: rz0 + it RSTEP
+  const int cl = tid / TZ, ct = tid % TZ;  // column phase
+  TwiddlesFor<NY, PY> ty;
+  load_twiddles(ty, twy, twly, rt);
+  TwiddlesFor<NZ, PZ> tz;
+  load_twiddles(tz, twz, C::SHARE_TW ? twly : twlz, ct);
+  const double inv_n = 1.0 / ((double)nx * (double)NY * (double)NZ);
+  const long long total = (long long)ninst * nx;
+  // this lane's first element of its first row line in a plane: y = rt, z = rz0
+  const int row_off = (rz0 >> 3) * (NY / 8) * 64 + (rz0 & 7) * 8 + rt;
+  double cached = -1.0;  // E_z depends on the instance and step only through a_j pi dt / L_z^2
+  for (long long g = blockIdx.x; g < total; g += gridDim.x) {
+    const int i = (int)(g / nx), x = (int)(g - (long long)i * nx);
+    const InstDev& I = inst[i];
+    if (!(s < step_limit(I, max_steps))) continue;  // block-uniform
+    double a, b;
+    sched_ab<Y4>(I, I.steps_done + s, a, b);
+    const double cz = a * I.kin_turns[2];
+    if (cz != cached) {
+      // the previous plane's readers of the table passed the barrier after its column phase
+      for (int k = tid; k < NZ; k += NT) {
+        const int nzf = freq(k, NZ);
+        const double2 e = phase_turns_d(cz * (double)(nzf * nzf));
+        ezl[k] = make_double2(e.x * inv_n, e.y * inv_n);
+      }
+      cached = cz;
+    }
+    float2* __restrict__ rowg = psi + I.psi_off + (long long)x * PLANE + row_off;
+    // row phase: F_y on every z-row, from HBM (slot q of a wavefront is one tile)
+#pragma unroll 1
+    for (int it = 0; it < ROW_ITS; ++it) {
+      float2* my = st + (rz0 + it * RSTEP) * RS;
+      const float2* rg = rowg + it * (RSTEP / 8) * (NY / 8) * 64;
+      float2 reg[PY];
+#pragma unroll
+      for (int q = 0; q < PY; ++q) reg[q] = rg[q * 64];
+      line_fft<NY, PY, -1, false, PlaneRowIx>(reg, rt, ty, my);
+#pragma unroll
+      for (int q = 0; q < PY; ++q) my[rt + q * TY] = reg[q];
+    }
+    __syncthreads();
+    // column phase: F_z . K . F_z^{-1}, K = E_x E_y E_z / (nx ny nz) in FP64
+    const int nxf = freq(x, nx);
+    const double cx = a * I.kin_turns[0] * (double)(nxf * nxf);
+#pragma unroll 1
+    for (int y = cl; y < NY; y += C::COLS_PER_IT) {
+      float2* mc = st + y;
+      float2 reg[PZ];
+#pragma unroll
+      for (int q = 0; q < PZ; ++q) reg[q] = mc[(ct + q * TZ) * RS];
+      double2 kd[PZ];
+      wave_lds_sync();
+      line_fft_io<NZ, PZ, -1, false, PlaneColIx<RS>>(reg, kd, ct, tz, mc);
+      const int nyf = freq(y, NY);
+      const double2 exy = phase_turns_d(fma(a * I.kin_turns[1], (double)(nyf * nyf), cx));
+#pragma unroll
+      for (int q = 0; q < PZ; ++q) {
+        const double2 ez = ezl[ct + q * TZ];
+        kd[q] = cmul_fd(kd[q], make_double2(fma(exy.x, ez.x, -exy.y * ez.y), fma(exy.x, ez.y, exy.y * ez.x)));
+      }
+      line_fft_io<NZ, PZ, +1, false, PlaneColIx<RS>>(kd, reg, ct, tz, mc);
+#pragma unroll
+      for (int q = 0; q < PZ; ++q) mc[(ct + q * TZ) * RS] = reg[q];
+    }
+    __syncthreads();
+    // row phase: F_y^{-1}, to HBM
+#pragma unroll 1
+    for (int it = 0; it < ROW_ITS; ++it) {
+      float2* my = st + (rz0 + it * RSTEP) * RS;
+      float2* rg = rowg + it * (RSTEP / 8) * (NY / 8) * 64;
+      float2 reg[PY];
+#pragma unroll
+      for (int q = 0; q < PY; ++q) reg[q] = my[rt + q * TY];
+      wave_lds_sync();
+      line_fft<NY, PY, +1, false, PlaneRowIx>(reg, rt, ty, my);
+#pragma unroll
+      for (int q = 0; q < PY; ++q) rg[q * 64] = reg[q];
+      wave_lds_sync();  // the next row line (or plane) reuses this wavefront's rows
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // observe in the plane layout: the x-pass's item and lane layout; closes the pending
 // F_x^{-1} and trailing half step, writes the user-layout psi / rho (optional), and one
 // FP64 partial triple per x-line (sum rho, sum f rho, sum of rho inside the success
@@ -368,8 +514,18 @@ hipError_t launch_x(int ny, int nz, const InstDev* inst, int ninst, const int* n
 template <int NY, int NZ>
 hipError_t launch_plane(int nx, const InstDev* inst, int ninst, const int* nact, float2* psi, const double2* twy,
                         const double2* twz, int s, long long max_steps, int cap, bool y4, hipStream_t stream) {
-  using C = PlaneCfg<NY, NZ>;
   const int blocks = blocks3d((long long)ninst * nx, cap);
+  if constexpr (NY >= 64) {
+    using C = PlaneDCfg<NY, NZ>;
+    if (y4)
+      hipLaunchKernelGGL((k_plane_direct_3d<NY, NZ, true>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, nx, psi,
+                         twy, twz, s, max_steps);
+    else
+      hipLaunchKernelGGL((k_plane_direct_3d<NY, NZ, false>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, nx,
+                         psi, twy, twz, s, max_steps);
+    return hipGetLastError();
+  }
+  using C = PlaneCfg<NY, NZ>;
   if (y4)
     hipLaunchKernelGGL((k_plane_3d<NY, NZ, true>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, nx, psi, twy, twz,
                        s, max_steps);
