@@ -57,8 +57,10 @@ def kernel_source_hash() -> str:
     """Hash of the pass kernels' code (comments and whitespace removed): the key under
     which HBM counter readings are kept."""
     h = hashlib.sha256()
-    for rel in ("paper_2303_01471_amd/csrc/qhd_kernels.hip", "paper_2303_01471_amd/csrc/line_fft.h",
-                "paper_2303_01471_amd/csrc/pass_common.h", "paper_2303_01471_amd/csrc/qhd_internal.h"):
+    for rel in ("paper_2303_01471_amd/csrc/qhd_kernels.hip", "paper_2303_01471_amd/csrc/qhd_kernels_3d.hip",
+                "paper_2303_01471_amd/csrc/qhd_kernels_mfma.hip", "paper_2303_01471_amd/csrc/rqp_kernels.hip",
+                "paper_2303_01471_amd/csrc/line_fft.h", "paper_2303_01471_amd/csrc/pass_common.h",
+                "paper_2303_01471_amd/csrc/qhd_internal.h", "paper_2303_01471_amd/csrc/rqp_internal.h"):
         with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
             code = re.sub(r"/\*.*?\*/|//[^\n]*", " ", fh.read(), flags=re.S)
         h.update(" ".join(code.split()).encode())
@@ -87,6 +89,21 @@ def kernel_table(kt):
     return out
 
 
+def measured_traffic(family: str):
+    """HBM bytes per point of a family from the committed counter summary, when it was
+    taken on the current kernel sources; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        tj = json.load(open(TRAFFIC_FILE))
+        ent = tj.get("kernels", {}).get(family)
+        if tj.get("source_hash") == kernel_source_hash() and ent:
+            return ent["hbm_bytes_per_point"]
+    except Exception:
+        return None
+    return None
+
+
 def roofline_of(kt):
     """Dominant kernel family (largest summed time): algorithmic bytes per mean launch /
     mean HIP-event duration, and the counter-measured HBM bytes of a mean launch when the
@@ -97,15 +114,8 @@ def roofline_of(kt):
     if dom is None:
         return None
     achieved = dom["points"] * dom["bytes_per_point"] / (dom["total_ms"] * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            tj = json.load(open(TRAFFIC_FILE))
-            ent = tj.get("kernels", {}).get(dom["name"])
-            if tj.get("source_hash") == kernel_source_hash() and ent:
-                traffic = round(ent["hbm_bytes_per_point"] * dom["points"] / dom["launches"], 1)
-        except Exception:
-            traffic = None
+    hb = measured_traffic(dom["name"])
+    traffic = round(hb * dom["points"] / dom["launches"], 1) if hb is not None else None
     return {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "algorithmic_bytes_per_point": dom["bytes_per_point"],
@@ -219,12 +229,15 @@ def rqp_summary(secs, res, points, probs, nsteps, r):
     achieved = rate * bpp / 1e9
     flops = 8.0 * np_ * d  # every axis: np_ complex multiply-adds per point in FP64
     k = rqp_fused_axes(d, np_)
+    hb = measured_traffic("rqp_step")  # HBM bytes per lattice point and step (counters)
+    step_points = float(points) * len(probs)
     return {"gp_steps_per_s": round(rate, 1), "grid_point_steps": gp,
             "roofline": {"bound": "hbm",
                          "kernel": f"relaxed-QP step (axes 1-{k} fused in one LDS pass, {d - k} more axis "
                                    f"passes, r+1={np_})",
                          "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": round(hb * step_points, 1) if hb is not None else None,
                          "algorithmic_bytes_per_point": bpp,
                          "fp64_flop_per_point": flops,
                          "fp64_achieved_tflops": round(rate * flops / 1e12, 2),
@@ -235,10 +248,19 @@ def rqp_summary(secs, res, points, probs, nsteps, r):
             "mean_gap_e_f_minus_f_min": round(float(np.mean([x["e_f"] - x["f_min"] for x in res])), 4)}
 
 
+def rqp_points(q, qhd_inputs, count=256, d=5, r=8):
+    """Lattice points per step of the relaxed-QP batch and its algorithmic bytes per
+    point-step (for the counter summary's rqp_step entry)."""
+    return {"rqp_step": count * (r + 1) ** d, "rqp_bytes_per_point": RQP_BYTES_PER_POINT_STEP(d, r + 1)}
+
+
 def main_rqp(args, q, np, torch, qhd_inputs):
     """--workload rqp: the relaxed-QP batch is the measured workload."""
     probs = qhd_inputs.qp_instances(256, 5)
     r, dt, nsteps = 8, 1e-2, 1000
+    if args.points_json:
+        with open(args.points_json, "w") as fh:
+            json.dump(rqp_points(q, qhd_inputs, len(probs), 5, r), fh)
     if args.cap_steps > 0:
         nsteps = min(nsteps, args.cap_steps)
     stream = torch.cuda.current_stream()
@@ -315,8 +337,10 @@ def main():
                          "steps (QHD_OPT_RESIDENT); by default that configuration is timed separately")
     ap.add_argument("--no-resident", action="store_true",
                     help="skip the resident-vs-streaming leg (it reuses the 64^2/128^2 pass kernels)")
-    ap.add_argument("--surrogate-pairs", type=int, default=4096)
+    ap.add_argument("--surrogate-pairs", type=int, default=20000,
+                    help="solver-generated training pairs of the surrogate leg (1 %% more are held out)")
     ap.add_argument("--surrogate-epochs", type=float, default=4.0)
+    ap.add_argument("--surrogate-batch", type=int, default=4096, help="surrogate inference batch")
     ap.add_argument("--cpu-sample-steps", type=int, default=1000000,
                     help="cap on the oracle steps of the CPU-baseline sample")
     ap.add_argument("--cpu-sample-gp", type=float, default=1.2e9,
@@ -356,7 +380,8 @@ def main():
     if not args.no_surrogate and args.workload == "batched2d":
         from paper_2303_01471_amd import screen
         t0 = time.time()
-        sur_f = screen.make_landscapes(args.surrogate_pairs, 5_000_000, 128, workers=16)
+        n_hold = max(64, args.surrogate_pairs // 100)  # a 1 % held-out slice beside the training pairs
+        sur_f = screen.make_landscapes(args.surrogate_pairs + n_hold, 5_000_000, 128, workers=16)
         log(f"surrogate landscapes: {len(sur_f)} x 128^2 in {time.time() - t0:.1f}s")
 
     import torch
@@ -366,9 +391,6 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     q.load_library()
-    if args.workload == "rqp":
-        return main_rqp(args, q, np, torch, qhd_inputs)
-
     if args.copy_calibration_mib > 0:
         # one elementwise kernel that reads and writes the buffer once (the only
         # torch elementwise launch of a counter run)
@@ -380,6 +402,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log(f"copy calibration: {args.copy_calibration_mib} MiB read + written by one elementwise kernel")
+    if args.workload == "rqp":
+        return main_rqp(args, q, np, torch, qhd_inputs)
 
     qaa = args.workload == "qaa"
     if args.workload == "3d":
@@ -403,10 +427,15 @@ def main():
         for leg, tag in legs:
             for s in leg:
                 n = s.shape[0]
-                fams = ((f"xpass_3d/n{n}", f"plane_3d/n{n}x{n}") if len(s.shape) == 3
-                        else (f"row_pass_2d{tag}/n{n}", f"col_pass_2d{tag}/n{n}"))
+                if len(s.shape) == 3:
+                    fams = ((f"xpass_3d_mfma/n{n}", f"ypass_3d_mfma/n{n}", f"zpass_3d_mfma/n{n}") if args.mfma_dft
+                            else (f"xpass_3d/n{n}", f"plane_3d/n{n}x{n}"))
+                else:
+                    fams = (f"row_pass_2d{tag}/n{n}", f"col_pass_2d{tag}/n{n}")
                 for fam in fams:
                     pts[fam] = pts.get(fam, 0) + s.points
+        if args.workload == "batched2d" and not args.no_qaa_summary:
+            pts.update(rqp_points(q, qhd_inputs))  # the relaxed-QP leg
         with open(args.points_json, "w") as fh:
             json.dump(pts, fh)
     total_gp = float(sum(s.points * s.nsteps for s in specs))
@@ -746,16 +775,18 @@ def main():
         rho_dev, succ, solve_s = screen.solve(f_dev, T=10.0, dt=0.01)
         n_plain = 8
         _, _, plain_s = screen.solve(f_dev[:n_plain], T=10.0, dt=0.01, chunk=1)
-        n_hold = max(64, len(sur_f) // 16)
-        n_train = len(sur_f) - n_hold
+        n_train = args.surrogate_pairs
+        n_hold = len(sur_f) - n_train
         net = Surrogate(grid=128, width=32, modes=16, layers=4, max_batch=32, precision="bf16", train=True, seed=1)
         hist = screen.train(net, f_dev[:n_train], rho_dev[:n_train], args.surrogate_epochs, 32, 2e-3)
         params = net.get_params()
         net.close()
-        inf = Surrogate(grid=128, width=32, modes=16, layers=4, max_batch=1024, precision="bf16", train=False)
+        ib = min(args.surrogate_batch, len(sur_f))
+        inf = Surrogate(grid=128, width=32, modes=16, layers=4, max_batch=ib, precision="bf16", train=False)
         inf.set_params(params)
-        pred = screen.predict(inf, f_dev[n_train:], min(1024, n_hold)).cpu().numpy().astype(np.float64)
-        rate = screen.throughput(inf, f_dev, min(1024, len(sur_f)))
+        pred = screen.predict(inf, f_dev[n_train:], min(ib, n_hold)).cpu().numpy().astype(np.float64)
+        rate = screen.throughput(inf, f_dev, ib)
+        rate_1024 = screen.throughput(inf, f_dev, min(1024, ib))
         inf.close()
         ev = screen.evaluate(pred, rho_dev[n_train:].cpu().numpy().astype(np.float64), sur_f[n_train:],
                              succ[n_train:], rho_dev[:n_train].mean(dim=0).cpu().numpy().astype(np.float64))
@@ -765,7 +796,8 @@ def main():
                      "train_pairs": n_train, "heldout": n_hold, "epochs": round(hist["epochs"], 2),
                      "train_seconds": round(hist["seconds"], 2),
                      "train_samples_per_s": round(hist["samples_per_s"], 1),
-                     "inference_landscapes_per_s": round(rate, 1), "inference_batch": 1024,
+                     "inference_landscapes_per_s": round(rate, 1), "inference_batch": ib,
+                     "inference_landscapes_per_s_batch_1024": round(rate_1024, 1),
                      "solver_batched_landscapes_per_s": round(batched_rate, 1),
                      "solver_plain_landscapes_per_s": round(plain_rate, 1),
                      "speedup_vs_batched_solver": round(rate / batched_rate, 2),

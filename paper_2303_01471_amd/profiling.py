@@ -5,11 +5,12 @@
         --kernel-trace --stats view), one line per kernel
     python -m paper_2303_01471_amd.profiling counters DB
         mean value per dispatch of every collected counter, per kernel
-    python -m paper_2303_01471_amd.profiling traffic FETCH_DB WRITE_DB --copy-bytes B --source-hash H
+    python -m paper_2303_01471_amd.profiling traffic FETCH_DB:WRITE_DB:POINTS_JSON [...] --copy-bytes B --source-hash H
         HBM bytes per grid point of every pass kernel from FETCH_SIZE and
         WRITE_SIZE, each scaled by what the same counter reads for one
-        elementwise kernel that reads and writes B bytes in the same run; JSON
-        (profiles/traffic.json format)
+        elementwise kernel that reads and writes B bytes in the same run; one
+        triple per benchmark run (its two counter databases and its points-per-
+        dispatch map), merged into one JSON (profiles/traffic.json format)
 
 Dispatch sizes (grid points per launch) come from the kernel arguments of the
 pass kernels as recorded by the benchmark (every instance active, steps capped).
@@ -61,18 +62,29 @@ def counter_means(db: str):
 # pass kernel -> (family name used by the library's timing, algorithmic bytes per point);
 # the 2-D kernels' third template argument is the model (0 QHD, 1 QAA), a last boolean
 # one whether the fourth-order stage arithmetic is compiled in
+def _model_suffix(m, i=2):
+    return "_qaa" if (m.re.groups >= i and m.group(i) == "1") else ""
+
+
 _FAMILY = [
-    (re.compile(r"k_row_pass_2d<(\d+), \d+(?:, (\d+))?(?:, (?:true|false))?>"), "row_pass_2d{}/n{}", 24.0),
-    (re.compile(r"k_col_pass_(?:2d|tw)<(\d+), \d+(?:, (\d+))?(?:, (?:true|false))?>"), "col_pass_2d{}/n{}", 16.0),
-    (re.compile(r"k_lf_row_2d<(\d+), \d+>()"), "row_pass_2d_qaa_lf{}/n{}", 20.0),
-    (re.compile(r"k_lf_col_2d<(\d+), \d+>()"), "col_pass_2d_qaa_lf{}/n{}", 20.0),
-    (re.compile(r"k_line_pass_1d<(\d+),"), "line_pass_1d{}/n{}", 24.0),
+    (re.compile(r"k_row_pass_2d<(\d+), \d+(?:, (\d+))?(?:, (?:true|false))?>"),
+     lambda m: f"row_pass_2d{_model_suffix(m)}/n{m.group(1)}", 24.0),
+    (re.compile(r"k_col_pass_(?:2d|tw)<(\d+), \d+(?:, (\d+))?(?:, (?:true|false))?>"),
+     lambda m: f"col_pass_2d{_model_suffix(m)}/n{m.group(1)}", 16.0),
+    (re.compile(r"k_lf_row_2d<(\d+), \d+>"), lambda m: f"row_pass_2d_qaa_lf/n{m.group(1)}", 20.0),
+    (re.compile(r"k_lf_col_2d<(\d+), \d+>"), lambda m: f"col_pass_2d_qaa_lf/n{m.group(1)}", 20.0),
+    (re.compile(r"k_line_pass_1d<(\d+),"), lambda m: f"line_pass_1d/n{m.group(1)}", 24.0),
+    # 3-D: the x-pass (psi read and written, f read) and the (y, z)-plane pass
+    (re.compile(r"k_xpass_3d<(\d+),"), lambda m: f"xpass_3d/n{m.group(1)}", 24.0),
+    (re.compile(r"k_plane(?:_direct)?_3d<(\d+), (\d+),"), lambda m: f"plane_3d/n{m.group(1)}x{m.group(2)}", 16.0),
+    # matrix-core DFT passes (128^3): AXIS 0 MODE 1 is the x-pass, MODE 0 the y-pass, MODE 2 the z-pass
+    (re.compile(r"k_mfma_pass_3d<0, 1>"), lambda m: "xpass_3d_mfma/n128", 24.0),
+    (re.compile(r"k_mfma_pass_3d<1, 0>"), lambda m: "ypass_3d_mfma/n128", 16.0),
+    (re.compile(r"k_mfma_pass_3d<2, 2>"), lambda m: "zpass_3d_mfma/n128", 16.0),
 ]
 
-
-def _family_name(fam: str, m) -> str:
-    model = m.group(2) if m.re.groups >= 2 else None
-    return fam.format("_qaa" if model == "1" else "", m.group(1))
+# relaxed-QP kernels of one step (psi read and written per axis pass, f read once)
+_RQP_STEP = re.compile(r"k_rqp_(?:fused|axis_staged|axis_direct)\b")
 
 
 def family_of(kernel: str):
@@ -80,7 +92,7 @@ def family_of(kernel: str):
     for rx, fam, bpp in _FAMILY:
         m = rx.search(kernel)
         if m:
-            return _family_name(fam, m), bpp
+            return fam(m), bpp
     return None
 
 
@@ -119,6 +131,19 @@ def traffic(fetch_db: str, write_db: str, copy_bytes: float, points_per_dispatch
                                     "write_bytes_per_point": write / pts,
                                     "hbm_bytes_per_point": (fetch + write) / pts,
                                     "algorithmic_bytes_per_point": bpp}
+    # relaxed QP: all step kernels together (one fused pass per step, then one pass per
+    # remaining axis), bytes per lattice point and step
+    rq = sorted(k for k in fe if _RQP_STEP.search(k))
+    pts = points_per_dispatch.get("rqp_step")
+    steps = sum(nfe[k] for k in rq if "fused" in k)
+    if rq and pts and steps:
+        fetch = sum(fe[k]["FETCH_SIZE"] * nfe[k] for k in rq) * 1024.0 * f_scale
+        write = sum(wr.get(k, {}).get("WRITE_SIZE", 0.0) * nwr.get(k, 0) for k in rq) * 1024.0 * w_scale
+        out["kernels"]["rqp_step"] = {"kernel": " + ".join(rq), "points_per_dispatch": pts, "steps": steps,
+                                      "fetch_bytes_per_point": fetch / (pts * steps),
+                                      "write_bytes_per_point": write / (pts * steps),
+                                      "hbm_bytes_per_point": (fetch + write) / (pts * steps),
+                                      "algorithmic_bytes_per_point": points_per_dispatch.get("rqp_bytes_per_point")}
     return out
 
 
@@ -130,10 +155,8 @@ def main(argv=None):
     b = sub.add_parser("counters")
     b.add_argument("db")
     c = sub.add_parser("traffic")
-    c.add_argument("fetch_db")
-    c.add_argument("write_db")
+    c.add_argument("runs", nargs="+", help="FETCH_DB:WRITE_DB:POINTS_JSON (points: family -> points per dispatch)")
     c.add_argument("--copy-bytes", type=float, required=True)
-    c.add_argument("--points", required=True, help="JSON map family -> points per dispatch")
     c.add_argument("--source-hash", required=True)
     args = ap.parse_args(argv)
     if args.cmd == "kernels":
@@ -146,9 +169,19 @@ def main(argv=None):
         for k, d in sorted(means.items()):
             print(f"{k} dispatches={n[k]} " + " ".join(f"{c}={v:.1f}" for c, v in sorted(d.items())))
     else:
-        pts = json.loads(args.points)
-        json.dump(traffic(args.fetch_db, args.write_db, args.copy_bytes, pts, args.source_hash),
-                  sys.stdout, indent=1)
+        merged = None
+        for run in args.runs:
+            fdb, wdb, pfile = run.split(":")
+            with open(pfile) as fh:
+                pts = json.load(fh)
+            t = traffic(fdb, wdb, args.copy_bytes, pts, args.source_hash)
+            t["runs"] = [{k: t[k] for k in ("copy_kernel", "fetch_scale", "write_scale")} | {"fetch_db": fdb}]
+            if merged is None:
+                merged = t
+            else:
+                merged["kernels"].update(t["kernels"])
+                merged["runs"] += t["runs"]
+        json.dump(merged, sys.stdout, indent=1)
         print()
 
 

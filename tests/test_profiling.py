@@ -13,6 +13,12 @@ def test_families_of_the_pass_kernels():
     assert f("k_col_pass_tw<256, 8, true>") == ("col_pass_2d/n256", 16.0)
     assert f("k_lf_row_2d<64, 8>") == ("row_pass_2d_qaa_lf/n64", 20.0)
     assert f("k_argmin") is None
+    assert f("k_xpass_3d<128, false>") == ("xpass_3d/n128", 24.0)
+    assert f("k_plane_direct_3d<128, 128, true>") == ("plane_3d/n128x128", 16.0)
+    assert f("k_plane_3d<32, 16, false>") == ("plane_3d/n32x16", 16.0)
+    assert f("k_mfma_pass_3d<0, 1>") == ("xpass_3d_mfma/n128", 24.0)
+    assert f("k_mfma_pass_3d<1, 0>") == ("ypass_3d_mfma/n128", 16.0)
+    assert f("k_mfma_pass_3d<2, 2>") == ("zpass_3d_mfma/n128", 16.0)
     assert profiling._short("void qhd::(anonymous namespace)::k_rqp_fused<9>(HIP_vector_type<float, 2u>*, "
                             "double const*)") == "k_rqp_fused<9>"
 
@@ -46,3 +52,28 @@ def test_traffic_scales_by_the_copy_kernel_and_takes_the_main_instantiation(tmp_
     k = out["kernels"]["col_pass_2d/n512"]
     assert k["kernel"] == main
     assert abs(k["hbm_bytes_per_point"] - 16.0) < 1e-9 and k["algorithmic_bytes_per_point"] == 16.0
+
+
+def test_relaxed_qp_step_traffic_sums_the_step_kernels(tmp_path):
+    """One fused pass (24 B/pt) and one axis pass (16 B/pt) per step, two steps."""
+    copy = "at::native::vectorized_elementwise_kernel<4, MulFunctor>"
+    pts = 1 << 16
+    fe = [(copy, "FETCH_SIZE", 1024.0, 1)]
+    wr = [(copy, "WRITE_SIZE", 1024.0, 1)]
+    d = 10
+    for step in range(2):
+        fe.append(("k_rqp_fused<9>", "FETCH_SIZE", pts * 16 / 1024, d))
+        wr.append(("k_rqp_fused<9>", "WRITE_SIZE", pts * 8 / 1024, d))
+        fe.append(("k_rqp_axis_direct<9>", "FETCH_SIZE", pts * 8 / 1024, d + 1))
+        wr.append(("k_rqp_axis_direct<9>", "WRITE_SIZE", pts * 8 / 1024, d + 1))
+        fe.append(("k_rqp_matrix<9>", "FETCH_SIZE", 5.0, d + 2))  # not a pass over the lattice
+        wr.append(("k_rqp_matrix<9>", "WRITE_SIZE", 1.0, d + 2))
+        d += 3
+    _db(tmp_path / "fe.db", fe)
+    _db(tmp_path / "wr.db", wr)
+    out = profiling.traffic(str(tmp_path / "fe.db"), str(tmp_path / "wr.db"), float(1 << 20),
+                            {"rqp_step": pts, "rqp_bytes_per_point": 40.0}, "h")
+    k = out["kernels"]["rqp_step"]
+    assert k["steps"] == 2
+    assert abs(k["fetch_bytes_per_point"] - 24.0) < 1e-9 and abs(k["write_bytes_per_point"] - 16.0) < 1e-9
+    assert abs(k["hbm_bytes_per_point"] - 40.0) < 1e-9 and k["algorithmic_bytes_per_point"] == 40.0
