@@ -271,7 +271,7 @@ __global__ void __launch_bounds__((PlaneDCfg<NY, NZ>::NT)) k_plane_direct_3d(con
                                                                              float2* __restrict__ psi,
                                                                              const double2* __restrict__ twy,
                                                                              const double2* __restrict__ twz, int s,
-                                                                             long long max_steps) {
+                                                                             long long max_steps, double inv_n) {
   const int ninst = *nact_p;  // members active in this sub-step (device, set per chunk)
   using C = PlaneDCfg<NY, NZ>;
   constexpr int TY = C::TY, PY = C::PY, PZ = C::PZ, TZ = C::TZ, NT = C::NT, RS = C::RS;
@@ -292,7 +292,6 @@ __global__ void __launch_bounds__((PlaneDCfg<NY, NZ>::NT)) k_plane_direct_3d(con
   load_twiddles(ty, twy, twly, rt);
   TwiddlesFor<NZ, PZ> tz;
   load_twiddles(tz, twz, C::SHARE_TW ? twly : twlz, ct);
-  const double inv_n = 1.0 / ((double)nx * (double)NY * (double)NZ);
   const long long total = (long long)ninst * nx;
   // this lane's first element of its first row line in a plane: y = rt, z = rz0
   const int row_off = (rz0 >> 3) * (NY / 8) * 64 + (rz0 & 7) * 8 + rt;
@@ -517,12 +516,13 @@ hipError_t launch_plane(int nx, const InstDev* inst, int ninst, const int* nact,
   const int blocks = blocks3d((long long)ninst * nx, cap);
   if constexpr (NY >= 64) {
     using C = PlaneDCfg<NY, NZ>;
+    const double inv_n = 1.0 / ((double)nx * (double)NY * (double)NZ);
     if (y4)
       hipLaunchKernelGGL((k_plane_direct_3d<NY, NZ, true>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, nx, psi,
-                         twy, twz, s, max_steps);
+                         twy, twz, s, max_steps, inv_n);
     else
       hipLaunchKernelGGL((k_plane_direct_3d<NY, NZ, false>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, nx,
-                         psi, twy, twz, s, max_steps);
+                         psi, twy, twz, s, max_steps, inv_n);
     return hipGetLastError();
   }
   using C = PlaneCfg<NY, NZ>;
