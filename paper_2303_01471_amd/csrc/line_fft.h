@@ -475,6 +475,51 @@ __device__ __forceinline__ void fft_stage_io(const A (&src)[P], B (&dst)[P], int
   }
 }
 
+// The compute-and-write half of an exchanged stage: stage STAGE of the lane's values
+// (working type W) written to its LDS line at the Stockham output positions, with no
+// synchronisation and no read-back.  The caller synchronises (a workgroup barrier when
+// other lanes read the line next) and reads the next stage's inputs with
+// stage_inputs(); fft_stage_io is these two halves with wavefront-local syncs.
+template <int N, int P, int S, int STAGE, typename W, typename IX, typename A, typename TW>
+__device__ __forceinline__ void stage_outputs_to_lds(const A (&src)[P], int t, const TW& tw, float2* __restrict__ lds) {
+  using SP = StagePlan<N, P>;
+  constexpr int NS = SP::ns(STAGE);
+  constexpr int R = SP::radix(STAGE);
+  constexpr int NB = P / R;
+  constexpr int TPL = N / P;
+  static_assert(STAGE < SP::count() - 1, "the last stage keeps its results in registers");
+#pragma unroll
+  for (int m = 0; m < NB; ++m) {
+    W u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) assign(u[r], src[m + r * NB]);
+    if constexpr (STAGE > 0) {
+      if constexpr (TwPowers<TW>::value) {
+        apply_twiddle_powers<S, STAGE>(u, tw, m);
+      } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const double2 w = tw.template get<STAGE>(m * (R - 1) + (r - 1));
+          u[r] = S < 0 ? cmul_fd(u[r], w) : cmul_fd_conj(u[r], w);
+        }
+      }
+    }
+    dft<R, S>(u);
+    const int v = t + m * TPL;
+    const int base = (v / NS) * NS * R + (v % NS);
+#pragma unroll
+    for (int r = 0; r < R; ++r) assign(lds[IX::at(base + r * NS)], u[r]);
+  }
+}
+
+// the inputs of the next stage, positions t + q TPL of the LDS line
+template <int N, int P, typename IX>
+__device__ __forceinline__ void stage_inputs(float2 (&dst)[P], int t, const float2* __restrict__ lds) {
+  constexpr int TPL = N / P;
+#pragma unroll
+  for (int q = 0; q < P; ++q) dst[q] = lds[IX::at(t + q * TPL)];
+}
+
 template <int N, int P, int S, bool BLOCK_SYNC, int STAGE, typename IX, typename TW>
 __device__ __forceinline__ void fft_mid_stages(float2 (&reg)[P], int t, const TW& tw, float2* __restrict__ lds) {
   if constexpr (STAGE < StagePlan<N, P>::count() - 1) {

@@ -425,7 +425,7 @@ bool tune_lookup(const std::string& path, const std::string& key, ShapeClass& c)
     if (strncmp(line, key.c_str(), k) != 0 || line[k] != ' ') continue;
     int v = 0, cr = 0, cc = 0, rp = 8;
     const int got = sscanf(line + k, "%d %d %d %d", &v, &cr, &cc, &rp);
-    if (got >= 3 && v >= kColAuto && v <= kColStaged16 && cr >= 0 && cc >= 0 && (rp == 8 || rp == 16)) {
+    if (got >= 3 && v >= kColAuto && v <= kColSplit && cr >= 0 && cc >= 0 && (rp == 8 || rp == 16)) {
       c.col_variant = v;  // the last matching line wins
       c.cap_row = cr;
       c.cap_col = cc;
@@ -492,6 +492,7 @@ qhd_status autotune_class(qhd_plan p, ShapeClass& c, double& us_row, double& us_
   std::vector<int> variants = {kColStaged};
   if (col_variant_resolve(c.ny, kColTileWave) == kColTileWave) variants.push_back(kColTileWave);
   if (col_variant_resolve(c.ny, kColStaged16) == kColStaged16) variants.push_back(kColStaged16);
+  if (c.model == kModelQHD && col_variant_resolve(c.ny, kColSplit) == kColSplit) variants.push_back(kColSplit);
   for (int v : variants)
     for (int cap : caps) {
       const double t = time_launches(p->internal, a, b, reps, [&] {

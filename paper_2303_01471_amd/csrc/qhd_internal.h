@@ -64,9 +64,11 @@ hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, co
                               int grid_cap, int points_per_lane, hipStream_t stream, int model = kModelQHD,
                               bool y4 = true);
 // column-pass variants: staged (tile column through LDS, one wavefront per line, 8
-// or 16 points per lane) or tile-wave (8x8 tiles straight to registers, a line spread
-// over TPL/8 wavefronts); kColAuto takes the measured default for the size
-enum { kColAuto = 0, kColStaged = 1, kColTileWave = 2, kColStaged16 = 3 };
+// or 16 points per lane), tile-wave (8x8 tiles straight to registers, a line spread
+// over TPL/8 wavefronts) or split (512 points: the first forward and the last inverse
+// stage in the tile-wave layout, straight from and to HBM, the stages between one
+// wavefront per line); kColAuto takes the measured default for the size
+enum { kColAuto = 0, kColStaged = 1, kColTileWave = 2, kColStaged16 = 3, kColSplit = 4 };
 int col_variant_resolve(int ny, int variant);
 // points per lane of the row pass: 8, or 16 (chosen for 256 and 512; always at 1024)
 int row_points_resolve(int nx, int points_per_lane);

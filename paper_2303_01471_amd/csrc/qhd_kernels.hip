@@ -381,6 +381,125 @@ __global__ void __launch_bounds__((ColCfg<NY, P, true>::NT)) __attribute__((amdg
 }
 
 // ------------------------------------------------------------------------------------
+// 2-D column pass, split form (512-point columns, QHD).  A block of 8 wavefronts takes
+// one tile column (8 columns x 512 rows) per item, in two lane layouts:
+//   tile view   lane l of wavefront w holds column l & 7, rows t + 64 q with
+//               t = (l >> 3) + 8 w: slot q of a wavefront is one whole 8x8 tile, loaded
+//               from (and stored to) HBM straight into registers;
+//   line view   wavefront w holds column w as one line, lane t = l with rows t + 64 q.
+// The tile view runs the first forward stage and writes its outputs to the columns'
+// LDS lines; after a block barrier each wavefront transforms its line (forward stages
+// 1-2, the last in FP64, K = E_x E_y / (nx ny) in FP64, inverse stage 0 in FP64 and
+// stage 1) with wavefront-local exchanges and writes the last stage's inputs back; after
+// a second barrier the tile view runs the last inverse stage and stores.  The staged
+// form's tile scatter, line read, line write and tile gather (four LDS round trips per
+// point) become two.  The next item's tiles are loaded into registers while the current
+// item's lines are transformed.
+
+template <int NY>
+struct ColSplitCfg {
+  static constexpr int P = 8, TPL = NY / P, NT = 512;
+  static constexpr int STRIDE = ColCfg<NY, P, true>::STRIDE;  // line stride in LDS slots
+};
+
+template <int NY, bool Y4>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_col_pass_split(
+    const InstDev* __restrict__ inst, const int* __restrict__ nact_p, int nx_log2, float2* __restrict__ psi,
+    const double2* __restrict__ twtab, int s, long long max_steps) {
+  const int ninst = *nact_p;  // members active in this sub-step (device, set per chunk)
+  using C = ColSplitCfg<NY>;
+  constexpr int P = C::P, TPL = C::TPL, NT = C::NT, STRIDE = C::STRIDE;
+  static_assert(TPL == 64 && StagePlan<NY, P>::count() == 3, "split form: 512-point lines, radices 8, 8, 8");
+  __shared__ float2 lds[8 * STRIDE];
+  __shared__ double2 eyl[NY];
+  __shared__ double2 twl[TwLdsSize<NY, P>::value];
+  // the wavefront index is uniform: tile offsets are then scalar and not held per lane
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c_tv = lane & 7, t_tv = (lane >> 3) + 8 * wave;  // tile view: column, line position
+  float2* my = lds + wave * STRIDE;                           // line view: this wavefront's column
+  float2* mc = lds + c_tv * STRIDE;                           // tile view: this lane's column
+  TwiddlesFor<NY, P> tw;
+  load_twiddles(tw, twtab, twl, lane);
+  TwiddlesFor<NY, P> twt = tw;  // the same table seen from the tile view's line positions
+  twt.tab = twl + t_tv;
+  const int nx = 1 << nx_log2, tc_log2 = nx_log2 - 3, tcols = nx >> 3;
+  const long long total = (long long)ninst << tc_log2;
+  const double inv_n = 1.0 / ((double)nx * (double)NY);
+  long long begin, end;
+  block_share(total, 1, begin, end);
+  double cached = -1.0;  // E_y depends on the instance only through a_j * pi dt / L_y^2
+  // tile view: slot q of the item is tile row wave + 8 q of its tile column, lane = the
+  // position inside the tile
+  float2 pf[P];
+  auto fetch = [&](long long g) -> bool {
+    const int i = (int)(g >> tc_log2), tc = (int)(g & (tcols - 1));
+    const InstDev& I = inst[i];
+    if (!(s < step_limit(I, max_steps))) return false;
+    const float2* __restrict__ src = psi + I.psi_off + tc * 64 + lane;
+#pragma unroll
+    for (int q = 0; q < P; ++q) pf[q] = src[(long long)(wave + 8 * q) * tcols * 64];
+    return true;
+  };
+  bool pf_live = begin < end && fetch(begin);
+  for (long long g0 = begin; g0 < end; ++g0) {
+    const int i = (int)(g0 >> tc_log2), tc = (int)(g0 & (tcols - 1));
+    const InstDev& I = inst[i];
+    const bool active = pf_live;  // the item's instance takes this sub-step
+    double a, b;
+    sched_ab<Y4>(I, I.steps_done + s, a, b);
+    const double cy = a * I.kin_turns[1];
+    if (cy != cached) {
+      // E_y / (nx ny) for the item's instance; the previous item's readers passed its
+      // second barrier
+      for (int k = tid; k < NY; k += NT) {
+        const int nyf = freq(k, NY);
+        const double2 e = phase_turns_d(cy * (double)(nyf * nyf));
+        eyl[k] = make_double2(e.x * inv_n, e.y * inv_n);
+      }
+      cached = cy;
+    }
+    // tile view: forward stage 0 into the lines
+    stage_outputs_to_lds<NY, P, -1, 0, float2, SlotIx>(pf, t_tv, twt, mc);
+    __syncthreads();
+    pf_live = g0 + 1 < end && fetch(g0 + 1);
+    // line view: forward stages 1 and 2 (FP64), K, inverse stages 0 (FP64) and 1
+    {
+      float2 reg[P];
+      stage_inputs<NY, P, SlotIx>(reg, lane, my);
+      wave_lds_sync();
+      fft_stage_io<NY, P, -1, 1, false, float2, SlotIx>(reg, reg, lane, tw, my);
+      double2 kd[P];
+      fft_stage_io<NY, P, -1, 2, false, double2, SlotIx>(reg, kd, lane, tw, my);
+      const int nxf = freq(tc * 8 + wave, nx);
+      const double2 ex = phase_turns_d(a * I.kin_turns[0] * (double)(nxf * nxf));
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        // E_x E_y and its product with psi in FP64 (a factor rounded to FP32 has a
+        // one-sided magnitude error where its phase is tiny)
+        const double2 eq = eyl[lane + q * TPL];
+        const double2 k = make_double2(fma(ex.x, eq.x, -ex.y * eq.y), fma(ex.x, eq.y, ex.y * eq.x));
+        kd[q] = cmul_fd(kd[q], k);
+      }
+      fft_stage_io<NY, P, +1, 0, false, double2, SlotIx>(kd, reg, lane, tw, my);
+      stage_outputs_to_lds<NY, P, +1, 1, float2, SlotIx>(reg, lane, tw, my);
+    }
+    __syncthreads();
+    // tile view: inverse stage 2, to HBM
+    {
+      float2 x[P];
+      stage_inputs<NY, P, SlotIx>(x, t_tv, mc);
+      fft_stage_io<NY, P, +1, 2, false, float2, SlotIx>(x, x, t_tv, twt, mc);
+      if (active) {
+        float2* __restrict__ dst = psi + I.psi_off + tc * 64 + lane;
+#pragma unroll
+        for (int q = 0; q < P; ++q) dst[(long long)(wave + 8 * q) * tcols * 64] = x[q];
+      }
+    }
+    __syncthreads();  // the next item's first stage rewrites the lines
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // 2-D column pass, tile-wave form (NY >= 64).  Lane l of wavefront w of an item
 // owns column c = l & 7 of a tile column and row group t = (l >> 3) + 8 w, and
 // holds the rows t + q*TPL (q = 0..P-1).  Slot q of a wavefront is then exactly
@@ -1126,8 +1245,10 @@ int col_variant_resolve(int ny, int variant) {
   const bool tw_ok = ny >= 64 && ny <= 512;
   if (variant == kColTileWave && tw_ok) return kColTileWave;
   if (variant == kColStaged16 && (ny == 256 || ny == 512)) return kColStaged16;
+  if (variant == kColSplit && ny == 512) return kColSplit;
   if (variant == kColStaged) return kColStaged;
-  return (ny >= 64 && ny <= 256) ? kColTileWave : kColStaged;  // measured defaults
+  // measured defaults (the split form: 62 vs 66-72 us for the staged one on 48 x 512^2)
+  return (ny >= 64 && ny <= 256) ? kColTileWave : (ny == 512 ? kColSplit : kColStaged);
 }
 
 int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant) {
@@ -1140,6 +1261,8 @@ int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant) {
   } else if (v == kColStaged16) {
     const int tpl = ny / 16;
     items = (8 * tpl >= 256) ? 1 : 256 / (8 * tpl);
+  } else if (v == kColSplit) {
+    items = 1;
   } else {
     const int tpl = ny / 8;
     items = (8 * tpl >= 256) ? 1 : 256 / (8 * tpl);
@@ -1192,6 +1315,11 @@ hipError_t col_pass_qhd(int nx, int ny, const InstDev* inst, int ninst, const in
   const int v = col_variant_resolve(ny, variant);
   if (v == kColTileWave) {
     QHD_SWITCH_N(ny, { return (launch_col_tw<N_, Y4>)(blocks, nx, inst, ninst, nact, psi, tw, s, max_steps, stream); });
+  }
+  if (v == kColSplit) {
+    hipLaunchKernelGGL((k_col_pass_split<512, Y4>), dim3(blocks), dim3(ColSplitCfg<512>::NT), 0, stream, inst, nact,
+                       ilog2(nx), psi, tw, s, max_steps);
+    return hipGetLastError();
   }
   if (v == kColStaged16) {
     if (ny == 256)

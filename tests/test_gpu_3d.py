@@ -1,5 +1,6 @@
-"""3-D parity of the HIP path with the FP64 oracle (four streaming passes per
-step: x, y forward, z with the kinetic factor, y inverse)."""
+"""3-D parity of the HIP path with the FP64 oracle (two passes per step: the x-pass
+and the (y, z)-plane pass; the plane pass takes its direct form, rows loaded and stored
+as whole tiles, for 64- and 128-point y-lines and its staged form below)."""
 import numpy as np
 import pytest
 
@@ -48,6 +49,26 @@ def test_3d_shapes_against_oracle():
     res, psis, _, st = run_gpu(specs, fs)
     assert st == q.QHD_OK
     _check(specs, fs, res, psis, "3d")
+
+
+def test_3d_direct_plane_shapes_against_oracle():
+    """The direct plane pass at every y-line length it takes (64, 128) against z-lines of
+    16 to 128 points (8 or 16 points per lane, one to sixteen tile rows of z), in one plan
+    with a staged-form shape beside them; x short so that the oracle stays quick."""
+    note("case: direct plane shapes")
+    specs = [
+        q.InstanceSpec(shape=(16, 64, 16), nsteps=50, dt=2e-3),
+        q.InstanceSpec(shape=(128, 64, 16), nsteps=30, dt=2e-3, box=[(0.0, 2.0), (-0.5, 0.5), (0.0, 1.0)],
+                       radius=0.25),
+        q.InstanceSpec(shape=(32, 128, 16), nsteps=40, dt=2e-3, sched=q.QHD_SCHED_CONST, sched_p=(0.6, 2.0)),
+        q.InstanceSpec(shape=(64, 128, 16), nsteps=35, dt=2e-3),
+        q.InstanceSpec(shape=(64, 64, 32), nsteps=25, dt=2e-3),
+        q.InstanceSpec(shape=(16, 32, 16), nsteps=40, dt=2e-3),
+    ]
+    fs = [_f3(40 + k, s.shape, s.box) for k, s in enumerate(specs)]
+    res, psis, _, st = run_gpu(specs, fs)
+    assert st == q.QHD_OK
+    _check(specs, fs, res, psis, "3d-direct")
 
 
 def test_3d_128_cubed_batch():

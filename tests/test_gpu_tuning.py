@@ -3,8 +3,9 @@ what they compute.
 
 * step-chunk graphs: bitwise identical to direct launches, over uneven evolve
   calls with readouts between them;
-* column-pass variants chosen through the tuning cache (staged / tile-wave,
-  grid sizes): each matches the FP64 oracle;
+* column-pass variants chosen through the tuning cache (staged / tile-wave / split,
+  grid sizes): each matches the FP64 oracle, and the split 512-point form is bitwise
+  the staged one (same stages in the same precision, other lanes);
 * the autotuner writes a cache entry that a later plan reads back."""
 import os
 
@@ -98,7 +99,8 @@ def test_uneven_multiclass_graph_replay_is_bitwise_identical_to_direct_launches(
 
 @pytest.mark.parametrize("n,variant,cap_row,cap_col,row_pts", [(512, 2, 1024, 512, 8), (256, 1, 4096, 8192, 16),
                                                                (128, 1, 512, 1024, 8), (64, 2, 2048, 512, 8),
-                                                               (512, 3, 2048, 4096, 16), (256, 3, 8192, 1024, 8)])
+                                                               (512, 3, 2048, 4096, 16), (256, 3, 8192, 1024, 8),
+                                                               (512, 4, 8192, 512, 16)])
 def test_cached_launch_choice_matches_oracle(tmp_path, n, variant, cap_row, cap_col, row_pts):
     import torch
     note(f"case: tuning-cache entry n={n} variant={variant} caps=({cap_row},{cap_col}) row points {row_pts}")
@@ -135,3 +137,31 @@ def test_autotune_writes_cache_that_a_later_plan_reads(tmp_path):
     for a, b in zip(p1, p2):
         assert np.array_equal(a, b)
     assert abs(r1[0]["norm"] - 1.0) < 1e-5
+
+
+def test_split_column_pass_is_bitwise_the_staged_form(tmp_path):
+    """512-point columns: the split form (first forward and last inverse stage in the
+    tile layout, straight from and to HBM) against the staged form, forced through the
+    tuning cache, on uneven members (the visited prefix shrinks) and over several grid
+    caps (items per block vary): bitwise equal states and readouts."""
+    import torch
+    note("case: split vs staged 512-point column pass")
+    arch = torch.cuda.get_device_properties(0).gcnArchName.replace(" ", "_").replace(":", "_")
+    specs = [q.InstanceSpec(shape=(512, 512), nsteps=n, dt=1e-3) for n in (120, 97, 64, 33)]
+    fs = [qhd_inputs.landscape_grid(110 + k, (512, 512)) for k in range(4)]
+    out = {}
+    for variant, cap in ((1, 512), (4, 512), (4, 96)):
+        cache = tmp_path / f"tune{variant}_{cap}.txt"
+        cache.write_text(f"qhd-tune 1 {arch} 512 512 4 {variant} 8192 {cap} 8\n")
+        res, psis, seen, info = _run(specs, fs, chunks=(40, 17), tune_cache=str(cache))
+        assert info["classes"][0]["col_variant"] == variant
+        out[(variant, cap)] = (res, psis, seen)
+    ref = out[(1, 512)]
+    for key in ((4, 512), (4, 96)):
+        res, psis, seen = out[key]
+        for a, b in zip(ref[2], seen):
+            assert np.array_equal(a, b)
+        for a, b in zip(ref[1], psis):
+            assert np.array_equal(a, b)
+        for a, b in zip(ref[0], res):
+            assert a == b
