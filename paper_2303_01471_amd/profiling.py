@@ -1,8 +1,9 @@
 """Summaries of rocprofv3 output (rocpd SQLite databases) for the engine.
 
-    python -m paper_2303_01471_amd.profiling kernels DB
+    python -m paper_2303_01471_amd.profiling kernels DB [--isolated]
         per-kernel dispatch count, total / mean / min / max duration (the
-        --kernel-trace --stats view), one line per kernel
+        --kernel-trace --stats view), one line per kernel; --isolated keeps only
+        dispatches that overlapped no other one
     python -m paper_2303_01471_amd.profiling counters DB
         mean value per dispatch of every collected counter, per kernel
     python -m paper_2303_01471_amd.profiling traffic FETCH_DB:WRITE_DB:POINTS_JSON [...] --copy-bytes B --source-hash H
@@ -32,9 +33,34 @@ def _short(name: str) -> str:
     return n.strip()
 
 
-def kernel_stats(db: str):
+def _isolated(rows):
+    """indices of the dispatches whose [start, end) overlaps no other dispatch"""
+    order = sorted(range(len(rows)), key=lambda i: rows[i][1])
+    keep = set()
+    max_end = None  # latest end among the dispatches started before
+    for pos, i in enumerate(order):
+        st, en = rows[i][1], rows[i][2]
+        nxt = rows[order[pos + 1]][1] if pos + 1 < len(order) else None
+        if (max_end is None or max_end <= st) and (nxt is None or nxt >= en):
+            keep.add(i)
+        max_end = en if max_end is None else max(max_end, en)
+    return keep
+
+
+def kernel_stats(db: str, isolated: bool = False):
+    """Per-kernel duration statistics; with ``isolated`` only over dispatches that ran
+    alone on the device (no other dispatch overlapping them), the view of the library's
+    serialised timing chunks."""
     con = sqlite3.connect(db)
-    rows = con.execute("select name, duration from kernels").fetchall()
+    if isolated:
+        cols = [r[1] for r in con.execute("pragma table_info(kernels)")]
+        st = "start" if "start" in cols else "start_ns"
+        en = "end" if "end" in cols else "end_ns"
+        rows = con.execute(f'select name, "{st}", "{en}" from kernels').fetchall()
+        keep = _isolated(rows)
+        rows = [(rows[i][0], rows[i][2] - rows[i][1]) for i in sorted(keep)]
+    else:
+        rows = con.execute("select name, duration from kernels").fetchall()
     agg = collections.defaultdict(list)
     for name, dur in rows:
         agg[_short(name)].append(dur)
@@ -71,6 +97,7 @@ _FAMILY = [
      lambda m: f"row_pass_2d{_model_suffix(m)}/n{m.group(1)}", 24.0),
     (re.compile(r"k_col_pass_(?:2d|tw)<(\d+), \d+(?:, (\d+))?(?:, (?:true|false))?>"),
      lambda m: f"col_pass_2d{_model_suffix(m)}/n{m.group(1)}", 16.0),
+    (re.compile(r"k_col_pass_split<(\d+),"), lambda m: f"col_pass_2d/n{m.group(1)}", 16.0),
     (re.compile(r"k_lf_row_2d<(\d+), \d+>"), lambda m: f"row_pass_2d_qaa_lf/n{m.group(1)}", 20.0),
     (re.compile(r"k_lf_col_2d<(\d+), \d+>"), lambda m: f"col_pass_2d_qaa_lf/n{m.group(1)}", 20.0),
     (re.compile(r"k_line_pass_1d<(\d+),"), lambda m: f"line_pass_1d/n{m.group(1)}", 24.0),
@@ -152,6 +179,8 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("kernels")
     a.add_argument("db")
+    a.add_argument("--isolated", action="store_true",
+                   help="only dispatches that overlap no other dispatch (serialised timing chunks)")
     b = sub.add_parser("counters")
     b.add_argument("db")
     c = sub.add_parser("traffic")
@@ -161,7 +190,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.cmd == "kernels":
         print(f"{'calls':>8} {'total_ms':>10} {'mean_us':>10} {'min_us':>9} {'max_us':>9}  kernel")
-        for r in kernel_stats(args.db):
+        for r in kernel_stats(args.db, args.isolated):
             print(f"{r['calls']:8d} {r['total_ns'] / 1e6:10.3f} {r['mean_ns'] / 1e3:10.2f} "
                   f"{r['min_ns'] / 1e3:9.2f} {r['max_ns'] / 1e3:9.2f}  {r['kernel']}")
     elif args.cmd == "counters":

@@ -13,6 +13,7 @@ def test_families_of_the_pass_kernels():
     assert f("k_col_pass_tw<256, 8, true>") == ("col_pass_2d/n256", 16.0)
     assert f("k_lf_row_2d<64, 8>") == ("row_pass_2d_qaa_lf/n64", 20.0)
     assert f("k_argmin") is None
+    assert f("k_col_pass_split<512, false>") == ("col_pass_2d/n512", 16.0)
     assert f("k_xpass_3d<128, false>") == ("xpass_3d/n128", 24.0)
     assert f("k_plane_direct_3d<128, 128, true>") == ("plane_3d/n128x128", 16.0)
     assert f("k_plane_3d<32, 16, false>") == ("plane_3d/n32x16", 16.0)
@@ -77,3 +78,19 @@ def test_relaxed_qp_step_traffic_sums_the_step_kernels(tmp_path):
     assert k["steps"] == 2
     assert abs(k["fetch_bytes_per_point"] - 24.0) < 1e-9 and abs(k["write_bytes_per_point"] - 16.0) < 1e-9
     assert abs(k["hbm_bytes_per_point"] - 40.0) < 1e-9 and k["algorithmic_bytes_per_point"] == 40.0
+
+
+def test_isolated_dispatches_are_those_that_overlap_no_other(tmp_path):
+    con = sqlite3.connect(tmp_path / "k.db")
+    con.execute('create table kernels (name text, start integer, "end" integer, duration integer)')
+    rows = [("a", 0, 10), ("b", 5, 12), ("a", 20, 30), ("c", 30, 35), ("a", 40, 50), ("b", 45, 60), ("c", 55, 58)]
+    con.executemany("insert into kernels values (?, ?, ?, ?)", [(n, s_, e, e - s_) for n, s_, e in rows])
+    con.commit()
+    con.close()
+    st = {r["kernel"]: r for r in profiling.kernel_stats(str(tmp_path / "k.db"), isolated=True)}
+    # alone: a at [20, 30) and c at [30, 35) (touching ends do not overlap)
+    assert st["a"]["calls"] == 1 and st["a"]["mean_ns"] == 10
+    assert st["c"]["calls"] == 1 and st["c"]["mean_ns"] == 5
+    assert "b" not in st
+    every = {r["kernel"]: r for r in profiling.kernel_stats(str(tmp_path / "k.db"))}
+    assert every["a"]["calls"] == 3 and every["b"]["calls"] == 2
