@@ -293,16 +293,23 @@ int host_nact(const ShapeClass& c, long long ks, long long s) {
 // timing: every pass launch is bracketed by HIP events (serialised on `stream`).
 qhd_status enqueue_chunk(qhd_plan p, long long ks, hipStream_t stream, bool timing, bool concurrent, bool full) {
   auto timed_on = [&](hipStream_t st, int fam, double points, auto&& fn) -> hipError_t {
+    (void)st;
     hipEvent_t a = nullptr, b = nullptr;
     if (timing) {
       a = take_event(p);
       b = take_event(p);
-      if (a && b) (void)hipEventRecord(a, st);
+      if (a && b) launch_timing() = LaunchTiming{a, b};  // the pass launch records them
     }
     hipError_t r = fn();
     if (timing && a && b) {
-      (void)hipEventRecord(b, st);
-      p->pending.push_back({a, b, fam, points});
+      if (launch_timing().start) {
+        // no launch took them (an error before the launch): back to the pool
+        launch_timing() = LaunchTiming{};
+        p->free_events.push_back(a);
+        p->free_events.push_back(b);
+      } else {
+        p->pending.push_back({a, b, fam, points});
+      }
     }
     return r;
   };
@@ -605,6 +612,11 @@ qhd_status build_chunk_graph(qhd_plan p) {
 }  // namespace
 
 namespace qhd {
+LaunchTiming& launch_timing() {
+  thread_local LaunchTiming t;
+  return t;
+}
+
 // shared with the surrogate's entry points, which report through qhd_last_error()
 void set_error_message(const char* msg) { g_err = msg ? msg : ""; }
 

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace qhd {
@@ -63,6 +64,25 @@ hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, co
                               const double* f, const double2* tw_nx, int s, long long max_steps,
                               int grid_cap, int points_per_lane, hipStream_t stream, int model = kModelQHD,
                               bool y4 = true);
+// Sampled pass timing.  When armed, the next pass launch of this host thread records
+// the two events itself: hipExtLaunchKernelGGL stamps them with the dispatch's own start
+// and end (what a kernel trace reports), where events recorded around a launch would
+// add the marker packets and the wait between them to every sampled duration.
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchTiming& launch_timing();
+#define QHD_LAUNCH(kernel, grid, block, shmem, stream, ...)                                                    \
+  do {                                                                                                        \
+    ::qhd::LaunchTiming& qhd_lt_ = ::qhd::launch_timing();                                                    \
+    if (qhd_lt_.start) {                                                                                      \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, qhd_lt_.start, qhd_lt_.stop, 0, __VA_ARGS__); \
+      qhd_lt_ = ::qhd::LaunchTiming{};                                                                        \
+    } else {                                                                                                  \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                                    \
+    }                                                                                                         \
+  } while (0)
+
 // column-pass variants: staged (tile column through LDS, one wavefront per line, 8
 // or 16 points per lane), tile-wave (8x8 tiles straight to registers, a line spread
 // over TPL/8 wavefronts) or split (512 points: the first forward and the last inverse

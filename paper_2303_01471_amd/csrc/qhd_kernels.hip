@@ -1233,7 +1233,7 @@ hipError_t launch_col_tw(int blocks, int nx, const InstDev* inst, int ninst, con
                          const double2* tw, int s, long long max_steps, hipStream_t stream) {
   if constexpr (N >= 64 && N <= 512) {
     constexpr int P_ = col_tw_p<N>();
-    hipLaunchKernelGGL((k_col_pass_tw<N, P_, Y4>), dim3(blocks), dim3(ColTwCfg<N, P_>::NT), 0, stream,
+    QHD_LAUNCH((k_col_pass_tw<N, P_, Y4>), dim3(blocks), dim3(ColTwCfg<N, P_>::NT), 0, stream,
                        inst, nact, ilog2(nx), psi, tw, s, max_steps);
     return hipGetLastError();
   } else {
@@ -1277,16 +1277,16 @@ hipError_t row_pass_qhd(int nx, int ny, const InstDev* inst, int ninst, const in
   const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap, points_per_lane);
   if (row_points_resolve(nx, points_per_lane) == 16 && nx < 1024) {
     if (nx == 256)
-      hipLaunchKernelGGL((k_row_pass_2d<256, 16, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, nact,
+      QHD_LAUNCH((k_row_pass_2d<256, 16, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, nact,
                          ilog2(ny), psi, f, tw, s, max_steps);
     else
-      hipLaunchKernelGGL((k_row_pass_2d<512, 16, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, nact,
+      QHD_LAUNCH((k_row_pass_2d<512, 16, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, nact,
                          ilog2(ny), psi, f, tw, s, max_steps);
     return hipGetLastError();
   }
   QHD_SWITCH_N(nx, {
     constexpr int P_ = pts_per_lane<N_>();
-    hipLaunchKernelGGL((k_row_pass_2d<N_, P_, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, nact,
+    QHD_LAUNCH((k_row_pass_2d<N_, P_, kModelQHD, Y4>), dim3(blocks), dim3(256), 0, stream, inst, nact,
                        ilog2(ny), psi, f, tw, s, max_steps);
     return hipGetLastError();
   });
@@ -1299,7 +1299,7 @@ hipError_t launch_row_pass_2d(int nx, int ny, const InstDev* inst, int ninst, co
     const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap, 8);
     QHD_SWITCH_N(nx, {
       constexpr int P_ = pts_per_lane<N_>();
-      hipLaunchKernelGGL((k_row_pass_2d<N_, P_, kModelQAA, false>), dim3(blocks), dim3(256), 0, stream, inst, nact,
+      QHD_LAUNCH((k_row_pass_2d<N_, P_, kModelQAA, false>), dim3(blocks), dim3(256), 0, stream, inst, nact,
                          ilog2(ny), psi, f, tw, s, max_steps);
       return hipGetLastError();
     });
@@ -1317,22 +1317,22 @@ hipError_t col_pass_qhd(int nx, int ny, const InstDev* inst, int ninst, const in
     QHD_SWITCH_N(ny, { return (launch_col_tw<N_, Y4>)(blocks, nx, inst, ninst, nact, psi, tw, s, max_steps, stream); });
   }
   if (v == kColSplit) {
-    hipLaunchKernelGGL((k_col_pass_split<512, Y4>), dim3(blocks), dim3(ColSplitCfg<512>::NT), 0, stream, inst, nact,
+    QHD_LAUNCH((k_col_pass_split<512, Y4>), dim3(blocks), dim3(ColSplitCfg<512>::NT), 0, stream, inst, nact,
                        ilog2(nx), psi, tw, s, max_steps);
     return hipGetLastError();
   }
   if (v == kColStaged16) {
     if (ny == 256)
-      hipLaunchKernelGGL((k_col_pass_2d<256, 16, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<256, 16, true>::NT), 0, stream,
+      QHD_LAUNCH((k_col_pass_2d<256, 16, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<256, 16, true>::NT), 0, stream,
                          inst, nact, ilog2(nx), psi, tw, s, max_steps);
     else
-      hipLaunchKernelGGL((k_col_pass_2d<512, 16, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<512, 16, true>::NT), 0, stream,
+      QHD_LAUNCH((k_col_pass_2d<512, 16, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<512, 16, true>::NT), 0, stream,
                          inst, nact, ilog2(nx), psi, tw, s, max_steps);
     return hipGetLastError();
   }
   QHD_SWITCH_N(ny, {
     constexpr int P_ = pts_per_lane<N_>();
-    hipLaunchKernelGGL((k_col_pass_2d<N_, P_, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<N_, P_, true>::NT), 0, stream,
+    QHD_LAUNCH((k_col_pass_2d<N_, P_, kModelQHD, Y4>), dim3(blocks), dim3(ColCfg<N_, P_, true>::NT), 0, stream,
                        inst, nact, ilog2(nx), psi, tw, s, max_steps);
     return hipGetLastError();
   });
@@ -1345,7 +1345,7 @@ hipError_t launch_col_pass_2d(int nx, int ny, const InstDev* inst, int ninst, co
     const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap, kColStaged);
     QHD_SWITCH_N(ny, {
       constexpr int P_ = pts_per_lane<N_>();
-      hipLaunchKernelGGL((k_col_pass_2d<N_, P_, kModelQAA, false>), dim3(blocks), dim3(ColCfg<N_, P_, true>::NT), 0,
+      QHD_LAUNCH((k_col_pass_2d<N_, P_, kModelQAA, false>), dim3(blocks), dim3(ColCfg<N_, P_, true>::NT), 0,
                          stream, inst, nact, ilog2(nx), psi, tw, s, max_steps);
       return hipGetLastError();
     });
@@ -1359,7 +1359,7 @@ hipError_t launch_lf_row_2d(int nx, int ny, const InstDev* inst, int ninst, cons
   const int blocks = pass_blocks_row_2d(nx, ny, ninst, grid_cap, 8);
   QHD_SWITCH_N(nx, {
     constexpr int P_ = pts_per_lane<N_>();
-    hipLaunchKernelGGL((k_lf_row_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, nact, ilog2(ny), psi, f,
+    QHD_LAUNCH((k_lf_row_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, nact, ilog2(ny), psi, f,
                        scratch, s, max_steps);
     return hipGetLastError();
   });
@@ -1370,7 +1370,7 @@ hipError_t launch_lf_col_2d(int nx, int ny, const InstDev* inst, int ninst, cons
   const int blocks = pass_blocks_col_2d(nx, ny, ninst, grid_cap, kColStaged);
   QHD_SWITCH_N(ny, {
     constexpr int P_ = pts_per_lane<N_>();
-    hipLaunchKernelGGL((k_lf_col_2d<N_, P_>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0, stream, inst, nact,
+    QHD_LAUNCH((k_lf_col_2d<N_, P_>), dim3(blocks), dim3(ColCfg<N_, P_>::NT), 0, stream, inst, nact,
                        ilog2(nx), psi, scratch, s, max_steps);
     return hipGetLastError();
   });
@@ -1384,14 +1384,14 @@ hipError_t launch_line_pass_1d(int n, const InstDev* inst, int ninst, const int*
     constexpr int TPL_ = N_ / P_;
     constexpr int LPW_ = (256 / TPL_) > 0 ? 256 / TPL_ : 1;
     const int blocks = blocks_for(ninst, LPW_, grid_cap);
-    hipLaunchKernelGGL((k_line_pass_1d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, nact,
+    QHD_LAUNCH((k_line_pass_1d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, nact,
                        psi, f, tw, s, max_steps);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_commit(InstDev* inst, int ninst, long long max_steps, hipStream_t stream) {
-  hipLaunchKernelGGL(k_commit, dim3((ninst + 255) / 256), dim3(256), 0, stream, inst, ninst,
+  QHD_LAUNCH(k_commit, dim3((ninst + 255) / 256), dim3(256), 0, stream, inst, ninst,
                      max_steps);
   return hipGetLastError();
 }
@@ -1399,12 +1399,12 @@ hipError_t launch_commit(InstDev* inst, int ninst, long long max_steps, hipStrea
 hipError_t launch_chunk_plan(const InstDev* inst, int ninst, long long max_steps, int S, int* nact,
                              hipStream_t stream) {
   if (S <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_chunk_plan, dim3((S + 255) / 256), dim3(256), 0, stream, inst, ninst, max_steps, S, nact);
+  QHD_LAUNCH(k_chunk_plan, dim3((S + 255) / 256), dim3(256), 0, stream, inst, ninst, max_steps, S, nact);
   return hipGetLastError();
 }
 
 hipError_t launch_reset_inst(InstDev* inst, int ninst, hipStream_t stream) {
-  hipLaunchKernelGGL(k_reset_inst, dim3((ninst + 255) / 256), dim3(256), 0, stream, inst, ninst);
+  QHD_LAUNCH(k_reset_inst, dim3((ninst + 255) / 256), dim3(256), 0, stream, inst, ninst);
   return hipGetLastError();
 }
 
@@ -1417,10 +1417,10 @@ hipError_t launch_observe_2d(int nx, int rows, int ny, const InstDev* inst, int 
     constexpr int LPW_ = 256 / (N_ / P_);
     const int blocks = blocks_for((long long)ninst * rows, LPW_, 4096);
     if (model == kModelQAA)
-      hipLaunchKernelGGL((k_observe_2d<N_, P_, kModelQAA>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+      QHD_LAUNCH((k_observe_2d<N_, P_, kModelQAA>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
                          ilog2(rows), ilog2(ny), psi, f, tw, out_psi, out_rho, partials);
     else
-      hipLaunchKernelGGL((k_observe_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+      QHD_LAUNCH((k_observe_2d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
                          ilog2(rows), ilog2(ny), psi, f, tw, out_psi, out_rho, partials);
     return hipGetLastError();
   });
@@ -1434,7 +1434,7 @@ hipError_t launch_observe_1d(int n, const InstDev* inst, int ninst, const float2
     constexpr int TPL_ = N_ / P_;
     constexpr int LPW_ = (256 / TPL_) > 0 ? 256 / TPL_ : 1;
     const int blocks = blocks_for(ninst, LPW_, 4096);
-    hipLaunchKernelGGL((k_observe_1d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
+    QHD_LAUNCH((k_observe_1d<N_, P_>), dim3(blocks), dim3(256), 0, stream, inst, ninst,
                        psi, f, out_psi, out_rho, partials);
     return hipGetLastError();
   });
@@ -1442,7 +1442,7 @@ hipError_t launch_observe_1d(int n, const InstDev* inst, int ninst, const float2
 
 hipError_t launch_finalize(const double* partials, int lines_per_inst, int ninst, double* results,
                            hipStream_t stream) {
-  hipLaunchKernelGGL(k_finalize, dim3(ninst), dim3(256), 0, stream, partials, lines_per_inst, ninst, results);
+  QHD_LAUNCH(k_finalize, dim3(ninst), dim3(256), 0, stream, partials, lines_per_inst, ninst, results);
   return hipGetLastError();
 }
 
@@ -1451,9 +1451,9 @@ hipError_t launch_import_f(int ndim, int nx, int ny, const double* user, double*
   const long long n = (long long)nx * ny;
   const int blocks = (int)((n + 255) / 256);
   if (ndim == 2)
-    hipLaunchKernelGGL(k_import_f_2d, dim3(blocks), dim3(256), 0, stream, user, dst, nx, ny);
+    QHD_LAUNCH(k_import_f_2d, dim3(blocks), dim3(256), 0, stream, user, dst, nx, ny);
   else
-    hipLaunchKernelGGL(k_copy_f, dim3(blocks), dim3(256), 0, stream, user, dst, n);
+    QHD_LAUNCH(k_copy_f, dim3(blocks), dim3(256), 0, stream, user, dst, n);
   return hipGetLastError();
 }
 
@@ -1462,23 +1462,23 @@ hipError_t launch_import_psi(int ndim, int nx, int ny, const float2* user, float
   const long long n = (long long)nx * ny;
   const int blocks = (int)((n + 255) / 256);
   if (ndim == 2)
-    hipLaunchKernelGGL(k_import_psi_2d, dim3(blocks), dim3(256), 0, stream, user, dst, nx, ny);
+    QHD_LAUNCH(k_import_psi_2d, dim3(blocks), dim3(256), 0, stream, user, dst, nx, ny);
   else
-    hipLaunchKernelGGL(k_copy_psi, dim3(blocks), dim3(256), 0, stream, user, dst, n);
+    QHD_LAUNCH(k_copy_psi, dim3(blocks), dim3(256), 0, stream, user, dst, n);
   return hipGetLastError();
 }
 
 hipError_t launch_fill_psi(float2* dst, long long count, float value, hipStream_t stream) {
   const int blocks = (int)((count + 255) / 256);
-  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, stream, dst, count, value);
+  QHD_LAUNCH(k_fill, dim3(blocks), dim3(256), 0, stream, dst, count, value);
   return hipGetLastError();
 }
 
 hipError_t launch_argmin(const double* f, long long count, double* out_val, long long* out_idx, double* part_val,
                          long long* part_idx, long long* part_bad, hipStream_t stream) {
-  hipLaunchKernelGGL(k_argmin_partial, dim3(kArgminBlocks), dim3(256), 0, stream, f, count, part_val, part_idx,
+  QHD_LAUNCH(k_argmin_partial, dim3(kArgminBlocks), dim3(256), 0, stream, f, count, part_val, part_idx,
                      part_bad);
-  hipLaunchKernelGGL(k_argmin_final, dim3(1), dim3(kArgminBlocks), 0, stream, part_val, part_idx, part_bad, out_val,
+  QHD_LAUNCH(k_argmin_final, dim3(1), dim3(kArgminBlocks), 0, stream, part_val, part_idx, part_bad, out_val,
                      out_idx);
   return hipGetLastError();
 }

@@ -502,10 +502,10 @@ hipError_t launch_x(int ny, int nz, const InstDev* inst, int ninst, const int* n
   using C = XCfg<NX>;
   const int blocks = blocks3d((long long)ninst * (ny / 8) * (nz / 8), cap);
   if (y4)
-    hipLaunchKernelGGL((k_xpass_3d<NX, true>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, ilog2_3d(ny),
+    QHD_LAUNCH((k_xpass_3d<NX, true>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, ilog2_3d(ny),
                        ilog2_3d(nz), psi, f, tw, s, max_steps);
   else
-    hipLaunchKernelGGL((k_xpass_3d<NX, false>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, ilog2_3d(ny),
+    QHD_LAUNCH((k_xpass_3d<NX, false>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, ilog2_3d(ny),
                        ilog2_3d(nz), psi, f, tw, s, max_steps);
   return hipGetLastError();
 }
@@ -518,19 +518,19 @@ hipError_t launch_plane(int nx, const InstDev* inst, int ninst, const int* nact,
     using C = PlaneDCfg<NY, NZ>;
     const double inv_n = 1.0 / ((double)nx * (double)NY * (double)NZ);
     if (y4)
-      hipLaunchKernelGGL((k_plane_direct_3d<NY, NZ, true>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, nx, psi,
+      QHD_LAUNCH((k_plane_direct_3d<NY, NZ, true>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, nx, psi,
                          twy, twz, s, max_steps, inv_n);
     else
-      hipLaunchKernelGGL((k_plane_direct_3d<NY, NZ, false>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, nx,
+      QHD_LAUNCH((k_plane_direct_3d<NY, NZ, false>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, nx,
                          psi, twy, twz, s, max_steps, inv_n);
     return hipGetLastError();
   }
   using C = PlaneCfg<NY, NZ>;
   if (y4)
-    hipLaunchKernelGGL((k_plane_3d<NY, NZ, true>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, nx, psi, twy, twz,
+    QHD_LAUNCH((k_plane_3d<NY, NZ, true>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, nx, psi, twy, twz,
                        s, max_steps);
   else
-    hipLaunchKernelGGL((k_plane_3d<NY, NZ, false>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, nx, psi, twy,
+    QHD_LAUNCH((k_plane_3d<NY, NZ, false>), dim3(blocks), dim3(C::NT), 0, stream, inst, nact, nx, psi, twy,
                        twz, s, max_steps);
   return hipGetLastError();
 }
@@ -581,7 +581,7 @@ hipError_t launch_observe_plane(int nx, int ny, int nz, const InstDev* inst, int
   const int blocks = blocks3d((long long)ninst * (ny / 8) * (nz / 8), 4096);
 #define QHD_OBS_PLANE(NXV)                                                                                      \
   case NXV:                                                                                                     \
-    hipLaunchKernelGGL((k_observe_plane<NXV>), dim3(blocks), dim3(XCfg<NXV>::NT), 0, stream, inst, ninst,       \
+    QHD_LAUNCH((k_observe_plane<NXV>), dim3(blocks), dim3(XCfg<NXV>::NT), 0, stream, inst, ninst,       \
                        ilog2_3d(ny), ilog2_3d(nz), psi, f, tw_x, out_psi, out_rho, partials);                   \
     return hipGetLastError();
   switch (nx) {
@@ -597,14 +597,14 @@ hipError_t launch_observe_plane(int nx, int ny, int nz, const InstDev* inst, int
 
 hipError_t launch_import_f_plane(int nx, int ny, int nz, const double* user, double* dst, hipStream_t stream) {
   const long long n = (long long)nx * ny * nz;
-  hipLaunchKernelGGL(k_import_plane<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, user, dst, nx,
+  QHD_LAUNCH(k_import_plane<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, user, dst, nx,
                      ny, nz);
   return hipGetLastError();
 }
 
 hipError_t launch_import_psi_plane(int nx, int ny, int nz, const float2* user, float2* dst, hipStream_t stream) {
   const long long n = (long long)nx * ny * nz;
-  hipLaunchKernelGGL(k_import_plane<float2>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, user, dst, nx,
+  QHD_LAUNCH(k_import_plane<float2>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, user, dst, nx,
                      ny, nz);
   return hipGetLastError();
 }

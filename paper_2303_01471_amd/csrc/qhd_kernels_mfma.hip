@@ -288,11 +288,11 @@ hipError_t launch_mfma_pass_3d(int axis, int dir, const InstDev* inst, int ninst
   const dim3 grid((unsigned)items), block(256);
   const WEntry* t = static_cast<const WEntry*>(tables);
   if (axis == 0)
-    hipLaunchKernelGGL((k_mfma_pass_3d<0, 1>), grid, block, 0, stream, inst, nact, t, psi, f, dir, s, max_steps);
+    QHD_LAUNCH((k_mfma_pass_3d<0, 1>), grid, block, 0, stream, inst, nact, t, psi, f, dir, s, max_steps);
   else if (axis == 1)
-    hipLaunchKernelGGL((k_mfma_pass_3d<1, 0>), grid, block, 0, stream, inst, nact, t, psi, f, dir, s, max_steps);
+    QHD_LAUNCH((k_mfma_pass_3d<1, 0>), grid, block, 0, stream, inst, nact, t, psi, f, dir, s, max_steps);
   else if (axis == 2)
-    hipLaunchKernelGGL((k_mfma_pass_3d<2, 2>), grid, block, 0, stream, inst, nact, t, psi, f, dir, s, max_steps);
+    QHD_LAUNCH((k_mfma_pass_3d<2, 2>), grid, block, 0, stream, inst, nact, t, psi, f, dir, s, max_steps);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

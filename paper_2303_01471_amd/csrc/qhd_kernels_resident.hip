@@ -190,13 +190,13 @@ hipError_t launch_resident_2d(int nx, int ny, const InstDev* inst, int ninst, co
   if (nx == NX_ && ny == NY_) {                                                                               \
     constexpr int NT_ = ResCfg<NX_, NY_>::NT, NTQ_ = ResCfg<NX_, NY_, kModelQAA>::NT;                         \
     if (model == kModelQAA)                                                                                   \
-      hipLaunchKernelGGL((k_resident_2d<NX_, NY_, kModelQAA, false>), dim3(ninst), dim3(NTQ_), 0, stream,     \
+      QHD_LAUNCH((k_resident_2d<NX_, NY_, kModelQAA, false>), dim3(ninst), dim3(NTQ_), 0, stream,     \
                          inst, nact, psi, f, tw_nx, tw_ny, max_steps);                                       \
     else if (y4)                                                                                              \
-      hipLaunchKernelGGL((k_resident_2d<NX_, NY_, kModelQHD, true>), dim3(ninst), dim3(NT_), 0, stream,       \
+      QHD_LAUNCH((k_resident_2d<NX_, NY_, kModelQHD, true>), dim3(ninst), dim3(NT_), 0, stream,       \
                          inst, nact, psi, f, tw_nx, tw_ny, max_steps);                                       \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_resident_2d<NX_, NY_, kModelQHD, false>), dim3(ninst), dim3(NT_), 0, stream,      \
+      QHD_LAUNCH((k_resident_2d<NX_, NY_, kModelQHD, false>), dim3(ninst), dim3(NT_), 0, stream,      \
                          inst, nact, psi, f, tw_nx, tw_ny, max_steps);                                       \
     return hipGetLastError();                                                                                 \
   }

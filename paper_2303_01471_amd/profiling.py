@@ -1,9 +1,10 @@
 """Summaries of rocprofv3 output (rocpd SQLite databases) for the engine.
 
-    python -m paper_2303_01471_amd.profiling kernels DB [--isolated]
+    python -m paper_2303_01471_amd.profiling kernels DB [--isolated] [--largest-grid]
         per-kernel dispatch count, total / mean / min / max duration (the
         --kernel-trace --stats view), one line per kernel; --isolated keeps only
-        dispatches that overlapped no other one
+        dispatches that overlapped no other one, --largest-grid only each kernel's
+        dispatches of its largest grid
     python -m paper_2303_01471_amd.profiling counters DB
         mean value per dispatch of every collected counter, per kernel
     python -m paper_2303_01471_amd.profiling traffic FETCH_DB:WRITE_DB:POINTS_JSON [...] --copy-bytes B --source-hash H
@@ -47,20 +48,25 @@ def _isolated(rows):
     return keep
 
 
-def kernel_stats(db: str, isolated: bool = False):
+def kernel_stats(db: str, isolated: bool = False, largest_grid: bool = False):
     """Per-kernel duration statistics; with ``isolated`` only over dispatches that ran
     alone on the device (no other dispatch overlapping them), the view of the library's
-    serialised timing chunks."""
+    serialised timing chunks; with ``largest_grid`` only over each kernel's dispatches of
+    its largest grid (a batch's launches, not those of single-instance runs of the same
+    kernel)."""
     con = sqlite3.connect(db)
-    if isolated:
-        cols = [r[1] for r in con.execute("pragma table_info(kernels)")]
-        st = "start" if "start" in cols else "start_ns"
-        en = "end" if "end" in cols else "end_ns"
-        rows = con.execute(f'select name, "{st}", "{en}" from kernels').fetchall()
-        keep = _isolated(rows)
-        rows = [(rows[i][0], rows[i][2] - rows[i][1]) for i in sorted(keep)]
-    else:
-        rows = con.execute("select name, duration from kernels").fetchall()
+    cols = [r[1] for r in con.execute("pragma table_info(kernels)")]
+    st = "start" if "start" in cols else "start_ns"
+    en = "end" if "end" in cols else "end_ns"
+    grid = "grid_x * grid_y * grid_z" if "grid_x" in cols else "0"
+    rows = con.execute(f'select name, "{st}", "{en}", {grid} from kernels').fetchall()
+    keep = _isolated(rows) if isolated else set(range(len(rows)))
+    if largest_grid:
+        big = collections.defaultdict(int)
+        for r in rows:
+            big[_short(r[0])] = max(big[_short(r[0])], r[3])
+        keep = {i for i in keep if rows[i][3] == big[_short(rows[i][0])]}
+    rows = [(rows[i][0], rows[i][2] - rows[i][1]) for i in sorted(keep)]
     agg = collections.defaultdict(list)
     for name, dur in rows:
         agg[_short(name)].append(dur)
@@ -181,6 +187,8 @@ def main(argv=None):
     a.add_argument("db")
     a.add_argument("--isolated", action="store_true",
                    help="only dispatches that overlap no other dispatch (serialised timing chunks)")
+    a.add_argument("--largest-grid", action="store_true",
+                   help="only each kernel's dispatches of its largest grid (the batch's launches)")
     b = sub.add_parser("counters")
     b.add_argument("db")
     c = sub.add_parser("traffic")
@@ -190,7 +198,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.cmd == "kernels":
         print(f"{'calls':>8} {'total_ms':>10} {'mean_us':>10} {'min_us':>9} {'max_us':>9}  kernel")
-        for r in kernel_stats(args.db, args.isolated):
+        for r in kernel_stats(args.db, args.isolated, args.largest_grid):
             print(f"{r['calls']:8d} {r['total_ns'] / 1e6:10.3f} {r['mean_ns'] / 1e3:10.2f} "
                   f"{r['min_ns'] / 1e3:9.2f} {r['max_ns'] / 1e3:9.2f}  {r['kernel']}")
     elif args.cmd == "counters":

@@ -62,10 +62,10 @@ def test_every_shape_matches_streaming_and_oracle():
     for i in range(len(specs)):
         d = float(np.max(np.abs(psi_r[i] - psi_s[i])))
         note(f"  {SHAPES[i]}: resident vs streaming max|dpsi| = {d:.3e}")
-        # the same arithmetic where both take 8 points per lane on the columns; the
-        # streaming 128-point columns take 16 (another FFT factorisation, same rounding order
-        # of magnitude)
-        if SHAPES[i][0] <= 64:
+        # the same arithmetic where both take 8 points per lane on the columns and FP32
+        # rows; the streaming 128-point columns take 16 (another FFT factorisation) and
+        # its 128-point rows FP64 end stages (same rounding order of magnitude)
+        if SHAPES[i][0] <= 64 and SHAPES[i][1] != 128:
             assert np.array_equal(psi_r[i], psi_s[i])
         else:
             assert d <= 1e-6

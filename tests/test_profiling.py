@@ -82,15 +82,20 @@ def test_relaxed_qp_step_traffic_sums_the_step_kernels(tmp_path):
 
 def test_isolated_dispatches_are_those_that_overlap_no_other(tmp_path):
     con = sqlite3.connect(tmp_path / "k.db")
-    con.execute('create table kernels (name text, start integer, "end" integer, duration integer)')
-    rows = [("a", 0, 10), ("b", 5, 12), ("a", 20, 30), ("c", 30, 35), ("a", 40, 50), ("b", 45, 60), ("c", 55, 58)]
-    con.executemany("insert into kernels values (?, ?, ?, ?)", [(n, s_, e, e - s_) for n, s_, e in rows])
+    con.execute('create table kernels (name text, start integer, "end" integer, duration integer, grid_x integer, '
+                'grid_y integer, grid_z integer)')
+    rows = [("a", 0, 10, 64), ("b", 5, 12, 8), ("a", 20, 30, 64), ("c", 30, 35, 8), ("a", 40, 50, 8), ("b", 45, 60, 8),
+            ("c", 55, 58, 8), ("a", 70, 90, 64)]
+    con.executemany("insert into kernels values (?, ?, ?, ?, ?, 1, 1)", [(n, s_, e, e - s_, g) for n, s_, e, g in rows])
     con.commit()
     con.close()
     st = {r["kernel"]: r for r in profiling.kernel_stats(str(tmp_path / "k.db"), isolated=True)}
-    # alone: a at [20, 30) and c at [30, 35) (touching ends do not overlap)
-    assert st["a"]["calls"] == 1 and st["a"]["mean_ns"] == 10
+    # alone: a at [20, 30) and [70, 90), c at [30, 35) (touching ends do not overlap)
+    assert st["a"]["calls"] == 2 and st["a"]["mean_ns"] == 15
     assert st["c"]["calls"] == 1 and st["c"]["mean_ns"] == 5
     assert "b" not in st
     every = {r["kernel"]: r for r in profiling.kernel_stats(str(tmp_path / "k.db"))}
-    assert every["a"]["calls"] == 3 and every["b"]["calls"] == 2
+    assert every["a"]["calls"] == 4 and every["b"]["calls"] == 2
+    big = {r["kernel"]: r for r in profiling.kernel_stats(str(tmp_path / "k.db"), largest_grid=True)}
+    assert big["a"]["calls"] == 3 and big["a"]["mean_ns"] == 40 / 3  # the grid-64 dispatches
+    assert big["c"]["calls"] == 2
