@@ -153,6 +153,32 @@ __device__ __forceinline__ long long row_slot(int t, int q, int y) {
   }
 }
 
+// 8-byte values (complex FP32 or FP64) of one instance reached through a raw buffer
+// resource: a wave-uniform base in scalar registers, the lane's element offset in one
+// vector register and each access's wave-uniform element offset as the scalar soffset.
+// A slot loop over 64-bit vector addresses holds two registers per slot from the loads
+// to the stores (a 16-slot line: 32 registers); here it holds one.  Every mesh fits the
+// 32-bit byte offsets (at most 2^21 points per instance).
+template <typename T>
+struct LaneView {
+  static_assert(sizeof(T) == 8, "8-byte elements");
+  __amdgpu_buffer_rsrc_t r;
+  int vo;  // the lane's byte offset
+  __device__ __forceinline__ LaneView(const T* base, int lane_elem)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), 0, 0x7fffffff, 0x00020000)), vo(lane_elem * 8) {}
+  __device__ __forceinline__ T load(int elem) const {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, elem * 8, 0);
+    T out;
+    __builtin_memcpy(&out, &v, 8);
+    return out;
+  }
+  __device__ __forceinline__ void store(int elem, T z) const {
+    __attribute__((ext_vector_type(2))) unsigned v;
+    __builtin_memcpy(&v, &z, 8);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, elem * 8, 0);
+  }
+};
+
 // contiguous share [begin, end) of `total` work items for this block, in units of `step`
 __device__ __forceinline__ void block_share(long long total, int step, long long& begin, long long& end) {
   const long long units = (total + step - 1) / step;

@@ -435,9 +435,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     const int i = (int)(g >> tc_log2), tc = (int)(g & (tcols - 1));
     const InstDev& I = inst[i];
     if (!(s < step_limit(I, max_steps))) return false;
-    const float2* __restrict__ src = psi + I.psi_off + tc * 64 + lane;
+    const LaneView<float2> src(psi + I.psi_off + tc * 64, lane);
 #pragma unroll
-    for (int q = 0; q < P; ++q) pf[q] = src[(long long)(wave + 8 * q) * tcols * 64];
+    for (int q = 0; q < P; ++q) pf[q] = src.load((wave + 8 * q) * tcols * 64);
     return true;
   };
   bool pf_live = begin < end && fetch(begin);
@@ -490,9 +490,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
       stage_inputs<NY, P, SlotIx>(x, t_tv, mc);
       fft_stage_io<NY, P, +1, 2, false, float2, SlotIx>(x, x, t_tv, twt, mc);
       if (active) {
-        float2* __restrict__ dst = psi + I.psi_off + tc * 64 + lane;
+        const LaneView<float2> dst(psi + I.psi_off + tc * 64, lane);
 #pragma unroll
-        for (int q = 0; q < P; ++q) dst[(long long)(wave + 8 * q) * tcols * 64] = x[q];
+        for (int q = 0; q < P; ++q) dst.store((wave + 8 * q) * tcols * 64, x[q]);
       }
     }
     __syncthreads();  // the next item's first stage rewrites the lines
@@ -524,11 +524,13 @@ struct ColTwCfg {
   static constexpr int NT = ITEMS * W * 64;
   static constexpr int STRIDE = ((LineLds<NY>::kSlots + 13) / 16) * 16 + 2;
   static constexpr bool EY_LDS = P >= 16;                 // E_y / (nx ny) per item in LDS
+  // 16 points per lane: three waves per SIMD (168 VGPRs; the LDS of a block admits three)
+  static constexpr int MIN_WAVES = P >= 16 ? 3 : 1;
   static_assert(TPL % 8 == 0, "tile-wave column pass needs TPL multiple of 8");
 };
 
 template <int NY, int P, bool Y4 = true>
-__global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
+__global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) __attribute__((amdgpu_waves_per_eu(ColTwCfg<NY, P>::MIN_WAVES))) k_col_pass_tw(
     const InstDev* __restrict__ inst, const int* __restrict__ nact_p, int nx_log2, float2* __restrict__ psi,
     const double2* __restrict__ twtab, int s, long long max_steps) {
   const int ninst = *nact_p;  // members active in this sub-step (device, set per chunk)
@@ -606,10 +608,12 @@ __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
     }
     const int nxf = freq(tc * 8 + c, nx);
     const double2 ex = phase_turns_d(a * I.kin_turns[0] * (double)(nxf * nxf));
-    float2* __restrict__ base = psi + I.psi_off + ((long long)(wv * tcols + tc) << 6) + lane;
+    // the item's tile column: scalar base, the lane's offset in one register, slot
+    // offsets scalar (tile rows t + q TPL, W tile rows apart)
+    const LaneView<float2> col(psi + I.psi_off + ((long long)tc << 6), lane + wv * tcols * 64);
     float2 reg[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) reg[q] = base[(long long)q * W * tcols * 64];
+    for (int q = 0; q < P; ++q) reg[q] = col.load(q * W * tcols * 64);
     double2 kd[P];
     line_fft_io<NY, P, -1, (W > 1)>(reg, kd, t, tw, my);
 #pragma unroll
@@ -621,7 +625,7 @@ __global__ void __launch_bounds__((ColTwCfg<NY, P>::NT)) k_col_pass_tw(
     line_fft_io<NY, P, +1, (W > 1)>(kd, reg, t, tw, my);
     if (active) {
 #pragma unroll
-      for (int q = 0; q < P; ++q) base[(long long)q * W * tcols * 64] = reg[q];
+      for (int q = 0; q < P; ++q) col.store(q * W * tcols * 64, reg[q]);
     }
   }
 }

@@ -77,19 +77,22 @@ __global__ void __launch_bounds__((XCfg<NX>::NT)) k_xpass_3d(const InstDev* __re
     const long long j = I.steps_done + s;
     const bool entry = (s == 0 && I.mode == kModeClean);
     const double cpot = potential_turns<Y4>(I, j, entry);
-    const long long off = I.psi_off + ((long long)tile << 6) + lane + (long long)t * plane;
-    float2* __restrict__ base = psi + off;
-    const double* __restrict__ fb = f + off;
+    // scalar base (the item's tile), the lane's offset (its point and plane t) in one
+    // register, the slot offsets (planes t + q W) scalar
+    const long long off = I.psi_off + ((long long)tile << 6);
+    const int lane_off = lane + t * (int)plane;
+    const LaneView<float2> pv(psi + off, lane_off);
+    const LaneView<double> fv(f + off, lane_off);
     float2 reg[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) reg[q] = base[(long long)q * W * plane];
+    for (int q = 0; q < P; ++q) reg[q] = pv.load(q * W * (int)plane);
     if (!entry) line_fft<NX, P, +1, (W > 1)>(reg, t, tw, my);
 #pragma unroll
-    for (int q = 0; q < P; ++q) reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fb[(long long)q * W * plane]));
+    for (int q = 0; q < P; ++q) reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * fv.load(q * W * (int)plane)));
     line_fft<NX, P, -1, (W > 1)>(reg, t, tw, my);
     if (active) {
 #pragma unroll
-      for (int q = 0; q < P; ++q) base[(long long)q * W * plane] = reg[q];
+      for (int q = 0; q < P; ++q) pv.store(q * W * (int)plane, reg[q]);
     }
     if constexpr (W > 1) __syncthreads();  // the next item's first exchange reuses the LDS
   }
