@@ -219,6 +219,53 @@ template <int STRIDE>
 struct StrideIx {
   __device__ static constexpr int at(int i) { return i * STRIDE; }
 };
+// Placements of the form at(i) = i + (i >> S) (one pad slot per 2^S entries) or
+// linear (S = 0) split over a sum, at(a + b) = at(a) + at(b), whenever b is a multiple
+// of 2^S (no carry out of the low S bits).  An exchange access t + q TPL (or base +
+// r NS) is then one per-lane address plus a compile-time offset instead of an address
+// register per slot.
+template <typename IX>
+struct IxShift {
+  static constexpr int value = -1;  // no such split
+};
+template <>
+struct IxShift<SlotIx> {
+  static constexpr int value = 3;
+};
+template <int STRIDE>
+struct IxShift<StrideIx<STRIDE>> {
+  static constexpr int value = 0;
+};
+template <typename IX, int K>
+__host__ __device__ constexpr bool ix_splits() {
+  return IxShift<IX>::value >= 0 && K % (1 << (IxShift<IX>::value < 0 ? 0 : IxShift<IX>::value)) == 0;
+}
+// the P slots t + q TPL of a lane
+template <int N, int P, typename IX, typename T, typename V>
+__device__ __forceinline__ void lds_read_slots(V (&dst)[P], int t, const T* __restrict__ lds) {
+  constexpr int TPL = N / P;
+  if constexpr (ix_splits<IX, TPL>()) {
+    const T* __restrict__ b = lds + IX::at(t);
+#pragma unroll
+    for (int q = 0; q < P; ++q) assign(dst[q], b[IX::at(q * TPL)]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < P; ++q) assign(dst[q], lds[IX::at(t + q * TPL)]);
+  }
+}
+// the R Stockham outputs base + r NS of one butterfly (base = a multiple of R when NS = 1)
+template <int R, int NS, typename IX, typename T, typename V>
+__device__ __forceinline__ void lds_write_outputs(T* __restrict__ lds, int base, const V (&u)[R]) {
+  if constexpr (ix_splits<IX, NS>() || (NS == 1 && ix_splits<IX, R>())) {
+    T* __restrict__ b = lds + IX::at(base);
+#pragma unroll
+    for (int r = 0; r < R; ++r) assign(b[IX::at(r * NS)], u[r]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) assign(lds[IX::at(base + r * NS)], u[r]);
+  }
+}
+
 template <int N>
 struct LineLds {
   static constexpr int kSlots = N + N / 8;
@@ -388,14 +435,12 @@ __device__ __forceinline__ void fft_stage(float2 (&reg)[P], int t, const TW& tw,
     } else {
       const int v = t + m * TPL;
       const int base = (v / NS) * NS * R + (v % NS);
-#pragma unroll
-      for (int r = 0; r < R; ++r) lds[IX::at(base + r * NS)] = u[r];
+      lds_write_outputs<R, NS, IX>(lds, base, u);
     }
   }
   if constexpr (!LAST) {
     line_lds_sync<BLOCK_SYNC>();
-#pragma unroll
-    for (int q = 0; q < P; ++q) reg[q] = lds[IX::at(t + q * TPL)];
+    lds_read_slots<N, P, IX>(reg, t, lds);
     line_lds_sync<BLOCK_SYNC>();
   }
 }
@@ -463,14 +508,12 @@ __device__ __forceinline__ void fft_stage_io(const A (&src)[P], B (&dst)[P], int
     } else {
       const int v = t + m * TPL;
       const int base = (v / NS) * NS * R + (v % NS);
-#pragma unroll
-      for (int r = 0; r < R; ++r) assign(lds[IX::at(base + r * NS)], u[r]);
+      lds_write_outputs<R, NS, IX>(lds, base, u);
     }
   }
   if constexpr (!LAST) {
     line_lds_sync<BLOCK_SYNC>();
-#pragma unroll
-    for (int q = 0; q < P; ++q) dst[q] = lds[IX::at(t + q * TPL)];
+    lds_read_slots<N, P, IX>(dst, t, lds);
     line_lds_sync<BLOCK_SYNC>();
   }
 }
@@ -507,8 +550,7 @@ __device__ __forceinline__ void stage_outputs_to_lds(const A (&src)[P], int t, c
     dft<R, S>(u);
     const int v = t + m * TPL;
     const int base = (v / NS) * NS * R + (v % NS);
-#pragma unroll
-    for (int r = 0; r < R; ++r) assign(lds[IX::at(base + r * NS)], u[r]);
+    lds_write_outputs<R, NS, IX>(lds, base, u);
   }
 }
 
@@ -516,8 +558,7 @@ __device__ __forceinline__ void stage_outputs_to_lds(const A (&src)[P], int t, c
 template <int N, int P, typename IX>
 __device__ __forceinline__ void stage_inputs(float2 (&dst)[P], int t, const float2* __restrict__ lds) {
   constexpr int TPL = N / P;
-#pragma unroll
-  for (int q = 0; q < P; ++q) dst[q] = lds[IX::at(t + q * TPL)];
+  lds_read_slots<N, P, IX>(dst, t, lds);
 }
 
 template <int N, int P, int S, bool BLOCK_SYNC, int STAGE, typename IX, typename TW>

@@ -58,10 +58,38 @@ namespace qhd {
 // ------------------------------------------------------------------------------------
 // 2-D row pass: lines along x, one line per TPL lanes.
 
-// (512 points with 16 per lane: the LDS of a block admits three waves per SIMD, so the
-// register budget is held to that.)
+// 512-point QHD rows with 16 points per lane (R4): four blocks per CU, four waves per
+// SIMD.  Their LDS fits four blocks (39 KB each) with one pad slot per 16 line entries
+// (the radix-16 scatter of the first stage then puts a group of 16 lanes on 16 distinct
+// bank pairs) and a table of first twiddle powers (the powers formed in FP64); the slot
+// loads and stores go through buffer views, so 112 registers hold the line.  Measured
+// against the three-wave form (eight-entry padding, full twiddle table, 64-bit slot
+// addresses): 208 vs 213 us per launch on 160 x 512^2.  Other shapes keep three waves
+// (512 points with 16 per lane, QAA) or the compiler's choice.
+template <int NX, int P, int MODEL>
+struct RowCfg {
+  static constexpr bool R4 = MODEL == kModelQHD && NX == 512 && P == 16;
+  static constexpr int SLOTS = R4 ? NX + NX / 16 : LineLds<NX>::kSlots;
+  static constexpr int WAVES = R4 ? 4 : ((P == 16 && NX == 512) ? 3 : 1);
+};
+struct Slot16Ix {
+  __device__ static constexpr int at(int i) { return i + (i >> 4); }
+};
+template <>
+struct IxShift<Slot16Ix> {
+  static constexpr int value = 4;
+};
+// a row's psi and f slots at the lane's offset (the instance is wave-uniform)
+template <int NX, int TPL>
+struct RowView {
+  LaneView<float2> ps;
+  LaneView<double> fs;
+  __device__ __forceinline__ RowView(float2* psi_i, const double* f_i, int t, int y)
+      : ps(psi_i, (int)row_slot<NX, TPL>(t, 0, y)), fs(f_i, (int)row_slot<NX, TPL>(t, 0, y)) {}
+};
+
 template <int NX, int P, int MODEL = kModelQHD, bool Y4 = true>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((P == 16 && NX == 512) ? 3 : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RowCfg<NX, P, MODEL>::WAVES)))
 k_row_pass_2d(const InstDev* __restrict__ inst, const int* __restrict__ nact_p,
                                                      int ny_log2, float2* __restrict__ psi,
                                                      const double* __restrict__ f,
@@ -70,12 +98,14 @@ k_row_pass_2d(const InstDev* __restrict__ inst, const int* __restrict__ nact_p,
   const int ninst = *nact_p;  // members active in this sub-step (device, set per chunk)
   constexpr int TPL = NX / P;
   constexpr int LPW = 256 / TPL;
-  constexpr int SLOTS = LineLds<NX>::kSlots;
+  using RC = RowCfg<NX, P, MODEL>;
+  constexpr int SLOTS = RC::SLOTS;
   __shared__ float2 lds[LPW * SLOTS];
   const int ll = threadIdx.x / TPL, t = threadIdx.x % TPL;
   float2* my = lds + ll * SLOTS;
-  __shared__ double2 twl[TwLdsSize<NX, P>::value];
-  TwiddlesFor<NX, P> tw;
+  using TW = typename std::conditional<RC::R4, TwiddlesLds<NX, P, true>, TwiddlesFor<NX, P>>::type;
+  __shared__ double2 twl[RC::R4 ? TwiddlesLds<NX, P, true>::kEntries : TwLdsSize<NX, P>::value];
+  TW tw;
   load_twiddles(tw, twtab, twl, t);
   const long long total = (long long)ninst << ny_log2;
   long long begin, end;
@@ -135,6 +165,20 @@ k_row_pass_2d(const InstDev* __restrict__ inst, const int* __restrict__ nact_p,
       if (active) {
 #pragma unroll
         for (int q = 0; q < P; ++q) assign(pl[row_slot<NX, TPL>(t, q, y)], out[q]);
+      }
+    } else if constexpr (RC::R4) {
+      static_assert(64 * P <= 8 * NX && TPL % 8 == 0, "wave-uniform instance, whole-tile slot stride");
+      const RowView<NX, TPL> row(pl, fl, t, y);
+      float2 reg[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) reg[q] = row.ps.load(q * TPL * 8);
+      if (!entry) line_fft<NX, P, +1, false, Slot16Ix>(reg, t, tw, my);
+#pragma unroll
+      for (int q = 0; q < P; ++q) reg[q] = cmul_fd(reg[q], phase_turns_d(cpot * row.fs.load(q * TPL * 8)));
+      line_fft<NX, P, -1, false, Slot16Ix>(reg, t, tw, my);
+      if (active) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) row.ps.store(q * TPL * 8, reg[q]);
       }
     } else {
       float2 reg[P];
