@@ -557,7 +557,6 @@ __device__ __forceinline__ void stage_outputs_to_lds(const A (&src)[P], int t, c
 // the inputs of the next stage, positions t + q TPL of the LDS line
 template <int N, int P, typename IX>
 __device__ __forceinline__ void stage_inputs(float2 (&dst)[P], int t, const float2* __restrict__ lds) {
-  constexpr int TPL = N / P;
   lds_read_slots<N, P, IX>(dst, t, lds);
 }
 

@@ -192,8 +192,15 @@ hipError_t spec_finish(float2* out, const float2* w, const float2* v, const doub
                        hipStream_t st);
 hipError_t spec_multidot(const float2* V, long long n, int count, const float2* w, double* partials, int nblk,
                          hipStream_t st);
+// (with `part`, groups x n FP64 pairs of scratch, long bases take the grouped two-kernel
+// form; scale_dev: the scale read from device memory)
 hipError_t spec_multiaxpy(float2* w, const float2* V, long long n, int count, const double* c, double scale,
-                          hipStream_t st);
+                          hipStream_t st, const double* scale_dev = nullptr, double2* part = nullptr,
+                          int groups = 1);
+// device-side reductions of the multidot partials (block order, FP64): coefficients
+// (optionally keeping the newest one), and a vector's norm with its reciprocal
+hipError_t spec_coef(const double* partials, int count, int nblk, double* coef, double* keep, hipStream_t st);
+hipError_t spec_norm(const double* partials, int nblk, double* keep, double* scale, hipStream_t st);
 hipError_t spec_random(float2* v, long long n, unsigned long long seed, hipStream_t st);
 
 }  // namespace qhd

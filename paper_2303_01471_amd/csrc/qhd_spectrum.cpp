@@ -46,7 +46,8 @@ qhd_status sfail(qhd_status st, const char* fmt, ...) {
   } while (0)
 
 constexpr int kMaxKrylov = 400;
-constexpr int kDotBlocks = 128;
+constexpr int kDotBlocks = 16;  // blocks per vector of a multidot (partials summed in order)
+constexpr int kAxpyGroups = 8;  // groups of the grouped multiaxpy
 
 // a(t), b(t) of the instance's schedule at time t
 qhd_status schedule_at(const InstanceView& v, double t, double& a, double& b) {
@@ -71,48 +72,114 @@ qhd_status schedule_at(const InstanceView& v, double t, double& a, double& b) {
   return QHD_OK;
 }
 
-// Eigen-decomposition of a real symmetric m x m matrix (row-major) by cyclic Jacobi
-// rotations; eigenvalues in w, eigenvectors in the columns of z.
-void jacobi_eigen(std::vector<double> A, int m, std::vector<double>& w, std::vector<double>& z) {
-  z.assign((size_t)m * m, 0.0);
-  for (int k = 0; k < m; ++k) z[(size_t)k * m + k] = 1.0;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int p = 0; p < m; ++p)
-      for (int q = 0; q < m; ++q) {
-        const double v2 = A[(size_t)p * m + q] * A[(size_t)p * m + q];
-        tot += v2;
-        if (p != q) off += v2;
-      }
-    if (off <= 1e-30 * tot || off == 0.0) break;
-    for (int p = 0; p < m - 1; ++p)
-      for (int q = p + 1; q < m; ++q) {
-        const double apq = A[(size_t)p * m + q];
-        if (std::fabs(apq) < 1e-300) continue;
-        const double app = A[(size_t)p * m + p], aqq = A[(size_t)q * m + q];
-        // rotation angle that zeroes A[p][q]: tan(2 phi) = 2 apq / (aqq - app)
-        const double theta = (aqq - app) / (2.0 * apq);
-        const double tt = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(tt * tt + 1.0), s = tt * c;
-        for (int k = 0; k < m; ++k) {  // columns p, q
-          const double akp = A[(size_t)k * m + p], akq = A[(size_t)k * m + q];
-          A[(size_t)k * m + p] = c * akp - s * akq;
-          A[(size_t)k * m + q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < m; ++k) {  // rows p, q
-          const double apk = A[(size_t)p * m + k], aqk = A[(size_t)q * m + k];
-          A[(size_t)p * m + k] = c * apk - s * aqk;
-          A[(size_t)q * m + k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < m; ++k) {
-          const double zkp = z[(size_t)k * m + p], zkq = z[(size_t)k * m + q];
-          z[(size_t)k * m + p] = c * zkp - s * zkq;
-          z[(size_t)k * m + q] = s * zkp + c * zkq;
-        }
-      }
+// Lowest eigenpairs of the Lanczos matrix: the symmetric tridiagonal T with diagonal
+// d[0..m) and off-diagonal e[0..m-1) (e[i] couples i and i+1).
+
+// number of eigenvalues of T below x (Sylvester's law of inertia on the LDL^T pivots)
+int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x, double tiny) {
+  int neg = 0;
+  double q = 1.0;
+  for (size_t i = 0; i < d.size(); ++i) {
+    const double e2 = i > 0 ? e[i - 1] * e[i - 1] : 0.0;
+    q = (d[i] - x) - (i > 0 ? e2 / q : 0.0);
+    if (q == 0.0) q = -tiny;
+    if (q < 0.0) ++neg;
   }
-  w.resize(m);
-  for (int k = 0; k < m; ++k) w[k] = A[(size_t)k * m + k];
+  return neg;
+}
+
+// the k-th smallest eigenvalue (k from 0) by bisection on the Sturm count inside the
+// Gershgorin interval [lo, hi]
+double kth_eigenvalue(const std::vector<double>& d, const std::vector<double>& e, int k, double lo, double hi,
+                      double tiny) {
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;  // the interval is one ulp wide
+    if (sturm_count(d, e, mid, tiny) > k) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// eigenvector of T for the eigenvalue lam by inverse iteration: (T - lam I) x = b solved
+// by Gaussian elimination with row interchanges (the band of U grows to two
+// super-diagonals), x orthogonalised against the vectors of eigenvalues closer than
+// `gap` (earlier members of a cluster) and normalised, three times from a fixed start
+void inverse_iteration(const std::vector<double>& d, const std::vector<double>& e, double lam, double tiny,
+                       const std::vector<std::vector<double>>& close, std::vector<double>& x) {
+  const int m = (int)d.size();
+  std::vector<double> dd(m), du(m, 0.0), du2(m, 0.0), dl(m, 0.0);
+  std::vector<char> swp(m, 0);
+  for (int i = 0; i < m; ++i) dd[i] = d[i] - lam;
+  for (int i = 0; i + 1 < m; ++i) du[i] = dl[i] = e[i];
+  for (int i = 0; i + 1 < m; ++i) {
+    if (std::fabs(dd[i]) >= std::fabs(dl[i])) {
+      if (dd[i] == 0.0) dd[i] = tiny;
+      const double f = dl[i] / dd[i];
+      dl[i] = f;
+      dd[i + 1] -= f * du[i];
+    } else {  // interchange rows i and i + 1
+      const double f = dd[i] / dl[i];
+      dd[i] = dl[i];
+      dl[i] = f;
+      const double t = du[i];
+      du[i] = dd[i + 1];
+      dd[i + 1] = t - f * dd[i + 1];
+      if (i + 2 < m) {
+        du2[i] = du[i + 1];
+        du[i + 1] = -f * du[i + 1];
+      }
+      swp[i] = 1;
+    }
+  }
+  if (dd[m - 1] == 0.0) dd[m - 1] = tiny;
+  x.assign(m, 0.0);
+  std::vector<double> b(m);
+  for (int i = 0; i < m; ++i) b[i] = 1.0 + 0.1 * std::sin(1.0 + 2.3 * i);  // fixed, no special structure
+  for (int it = 0; it < 3; ++it) {
+    for (int i = 0; i + 1 < m; ++i) {  // L
+      if (swp[i]) std::swap(b[i], b[i + 1]);
+      b[i + 1] -= dl[i] * b[i];
+    }
+    for (int i = m - 1; i >= 0; --i) {  // U
+      double v = b[i];
+      if (i + 1 < m) v -= du[i] * x[i + 1];
+      if (i + 2 < m) v -= du2[i] * x[i + 2];
+      x[i] = v / dd[i];
+    }
+    for (const auto& u : close) {
+      double p = 0.0;
+      for (int i = 0; i < m; ++i) p += u[i] * x[i];
+      for (int i = 0; i < m; ++i) x[i] -= p * u[i];
+    }
+    double nn = 0.0;
+    for (int i = 0; i < m; ++i) nn += x[i] * x[i];
+    nn = std::sqrt(nn);
+    for (int i = 0; i < m; ++i) b[i] = x[i] /= nn;
+  }
+}
+
+// the nev lowest eigenvalues of T (ascending) and their unit eigenvectors
+void tridiag_lowest(const std::vector<double>& d, const std::vector<double>& e, int nev, std::vector<double>& w,
+                    std::vector<std::vector<double>>& z) {
+  const int m = (int)d.size();
+  double lo = d[0], hi = d[0], big = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+    big = std::max(big, std::fabs(d[i]) + r);
+  }
+  const double tiny = 1e-300 + 1e-16 * big;
+  w.resize(nev);
+  z.assign(nev, {});
+  for (int k = 0; k < nev; ++k) w[k] = kth_eigenvalue(d, e, k, lo, hi, tiny);
+  for (int k = 0; k < nev; ++k) {
+    std::vector<std::vector<double>> close;
+    for (int j = 0; j < k; ++j)
+      if (std::fabs(w[k] - w[j]) < 1e-8 * big) close.push_back(z[j]);
+    inverse_iteration(d, e, w[k], tiny, close, z[k]);
+  }
 }
 
 struct Work {
@@ -122,7 +189,11 @@ struct Work {
   float2* r = nullptr;   // residual
   double* partials = nullptr;
   double* coef = nullptr;
+  double* hist = nullptr;  // Lanczos diagonal and off-diagonal entries, norm and scale
+  double2* part = nullptr;  // grouped multiaxpy sums
   ~Work() {
+    (void)hipFree(hist);
+    (void)hipFree(part);
     (void)hipFree(V);
     (void)hipFree(u);
     (void)hipFree(x);
@@ -176,7 +247,7 @@ struct Ctx {
       SP_TRY(hipMemcpyAsync(w.coef, c.data(), sizeof(double) * 2 * count, hipMemcpyHostToDevice, st));
       SP_TRY(hipStreamSynchronize(st));
     }
-    SP_TRY(spec_multiaxpy(y, Vb, n, count, w.coef, scale, st));
+    SP_TRY(spec_multiaxpy(y, Vb, n, count, w.coef, scale, st, nullptr, w.part, kAxpyGroups));
     return QHD_OK;
   }
 
@@ -222,41 +293,55 @@ extern "C" qhd_status qhd_spectrum(qhd_plan plan, int32_t i, double t, int32_t n
   SP_TRY(hipMalloc(&c.w.r, sizeof(float2) * n));
   SP_TRY(hipMalloc(&c.w.partials, sizeof(double) * 2 * kDotBlocks * (m + 1)));
   SP_TRY(hipMalloc(&c.w.coef, sizeof(double) * 2 * (m + 1)));
+  SP_TRY(hipMalloc(&c.w.hist, sizeof(double) * (2 * m + 2)));
+  SP_TRY(hipMalloc(&c.w.part, sizeof(double2) * n * kAxpyGroups));
   float2* V = c.w.V;
   std::vector<double> alpha, beta, co;
+  // The Lanczos recurrence runs on the stream without host round trips: the
+  // Gram-Schmidt coefficients and norms are reduced on the device (block partials summed
+  // in block order in FP64, the sums a host loop would form) and used there; the
+  // diagonal and off-diagonal entries are kept in device memory and read once at the
+  // end.  A breakdown (an invariant subspace) is found there too: the recurrence keeps
+  // going on meaningless vectors and the tridiagonal matrix is cut at the first
+  // vanishing off-diagonal entry.
+  double* d_alpha = c.w.hist;
+  double* d_beta = c.w.hist + m;
+  double* d_nrm = c.w.hist + 2 * m;
+  double* d_scale = c.w.hist + 2 * m + 1;
   // deterministic start vector, normalised
   SP_TRY(spec_random(V, n, 0x51ED5EEDull + (unsigned long long)i, st));
-  double nrm = 0.0;
-  if ((s = c.norm(V, nrm)) != QHD_OK) return s;
-  if ((s = c.axpy(V, V, 0, co, 1.0 / nrm)) != QHD_OK) return s;
-  int mm = 0;
+  SP_TRY(spec_multidot(V, n, 1, V, c.w.partials, kDotBlocks, st));
+  SP_TRY(spec_norm(c.w.partials, kDotBlocks, d_nrm, d_scale, st));
+  SP_TRY(spec_multiaxpy(V, V, n, 0, c.w.coef, 0.0, st, d_scale));
   for (int j = 0; j < m; ++j) {
     float2* w = V + (long long)(j + 1) * n;
     if ((s = c.matvec(V + (long long)j * n, w)) != QHD_OK) return s;
-    double a_j = 0.0;
     for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
-      if ((s = c.dots(V, j + 1, w, co)) != QHD_OK) return s;
-      if (pass == 0) a_j = co[2 * j];
-      if ((s = c.axpy(w, V, j + 1, co, 1.0)) != QHD_OK) return s;
+      SP_TRY(spec_multidot(V, n, j + 1, w, c.w.partials, kDotBlocks, st));
+      SP_TRY(spec_coef(c.w.partials, j + 1, kDotBlocks, c.w.coef, pass == 0 ? d_alpha + j : nullptr, st));
+      SP_TRY(spec_multiaxpy(w, V, n, j + 1, c.w.coef, 1.0, st, nullptr, c.w.part, kAxpyGroups));
     }
-    double b_j = 0.0;
-    if ((s = c.norm(w, b_j)) != QHD_OK) return s;
-    alpha.push_back(a_j);
-    mm = j + 1;
-    if (!(b_j > 1e-10 * std::max(1.0, std::fabs(a_j)))) break;  // invariant subspace
-    beta.push_back(b_j);
-    if ((s = c.axpy(w, V, 0, co, 1.0 / b_j)) != QHD_OK) return s;
+    SP_TRY(spec_multidot(w, n, 1, w, c.w.partials, kDotBlocks, st));
+    SP_TRY(spec_norm(c.w.partials, kDotBlocks, d_beta + j, d_scale, st));
+    SP_TRY(spec_multiaxpy(w, V, n, 0, c.w.coef, 0.0, st, d_scale));
   }
+  {
+    std::vector<double> hab((size_t)2 * m);
+    SP_TRY(hipMemcpyAsync(hab.data(), c.w.hist, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, st));
+    SP_TRY(hipStreamSynchronize(st));
+    for (int j = 0; j < m; ++j) {
+      const double a_j = hab[j], b_j = hab[m + j];
+      alpha.push_back(a_j);
+      if (!(b_j > 1e-10 * std::max(1.0, std::fabs(a_j)))) break;  // invariant subspace
+      beta.push_back(b_j);
+    }
+  }
+  const int mm = (int)alpha.size();
   if (mm < nev) return sfail(QHD_ENUMERIC, "Krylov space exhausted after %d steps (< nev = %d)", mm, nev);
-  std::vector<double> T((size_t)mm * mm, 0.0), evals, evecs;
-  for (int k = 0; k < mm; ++k) {
-    T[(size_t)k * mm + k] = alpha[k];
-    if (k + 1 < mm) T[(size_t)k * mm + k + 1] = T[(size_t)(k + 1) * mm + k] = beta[k];
-  }
-  jacobi_eigen(T, mm, evals, evecs);
-  std::vector<int> order(mm);
-  std::iota(order.begin(), order.end(), 0);
-  std::sort(order.begin(), order.end(), [&](int p, int q) { return evals[p] < evals[q]; });
+  std::vector<double> evals;
+  std::vector<std::vector<double>> evecs;
+  beta.resize(mm > 0 ? mm - 1 : 0);
+  tridiag_lowest(alpha, beta, nev, evals, evecs);
   double psi_norm2 = 0.0;
   if (psi_dev) {
     std::vector<double> pc;
@@ -264,12 +349,11 @@ extern "C" qhd_status qhd_spectrum(qhd_plan plan, int32_t i, double t, int32_t n
     psi_norm2 = pc[0];
   }
   for (int k = 0; k < nev; ++k) {
-    const int col = order[k];
-    energies[k] = evals[col];
+    energies[k] = evals[k];
     if (!residuals && !overlaps) continue;
     // Ritz vector x = sum_j y_j V_j
     std::vector<double> y(2 * (size_t)mm, 0.0);
-    for (int j = 0; j < mm; ++j) y[2 * j] = -evecs[(size_t)j * mm + col];
+    for (int j = 0; j < mm; ++j) y[2 * j] = -evecs[k][j];
     SP_TRY(hipMemsetAsync(c.w.x, 0, sizeof(float2) * n, st));
     if ((s = c.axpy(c.w.x, V, mm, y, 1.0)) != QHD_OK) return s;
     double xn = 0.0;
@@ -277,7 +361,7 @@ extern "C" qhd_status qhd_spectrum(qhd_plan plan, int32_t i, double t, int32_t n
     if ((s = c.axpy(c.w.x, V, 0, co, 1.0 / xn)) != QHD_OK) return s;
     if (residuals) {
       if ((s = c.matvec(c.w.x, c.w.r)) != QHD_OK) return s;
-      std::vector<double> th = {evals[col], 0.0};
+      std::vector<double> th = {evals[k], 0.0};
       if ((s = c.axpy(c.w.r, c.w.x, 1, th, 1.0)) != QHD_OK) return s;
       if ((s = c.norm(c.w.r, residuals[k])) != QHD_OK) return s;
     }

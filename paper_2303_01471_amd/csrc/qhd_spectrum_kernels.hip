@@ -121,17 +121,79 @@ __global__ void __launch_bounds__(256) k_spec_multidot(const float2* __restrict_
   }
 }
 
-// w <- scale (w - sum_i c_i V_i), c_i complex (FP64, device copy)
+// coef[2 i + {0,1}] = sum over the nblk block partials of <V_i, w>, in block order (the
+// same FP64 additions in the same order as a host-side sum); when `keep` is set,
+// keep[0] = coef[2 (count - 1)] (the Lanczos diagonal entry of the newest vector)
+__global__ void k_spec_coef(const double* __restrict__ partials, int count, int nblk, double* __restrict__ coef,
+                            double* __restrict__ keep) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 2 * count) return;
+  const int i = k >> 1, c = k & 1;
+  double acc = 0.0;
+  for (int b = 0; b < nblk; ++b) acc += partials[((long long)i * nblk + b) * 2 + c];
+  coef[k] = acc;
+  if (keep && k == 2 * (count - 1)) keep[0] = acc;
+}
+
+// norm of one vector from its <y, y> partials: keep[0] = sqrt(max(sum, 0)), and
+// scale[0] = 1 / that (the factor of the normalising multiaxpy)
+__global__ void k_spec_norm(const double* __restrict__ partials, int nblk, double* __restrict__ keep,
+                            double* __restrict__ scale) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double acc = 0.0;
+  for (int b = 0; b < nblk; ++b) acc += partials[2 * b];
+  const double nrm = sqrt(acc > 0.0 ? acc : 0.0);
+  keep[0] = nrm;
+  scale[0] = 1.0 / nrm;
+}
+
+// w <- scale (w - sum_i c_i V_i), c_i complex (FP64, device copy); the scale from
+// device memory when scale_dev is given
 __global__ void k_spec_multiaxpy(float2* __restrict__ w, const float2* __restrict__ V, long long n, int count,
-                                 const double* __restrict__ c, double scale) {
+                                 const double* __restrict__ c, double scale_host, const double* __restrict__ scale_dev) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
+  const double scale = scale_dev ? scale_dev[0] : scale_host;
   double xr = w[e].x, xi = w[e].y;
   for (int i = 0; i < count; ++i) {
     const float2 a = V[(long long)i * n + e];
     const double cr = c[2 * i], ci = c[2 * i + 1];
     xr -= cr * a.x - ci * a.y;
     xi -= cr * a.y + ci * a.x;
+  }
+  w[e] = make_float2((float)(scale * xr), (float)(scale * xi));
+}
+
+// Grouped form of the same update for long bases: group g of the grid's y dimension
+// sums c_i V_i over its share of i into part[g] (FP64), then k_spec_axpy_fin subtracts
+// the groups' sums in group order.  One thread per element and group instead of one per
+// element gives the loads of a 16 K-point vector enough waves to be in flight.
+__global__ void k_spec_axpy_part(const float2* __restrict__ V, long long n, int count, const double* __restrict__ c,
+                                 double2* __restrict__ part) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int g = blockIdx.y, groups = gridDim.y;
+  const int per = (count + groups - 1) / groups;
+  const int i0 = g * per, i1 = min(count, i0 + per);
+  double xr = 0.0, xi = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    const float2 a = V[(long long)i * n + e];
+    const double cr = c[2 * i], ci = c[2 * i + 1];
+    xr += cr * a.x - ci * a.y;
+    xi += cr * a.y + ci * a.x;
+  }
+  part[(long long)g * n + e] = make_double2(xr, xi);
+}
+
+__global__ void k_spec_axpy_fin(float2* __restrict__ w, long long n, const double2* __restrict__ part, int groups,
+                                double scale) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double xr = w[e].x, xi = w[e].y;
+  for (int g = 0; g < groups; ++g) {
+    const double2 p = part[(long long)g * n + e];
+    xr -= p.x;
+    xi -= p.y;
   }
   w[e] = make_float2((float)(scale * xr), (float)(scale * xi));
 }
@@ -202,8 +264,24 @@ hipError_t spec_multidot(const float2* V, long long n, int count, const float2* 
 }
 
 hipError_t spec_multiaxpy(float2* w, const float2* V, long long n, int count, const double* c, double scale,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_spec_multiaxpy, dim3(grid1(n)), dim3(256), 0, st, w, V, n, count, c, scale);
+                          hipStream_t st, const double* scale_dev, double2* part, int groups) {
+  if (part && groups > 1 && count >= 2 * groups && !scale_dev) {
+    hipLaunchKernelGGL(k_spec_axpy_part, dim3(grid1(n), groups), dim3(256), 0, st, V, n, count, c, part);
+    hipLaunchKernelGGL(k_spec_axpy_fin, dim3(grid1(n)), dim3(256), 0, st, w, n, part, groups, scale);
+  } else {
+    hipLaunchKernelGGL(k_spec_multiaxpy, dim3(grid1(n)), dim3(256), 0, st, w, V, n, count, c, scale, scale_dev);
+  }
+  return hipGetLastError();
+}
+
+hipError_t spec_coef(const double* partials, int count, int nblk, double* coef, double* keep, hipStream_t st) {
+  hipLaunchKernelGGL(k_spec_coef, dim3((unsigned)((2 * count + 255) / 256)), dim3(256), 0, st, partials, count, nblk,
+                     coef, keep);
+  return hipGetLastError();
+}
+
+hipError_t spec_norm(const double* partials, int nblk, double* keep, double* scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_spec_norm, dim3(1), dim3(64), 0, st, partials, nblk, keep, scale);
   return hipGetLastError();
 }
 
