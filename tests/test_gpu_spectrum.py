@@ -91,6 +91,27 @@ def test_spectrum_errors():
         plan.close()
 
 
+def test_invariant_start_vector_ends_the_recurrence():
+    """H = b f with f = 2 everywhere and a = 0 (no kinetic term): every vector is an
+    eigenvector, so the Krylov space of the start vector has dimension one.  The
+    recurrence (run on the device, its tridiagonal entries read at the end) must stop
+    there: one Ritz value, 2, and asking for two levels is a numerical error."""
+    spec = q.InstanceSpec(shape=(16, 16), nsteps=1, dt=1e-3, sched=q.QHD_SCHED_CONST, sched_p=(0.0, 1.0))
+    plan = _plan(spec, np.full((16, 16), 2.0))
+    try:
+        e, _, res = plan.spectrum(0, 0.5, nev=1, krylov=20)
+        note(f"  E = {e}, residual {res}")
+        assert abs(e[0] - 2.0) < 1e-6 and res[0] < 1e-6
+        with pytest.raises(q.QHDError) as err:
+            plan.spectrum(0, 0.5, nev=2, krylov=20)
+        assert err.value.status == q.QHD_ENUMERIC
+        # the plan stays usable after the error
+        e2, _, _ = plan.spectrum(0, 0.5, nev=1, krylov=20)
+        assert e2[0] == e[0]
+    finally:
+        plan.close()
+
+
 def test_trajectory_snapshots_match_oracle_and_weights_are_a_distribution():
     from gpu_helpers import run_oracle
     from paper_2303_01471_amd import trajectory
