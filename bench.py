@@ -660,6 +660,25 @@ def main():
             p1.close()
             plain["single_256x256_10k_steps_gp_steps_per_s"] = round(c1_rate, 1)
             plain["single_256x256_norm_drift"] = abs(r1[0]["norm"] - 1.0)
+            # the single-instance configuration at 256^2, 512^2 and 1024^2 (roofline scaling):
+            # 1000 steps after 200 warm ones, HBM rate at the 40 B per grid-point-step of the
+            # row and column passes
+            scaling = {}
+            for n_s in (256, 512, 1024):
+                cs = qhd_inputs.single_2d(n_s)
+                ps_ = build_plan([type(cs)(cs.seed, cs.shape, 1200, cs.dt, cs.n_terms, cs.kmax)], q)
+                ps_.set_potential(0, cs.grid())
+                ps_.evolve(200, stream)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                ps_.evolve(-1, stream)
+                torch.cuda.synchronize()
+                r_s = cs.points * 1000 / (time.perf_counter() - t)
+                ps_.close()
+                scaling[str(n_s)] = {"gp_steps_per_s": round(r_s, 1), "hbm_GBps_at_40B": round(r_s * 40 / 1e9, 1),
+                                     "frac_of_8TBs": round(r_s * 40 / (HBM_PEAK_GBS * 1e9), 4)}
+                log(f"single {n_s}x{n_s}: {r_s / 1e9:.2f} G gp-steps/s = {r_s * 40 / 1e9:.0f} GB/s at 40 B")
+            plain["single_instance_roofline_scaling"] = scaling
         plain.update({
                  "method": "per-size rates of the single-instance solver (one plan per instance, "
                            "2000/1000 steps after 200 warm steps), applied to the batch's own sizes "
