@@ -569,7 +569,7 @@ struct ColTwCfg {
   static constexpr int STRIDE = ((LineLds<NY>::kSlots + 13) / 16) * 16 + 2;
   static constexpr bool EY_LDS = P >= 16;                 // E_y / (nx ny) per item in LDS
   // 16 points per lane: three waves per SIMD (168 VGPRs; the LDS of a block admits three)
-  static constexpr int MIN_WAVES = P >= 16 ? 3 : 1;
+  static constexpr int MIN_WAVES = (NT == 512) ? 2 : (P >= 16 ? 3 : 1);
   static_assert(TPL % 8 == 0, "tile-wave column pass needs TPL multiple of 8");
 };
 
@@ -1279,7 +1279,7 @@ constexpr int col_tw_p() { return (N >= 1024 || N == 256 || N == 128) ? 16 : 8; 
 template <int N, bool Y4>
 hipError_t launch_col_tw(int blocks, int nx, const InstDev* inst, int ninst, const int* nact, float2* psi,
                          const double2* tw, int s, long long max_steps, hipStream_t stream) {
-  if constexpr (N >= 64 && N <= 512) {
+  if constexpr (N >= 64 && N <= 1024) {
     constexpr int P_ = col_tw_p<N>();
     QHD_LAUNCH((k_col_pass_tw<N, P_, Y4>), dim3(blocks), dim3(ColTwCfg<N, P_>::NT), 0, stream,
                        inst, nact, ilog2(nx), psi, tw, s, max_steps);
@@ -1290,7 +1290,7 @@ hipError_t launch_col_tw(int blocks, int nx, const InstDev* inst, int ninst, con
 }
 
 int col_variant_resolve(int ny, int variant) {
-  const bool tw_ok = ny >= 64 && ny <= 512;
+  const bool tw_ok = ny >= 64 && ny <= 1024;
   if (variant == kColTileWave && tw_ok) return kColTileWave;
   if (variant == kColStaged16 && (ny == 256 || ny == 512)) return kColStaged16;
   if (variant == kColSplit && ny == 512) return kColSplit;
@@ -1303,7 +1303,7 @@ int pass_blocks_col_2d(int nx, int ny, int ninst, int grid_cap, int variant) {
   int items;
   const int v = col_variant_resolve(ny, variant);
   if (v == kColTileWave) {
-    const int P = (ny == 256 || ny == 128) ? 16 : 8;  // col_tw_p<N>() for every tile-wave size
+    const int P = (ny >= 1024 || ny == 256 || ny == 128) ? 16 : 8;  // col_tw_p<N>() for every tile-wave size
     const int w = ny / P / 8;
     items = w >= 4 ? 1 : 4 / w;
   } else if (v == kColStaged16) {

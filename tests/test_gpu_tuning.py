@@ -100,7 +100,7 @@ def test_uneven_multiclass_graph_replay_is_bitwise_identical_to_direct_launches(
 @pytest.mark.parametrize("n,variant,cap_row,cap_col,row_pts", [(512, 2, 1024, 512, 8), (256, 1, 4096, 8192, 16),
                                                                (128, 1, 512, 1024, 8), (64, 2, 2048, 512, 8),
                                                                (512, 3, 2048, 4096, 16), (256, 3, 8192, 1024, 8),
-                                                               (512, 4, 8192, 512, 16)])
+                                                               (512, 4, 8192, 512, 16), (1024, 2, 1024, 256, 16)])
 def test_cached_launch_choice_matches_oracle(tmp_path, n, variant, cap_row, cap_col, row_pts):
     import torch
     note(f"case: tuning-cache entry n={n} variant={variant} caps=({cap_row},{cap_col}) row points {row_pts}")
