@@ -301,7 +301,9 @@ qhd_status forward(qhd_sno_s* m, const double* f, int B, hipStream_t st) {
   ST_TRY(gemm(m, (int)npix, C, 3, B, m->in, 3, npix * 3, false, m->T(m->pt, m->o_wl), 3, 0, true, z0, C,
               npix * C, false, 1.0f, 0.0f, st));
   ST_TRY(check(m, m->h[0], rows * C * es, "h0"));
-  ST_TRY(launch(m, DEV(m, sno_bias_act(z0, m->params + m->o_bl, rows, C, m->h[0], m->bf16, 0, st)), "lift bias"));
+  // (the biased pre-activations are kept only for the backward pass of training)
+  ST_TRY(launch(m, DEV(m, sno_bias_act(z0, m->params + m->o_bl, rows, C, m->h[0], m->bf16, 0, st, m->train)),
+                "lift bias"));
   for (int l = 0; l < m->L; ++l) {
     void* hin = m->train ? m->h[l] : m->h[l % 2];
     void* hout = m->train ? m->h[l + 1] : m->h[(l + 1) % 2];
@@ -310,12 +312,19 @@ qhd_status forward(qhd_sno_s* m, const double* f, int B, hipStream_t st) {
     ST_TRY(fwd_dft(m, hin, m->Fx, Hl, B, st));
     ST_TRY(mix(m, Hl, m->G, l, B, st));
     ST_TRY(inv_dft(m, m->G, m->Gxw, zl, B, 0.0f, st));
-    // z += h W^T
-    ST_TRY(gemm(m, (int)npix, C, C, B, hin, C, npix * C, false, m->T(m->pt, m->o_w[l]), C, 0, true, zl, C,
-                npix * C, false, 1.0f, 1.0f, st));
     ST_TRY(check(m, hout, rows * C * es, "layer output"));
     ST_TRY(check(m, zl, rows * C * 4, "layer pre-activation"));
-    ST_TRY(launch(m, DEV(m, sno_bias_act(zl, m->params + m->o_b[l], rows, C, hout, m->bf16, 1, st)), "bias+GELU"));
+    if (!m->train && m->bf16 && C == 32) {
+      // inference: the 1x1 map, bias and GELU in one pass (the pre-activation is not kept)
+      ST_TRY(launch(m, DEV(m, sno_pointwise32(hin, m->T(m->pt, m->o_w[l]), zl, m->params + m->o_b[l], rows, hout,
+                                              1, st)), "1x1 map+GELU"));
+    } else {
+      // z += h W^T
+      ST_TRY(gemm(m, (int)npix, C, C, B, hin, C, npix * C, false, m->T(m->pt, m->o_w[l]), C, 0, true, zl, C,
+                  npix * C, false, 1.0f, 1.0f, st));
+      ST_TRY(launch(m, DEV(m, sno_bias_act(zl, m->params + m->o_b[l], rows, C, hout, m->bf16, 1, st, m->train)),
+                    "bias+GELU"));
+    }
   }
   void* hL = m->train ? m->h[m->L] : m->h[m->L % 2];
   ST_TRY(check(m, m->rho_hat, rows * 4, "density"));

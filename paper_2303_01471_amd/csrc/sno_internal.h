@@ -39,7 +39,10 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t stream);
 hipError_t sno_prep_input(const double* f, int batch, int S, void* in, bool bf16, hipStream_t st);
 // z += bias; h = z (act 0) or GELU(z) (act 1)
 hipError_t sno_bias_act(float* z, const float* bias, long long rows, int C, void* h, bool bf16, int act,
-                        hipStream_t st);
+                        hipStream_t st, bool keep_z = true);
+// inference: out = act(z + h W^T + b) in BF16 for width 32 (h, W, out BF16; z, b FP32)
+hipError_t sno_pointwise32(const void* h, const void* W, const float* z, const float* bias, long long npix,
+                           void* out, int act, hipStream_t st);
 hipError_t sno_project_softmax(const void* h, const float* wp, const float* bp, int batch, int npix,
                                int C, bool bf16, float* rho, hipStream_t st);
 hipError_t sno_loss_grad(const float* rho_hat, const float* rho, int batch, int npix, float* dq,

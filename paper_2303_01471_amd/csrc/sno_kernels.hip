@@ -66,15 +66,76 @@ __global__ void __launch_bounds__(256) k_prep(const double* __restrict__ f, int 
   }
 }
 
-// z += bias (kept for the backward pass); h = act(z), act = identity (0) or GELU (1)
+// z += bias (kept for the backward pass when keep_z); h = act(z), act = identity (0)
+// or GELU (1)
 template <typename T>
 __global__ void k_bias_act(float* __restrict__ z, const float* __restrict__ bias, long long n, int C,
-                           T* __restrict__ h, int act) {
+                           T* __restrict__ h, int act, int keep_z) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const float v = z[e] + bias[e % C];
-  z[e] = v;
+  if (keep_z) z[e] = v;
   h[e] = (T)(act ? gelu(v) : v);
+}
+
+// the same with 4 consecutive elements per thread, for C a multiple of 4 dividing 1024
+// (a block's 1024 elements then start on a row boundary: the channel of element 4 t + i
+// is (4 t + i) mod C, no 64-bit division); n a multiple of 4
+template <typename T>
+__global__ void __launch_bounds__(256) k_bias_act4(float* __restrict__ z, const float* __restrict__ bias,
+                                                   long long n4, int C, T* __restrict__ h, int act, int keep_z) {
+  const long long e4 = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e4 >= n4) return;
+  const int c0 = (4 * (int)threadIdx.x) & (C - 1);
+  const float4 zv = reinterpret_cast<const float4*>(z)[e4];
+  float v[4] = {zv.x + bias[c0], zv.y + bias[c0 + 1], zv.z + bias[c0 + 2], zv.w + bias[c0 + 3]};
+  if (keep_z) reinterpret_cast<float4*>(z)[e4] = make_float4(v[0], v[1], v[2], v[3]);
+  T o[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) o[i] = (T)(act ? gelu(v[i]) : v[i]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) h[4 * e4 + i] = o[i];
+}
+
+// Inference form of a layer's closing 1x1 map for width 32: out[p][n] = act(z[p][n] +
+// sum_k h[p][k] W[n][k] + b[n]) in BF16, z the layer's spectral part (FP32).  One
+// wavefront per 32 pixels on v_mfma_f32_32x32x16_bf16 (two k steps): the A operand is
+// the pixels' rows of h straight from HBM (lane l: pixel l mod 32, k 8 (l / 32) + i), the
+// B operand the weights, loaded once per wavefront (lane l: n = l mod 32, same k), and
+// the 32 x 32 result (register r: pixel 8 (r / 4) + 4 (l / 32) + r mod 4, channel
+// l mod 32) gets z, the bias and the activation before its one store.  The pre-activation
+// is not written back (the backward pass of training keeps the GEMM + bias_act form).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+template <int ACT>
+__global__ void __launch_bounds__(256) k_pointwise32(const __bf16* __restrict__ h, const __bf16* __restrict__ W,
+                                                     const float* __restrict__ z, const float* __restrict__ bias,
+                                                     long long npix, __bf16* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const long long p0 = (((long long)blockIdx.x * 256 + threadIdx.x) >> 6) * 32;
+  if (p0 >= npix) return;  // wavefront-uniform
+  const int n = lane & 31, kh = 8 * (lane >> 5);
+  const bf16x8_t b0 = *reinterpret_cast<const bf16x8_t*>(W + n * 32 + kh);
+  const bf16x8_t b1 = *reinterpret_cast<const bf16x8_t*>(W + n * 32 + 16 + kh);
+  const long long pa = p0 + n;
+  bf16x8_t a0 = {}, a1 = {};
+  if (pa < npix) {
+    a0 = *reinterpret_cast<const bf16x8_t*>(h + pa * 32 + kh);
+    a1 = *reinterpret_cast<const bf16x8_t*>(h + pa * 32 + 16 + kh);
+  }
+  f32x16_t acc = {};
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc, 0, 0, 0);
+  const float bn = bias[n];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const long long p = p0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (p < npix) {
+      const float v = acc[r] + z[p * 32 + n] + bn;
+      out[p * 32 + n] = (__bf16)(ACT ? gelu(v) : v);
+    }
+  }
 }
 
 // one block per sample: logits q = h . wp + bp, then softmax over the grid
@@ -259,10 +320,36 @@ hipError_t sno_prep_input(const double* f, int batch, int S, void* in, bool bf16
 }
 
 hipError_t sno_bias_act(float* z, const float* bias, long long rows, int C, void* h, bool bf16, int act,
-                        hipStream_t st) {
+                        hipStream_t st, bool keep_z) {
   const long long n = rows * C;
-  if (bf16) hipLaunchKernelGGL(k_bias_act<__bf16>, grid1(n), dim3(256), 0, st, z, bias, n, C, (__bf16*)h, act);
-  else hipLaunchKernelGGL(k_bias_act<float>, grid1(n), dim3(256), 0, st, z, bias, n, C, (float*)h, act);
+  const bool pow2 = C >= 4 && (C & (C - 1)) == 0 && 1024 % C == 0;
+  if (pow2 && (reinterpret_cast<uintptr_t>(z) & 15) == 0) {
+    const long long n4 = n / 4;
+    if (bf16)
+      hipLaunchKernelGGL(k_bias_act4<__bf16>, grid1(n4), dim3(256), 0, st, z, bias, n4, C, (__bf16*)h, act,
+                         keep_z ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_bias_act4<float>, grid1(n4), dim3(256), 0, st, z, bias, n4, C, (float*)h, act,
+                         keep_z ? 1 : 0);
+    return hipGetLastError();
+  }
+  if (bf16)
+    hipLaunchKernelGGL(k_bias_act<__bf16>, grid1(n), dim3(256), 0, st, z, bias, n, C, (__bf16*)h, act, keep_z ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_bias_act<float>, grid1(n), dim3(256), 0, st, z, bias, n, C, (float*)h, act, keep_z ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t sno_pointwise32(const void* h, const void* W, const float* z, const float* bias, long long npix,
+                           void* out, int act, hipStream_t st) {
+  const long long waves = (npix + 31) / 32;
+  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  if (act)
+    hipLaunchKernelGGL(k_pointwise32<1>, dim3(blocks), dim3(256), 0, st, (const __bf16*)h, (const __bf16*)W, z, bias,
+                       npix, (__bf16*)out);
+  else
+    hipLaunchKernelGGL(k_pointwise32<0>, dim3(blocks), dim3(256), 0, st, (const __bf16*)h, (const __bf16*)W, z, bias,
+                       npix, (__bf16*)out);
   return hipGetLastError();
 }
 

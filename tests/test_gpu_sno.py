@@ -129,6 +129,36 @@ def test_bf16_forward_and_gradient_within_rounding_bounds():
     assert cos > 0.99
 
 
+def test_bf16_inference_forward_within_rounding_bounds():
+    """The inference form (train=False: each layer's 1x1 map, bias and GELU in one
+    matrix-core pass, the pre-activation not kept) against the FP64 reference and the
+    training form's forward on the same parameters, at the production shape."""
+    import torch
+    cfg = ref.Config(S=128, C=32, M=16, L=4)
+    B = 3
+    note("case: surrogate bf16 inference forward, production shape")
+    p = ref.random_params(cfg, 43).astype(np.float32)
+    f, _ = _inputs(cfg, B, 44)
+    outs = {}
+    for train in (False, True):
+        net = _net(cfg, B, "bf16", train=train)
+        try:
+            net.set_params(p)
+            out = net.forward(_dev(f, torch.float64))
+            torch.cuda.synchronize()
+            outs[train] = out.cpu().numpy().astype(np.float64)
+        finally:
+            net.close()
+    want = ref.forward(p.astype(np.float64), f, cfg)
+    l1 = np.abs(outs[False] - want).reshape(B, -1).sum(axis=1)
+    l1_tt = np.abs(outs[False] - outs[True]).reshape(B, -1).sum(axis=1)
+    l1_t = np.abs(outs[True] - want).reshape(B, -1).sum(axis=1)
+    note(f"  L1(inference, fp64) = {l1}; L1(training form, fp64) = {l1_t}; L1(inference, training form) = {l1_tt}")
+    assert np.all(l1 < 0.05)
+    assert np.all(l1_tt < 0.05)
+    assert np.allclose(outs[False].reshape(B, -1).sum(axis=1), 1.0, atol=1e-4)
+
+
 def test_adam_step_matches_closed_form_first_step():
     import torch
     cfg = ref.Config(S=32, C=8, M=4, L=1)
