@@ -202,14 +202,20 @@ qhd_status fwd_dft(qhd_sno_s* m, const void* X, const void* fx, void* H, int B, 
 }
 
 // truncated inverse (c2r) of G [B][4M][M][C] into out FP32 [B][S][S][C]; gx = Gxw or Gx
+// y-contraction of the truncated inverse, per b: Ur (S x MC) = GyR (S x 4M) . G_b ; Ui = GyI . G_b
+// -> U in the T1 buffer, [B][S][2M][C]
+qhd_status inv_dft_y(qhd_sno_s* m, const void* Gsp, int B, hipStream_t st) {
+  const int S = m->S, C = m->C, M = m->M;
+  ST_TRY(gemm(m, S, M * C, 4 * M, B, m->GyR, 4 * M, 0, false, Gsp, M * C, m->spec, false, m->T1, 2 * M * C,
+              (long long)S * 2 * M * C, true, 1.0f, 0.0f, st));
+  return gemm(m, S, M * C, 4 * M, B, m->GyI, 4 * M, 0, false, Gsp, M * C, m->spec, false,
+              m->T(m->T1, (long long)M * C), 2 * M * C, (long long)S * 2 * M * C, true, 1.0f, 0.0f, st);
+}
+
 qhd_status inv_dft(qhd_sno_s* m, const void* Gsp, const void* gx, float* out, int B, float beta,
                    hipStream_t st) {
   const int S = m->S, C = m->C, M = m->M;
-  // y-contraction, per b: Ur (S x MC) = GyR (S x 4M) . G_b ; Ui = GyI . G_b  -> U = T1 buffer
-  ST_TRY(gemm(m, S, M * C, 4 * M, B, m->GyR, 4 * M, 0, false, Gsp, M * C, m->spec, false, m->T1, 2 * M * C,
-              (long long)S * 2 * M * C, true, 1.0f, 0.0f, st));
-  ST_TRY(gemm(m, S, M * C, 4 * M, B, m->GyI, 4 * M, 0, false, Gsp, M * C, m->spec, false,
-              m->T(m->T1, (long long)M * C), 2 * M * C, (long long)S * 2 * M * C, true, 1.0f, 0.0f, st));
+  ST_TRY(inv_dft_y(m, Gsp, B, st));
   // x-contraction, per (b, y): out_by (S x C) = gx (S x 2M) . U_by (2M x C)
   return gemm(m, S, C, 2 * M, B * S, gx, 2 * M, 0, false, m->T1, C, 2LL * M * C, false, out, C,
               (long long)S * C, false, 1.0f, beta, st);
@@ -294,16 +300,22 @@ qhd_status forward(qhd_sno_s* m, const double* f, int B, hipStream_t st) {
   const int C = m->C;
   const long long npix = m->npix, rows = (long long)B * npix;
   const long long es = (long long)m->es;
-  ST_TRY(check(m, m->in, rows * 3 * es, "features"));
-  ST_TRY(launch(m, DEV(m, sno_prep_input(f, B, m->S, m->in, m->bf16, st)), "features launch"));
-  // lift: z = x0 Wl^T (per sample: npix x C), then h0 = z + bl
-  float* z0 = m->z[0];
-  ST_TRY(gemm(m, (int)npix, C, 3, B, m->in, 3, npix * 3, false, m->T(m->pt, m->o_wl), 3, 0, true, z0, C,
-              npix * C, false, 1.0f, 0.0f, st));
   ST_TRY(check(m, m->h[0], rows * C * es, "h0"));
-  // (the biased pre-activations are kept only for the backward pass of training)
-  ST_TRY(launch(m, DEV(m, sno_bias_act(z0, m->params + m->o_bl, rows, C, m->h[0], m->bf16, 0, st, m->train)),
-                "lift bias"));
+  if (!m->train && m->bf16 && C == 32) {
+    // inference: features and lift in one pass (the features are kept only for the lift's gradient)
+    ST_TRY(launch(m, DEV(m, sno_prep_lift32(f, B, m->S, m->T(m->pt, m->o_wl), m->params + m->o_bl, m->h[0], st)),
+                  "features+lift"));
+  } else {
+    ST_TRY(check(m, m->in, rows * 3 * es, "features"));
+    ST_TRY(launch(m, DEV(m, sno_prep_input(f, B, m->S, m->in, m->bf16, st)), "features launch"));
+    // lift: z = x0 Wl^T (per sample: npix x C), then h0 = z + bl
+    float* z0 = m->z[0];
+    ST_TRY(gemm(m, (int)npix, C, 3, B, m->in, 3, npix * 3, false, m->T(m->pt, m->o_wl), 3, 0, true, z0, C,
+                npix * C, false, 1.0f, 0.0f, st));
+    // (the biased pre-activations are kept only for the backward pass of training)
+    ST_TRY(launch(m, DEV(m, sno_bias_act(z0, m->params + m->o_bl, rows, C, m->h[0], m->bf16, 0, st, m->train)),
+                  "lift bias"));
+  }
   for (int l = 0; l < m->L; ++l) {
     void* hin = m->train ? m->h[l] : m->h[l % 2];
     void* hout = m->train ? m->h[l + 1] : m->h[(l + 1) % 2];
@@ -311,8 +323,17 @@ qhd_status forward(qhd_sno_s* m, const double* f, int B, hipStream_t st) {
     void* Hl = m->train ? m->Hs[l] : m->Hs[0];
     ST_TRY(fwd_dft(m, hin, m->Fx, Hl, B, st));
     ST_TRY(mix(m, Hl, m->G, l, B, st));
-    ST_TRY(inv_dft(m, m->G, m->Gxw, zl, B, 0.0f, st));
     ST_TRY(check(m, hout, rows * C * es, "layer output"));
+    if (!m->train && m->bf16 && C == 32 && m->M == 16 && m->S % 32 == 0) {
+      // inference: the inverse's x-contraction, the 1x1 map, bias and GELU in one pass
+      ST_TRY(inv_dft_y(m, m->G, B, st));
+      ST_TRY(check(m, m->T1, (long long)B * m->S * 2 * m->M * C * es, "inverse y-contraction"));
+      ST_TRY(launch(m, DEV(m, sno_spectral_pointwise32(m->Gxw, m->T1, hin, m->T(m->pt, m->o_w[l]),
+                                                       m->params + m->o_b[l], m->S, (long long)B * m->S, hout, 1,
+                                                       st)), "inverse+1x1 map+GELU"));
+      continue;
+    }
+    ST_TRY(inv_dft(m, m->G, m->Gxw, zl, B, 0.0f, st));
     ST_TRY(check(m, zl, rows * C * 4, "layer pre-activation"));
     if (!m->train && m->bf16 && C == 32) {
       // inference: the 1x1 map, bias and GELU in one pass (the pre-activation is not kept)

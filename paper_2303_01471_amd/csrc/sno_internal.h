@@ -41,6 +41,13 @@ hipError_t sno_prep_input(const double* f, int batch, int S, void* in, bool bf16
 hipError_t sno_bias_act(float* z, const float* bias, long long rows, int C, void* h, bool bf16, int act,
                         hipStream_t st, bool keep_z = true);
 // inference: out = act(z + h W^T + b) in BF16 for width 32 (h, W, out BF16; z, b FP32)
+// inference at width 32 in BF16: features and lift (h0 = x0 Wl^T + bl, Wl is C x 3) in one pass
+hipError_t sno_prep_lift32(const double* f, int batch, int S, const void* Wl, const float* bl, void* h,
+                           hipStream_t st);
+// inference at width 32, 16 modes, BF16: per row of S pixels (nrows = batch x S rows),
+// out = act(gx U_row + h W^T + bias); gx is S x 32, U holds a 32 x 32 block per row, S % 32 == 0
+hipError_t sno_spectral_pointwise32(const void* gx, const void* U, const void* h, const void* W, const float* bias,
+                                    int S, long long nrows, void* out, int act, hipStream_t st);
 hipError_t sno_pointwise32(const void* h, const void* W, const float* z, const float* bias, long long npix,
                            void* out, int act, hipStream_t st);
 hipError_t sno_project_softmax(const void* h, const float* wp, const float* bp, int batch, int npix,

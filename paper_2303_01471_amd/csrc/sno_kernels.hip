@@ -149,11 +149,28 @@ __global__ void __launch_bounds__(256) k_project_softmax(const T* __restrict__ h
   const T* hb = h + (long long)b * npix * C;
   float* rb = rho + (long long)b * npix;
   float mx = -INFINITY;
-  for (int p = threadIdx.x; p < npix; p += 256) {
-    float q = bp[0];
-    for (int c = 0; c < C; ++c) q = fmaf(ld(hb, (long long)p * C + c), wp[c], q);
-    rb[p] = q;
-    mx = fmaxf(mx, q);
+  if (sizeof(T) == 2 && C == 32) {
+    // width 32 in BF16: a pixel's 64-byte row in four 16-byte loads, the same FMA order
+    typedef T t8 __attribute__((ext_vector_type(8)));
+    for (int p = threadIdx.x; p < npix; p += 256) {
+      const t8* row = reinterpret_cast<const t8*>(hb + (long long)p * 32);
+      float q = bp[0];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const t8 x = row[v];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) q = fmaf((float)x[i], wp[8 * v + i], q);
+      }
+      rb[p] = q;
+      mx = fmaxf(mx, q);
+    }
+  } else {
+    for (int p = threadIdx.x; p < npix; p += 256) {
+      float q = bp[0];
+      for (int c = 0; c < C; ++c) q = fmaf(ld(hb, (long long)p * C + c), wp[c], q);
+      rb[p] = q;
+      mx = fmaxf(mx, q);
+    }
   }
   mx = block_max(mx, shf);
   double s = 0.0;
@@ -337,6 +354,111 @@ hipError_t sno_bias_act(float* z, const float* bias, long long rows, int C, void
     hipLaunchKernelGGL(k_bias_act<__bf16>, grid1(n), dim3(256), 0, st, z, bias, n, C, (__bf16*)h, act, keep_z ? 1 : 0);
   else
     hipLaunchKernelGGL(k_bias_act<float>, grid1(n), dim3(256), 0, st, z, bias, n, C, (float*)h, act, keep_z ? 1 : 0);
+  return hipGetLastError();
+}
+
+// inference form at width 32 in BF16: one sample's features, formed as k_prep forms them and
+// rounded to BF16 like the lift's operands, and the lift h0 = x0 Wl^T + bl in one pass; the
+// features are not stored. Thread t writes channels 8(t%4) .. 8(t%4)+7 of its pixels.
+__global__ void __launch_bounds__(256) k_prep_lift32(const double* __restrict__ f, int S,
+                                                     const __bf16* __restrict__ Wl, const float* __restrict__ bl,
+                                                     __bf16* __restrict__ h) {
+  __shared__ double sh[256];
+  const int b = blockIdx.x, npix = S * S;
+  const double* fb = f + (long long)b * npix;
+  double s1 = 0.0, s2 = 0.0;
+  for (int p = threadIdx.x; p < npix; p += 256) {
+    s1 += fb[p];
+    s2 += fb[p] * fb[p];
+  }
+  const double mean = block_sum(s1, sh) / npix;
+  const double var = block_sum(s2, sh) / npix - mean * mean;
+  const double inv = 1.0 / sqrt(var > 1e-24 ? var : 1e-24);
+  const int c = threadIdx.x & 3;
+  float w0[8], w1[8], w2[8], bb[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int n = 8 * c + i;
+    w0[i] = (float)Wl[3 * n];
+    w1[i] = (float)Wl[3 * n + 1];
+    w2[i] = (float)Wl[3 * n + 2];
+    bb[i] = bl[n];
+  }
+  bf16x8_t* hb = reinterpret_cast<bf16x8_t*>(h + (long long)b * npix * 32);
+  for (int e = threadIdx.x; e < npix * 4; e += 256) {
+    const int p = e >> 2;
+    const float x0 = (float)(__bf16)(float)((fb[p] - mean) * inv);
+    const float x1 = (float)(__bf16)((float)(p % S) / (float)S);
+    const float x2 = (float)(__bf16)((float)(p / S) / (float)S);
+    bf16x8_t o;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = (__bf16)(fmaf(x2, w2[i], fmaf(x1, w1[i], x0 * w0[i])) + bb[i]);
+    hb[e] = o;
+  }
+}
+
+hipError_t sno_prep_lift32(const double* f, int batch, int S, const void* Wl, const float* bl, void* h,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_prep_lift32, dim3(batch), dim3(256), 0, st, f, S, (const __bf16*)Wl, bl, (__bf16*)h);
+  return hipGetLastError();
+}
+
+// inference at width 32 with 16 modes per axis, BF16: the x-contraction of the truncated inverse
+// transform, the 1x1 map, bias and activation in one pass. For the row (b, y) of S pixels:
+// out (S x 32) = act(gx U_by + h_by W^T + b), gx (S x 32), U_by (32 x 32, [k][channel]), W
+// ([out][in]); all four products accumulate in one FP32 tile. One wave per row, 32 pixels per step.
+template <int ACT>
+__global__ void __launch_bounds__(256) k_spectral_pointwise32(const __bf16* __restrict__ gx,
+                                                              const __bf16* __restrict__ U,
+                                                              const __bf16* __restrict__ h,
+                                                              const __bf16* __restrict__ W,
+                                                              const float* __restrict__ bias, int S, long long nrows,
+                                                              __bf16* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const long long row = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
+  if (row >= nrows) return;  // wavefront-uniform
+  const int n = lane & 31, kh = 8 * (lane >> 5);
+  const bf16x8_t w0 = *reinterpret_cast<const bf16x8_t*>(W + n * 32 + kh);
+  const bf16x8_t w1 = *reinterpret_cast<const bf16x8_t*>(W + n * 32 + 16 + kh);
+  const __bf16* Ur = U + row * 1024;
+  bf16x8_t u0, u1;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    u0[i] = Ur[(kh + i) * 32 + n];
+    u1[i] = Ur[(16 + kh + i) * 32 + n];
+  }
+  const float bn = bias[n];
+  const long long pbase = row * S;
+  for (int x0 = 0; x0 < S; x0 += 32) {
+    const int x = x0 + n;
+    const long long pa = pbase + x;
+    const bf16x8_t g0 = *reinterpret_cast<const bf16x8_t*>(gx + x * 32 + kh);
+    const bf16x8_t g1 = *reinterpret_cast<const bf16x8_t*>(gx + x * 32 + 16 + kh);
+    const bf16x8_t a0 = *reinterpret_cast<const bf16x8_t*>(h + pa * 32 + kh);
+    const bf16x8_t a1 = *reinterpret_cast<const bf16x8_t*>(h + pa * 32 + 16 + kh);
+    f32x16_t acc = {};
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(g0, u0, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(g1, u1, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, w0, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, w1, acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const long long p = pbase + x0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const float v = acc[r] + bn;
+      out[p * 32 + n] = (__bf16)(ACT ? gelu(v) : v);
+    }
+  }
+}
+
+hipError_t sno_spectral_pointwise32(const void* gx, const void* U, const void* h, const void* W, const float* bias,
+                                    int S, long long nrows, void* out, int act, hipStream_t st) {
+  const unsigned blocks = (unsigned)((nrows + 3) / 4);
+  if (act)
+    hipLaunchKernelGGL(k_spectral_pointwise32<1>, dim3(blocks), dim3(256), 0, st, (const __bf16*)gx,
+                       (const __bf16*)U, (const __bf16*)h, (const __bf16*)W, bias, S, nrows, (__bf16*)out);
+  else
+    hipLaunchKernelGGL(k_spectral_pointwise32<0>, dim3(blocks), dim3(256), 0, st, (const __bf16*)gx,
+                       (const __bf16*)U, (const __bf16*)h, (const __bf16*)W, bias, S, nrows, (__bf16*)out);
   return hipGetLastError();
 }
 
