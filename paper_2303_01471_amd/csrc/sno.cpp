@@ -194,8 +194,14 @@ qhd_status gemm(const qhd_sno_s* m, int M, int N, int K, int batch, const void* 
 qhd_status fwd_dft(qhd_sno_s* m, const void* X, const void* fx, void* H, int B, hipStream_t st) {
   const int S = m->S, C = m->C, M = m->M;
   // x-contraction, per (b, y): T1 (2M x C) = fx (2M x S) . X_by (S x C)
-  ST_TRY(gemm(m, 2 * M, C, S, B * S, fx, S, 0, false, X, C, (long long)S * C, false, m->T1, C, 2LL * M * C,
-              true, 1.0f, 0.0f, st));
+  if (m->bf16 && C == 32 && M == 16 && S % 16 == 0) {
+    ST_TRY(check(m, X, (long long)B * S * S * C * m->es, "transform input"));
+    ST_TRY(check(m, m->T1, (long long)B * S * 2 * M * C * m->es, "x-contraction"));
+    ST_TRY(launch(m, DEV(m, sno_dft_x32(fx, X, S, (long long)B * S, m->T1, st)), "x-contraction"));
+  } else {
+    ST_TRY(gemm(m, 2 * M, C, S, B * S, fx, S, 0, false, X, C, (long long)S * C, false, m->T1, C, 2LL * M * C,
+                true, 1.0f, 0.0f, st));
+  }
   // y-contraction, per b: [Hr; Hi] (4M x MC) = Fy1 (4M x S) . Tr_b + Fy2 (4M x S) . Ti_b
   return gemm(m, 4 * M, M * C, S, B, m->Fy1, S, 0, false, m->T1, 2 * M * C, (long long)S * 2 * M * C,
               false, H, M * C, m->spec, true, 1.0f, 0.0f, st, m->Fy2, m->T(m->T1, (long long)M * C), 1.0f);

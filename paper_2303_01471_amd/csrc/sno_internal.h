@@ -48,6 +48,9 @@ hipError_t sno_prep_lift32(const double* f, int batch, int S, const void* Wl, co
 // out = act(gx U_row + h W^T + bias); gx is S x 32, U holds a 32 x 32 block per row, S % 32 == 0
 hipError_t sno_spectral_pointwise32(const void* gx, const void* U, const void* h, const void* W, const float* bias,
                                     int S, long long nrows, void* out, int act, hipStream_t st);
+// width 32, 16 modes, BF16: per row of S pixels (nrows = batch x S), T_row (32 x 32) = fx (32 x S) X_row;
+// S % 16 == 0
+hipError_t sno_dft_x32(const void* fx, const void* X, int S, long long nrows, void* T, hipStream_t st);
 hipError_t sno_pointwise32(const void* h, const void* W, const float* z, const float* bias, long long npix,
                            void* out, int act, hipStream_t st);
 hipError_t sno_project_softmax(const void* h, const float* wp, const float* bp, int batch, int npix,

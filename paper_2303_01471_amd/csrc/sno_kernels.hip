@@ -462,6 +462,37 @@ hipError_t sno_spectral_pointwise32(const void* gx, const void* U, const void* h
   return hipGetLastError();
 }
 
+// x-contraction of the truncated forward transform at width 32 with 16 modes, BF16: for the row
+// (b, y) of S pixels, T_row (32 x 32, [k][channel]) = fx (32 x S) X_row (S x 32), FP32 accumulation,
+// BF16 result. One wave per row; lane = channel, so each pixel's channels are gathered as the
+// k-operand of the matrix cores.
+__global__ void __launch_bounds__(256) k_dft_x32(const __bf16* __restrict__ fx, const __bf16* __restrict__ X,
+                                                 int S, long long nrows, __bf16* __restrict__ T) {
+  const int lane = threadIdx.x & 63;
+  const long long row = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
+  if (row >= nrows) return;  // wavefront-uniform
+  const int c = lane & 31, kh = 8 * (lane >> 5);
+  const __bf16* Xr = X + row * S * 32;
+  f32x16_t acc = {};
+#pragma unroll 4
+  for (int x0 = 0; x0 < S; x0 += 16) {
+    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(fx + c * S + x0 + kh);
+    bf16x8_t b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b[i] = Xr[(x0 + kh + i) * 32 + c];
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+  __bf16* Tr = T + row * 1024;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) Tr[(8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * 32 + c] = (__bf16)acc[r];
+}
+
+hipError_t sno_dft_x32(const void* fx, const void* X, int S, long long nrows, void* T, hipStream_t st) {
+  hipLaunchKernelGGL(k_dft_x32, dim3((unsigned)((nrows + 3) / 4)), dim3(256), 0, st, (const __bf16*)fx,
+                     (const __bf16*)X, S, nrows, (__bf16*)T);
+  return hipGetLastError();
+}
+
 hipError_t sno_pointwise32(const void* h, const void* W, const float* z, const float* bias, long long npix,
                            void* out, int act, hipStream_t st) {
   const long long waves = (npix + 31) / 32;
