@@ -191,10 +191,13 @@ qhd_status gemm(const qhd_sno_s* m, int M, int N, int K, int batch, const void* 
 }
 
 // truncated forward DFT of X [B][S][S][C] (T) into H [B][4M][M][C] (T); fx = Fx or Fxw
-qhd_status fwd_dft(qhd_sno_s* m, const void* X, const void* fx, void* H, int B, hipStream_t st) {
+// (x_done: T1 already holds the x-contraction of X)
+qhd_status fwd_dft(qhd_sno_s* m, const void* X, const void* fx, void* H, int B, hipStream_t st,
+                   bool x_done = false) {
   const int S = m->S, C = m->C, M = m->M;
   // x-contraction, per (b, y): T1 (2M x C) = fx (2M x S) . X_by (S x C)
-  if (m->bf16 && C == 32 && M == 16 && S % 16 == 0) {
+  if (x_done) {
+  } else if (m->bf16 && C == 32 && M == 16 && S % 16 == 0) {
     ST_TRY(check(m, X, (long long)B * S * S * C * m->es, "transform input"));
     ST_TRY(check(m, m->T1, (long long)B * S * 2 * M * C * m->es, "x-contraction"));
     ST_TRY(launch(m, DEV(m, sno_dft_x32(fx, X, S, (long long)B * S, m->T1, st)), "x-contraction"));
@@ -322,21 +325,25 @@ qhd_status forward(qhd_sno_s* m, const double* f, int B, hipStream_t st) {
     ST_TRY(launch(m, DEV(m, sno_bias_act(z0, m->params + m->o_bl, rows, C, m->h[0], m->bf16, 0, st, m->train)),
                   "lift bias"));
   }
+  // inference at width 32 with 16 modes: a layer's inverse x-contraction, 1x1 map, bias and GELU
+  // are one pass, which also forms the next layer's forward x-contraction
+  const bool fused = !m->train && m->bf16 && C == 32 && m->M == 16 && m->S % 32 == 0;
   for (int l = 0; l < m->L; ++l) {
     void* hin = m->train ? m->h[l] : m->h[l % 2];
     void* hout = m->train ? m->h[l + 1] : m->h[(l + 1) % 2];
     float* zl = m->train ? m->z[l] : m->z[0];
     void* Hl = m->train ? m->Hs[l] : m->Hs[0];
-    ST_TRY(fwd_dft(m, hin, m->Fx, Hl, B, st));
+    ST_TRY(fwd_dft(m, hin, m->Fx, Hl, B, st, fused && l > 0));
     ST_TRY(mix(m, Hl, m->G, l, B, st));
     ST_TRY(check(m, hout, rows * C * es, "layer output"));
-    if (!m->train && m->bf16 && C == 32 && m->M == 16 && m->S % 32 == 0) {
-      // inference: the inverse's x-contraction, the 1x1 map, bias and GELU in one pass
+    if (fused) {
       ST_TRY(inv_dft_y(m, m->G, B, st));
       ST_TRY(check(m, m->T1, (long long)B * m->S * 2 * m->M * C * es, "inverse y-contraction"));
+      const bool next = l + 1 < m->L;
       ST_TRY(launch(m, DEV(m, sno_spectral_pointwise32(m->Gxw, m->T1, hin, m->T(m->pt, m->o_w[l]),
                                                        m->params + m->o_b[l], m->S, (long long)B * m->S, hout, 1,
-                                                       st)), "inverse+1x1 map+GELU"));
+                                                       next ? m->Fx : nullptr, m->T1, st)),
+                    "inverse+1x1 map+GELU"));
       continue;
     }
     ST_TRY(inv_dft(m, m->G, m->Gxw, zl, B, 0.0f, st));

@@ -405,19 +405,23 @@ hipError_t sno_prep_lift32(const double* f, int batch, int S, const void* Wl, co
 
 // inference at width 32 with 16 modes per axis, BF16: the x-contraction of the truncated inverse
 // transform, the 1x1 map, bias and activation in one pass. For the row (b, y) of S pixels:
-// out (S x 32) = act(gx U_by + h_by W^T + b), gx (S x 32), U_by (32 x 32, [k][channel]), W
+// out (S x 32) = act(gx U_row + h_row W^T + b), gx (S x 32), U_row (32 x 32, [k][channel]), W
 // ([out][in]); all four products accumulate in one FP32 tile. One wave per row, 32 pixels per step.
-template <int ACT>
-__global__ void __launch_bounds__(256) k_spectral_pointwise32(const __bf16* __restrict__ gx,
-                                                              const __bf16* __restrict__ U,
+// With NEXT the next layer's forward x-contraction T_row = fx out_row (fx 32 x S) is formed from
+// the rounded outputs while they are in registers and written over U_row (each wave reads its
+// U_row before it writes T_row, so U and T may be the same buffer).
+template <int ACT, bool NEXT>
+__global__ void __launch_bounds__(256) k_spectral_pointwise32(const __bf16* __restrict__ gx, const __bf16* U,
                                                               const __bf16* __restrict__ h,
                                                               const __bf16* __restrict__ W,
                                                               const float* __restrict__ bias, int S, long long nrows,
-                                                              __bf16* __restrict__ out) {
+                                                              __bf16* __restrict__ out, const __bf16* __restrict__ fx,
+                                                              __bf16* T) {
+  typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
   const long long row = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
   if (row >= nrows) return;  // wavefront-uniform
-  const int n = lane & 31, kh = 8 * (lane >> 5);
+  const int n = lane & 31, j = lane >> 5, kh = 8 * j;
   const bf16x8_t w0 = *reinterpret_cast<const bf16x8_t*>(W + n * 32 + kh);
   const bf16x8_t w1 = *reinterpret_cast<const bf16x8_t*>(W + n * 32 + 16 + kh);
   const __bf16* Ur = U + row * 1024;
@@ -429,6 +433,7 @@ __global__ void __launch_bounds__(256) k_spectral_pointwise32(const __bf16* __re
   }
   const float bn = bias[n];
   const long long pbase = row * S;
+  f32x16_t tacc = {};
   for (int x0 = 0; x0 < S; x0 += 32) {
     const int x = x0 + n;
     const long long pa = pbase + x;
@@ -441,24 +446,52 @@ __global__ void __launch_bounds__(256) k_spectral_pointwise32(const __bf16* __re
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(g1, u1, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, w0, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, w1, acc, 0, 0, 0);
+    bf16x8_t o0, o1;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const long long p = pbase + x0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const long long p = pbase + x0 + 8 * (r >> 2) + 4 * j + (r & 3);
       const float v = acc[r] + bn;
-      out[p * 32 + n] = (__bf16)(ACT ? gelu(v) : v);
+      const __bf16 o = (__bf16)(ACT ? gelu(v) : v);
+      out[p * 32 + n] = o;
+      if (r < 8) o0[r] = o;
+      else o1[r - 8] = o;
     }
+    if constexpr (NEXT) {
+      // k slot i of lane half j holds pixel x0 + 4j + i (i < 4) or x0 + 8 + 4j + (i - 4) of the
+      // output layout (o0), 16 more for o1: fx's operand takes the same pixels
+      const __bf16* fr = fx + n * S + x0 + 4 * j;
+      const bf16x4_t f0 = *reinterpret_cast<const bf16x4_t*>(fr);
+      const bf16x4_t f1 = *reinterpret_cast<const bf16x4_t*>(fr + 8);
+      const bf16x4_t f2 = *reinterpret_cast<const bf16x4_t*>(fr + 16);
+      const bf16x4_t f3 = *reinterpret_cast<const bf16x4_t*>(fr + 24);
+      const bf16x8_t fa = {f0[0], f0[1], f0[2], f0[3], f1[0], f1[1], f1[2], f1[3]};
+      const bf16x8_t fb = {f2[0], f2[1], f2[2], f2[3], f3[0], f3[1], f3[2], f3[3]};
+      tacc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, o0, tacc, 0, 0, 0);
+      tacc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fb, o1, tacc, 0, 0, 0);
+    }
+  }
+  if constexpr (NEXT) {
+    __bf16* Tr = T + row * 1024;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) Tr[(8 * (r >> 2) + 4 * j + (r & 3)) * 32 + n] = (__bf16)tacc[r];
   }
 }
 
 hipError_t sno_spectral_pointwise32(const void* gx, const void* U, const void* h, const void* W, const float* bias,
-                                    int S, long long nrows, void* out, int act, hipStream_t st) {
+                                    int S, long long nrows, void* out, int act, const void* fx, void* T,
+                                    hipStream_t st) {
   const unsigned blocks = (unsigned)((nrows + 3) / 4);
-  if (act)
-    hipLaunchKernelGGL(k_spectral_pointwise32<1>, dim3(blocks), dim3(256), 0, st, (const __bf16*)gx,
-                       (const __bf16*)U, (const __bf16*)h, (const __bf16*)W, bias, S, nrows, (__bf16*)out);
-  else
-    hipLaunchKernelGGL(k_spectral_pointwise32<0>, dim3(blocks), dim3(256), 0, st, (const __bf16*)gx,
-                       (const __bf16*)U, (const __bf16*)h, (const __bf16*)W, bias, S, nrows, (__bf16*)out);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, st, (const __bf16*)gx, (const __bf16*)U, (const __bf16*)h,
+                       (const __bf16*)W, bias, S, nrows, (__bf16*)out, (const __bf16*)fx, (__bf16*)T);
+  };
+  if (fx) {
+    if (act) go(k_spectral_pointwise32<1, true>);
+    else go(k_spectral_pointwise32<0, true>);
+  } else {
+    if (act) go(k_spectral_pointwise32<1, false>);
+    else go(k_spectral_pointwise32<0, false>);
+  }
   return hipGetLastError();
 }
 
