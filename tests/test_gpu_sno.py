@@ -197,7 +197,7 @@ def test_bf16_inference_forward_within_rounding_bounds(S, C, M, L, B):
     # FP64 emulation of the BF16 storage gives 3e-3 to 5e-3 on these inputs); the spectral
     # path alone moves them by 0.15 to 0.57, so a fault in it fails the bound
     bound = 0.05
-    assert np.all(l1(want, no_spec) > 3 * bound)
+    assert np.all(l1(want, no_spec) > 2.5 * bound)
     assert np.all(l1(outs[False], want) < bound)
     assert np.all(l1(outs[True], want) < bound)
     assert np.allclose(outs[False].reshape(B, -1).sum(axis=1), 1.0, atol=1e-4)
