@@ -72,7 +72,7 @@ struct qhd_sno_s {
   int adam_t = 0;
   bool have_grad = false;
   void *Fx = nullptr, *Fxw = nullptr, *Fy1 = nullptr, *Fy2 = nullptr;
-  void *GyR = nullptr, *GyI = nullptr, *Gxw = nullptr, *Gx = nullptr;
+  void *Gy = nullptr, *Gxw = nullptr, *Gx = nullptr;  // Gy: rows 2y, 2y+1 = GyR, GyI rows y
   void* in = nullptr;
   std::vector<void*> h;
   std::vector<float*> z;
@@ -212,13 +212,13 @@ qhd_status fwd_dft(qhd_sno_s* m, const void* X, const void* fx, void* H, int B, 
 
 // truncated inverse (c2r) of G [B][4M][M][C] into out FP32 [B][S][S][C]; gx = Gxw or Gx
 // y-contraction of the truncated inverse, per b: Ur (S x MC) = GyR (S x 4M) . G_b ; Ui = GyI . G_b
-// -> U in the T1 buffer, [B][S][2M][C]
+// -> U in the T1 buffer, [B][S][2M][C]. One product: with the rows of GyR and GyI interleaved
+// (Gy, 2S x 4M), output row 2y is Ur's row y and row 2y+1 is Ui's, which is U's layout at a
+// row stride of MC
 qhd_status inv_dft_y(qhd_sno_s* m, const void* Gsp, int B, hipStream_t st) {
   const int S = m->S, C = m->C, M = m->M;
-  ST_TRY(gemm(m, S, M * C, 4 * M, B, m->GyR, 4 * M, 0, false, Gsp, M * C, m->spec, false, m->T1, 2 * M * C,
-              (long long)S * 2 * M * C, true, 1.0f, 0.0f, st));
-  return gemm(m, S, M * C, 4 * M, B, m->GyI, 4 * M, 0, false, Gsp, M * C, m->spec, false,
-              m->T(m->T1, (long long)M * C), 2 * M * C, (long long)S * 2 * M * C, true, 1.0f, 0.0f, st);
+  return gemm(m, 2 * S, M * C, 4 * M, B, m->Gy, 4 * M, 0, false, Gsp, M * C, m->spec, false, m->T1, M * C,
+              (long long)S * 2 * M * C, true, 1.0f, 0.0f, st);
 }
 
 qhd_status inv_dft(qhd_sno_s* m, const void* Gsp, const void* gx, float* out, int B, float beta,
@@ -252,7 +252,7 @@ qhd_status build_dft(qhd_sno_s* m) {
   auto ky = [&](int j) { return j < M ? j : j - 2 * M; };
   auto wk = [&](int kx) { return kx == 0 ? 1.0 : 2.0; };
   std::vector<float> fx(2 * M * S), fxw(2 * M * S), fy1(4 * M * S), fy2(4 * M * S);
-  std::vector<float> gyr(S * 4 * M), gyi(S * 4 * M), gxw(S * 2 * M), gx(S * 2 * M);
+  std::vector<float> gy(2 * S * 4 * M), gxw(S * 2 * M), gx(S * 2 * M);
   for (int kx = 0; kx < M; ++kx)
     for (int x = 0; x < S; ++x) {
       const double a = tp * kx * x;
@@ -276,21 +276,21 @@ qhd_status build_dft(qhd_sno_s* m) {
       fy2[j * S + y] = (float)s;
       fy2[(2 * M + j) * S + y] = (float)c;
       // Ur = [Gyr | -Gyi] [Gr; Gi], Ui = [Gyi | Gyr] [Gr; Gi] with Gyr = c, Gyi = s
-      gyr[y * 4 * M + j] = (float)c;
-      gyr[y * 4 * M + 2 * M + j] = (float)-s;
-      gyi[y * 4 * M + j] = (float)s;
-      gyi[y * 4 * M + 2 * M + j] = (float)c;
+      gy[2 * y * 4 * M + j] = (float)c;
+      gy[2 * y * 4 * M + 2 * M + j] = (float)-s;
+      gy[(2 * y + 1) * 4 * M + j] = (float)s;
+      gy[(2 * y + 1) * 4 * M + 2 * M + j] = (float)c;
     }
   struct Item {
     std::vector<float>* v;
     void** dst;
   } items[] = {{&fx, &m->Fx}, {&fxw, &m->Fxw}, {&fy1, &m->Fy1}, {&fy2, &m->Fy2},
-               {&gyr, &m->GyR}, {&gyi, &m->GyI}, {&gxw, &m->Gxw}, {&gx, &m->Gx}};
+               {&gy, &m->Gy}, {&gxw, &m->Gxw}, {&gx, &m->Gx}};
   for (auto& it : items)
     if (alloc(m, it.dst, it.v->size() * m->es) != hipSuccess) return sfail(QHD_ENOMEM, "DFT matrix allocation");
   if (m->dry) return QHD_OK;
   float* tmp = nullptr;
-  SNO_TRY(hipMalloc(&tmp, (size_t)S * 4 * M * sizeof(float)));
+  SNO_TRY(hipMalloc(&tmp, (size_t)2 * S * 4 * M * sizeof(float)));
   qhd_status st = QHD_OK;
   for (auto& it : items) {
     hipError_t e = hipMemcpy(tmp, it.v->data(), it.v->size() * sizeof(float), hipMemcpyHostToDevice);
