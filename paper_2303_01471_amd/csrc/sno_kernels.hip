@@ -106,6 +106,13 @@ __global__ void __launch_bounds__(256) k_bias_act4(float* __restrict__ z, const 
 // l mod 32) gets z, the bias and the activation before its one store.  The pre-activation
 // is not written back (the backward pass of training keeps the GEMM + bias_act form).
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+// LDS writes of a wavefront visible to its own later LDS reads (no block barrier)
+__device__ __forceinline__ void sno_wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 template <int ACT>
@@ -433,6 +440,11 @@ __global__ void __launch_bounds__(256) k_spectral_pointwise32(const __bf16* __re
   }
   const float bn = bias[n];
   const long long pbase = row * S;
+  // the 32 x 32 output tile goes through LDS (row stride 40: the two lane halves' rows, 4
+  // apart, fall on disjoint banks) so that it leaves as two 16-byte stores per lane
+  __shared__ __attribute__((aligned(16))) __bf16 stage[4][32 * 40];
+  __bf16* sw = stage[threadIdx.x >> 6];
+  bf16x8_t* const ob = reinterpret_cast<bf16x8_t*>(out + pbase * 32);
   f32x16_t tacc = {};
   for (int x0 = 0; x0 < S; x0 += 32) {
     const int x = x0 + n;
@@ -449,13 +461,18 @@ __global__ void __launch_bounds__(256) k_spectral_pointwise32(const __bf16* __re
     bf16x8_t o0, o1;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const long long p = pbase + x0 + 8 * (r >> 2) + 4 * j + (r & 3);
       const float v = acc[r] + bn;
       const __bf16 o = (__bf16)(ACT ? gelu(v) : v);
-      out[p * 32 + n] = o;
+      sw[(8 * (r >> 2) + 4 * j + (r & 3)) * 40 + n] = o;
       if (r < 8) o0[r] = o;
       else o1[r - 8] = o;
     }
+    sno_wave_lds_sync();
+    const bf16x8_t s0 = *reinterpret_cast<const bf16x8_t*>(sw + (lane >> 2) * 40 + 8 * (lane & 3));
+    const bf16x8_t s1 = *reinterpret_cast<const bf16x8_t*>(sw + (16 + (lane >> 2)) * 40 + 8 * (lane & 3));
+    ob[x0 * 4 + lane] = s0;  // pixel x0 + lane / 4, channels 8 (lane % 4) ..
+    ob[x0 * 4 + 64 + lane] = s1;
+    sno_wave_lds_sync();  // the next step rewrites the tile
     if constexpr (NEXT) {
       // k slot i of lane half j holds pixel x0 + 4j + i (i < 4) or x0 + 8 + 4j + (i - 4) of the
       // output layout (o0), 16 more for o1: fx's operand takes the same pixels
