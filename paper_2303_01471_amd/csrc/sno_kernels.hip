@@ -488,9 +488,13 @@ __global__ void __launch_bounds__(256) k_spectral_pointwise32(const __bf16* __re
     }
   }
   if constexpr (NEXT) {
-    __bf16* Tr = T + row * 1024;
+    // T_row (32 x 32, [k][channel]) through the same LDS tile
 #pragma unroll
-    for (int r = 0; r < 16; ++r) Tr[(8 * (r >> 2) + 4 * j + (r & 3)) * 32 + n] = (__bf16)tacc[r];
+    for (int r = 0; r < 16; ++r) sw[(8 * (r >> 2) + 4 * j + (r & 3)) * 40 + n] = (__bf16)tacc[r];
+    sno_wave_lds_sync();
+    bf16x8_t* const tb = reinterpret_cast<bf16x8_t*>(T + row * 1024);
+    tb[lane] = *reinterpret_cast<const bf16x8_t*>(sw + (lane >> 2) * 40 + 8 * (lane & 3));
+    tb[64 + lane] = *reinterpret_cast<const bf16x8_t*>(sw + (16 + (lane >> 2)) * 40 + 8 * (lane & 3));
   }
 }
 
