@@ -446,18 +446,25 @@ __global__ void __launch_bounds__(256) k_spectral_pointwise32(const __bf16* __re
   __bf16* sw = stage[threadIdx.x >> 6];
   bf16x8_t* const ob = reinterpret_cast<bf16x8_t*>(out + pbase * 32);
   f32x16_t tacc = {};
+  // operands of the step at x0 are loaded during the step before it
+  bf16x8_t g0 = *reinterpret_cast<const bf16x8_t*>(gx + n * 32 + kh);
+  bf16x8_t g1 = *reinterpret_cast<const bf16x8_t*>(gx + n * 32 + 16 + kh);
+  bf16x8_t a0 = *reinterpret_cast<const bf16x8_t*>(h + (pbase + n) * 32 + kh);
+  bf16x8_t a1 = *reinterpret_cast<const bf16x8_t*>(h + (pbase + n) * 32 + 16 + kh);
   for (int x0 = 0; x0 < S; x0 += 32) {
-    const int x = x0 + n;
-    const long long pa = pbase + x;
-    const bf16x8_t g0 = *reinterpret_cast<const bf16x8_t*>(gx + x * 32 + kh);
-    const bf16x8_t g1 = *reinterpret_cast<const bf16x8_t*>(gx + x * 32 + 16 + kh);
-    const bf16x8_t a0 = *reinterpret_cast<const bf16x8_t*>(h + pa * 32 + kh);
-    const bf16x8_t a1 = *reinterpret_cast<const bf16x8_t*>(h + pa * 32 + 16 + kh);
     f32x16_t acc = {};
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(g0, u0, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(g1, u1, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, w0, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, w1, acc, 0, 0, 0);
+    if (x0 + 32 < S) {
+      const int x = x0 + 32 + n;
+      const long long pa = pbase + x;
+      g0 = *reinterpret_cast<const bf16x8_t*>(gx + x * 32 + kh);
+      g1 = *reinterpret_cast<const bf16x8_t*>(gx + x * 32 + 16 + kh);
+      a0 = *reinterpret_cast<const bf16x8_t*>(h + pa * 32 + kh);
+      a1 = *reinterpret_cast<const bf16x8_t*>(h + pa * 32 + 16 + kh);
+    }
     bf16x8_t o0, o1;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
