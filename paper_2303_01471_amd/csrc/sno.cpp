@@ -217,6 +217,11 @@ qhd_status fwd_dft(qhd_sno_s* m, const void* X, const void* fx, void* H, int B, 
 // row stride of MC
 qhd_status inv_dft_y(qhd_sno_s* m, const void* Gsp, int B, hipStream_t st) {
   const int S = m->S, C = m->C, M = m->M;
+  if (m->bf16 && C == 32 && M == 16 && S % 16 == 0) {
+    ST_TRY(check(m, Gsp, (long long)B * m->spec * m->es, "inverse input"));
+    ST_TRY(check(m, m->T1, (long long)B * S * 2 * M * C * m->es, "inverse y-contraction"));
+    return launch(m, DEV(m, sno_inv_y32(m->Gy, Gsp, m->spec, B, S, m->T1, st)), "inverse y-contraction");
+  }
   return gemm(m, 2 * S, M * C, 4 * M, B, m->Gy, 4 * M, 0, false, Gsp, M * C, m->spec, false, m->T1, M * C,
               (long long)S * 2 * M * C, true, 1.0f, 0.0f, st);
 }

@@ -54,6 +54,9 @@ hipError_t sno_spectral_pointwise32(const void* gx, const void* U, const void* h
 // width 32, 16 modes, BF16: per row of S pixels (nrows = batch x S), T_row (32 x 32) = fx (32 x S) X_row;
 // S % 16 == 0
 hipError_t sno_dft_x32(const void* fx, const void* X, int S, long long nrows, void* T, hipStream_t st);
+// width 32, 16 modes, BF16: per sample U (2S x 512, row stride 512, sample stride 1024 S) =
+// Gy (2S x 64) G_b (64 x 512, sample stride gstride); S % 16 == 0
+hipError_t sno_inv_y32(const void* Gy, const void* G, long long gstride, int batch, int S, void* U, hipStream_t st);
 hipError_t sno_pointwise32(const void* h, const void* W, const float* z, const float* bias, long long npix,
                            void* out, int act, hipStream_t st);
 hipError_t sno_project_softmax(const void* h, const float* wp, const float* bp, int batch, int npix,

@@ -554,6 +554,49 @@ hipError_t sno_dft_x32(const void* fx, const void* X, int S, long long nrows, vo
   return hipGetLastError();
 }
 
+// inverse transform's y-contraction at width 32 with 16 modes, BF16, one sample per
+// workgroup: U (2S x 512) = Gy (2S x 64) G_b (64 x 512), Gy's rows 2y, 2y+1 the cosine and
+// sine rows of y. G_b is staged in LDS transposed ([column][k], row stride 72: each lane's
+// 16-byte k operand is contiguous and aligned); each wavefront keeps the Gy operands of its
+// 32-row tiles in registers and runs over the 16 column tiles.
+__global__ void __launch_bounds__(256) k_inv_y32(const __bf16* __restrict__ Gy, const __bf16* __restrict__ G,
+                                                 long long gstride, int S, __bf16* __restrict__ U) {
+  __shared__ __attribute__((aligned(16))) __bf16 gt[512 * 72];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = lane & 31, h = lane >> 5;
+  const __bf16* Gb = G + (long long)blockIdx.x * gstride;
+  for (int e = tid; e < 64 * 64; e += 256) {  // 16-byte pieces: row k = e / 64, columns 8 (e % 64) ..
+    const int k = e >> 6, c0 = (e & 63) * 8;
+    const bf16x8_t v = *reinterpret_cast<const bf16x8_t*>(Gb + k * 512 + c0);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) gt[(c0 + i) * 72 + k] = v[i];
+  }
+  __syncthreads();
+  __bf16* Ub = U + (long long)blockIdx.x * S * 1024;
+  for (int rt = wave; rt < S / 16; rt += 4) {  // 2S rows in tiles of 32
+    bf16x8_t a[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) a[st] = *reinterpret_cast<const bf16x8_t*>(Gy + (32 * rt + c) * 64 + 16 * st + 8 * h);
+    for (int ct = 0; ct < 16; ++ct) {
+      f32x16_t acc = {};
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(gt + (32 * ct + c) * 72 + 16 * st + 8 * h);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[st], b, acc, 0, 0, 0);
+      }
+      __bf16* Ut = Ub + (long long)(32 * rt) * 512 + 32 * ct + c;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) Ut[(8 * (r >> 2) + 4 * h + (r & 3)) * 512] = (__bf16)acc[r];
+    }
+  }
+}
+
+hipError_t sno_inv_y32(const void* Gy, const void* G, long long gstride, int batch, int S, void* U, hipStream_t st) {
+  hipLaunchKernelGGL(k_inv_y32, dim3(batch), dim3(256), 0, st, (const __bf16*)Gy, (const __bf16*)G, gstride, S,
+                     (__bf16*)U);
+  return hipGetLastError();
+}
+
 hipError_t sno_pointwise32(const void* h, const void* W, const float* z, const float* bias, long long npix,
                            void* out, int act, hipStream_t st) {
   const long long waves = (npix + 31) / 32;
