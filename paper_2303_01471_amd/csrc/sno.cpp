@@ -206,6 +206,10 @@ qhd_status fwd_dft(qhd_sno_s* m, const void* X, const void* fx, void* H, int B, 
                 true, 1.0f, 0.0f, st));
   }
   // y-contraction, per b: [Hr; Hi] (4M x MC) = Fy1 (4M x S) . Tr_b + Fy2 (4M x S) . Ti_b
+  if (m->bf16 && C == 32 && M == 16 && S % 16 == 0 && S <= 256) {
+    ST_TRY(check(m, H, (long long)B * m->spec * m->es, "spectrum"));
+    return launch(m, DEV(m, sno_fwd_y32(m->Fy1, m->Fy2, m->T1, B, S, H, m->spec, st)), "y-contraction");
+  }
   return gemm(m, 4 * M, M * C, S, B, m->Fy1, S, 0, false, m->T1, 2 * M * C, (long long)S * 2 * M * C,
               false, H, M * C, m->spec, true, 1.0f, 0.0f, st, m->Fy2, m->T(m->T1, (long long)M * C), 1.0f);
 }

@@ -57,6 +57,10 @@ hipError_t sno_dft_x32(const void* fx, const void* X, int S, long long nrows, vo
 // width 32, 16 modes, BF16: per sample U (2S x 512, row stride 512, sample stride 1024 S) =
 // Gy (2S x 64) G_b (64 x 512, sample stride gstride); S % 16 == 0
 hipError_t sno_inv_y32(const void* Gy, const void* G, long long gstride, int batch, int S, void* U, hipStream_t st);
+// width 32, 16 modes, BF16, S % 16 == 0 and S <= 256: per sample [Hr; Hi] (64 x 512, row stride
+// 512, sample stride hstride) = Fy1 (64 x S) T_r + Fy2 (64 x S) T_i, T_b (S x 1024, halves r | i)
+hipError_t sno_fwd_y32(const void* Fy1, const void* Fy2, const void* T, int batch, int S, void* H, long long hstride,
+                       hipStream_t st);
 hipError_t sno_pointwise32(const void* h, const void* W, const float* z, const float* bias, long long npix,
                            void* out, int act, hipStream_t st);
 hipError_t sno_project_softmax(const void* h, const float* wp, const float* bp, int batch, int npix,

@@ -597,6 +597,62 @@ hipError_t sno_inv_y32(const void* Gy, const void* G, long long gstride, int bat
   return hipGetLastError();
 }
 
+// forward transform's y-contraction at width 32 with 16 modes, BF16, one sample per
+// workgroup: [Hr; Hi] (64 x 512) = Fy1 (64 x S) Tr + Fy2 (64 x S) Ti, with Tr and Ti the two
+// halves of each row of T_b (S x 1024). Fy1 and Fy2 are staged in LDS (row stride S + 8);
+// T's k operand (8 rows of one column per lane half) is gathered from HBM, each element
+// once; wavefront w takes the column tiles w, w + 4, ..., both 32-row tiles of each.
+__global__ void __launch_bounds__(256) k_fwd_y32(const __bf16* __restrict__ Fy1, const __bf16* __restrict__ Fy2,
+                                                 const __bf16* __restrict__ T, int S, __bf16* __restrict__ H,
+                                                 long long hstride) {
+  __shared__ __attribute__((aligned(16))) __bf16 fy[2 * 64 * 264];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = lane & 31, h = lane >> 5, ld = S + 8;
+  for (int e = tid; e < 64 * S / 8; e += 256) {  // 16-byte pieces of both matrices
+    const int r = e / (S / 8), k0 = (e - r * (S / 8)) * 8;
+    *reinterpret_cast<bf16x8_t*>(fy + r * ld + k0) = *reinterpret_cast<const bf16x8_t*>(Fy1 + r * S + k0);
+    *reinterpret_cast<bf16x8_t*>(fy + 64 * ld + r * ld + k0) =
+        *reinterpret_cast<const bf16x8_t*>(Fy2 + r * S + k0);
+  }
+  __syncthreads();
+  const __bf16* Tb = T + (long long)blockIdx.x * S * 1024;
+  __bf16* Hb = H + (long long)blockIdx.x * hstride;
+  for (int ct = wave; ct < 16; ct += 4) {
+    f32x16_t acc0 = {}, acc1 = {};
+    const __bf16* tc = Tb + 32 * ct + c;
+    for (int k0 = 0; k0 < S; k0 += 16) {
+      bf16x8_t br, bi;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        br[i] = tc[(k0 + 8 * h + i) * 1024];
+        bi[i] = tc[(k0 + 8 * h + i) * 1024 + 512];
+      }
+      const __bf16* f1 = fy + c * ld + k0 + 8 * h;
+      const __bf16* f2 = f1 + 64 * ld;
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8_t*>(f1), br, acc0, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8_t*>(f2), bi, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8_t*>(f1 + 32 * ld), br, acc1, 0,
+                                                     0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8_t*>(f2 + 32 * ld), bi, acc1, 0,
+                                                     0, 0);
+    }
+    __bf16* ho = Hb + 32 * ct + c;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+      ho[row * 512] = (__bf16)acc0[r];
+      ho[(32 + row) * 512] = (__bf16)acc1[r];
+    }
+  }
+}
+
+hipError_t sno_fwd_y32(const void* Fy1, const void* Fy2, const void* T, int batch, int S, void* H, long long hstride,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_fwd_y32, dim3(batch), dim3(256), 0, st, (const __bf16*)Fy1, (const __bf16*)Fy2,
+                     (const __bf16*)T, S, (__bf16*)H, hstride);
+  return hipGetLastError();
+}
+
 hipError_t sno_pointwise32(const void* h, const void* W, const float* z, const float* bias, long long npix,
                            void* out, int act, hipStream_t st) {
   const long long waves = (npix + 31) / 32;
