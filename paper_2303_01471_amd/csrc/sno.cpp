@@ -246,6 +246,11 @@ qhd_status mix(qhd_sno_s* m, const void* H, void* Gout, int l, int B, hipStream_
   const void* Rr = m->T(m->pt, m->o_rr[l]);
   const void* Ri = m->T(m->pt, m->o_ri[l]);
   const int ld = (int)m->spec;
+  if (m->bf16 && C == 32) {
+    ST_TRY(check(m, H, (long long)B * m->spec * m->es, "mixing input"));
+    ST_TRY(check(m, Gout, (long long)B * m->spec * m->es, "mixing output"));
+    return launch(m, DEV(m, sno_mix32(H, Rr, Ri, nm, m->spec, B, Gout, st)), "mixing");
+  }
   // Gr = Hr Rr^T - Hi Ri^T
   ST_TRY(gemm(m, B, C, C, nm, H, ld, C, false, Rr, C, (long long)C * C, true, Gout, ld, C, true, 1.0f, 0.0f,
               st, m->T(H, half), Ri, -1.0f));

@@ -61,6 +61,10 @@ hipError_t sno_inv_y32(const void* Gy, const void* G, long long gstride, int bat
 // 512, sample stride hstride) = Fy1 (64 x S) T_r + Fy2 (64 x S) T_i, T_b (S x 1024, halves r | i)
 hipError_t sno_fwd_y32(const void* Fy1, const void* Fy2, const void* T, int batch, int S, void* H, long long hstride,
                        hipStream_t st);
+// width 32, BF16: per mode m and sample b, G = R[m] H (complex; R [mode][out][in] as Rr, Ri;
+// spectra [b][re | im][mode][channel] with sample stride spec)
+hipError_t sno_mix32(const void* H, const void* Rr, const void* Ri, int nmodes, long long spec, int batch, void* G,
+                     hipStream_t st);
 hipError_t sno_pointwise32(const void* h, const void* W, const float* z, const float* bias, long long npix,
                            void* out, int act, hipStream_t st);
 hipError_t sno_project_softmax(const void* h, const float* wp, const float* bp, int batch, int npix,

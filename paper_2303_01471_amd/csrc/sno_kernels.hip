@@ -653,6 +653,66 @@ hipError_t sno_fwd_y32(const void* Fy1, const void* Fy2, const void* T, int batc
   return hipGetLastError();
 }
 
+// per-mode complex mixing at width 32, BF16: for mode m and 32 samples, Gr = Hr Rr[m]^T -
+// Hi Ri[m]^T and Gi = Hr Ri[m]^T + Hi Rr[m]^T (R[m] is [out][in]); spectra are [b][re | im]
+// [mode][channel], half = nmodes x 32 apart. One wavefront per (mode, 32 samples), modes
+// fastest; the sine products' weights are negated in BF16 (exact).
+__global__ void __launch_bounds__(256) k_mix32(const __bf16* __restrict__ H, const __bf16* __restrict__ Rr,
+                                               const __bf16* __restrict__ Ri, int nmodes, long long spec, int B,
+                                               __bf16* __restrict__ G) {
+  const int lane = threadIdx.x & 63;
+  const long long wid = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int mode = (int)(wid % nmodes);
+  const int b0 = (int)(wid / nmodes) * 32;
+  if (b0 >= B) return;  // wavefront-uniform
+  const int r = lane & 31, h = lane >> 5, kh = 8 * h;
+  const long long half = (long long)nmodes * 32;
+  bf16x8_t hr0 = {}, hr1 = {}, hi0 = {}, hi1 = {};
+  if (b0 + r < B) {
+    const __bf16* hb = H + (long long)(b0 + r) * spec + mode * 32 + kh;
+    hr0 = *reinterpret_cast<const bf16x8_t*>(hb);
+    hr1 = *reinterpret_cast<const bf16x8_t*>(hb + 16);
+    hi0 = *reinterpret_cast<const bf16x8_t*>(hb + half);
+    hi1 = *reinterpret_cast<const bf16x8_t*>(hb + half + 16);
+  }
+  const __bf16* rr = Rr + (long long)mode * 1024 + r * 32 + kh;
+  const __bf16* ri = Ri + (long long)mode * 1024 + r * 32 + kh;
+  const bf16x8_t rr0 = *reinterpret_cast<const bf16x8_t*>(rr), rr1 = *reinterpret_cast<const bf16x8_t*>(rr + 16);
+  const bf16x8_t ri0 = *reinterpret_cast<const bf16x8_t*>(ri), ri1 = *reinterpret_cast<const bf16x8_t*>(ri + 16);
+  bf16x8_t ni0, ni1;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    ni0[i] = -ri0[i];
+    ni1[i] = -ri1[i];
+  }
+  f32x16_t gr = {}, gi = {};
+  gr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hr0, rr0, gr, 0, 0, 0);
+  gr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hr1, rr1, gr, 0, 0, 0);
+  gr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi0, ni0, gr, 0, 0, 0);
+  gr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi1, ni1, gr, 0, 0, 0);
+  gi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hr0, ri0, gi, 0, 0, 0);
+  gi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hr1, ri1, gi, 0, 0, 0);
+  gi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi0, rr0, gi, 0, 0, 0);
+  gi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi1, rr1, gi, 0, 0, 0);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int b = b0 + 8 * (q >> 2) + 4 * h + (q & 3);
+    if (b < B) {
+      __bf16* g = G + (long long)b * spec + mode * 32 + r;
+      g[0] = (__bf16)gr[q];
+      g[half] = (__bf16)gi[q];
+    }
+  }
+}
+
+hipError_t sno_mix32(const void* H, const void* Rr, const void* Ri, int nmodes, long long spec, int batch, void* G,
+                     hipStream_t st) {
+  const long long waves = (long long)nmodes * ((batch + 31) / 32);
+  hipLaunchKernelGGL(k_mix32, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, (const __bf16*)H,
+                     (const __bf16*)Rr, (const __bf16*)Ri, nmodes, spec, batch, (__bf16*)G);
+  return hipGetLastError();
+}
+
 hipError_t sno_pointwise32(const void* h, const void* W, const float* z, const float* bias, long long npix,
                            void* out, int act, hipStream_t st) {
   const long long waves = (npix + 31) / 32;
