@@ -565,8 +565,10 @@ __global__ void __launch_bounds__(256) k_inv_y32(const __bf16* __restrict__ Gy, 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c = lane & 31, h = lane >> 5;
   const __bf16* Gb = G + (long long)blockIdx.x * gstride;
-  for (int e = tid; e < 64 * 64; e += 256) {  // 16-byte pieces: row k = e / 64, columns 8 (e % 64) ..
-    const int k = e >> 6, c0 = (e & 63) * 8;
+  for (int e = tid; e < 64 * 64; e += 256) {  // 16-byte pieces: row k = e % 64, columns 8 (e / 64) ..
+    // (a wavefront's lanes take the 64 rows of one column group, so each of its transposed
+    // 2-byte writes covers 64 consecutive entries of one LDS row)
+    const int k = e & 63, c0 = (e >> 6) * 8;
     const bf16x8_t v = *reinterpret_cast<const bf16x8_t*>(Gb + k * 512 + c0);
 #pragma unroll
     for (int i = 0; i < 8; ++i) gt[(c0 + i) * 72 + k] = v[i];
