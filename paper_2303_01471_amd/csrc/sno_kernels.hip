@@ -607,7 +607,7 @@ hipError_t sno_inv_y32(const void* Gy, const void* G, long long gstride, int bat
 __global__ void __launch_bounds__(256) k_fwd_y32(const __bf16* __restrict__ Fy1, const __bf16* __restrict__ Fy2,
                                                  const __bf16* __restrict__ T, int S, __bf16* __restrict__ H,
                                                  long long hstride) {
-  __shared__ __attribute__((aligned(16))) __bf16 fy[2 * 64 * 264];
+  extern __shared__ __attribute__((aligned(16))) __bf16 fy[];  // 2 x 64 x (S + 8), sized at launch
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c = lane & 31, h = lane >> 5, ld = S + 8;
   for (int e = tid; e < 64 * S / 8; e += 256) {  // 16-byte pieces of both matrices
@@ -650,7 +650,13 @@ __global__ void __launch_bounds__(256) k_fwd_y32(const __bf16* __restrict__ Fy1,
 
 hipError_t sno_fwd_y32(const void* Fy1, const void* Fy2, const void* T, int batch, int S, void* H, long long hstride,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_fwd_y32, dim3(batch), dim3(256), 0, st, (const __bf16*)Fy1, (const __bf16*)Fy2,
+  const size_t lds = (size_t)2 * 64 * (S + 8) * sizeof(__bf16);
+  if (lds > 65536) {  // above the default dynamic LDS limit (S = 256: 66 KB)
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_y32),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_fwd_y32, dim3(batch), dim3(256), lds, st, (const __bf16*)Fy1, (const __bf16*)Fy2,
                      (const __bf16*)T, S, (__bf16*)H, hstride);
   return hipGetLastError();
 }
