@@ -392,11 +392,14 @@ __global__ void __launch_bounds__(256) k_prep_lift32(const double* __restrict__ 
     bb[i] = bl[n];
   }
   bf16x8_t* hb = reinterpret_cast<bf16x8_t*>(h + (long long)b * npix * 32);
+  // S is a power of two: coordinates by mask and shift, scaled exactly by 1/S
+  const int sl = 31 - __clz(S);
+  const float rs = 1.0f / (float)S;
   for (int e = threadIdx.x; e < npix * 4; e += 256) {
     const int p = e >> 2;
     const float x0 = (float)(__bf16)(float)((fb[p] - mean) * inv);
-    const float x1 = (float)(__bf16)((float)(p % S) / (float)S);
-    const float x2 = (float)(__bf16)((float)(p / S) / (float)S);
+    const float x1 = (float)(__bf16)((float)(p & (S - 1)) * rs);
+    const float x2 = (float)(__bf16)((float)(p >> sl) * rs);
     bf16x8_t o;
 #pragma unroll
     for (int i = 0; i < 8; ++i) o[i] = (__bf16)(fmaf(x2, w2[i], fmaf(x1, w1[i], x0 * w0[i])) + bb[i]);
