@@ -297,13 +297,24 @@ __global__ void __launch_bounds__(256) k_colsum(const T* __restrict__ x, long lo
   }
 }
 
-__global__ void k_reduce_partials(const float* __restrict__ partials, int nparts, int len,
-                                  float* __restrict__ out, int accumulate) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= len) return;
+// out[j] (+)= sum over k of partials[k][j] in FP64, in a fixed order: 16 interleaved partial
+// sums per output (k = q, q + 16, ...), then those 16 in order q = 0..15. A block takes 16
+// outputs with 16 threads each.
+__global__ void __launch_bounds__(256) k_reduce_partials(const float* __restrict__ partials, int nparts, int len,
+                                                         float* __restrict__ out, int accumulate) {
+  __shared__ double sh[16][17];
+  const int jl = threadIdx.x & 15, q = threadIdx.x >> 4;
+  const int j = blockIdx.x * 16 + jl;
   double s = 0.0;
-  for (int k = 0; k < nparts; ++k) s += partials[(long long)k * len + j];
-  out[j] = accumulate ? out[j] + (float)s : (float)s;
+  if (j < len)
+    for (int k = q; k < nparts; k += 16) s += partials[(long long)k * len + j];
+  sh[q][jl] = s;
+  __syncthreads();
+  if (q == 0 && j < len) {
+    double t = 0.0;
+    for (int r = 0; r < 16; ++r) t += sh[r][jl];
+    out[j] = accumulate ? out[j] + (float)t : (float)t;
+  }
 }
 
 template <typename T>
@@ -790,8 +801,8 @@ hipError_t sno_colsum(const void* x, bool bf16, long long rows, int C, float* pa
 
 hipError_t sno_reduce_partials(const float* partials, int nparts, int len, float* out, bool accumulate,
                                hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_partials, grid1(len), dim3(256), 0, st, partials, nparts, len, out,
-                     accumulate ? 1 : 0);
+  hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, st, partials, nparts, len,
+                     out, accumulate ? 1 : 0);
   return hipGetLastError();
 }
 
