@@ -354,9 +354,12 @@ qhd_status forward(qhd_sno_s* m, const double* f, int B, hipStream_t st) {
       ST_TRY(inv_dft_y(m, m->G, B, st));
       ST_TRY(check(m, m->T1, (long long)B * m->S * 2 * m->M * C * es, "inverse y-contraction"));
       const bool next = l + 1 < m->L;
+      // the last layer projects its outputs to the logits (in the density buffer) in the same pass
+      ST_TRY(check(m, m->rho_hat, rows * 4, "logits"));
       ST_TRY(launch(m, DEV(m, sno_spectral_pointwise32(m->Gxw, m->T1, hin, m->T(m->pt, m->o_w[l]),
                                                        m->params + m->o_b[l], m->S, (long long)B * m->S, hout, 1,
-                                                       next ? m->Fx : nullptr, m->T1, st)),
+                                                       next ? m->Fx : nullptr, m->T1, m->params + m->o_wp,
+                                                       m->params + m->o_bp, next ? nullptr : m->rho_hat, st)),
                     "inverse+1x1 map+GELU"));
       continue;
     }
@@ -374,8 +377,9 @@ qhd_status forward(qhd_sno_s* m, const double* f, int B, hipStream_t st) {
                     "bias+GELU"));
     }
   }
-  void* hL = m->train ? m->h[m->L] : m->h[m->L % 2];
   ST_TRY(check(m, m->rho_hat, rows * 4, "density"));
+  if (fused) return launch(m, DEV(m, sno_softmax_rows(m->rho_hat, B, (int)npix, st)), "softmax");
+  void* hL = m->train ? m->h[m->L] : m->h[m->L % 2];
   ST_TRY(launch(m, DEV(m, sno_project_softmax(hL, m->params + m->o_wp, m->params + m->o_bp, B, (int)npix, C,
                                               m->bf16, m->rho_hat, st)), "projection"));
   return QHD_OK;

@@ -48,9 +48,13 @@ hipError_t sno_prep_lift32(const double* f, int batch, int S, const void* Wl, co
 // out = act(gx U_row + h W^T + bias); gx is S x 32, U holds a 32 x 32 block per row, S % 32 == 0.
 // With fx (32 x S) non-null, also T_row = fx out_row (the next layer's forward x-contraction) into
 // T, which may be U.
+// With q non-null (and fx null) the outputs are not stored: per pixel the logit
+// q = bp + sum_c out[c] wp[c] goes to q (nrows x S floats) instead.
 hipError_t sno_spectral_pointwise32(const void* gx, const void* U, const void* h, const void* W, const float* bias,
                                     int S, long long nrows, void* out, int act, const void* fx, void* T,
-                                    hipStream_t st);
+                                    const float* wp, const float* bp, float* q, hipStream_t st);
+// per sample, softmax of npix logits in place (as sno_project_softmax forms it)
+hipError_t sno_softmax_rows(float* rho, int batch, int npix, hipStream_t st);
 // width 32, 16 modes, BF16: per row of S pixels (nrows = batch x S), T_row (32 x 32) = fx (32 x S) X_row;
 // S % 16 == 0
 hipError_t sno_dft_x32(const void* fx, const void* X, int S, long long nrows, void* T, hipStream_t st);

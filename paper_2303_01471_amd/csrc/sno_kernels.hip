@@ -431,13 +431,17 @@ hipError_t sno_prep_lift32(const double* f, int batch, int S, const void* Wl, co
 // With NEXT the next layer's forward x-contraction T_row = fx out_row (fx 32 x S) is formed from
 // the rounded outputs while they are in registers and written over U_row (each wave reads its
 // U_row before it writes T_row, so U and T may be the same buffer).
-template <int ACT, bool NEXT>
+// With PROJ (the last layer) the rounded outputs are not stored: each is projected to its
+// pixel's logit q = bp + sum_c out[c] wp[c] (FP32, channels in order, as k_project_softmax
+// forms it) from the LDS tile, and q goes to qout.
+template <int ACT, bool NEXT, bool PROJ>
 __global__ void __launch_bounds__(256) k_spectral_pointwise32(const __bf16* __restrict__ gx, const __bf16* U,
                                                               const __bf16* __restrict__ h,
                                                               const __bf16* __restrict__ W,
                                                               const float* __restrict__ bias, int S, long long nrows,
                                                               __bf16* __restrict__ out, const __bf16* __restrict__ fx,
-                                                              __bf16* T) {
+                                                              __bf16* T, const float* __restrict__ wp,
+                                                              const float* __restrict__ bp, float* __restrict__ qout) {
   typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
   const long long row = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
@@ -489,10 +493,23 @@ __global__ void __launch_bounds__(256) k_spectral_pointwise32(const __bf16* __re
       else o1[r - 8] = o;
     }
     sno_wave_lds_sync();
-    const bf16x8_t s0 = *reinterpret_cast<const bf16x8_t*>(sw + (lane >> 2) * 40 + 8 * (lane & 3));
-    const bf16x8_t s1 = *reinterpret_cast<const bf16x8_t*>(sw + (16 + (lane >> 2)) * 40 + 8 * (lane & 3));
-    ob[x0 * 4 + lane] = s0;  // pixel x0 + lane / 4, channels 8 (lane % 4) ..
-    ob[x0 * 4 + 64 + lane] = s1;
+    if constexpr (PROJ) {
+      if (lane < 32) {  // pixel x0 + lane: its row of the tile
+        float q = bp[0];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bf16x8_t xv = *reinterpret_cast<const bf16x8_t*>(sw + lane * 40 + 8 * v);
+#pragma unroll
+          for (int i = 0; i < 8; ++i) q = fmaf((float)xv[i], wp[8 * v + i], q);
+        }
+        qout[pbase + x0 + lane] = q;
+      }
+    } else {
+      const bf16x8_t s0 = *reinterpret_cast<const bf16x8_t*>(sw + (lane >> 2) * 40 + 8 * (lane & 3));
+      const bf16x8_t s1 = *reinterpret_cast<const bf16x8_t*>(sw + (16 + (lane >> 2)) * 40 + 8 * (lane & 3));
+      ob[x0 * 4 + lane] = s0;  // pixel x0 + lane / 4, channels 8 (lane % 4) ..
+      ob[x0 * 4 + 64 + lane] = s1;
+    }
     sno_wave_lds_sync();  // the next step rewrites the tile
     if constexpr (NEXT) {
       // k slot i of lane half j holds pixel x0 + 4j + i (i < 4) or x0 + 8 + 4j + (i - 4) of the
@@ -521,19 +538,47 @@ __global__ void __launch_bounds__(256) k_spectral_pointwise32(const __bf16* __re
 
 hipError_t sno_spectral_pointwise32(const void* gx, const void* U, const void* h, const void* W, const float* bias,
                                     int S, long long nrows, void* out, int act, const void* fx, void* T,
-                                    hipStream_t st) {
+                                    const float* wp, const float* bp, float* q, hipStream_t st) {
   const unsigned blocks = (unsigned)((nrows + 3) / 4);
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, st, (const __bf16*)gx, (const __bf16*)U, (const __bf16*)h,
-                       (const __bf16*)W, bias, S, nrows, (__bf16*)out, (const __bf16*)fx, (__bf16*)T);
+                       (const __bf16*)W, bias, S, nrows, (__bf16*)out, (const __bf16*)fx, (__bf16*)T, wp, bp, q);
   };
   if (fx) {
-    if (act) go(k_spectral_pointwise32<1, true>);
-    else go(k_spectral_pointwise32<0, true>);
+    if (act) go(k_spectral_pointwise32<1, true, false>);
+    else go(k_spectral_pointwise32<0, true, false>);
+  } else if (q) {
+    if (act) go(k_spectral_pointwise32<1, false, true>);
+    else go(k_spectral_pointwise32<0, false, true>);
   } else {
-    if (act) go(k_spectral_pointwise32<1, false>);
-    else go(k_spectral_pointwise32<0, false>);
+    if (act) go(k_spectral_pointwise32<1, false, false>);
+    else go(k_spectral_pointwise32<0, false, false>);
   }
+  return hipGetLastError();
+}
+
+// per sample, rho = softmax of its logits in place: the max, the FP64 sum of exp(q - max)
+// and the scaling exactly as k_project_softmax takes them (same threads, same order)
+__global__ void __launch_bounds__(256) k_softmax_rows(float* __restrict__ rho, int npix) {
+  __shared__ double sh[256];
+  __shared__ float shf[256];
+  float* rb = rho + (long long)blockIdx.x * npix;
+  float mx = -INFINITY;
+  for (int p = threadIdx.x; p < npix; p += 256) mx = fmaxf(mx, rb[p]);
+  mx = block_max(mx, shf);
+  double s = 0.0;
+  for (int p = threadIdx.x; p < npix; p += 256) {
+    const float e = __expf(rb[p] - mx);
+    rb[p] = e;
+    s += e;
+  }
+  const double tot = block_sum(s, sh);
+  const float inv = (float)(1.0 / tot);
+  for (int p = threadIdx.x; p < npix; p += 256) rb[p] *= inv;
+}
+
+hipError_t sno_softmax_rows(float* rho, int batch, int npix, hipStream_t st) {
+  hipLaunchKernelGGL(k_softmax_rows, dim3(batch), dim3(256), 0, st, rho, npix);
   return hipGetLastError();
 }
 
