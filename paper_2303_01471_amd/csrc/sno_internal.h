@@ -40,7 +40,6 @@ hipError_t sno_prep_input(const double* f, int batch, int S, void* in, bool bf16
 // z += bias; h = z (act 0) or GELU(z) (act 1)
 hipError_t sno_bias_act(float* z, const float* bias, long long rows, int C, void* h, bool bf16, int act,
                         hipStream_t st, bool keep_z = true);
-// inference: out = act(z + h W^T + b) in BF16 for width 32 (h, W, out BF16; z, b FP32)
 // inference at width 32 in BF16: features and lift (h0 = x0 Wl^T + bl, Wl is C x 3) in one pass
 hipError_t sno_prep_lift32(const double* f, int batch, int S, const void* Wl, const float* bl, void* h,
                            hipStream_t st);
@@ -69,6 +68,7 @@ hipError_t sno_fwd_y32(const void* Fy1, const void* Fy2, const void* T, int batc
 // spectra [b][re | im][mode][channel] with sample stride spec)
 hipError_t sno_mix32(const void* H, const void* Rr, const void* Ri, int nmodes, long long spec, int batch, void* G,
                      hipStream_t st);
+// inference: out = act(z + h W^T + b) in BF16 for width 32 (h, W, out BF16; z, b FP32)
 hipError_t sno_pointwise32(const void* h, const void* W, const float* z, const float* bias, long long npix,
                            void* out, int act, hipStream_t st);
 hipError_t sno_project_softmax(const void* h, const float* wp, const float* bp, int batch, int npix,
