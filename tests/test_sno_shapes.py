@@ -30,6 +30,11 @@ SHAPES = [
     (32, 64, 1, 3, 5, (5,)),          # one mode, widest channel count
     (256, 64, 32, 2, 2, (1, 2)),
     (64, 8, 5, 2, 7, (7, 3)),         # odd mode count
+    # width 32 with 16 modes at every grid (the fused inference passes), and 8 modes
+    (32, 32, 16, 2, 4, (4, 1)),
+    (64, 32, 16, 2, 5, (5, 2)),
+    (256, 32, 16, 2, 2, (2, 1)),
+    (64, 32, 8, 2, 2, (2,)),
 ]
 
 
