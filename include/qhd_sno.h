@@ -67,7 +67,11 @@ qhd_status qhd_sno_get_params(qhd_sno sno, float *host_params);
 qhd_status qhd_sno_set_params(qhd_sno sno, const float *host_params);
 
 /* Densities for `batch` potentials: f_dev FP64 [batch][S*S] -> rho_dev FP32
- * [batch][S*S] (each row sums to 1).  Asynchronous on stream. */
+ * [batch][S*S] (each row sums to 1).  Asynchronous on stream.  On a handle created
+ * with train == 0 in BF16 at width 32 the layers run as fused matrix-core passes
+ * (with 16 modes: each layer's inverse x-contraction, 1x1 map, bias and GELU in one
+ * pass that also forms the next layer's forward x-contraction, or the logits in the
+ * last layer); the result equals the training form's to BF16 rounding. */
 qhd_status qhd_sno_forward(qhd_sno sno, const double *f_dev, int32_t batch, float *rho_dev,
                            void *stream);
 
